@@ -1,0 +1,141 @@
+"""Python face of the plain CPU SpGEMM oracle (test infrastructure).
+
+Only the tests, the smoke check and the benchmark's CPU-baseline leg may use
+this package. It wraps `spgemm_oracle.c` (sequential C, IEEE double, products
+rounded before each add) through ctypes and never touches the GPU library.
+
+Functions (each cites the passage of the paper it follows in the C source):
+  flops(A, B)             -> (f_m, max_row_flops, row_flops)    Background section
+  block_counts(B, width)  -> distinct col//width per row of B    Compression subsection
+  symbolic(A, B)          -> C.row_ptr                          Algorithm 2, line "symbolic"
+  spgemm(A, B, with_abs)  -> C (sorted columns) [, S]           Algorithm 1
+  grad(A, B, C, G)        -> (dA on pattern(A), dB on pattern(B))
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+from synth import Csr
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "spgemm_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle with gcc (-O2, no FMA contraction)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c99", "-ffp-contract=off", "-fno-fast-math",
+                               "-fPIC", "-shared", "-Wall", "-o", tmp, _SRC])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        build()
+        lib = ctypes.CDLL(_LIB)
+        P = ctypes.c_void_p
+        I = ctypes.c_int64
+        lib.spo_flops.restype = ctypes.c_int64
+        lib.spo_flops.argtypes = [I, I, P, P, P, P, P]
+        lib.spo_block_counts.restype = ctypes.c_int
+        lib.spo_block_counts.argtypes = [I, I, P, P, ctypes.c_int32, P]
+        lib.spo_symbolic.restype = ctypes.c_int
+        lib.spo_symbolic.argtypes = [I, I, I, P, P, P, P, P]
+        lib.spo_numeric.restype = ctypes.c_int
+        lib.spo_numeric.argtypes = [I, I, I, P, P, P, P, P, P, P, P, P, P]
+        lib.spo_grad.restype = ctypes.c_int
+        lib.spo_grad.argtypes = [I, I, I, P, P, P, P, P, P, P, P, P, P, P]
+        _lib = lib
+    return _lib
+
+
+def _p(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _norm(A: Csr):
+    rp = np.ascontiguousarray(A.row_ptr, dtype=np.int64)
+    ci = np.ascontiguousarray(A.col_idx, dtype=np.int32)
+    va = np.ascontiguousarray(A.values, dtype=np.float64)  # float32 widens exactly
+    return rp, ci, va
+
+
+def _check_dims(A: Csr, B: Csr):
+    if A.ncols != B.nrows:
+        raise ValueError(f"dimension mismatch: A is {A.nrows}x{A.ncols}, B is {B.nrows}x{B.ncols}")
+
+
+def flops(A: Csr, B: Csr):
+    _check_dims(A, B)
+    arp, aci, _ = _norm(A)
+    brp, _, _ = _norm(B)
+    rf = np.zeros(max(A.nrows, 1), dtype=np.int64)
+    mx = ctypes.c_int64(0)
+    fm = _load().spo_flops(A.nrows, A.ncols, _p(arp), _p(aci), _p(brp), _p(rf), ctypes.byref(mx))
+    if fm < 0:
+        raise ValueError("bad CSR input")
+    return int(fm), int(mx.value), rf[: A.nrows]
+
+
+def block_counts(B: Csr, width: int = 32) -> np.ndarray:
+    brp, bci, _ = _norm(B)
+    out = np.zeros(max(B.nrows, 1), dtype=np.int64)
+    rc = _load().spo_block_counts(B.nrows, B.ncols, _p(brp), _p(bci), width, _p(out))
+    if rc:
+        raise ValueError(f"spo_block_counts rc={rc}")
+    return out[: B.nrows]
+
+
+def symbolic(A: Csr, B: Csr) -> np.ndarray:
+    _check_dims(A, B)
+    arp, aci, _ = _norm(A)
+    brp, bci, _ = _norm(B)
+    crp = np.zeros(A.nrows + 1, dtype=np.int64)
+    rc = _load().spo_symbolic(A.nrows, A.ncols, B.ncols, _p(arp), _p(aci), _p(brp), _p(bci), _p(crp))
+    if rc:
+        raise ValueError(f"spo_symbolic rc={rc}")
+    return crp
+
+
+def spgemm(A: Csr, B: Csr, with_abs: bool = False):
+    """C = A*B in float64 with sorted columns; optionally S(i,j) = sum |a*b|."""
+    crp = symbolic(A, B)
+    arp, aci, ava = _norm(A)
+    brp, bci, bva = _norm(B)
+    nnz = int(crp[-1])
+    cci = np.zeros(max(nnz, 1), dtype=np.int32)
+    cva = np.zeros(max(nnz, 1), dtype=np.float64)
+    cab = np.zeros(max(nnz, 1), dtype=np.float64) if with_abs else None
+    rc = _load().spo_numeric(A.nrows, A.ncols, B.ncols, _p(arp), _p(aci), _p(ava),
+                             _p(brp), _p(bci), _p(bva), _p(crp), _p(cci), _p(cva),
+                             _p(cab) if with_abs else None)
+    if rc:
+        raise ValueError(f"spo_numeric rc={rc}")
+    C = Csr(A.nrows, B.ncols, crp, cci[:nnz], cva[:nnz])
+    return (C, cab[:nnz]) if with_abs else C
+
+
+def grad(A: Csr, B: Csr, C: Csr, G: np.ndarray):
+    """(dA, dB) of L = sum(G * C) over pattern(C); C must have sorted columns."""
+    _check_dims(A, B)
+    arp, aci, ava = _norm(A)
+    brp, bci, bva = _norm(B)
+    crp = np.ascontiguousarray(C.row_ptr, dtype=np.int64)
+    cci = np.ascontiguousarray(C.col_idx, dtype=np.int32)
+    g = np.ascontiguousarray(G, dtype=np.float64)
+    dA = np.zeros(max(A.nnz, 1))
+    dB = np.zeros(max(B.nnz, 1))
+    rc = _load().spo_grad(A.nrows, A.ncols, B.ncols, _p(arp), _p(aci), _p(ava),
+                          _p(brp), _p(bci), _p(bva), _p(crp), _p(cci), _p(g), _p(dA), _p(dB))
+    if rc:
+        raise ValueError(f"spo_grad rc={rc}")
+    return dA[: A.nnz], dB[: B.nnz]

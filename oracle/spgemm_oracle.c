@@ -1,0 +1,199 @@
+/*
+ * Plain sequential CPU oracle for two-phase sparse matrix-matrix multiply
+ * C = A * B on CSR.  TEST INFRASTRUCTURE ONLY: tests, the smoke check and the
+ * benchmark's CPU-baseline leg call it; the GPU library never does and shares
+ * no code, header or table with it.
+ *
+ * What it computes is the plain definition of the product (Gustavson's
+ * row-by-row formulation, Background section, Algorithm 1):
+ *   pattern(C) = { (i,j) : some k has A(i,k) and B(k,j) stored }   (structural:
+ *                entries that cancel to 0.0 stay, because the symbolic phase
+ *                never looks at values, Algorithms section, Algorithm 2)
+ *   C(i,j)     = sum over stored A(i,k) of A(i,k) * B(k,j)
+ * computed in IEEE double with each product rounded before the add (build with
+ * -ffp-contract=off), with a dense sparse-accumulator ("dense accumulator",
+ * Accumulators subsection: a value array of size k plus a marker array, the
+ * touched columns kept in a list) and the touched columns of each row sorted
+ * ascending on output.
+ *
+ * All index arithmetic is int64.  Inputs: row_ptr int64, col_idx int32,
+ * values double (callers widen float exactly).  Return codes: 0 ok,
+ * -1 bad argument or index out of range, -2 row_ptr mismatch, -3 out of memory.
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+static int check_csr(int64_t m, int64_t ncols, const int64_t *rp, const int32_t *ci) {
+    if (m < 0 || ncols < 0) return -1;
+    if (m > 0 && rp[0] != 0) return -1;
+    for (int64_t i = 0; i < m; ++i) {
+        if (rp[i + 1] < rp[i]) return -1;
+        for (int64_t e = rp[i]; e < rp[i + 1]; ++e)
+            if (ci[e] < 0 || (int64_t)ci[e] >= ncols) return -1;
+    }
+    return 0;
+}
+
+/* f_m: number of multiplications, i.e. sum over stored A(i,k) of |B(k,:)|
+ * (Background section).  row_flops (nullable) gets the per-row counts;
+ * *max_row_flops the largest one.  Returns f_m, or -1 on bad input. */
+int64_t spo_flops(int64_t m, int64_t n, const int64_t *arp, const int32_t *aci,
+                  const int64_t *brp, int64_t *row_flops, int64_t *max_row_flops) {
+    if (check_csr(m, n, arp, aci)) return -1;
+    int64_t total = 0, mx = 0;
+    for (int64_t i = 0; i < m; ++i) {
+        int64_t f = 0;
+        for (int64_t e = arp[i]; e < arp[i + 1]; ++e) {
+            int64_t r = aci[e];
+            f += brp[r + 1] - brp[r];
+        }
+        if (row_flops) row_flops[i] = f;
+        if (f > mx) mx = f;
+        total += f;
+    }
+    if (max_row_flops) *max_row_flops = mx;
+    return total;
+}
+
+/* Number of distinct column blocks col / width in each row of B: the row
+ * lengths of B after packing `width` columns into one bit-set word
+ * (Compression subsection).  Returns 0, or -1 / -3. */
+int spo_block_counts(int64_t n, int64_t k, const int64_t *brp, const int32_t *bci,
+                     int32_t width, int64_t *counts) {
+    if (width <= 0 || check_csr(n, k, brp, bci)) return -1;
+    int64_t nblk = (k + width - 1) / width;
+    int64_t *mark = (int64_t *)malloc((size_t)(nblk > 0 ? nblk : 1) * sizeof(int64_t));
+    if (!mark) return -3;
+    for (int64_t b = 0; b < nblk; ++b) mark[b] = -1;
+    for (int64_t r = 0; r < n; ++r) {
+        int64_t c = 0;
+        for (int64_t e = brp[r]; e < brp[r + 1]; ++e) {
+            int64_t blk = bci[e] / width;
+            if (mark[blk] != r) { mark[blk] = r; ++c; }
+        }
+        counts[r] = c;
+    }
+    free(mark);
+    return 0;
+}
+
+/* Symbolic phase by definition: crp[i+1]-crp[i] = |pattern(C(i,:))|,
+ * crp[0] = 0 (exclusive scan of the row sizes). */
+int spo_symbolic(int64_t m, int64_t n, int64_t k,
+                 const int64_t *arp, const int32_t *aci,
+                 const int64_t *brp, const int32_t *bci, int64_t *crp) {
+    if (check_csr(m, n, arp, aci) || check_csr(n, k, brp, bci)) return -1;
+    int64_t *mark = (int64_t *)malloc((size_t)(k > 0 ? k : 1) * sizeof(int64_t));
+    if (!mark) return -3;
+    for (int64_t j = 0; j < k; ++j) mark[j] = -1;
+    crp[0] = 0;
+    for (int64_t i = 0; i < m; ++i) {
+        int64_t cnt = 0;
+        for (int64_t e = arp[i]; e < arp[i + 1]; ++e) {
+            int64_t r = aci[e];
+            for (int64_t f = brp[r]; f < brp[r + 1]; ++f) {
+                int64_t j = bci[f];
+                if (mark[j] != i) { mark[j] = i; ++cnt; }
+            }
+        }
+        crp[i + 1] = crp[i] + cnt;
+    }
+    free(mark);
+    return 0;
+}
+
+static int cmp_i32(const void *x, const void *y) {
+    int32_t a = *(const int32_t *)x, b = *(const int32_t *)y;
+    return (a > b) - (a < b);
+}
+
+/* Numeric phase by definition.  crp must be the symbolic result.  Writes
+ * sorted columns cci and values cval; cabs (nullable) gets, per entry,
+ * sum over k of |A(i,k) * B(k,j)| (the scale the floating-point tolerances
+ * are stated against). */
+int spo_numeric(int64_t m, int64_t n, int64_t k,
+                const int64_t *arp, const int32_t *aci, const double *aval,
+                const int64_t *brp, const int32_t *bci, const double *bval,
+                const int64_t *crp, int32_t *cci, double *cval, double *cabs) {
+    if (check_csr(m, n, arp, aci) || check_csr(n, k, brp, bci)) return -1;
+    size_t kk = (size_t)(k > 0 ? k : 1);
+    int64_t *mark = (int64_t *)malloc(kk * sizeof(int64_t));
+    double *acc = (double *)malloc(kk * sizeof(double));
+    double *aab = (double *)malloc(kk * sizeof(double));
+    int32_t *touched = (int32_t *)malloc(kk * sizeof(int32_t));
+    if (!mark || !acc || !aab || !touched) {
+        free(mark); free(acc); free(aab); free(touched);
+        return -3;
+    }
+    for (int64_t j = 0; j < k; ++j) mark[j] = -1;
+    int rc = 0;
+    for (int64_t i = 0; i < m && rc == 0; ++i) {
+        int64_t nt = 0;
+        for (int64_t e = arp[i]; e < arp[i + 1]; ++e) {
+            int64_t r = aci[e];
+            double a = aval[e];
+            for (int64_t f = brp[r]; f < brp[r + 1]; ++f) {
+                int32_t j = bci[f];
+                double p = a * bval[f];
+                if (mark[j] != i) {
+                    mark[j] = i;
+                    acc[j] = 0.0;
+                    aab[j] = 0.0;
+                    touched[nt++] = j;
+                }
+                acc[j] = acc[j] + p;
+                aab[j] = aab[j] + (p < 0 ? -p : p);
+            }
+        }
+        if (crp[i + 1] - crp[i] != nt) { rc = -2; break; }
+        qsort(touched, (size_t)nt, sizeof(int32_t), cmp_i32);
+        int64_t base = crp[i];
+        for (int64_t t = 0; t < nt; ++t) {
+            int32_t j = touched[t];
+            cci[base + t] = j;
+            cval[base + t] = acc[j];
+            if (cabs) cabs[base + t] = aab[j];
+        }
+    }
+    free(mark); free(acc); free(aab); free(touched);
+    return rc;
+}
+
+/* Gradient of L = sum over pattern(C) of G(i,j) * C(i,j) with C = A * B,
+ * restricted to the stored entries of A and B:
+ *   dA(i,k) = sum over stored B(k,j) of G(i,j) * B(k,j)
+ *   dB(k,j) = sum over stored A(i,k) of A(i,k) * G(i,j)
+ * G is given on pattern(C) with sorted columns (crp, cci, gval).  Each C entry
+ * is located by binary search in its sorted row.  dA, dB are nnz(A), nnz(B). */
+static int64_t find_col(const int32_t *cci, int64_t lo, int64_t hi, int32_t j) {
+    while (lo < hi) {
+        int64_t mid = lo + (hi - lo) / 2;
+        if (cci[mid] < j) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
+int spo_grad(int64_t m, int64_t n, int64_t k,
+             const int64_t *arp, const int32_t *aci, const double *aval,
+             const int64_t *brp, const int32_t *bci, const double *bval,
+             const int64_t *crp, const int32_t *cci, const double *gval,
+             double *dA, double *dB) {
+    if (check_csr(m, n, arp, aci) || check_csr(n, k, brp, bci)) return -1;
+    int64_t nnzb = n > 0 ? brp[n] : 0;
+    for (int64_t f = 0; f < nnzb; ++f) dB[f] = 0.0;
+    for (int64_t i = 0; i < m; ++i) {
+        for (int64_t e = arp[i]; e < arp[i + 1]; ++e) {
+            int64_t r = aci[e];
+            double a = aval[e], s = 0.0;
+            for (int64_t f = brp[r]; f < brp[r + 1]; ++f) {
+                int64_t p = find_col(cci, crp[i], crp[i + 1], bci[f]);
+                if (p >= crp[i + 1] || cci[p] != bci[f]) return -2;
+                s = s + gval[p] * bval[f];
+                dB[f] = dB[f] + a * gval[p];
+            }
+            dA[e] = s;
+        }
+    }
+    return 0;
+}

@@ -1,0 +1,337 @@
+"""Pins for the CPU oracle, independent of the oracle's own code.
+
+Each test checks the oracle against something the mathematics fixes:
+closed forms of stencil products (derived from grid coordinates, never by
+multiplying), brute-force dense products on tiny inputs, counting identities
+and invariants. A dropped term, a wrong sign, a transposed operand, a lost
+structural zero or an unsorted row fails at least one of them.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+
+# ---------------------------------------------------------------- closed forms
+def closed_form_5pt_square(nx, ny):
+    """(4I - Adj)^2 = 16I - 8Adj + Adj^2 on the 5-point grid graph.
+
+    Adj^2(p,p) = deg(p); Adj^2(p,q) = 2 for diagonal neighbours (two paths),
+    1 for axial distance-2 neighbours. Built from coordinates only.
+    """
+    rows = []
+    for y in range(ny):
+        for x in range(nx):
+            ent = {}
+            deg = (x > 0) + (x < nx - 1) + (y > 0) + (y < ny - 1)
+            for dy in range(-2, 3):
+                for dx in range(-2, 3):
+                    qx, qy = x + dx, y + dy
+                    if not (0 <= qx < nx and 0 <= qy < ny):
+                        continue
+                    d1 = abs(dx) + abs(dy)
+                    q = qy * nx + qx
+                    if d1 == 0:
+                        ent[q] = 16.0 + deg
+                    elif d1 == 1:
+                        ent[q] = -8.0
+                    elif abs(dx) == 1 and abs(dy) == 1:
+                        ent[q] = 2.0
+                    elif d1 == 2:
+                        ent[q] = 1.0
+            rows.append(sorted(ent.items()))
+    return rows
+
+
+def assert_rows_equal(C, rows):
+    assert C.nrows == len(rows)
+    for i, r in enumerate(rows):
+        s, e = C.row_ptr[i], C.row_ptr[i + 1]
+        assert list(C.col_idx[s:e]) == [q for q, _ in r], f"row {i} pattern"
+        assert list(C.values[s:e]) == [v for _, v in r], f"row {i} values"
+
+
+@pytest.mark.parametrize("nx,ny", [(1, 1), (2, 3), (7, 5), (16, 16)])
+def test_5pt_square_closed_form_small(nx, ny):
+    A = synth.laplace2d_5pt(nx, ny)
+    assert_rows_equal(oracle.spgemm(A, A), closed_form_5pt_square(nx, ny))
+
+
+def test_5pt_square_64x64_counts_and_values():
+    A = synth.laplace2d_5pt(64, 64)
+    C = oracle.spgemm(A, A)
+    fm, maxrf, _ = oracle.flops(A, A)
+    assert A.nnz == 5 * 64 * 64 - 2 * 128 == 20224
+    assert fm == 100104 and maxrf == 25
+    assert C.nnz == 51972 and np.diff(C.row_ptr).max() == 13
+    assert_rows_equal(C, closed_form_5pt_square(64, 64))
+    # diagonal value classes: 20 interior, 19 edge, 18 corner
+    diag = np.array([C.values[C.row_ptr[i] + np.searchsorted(C.col_idx[C.row_ptr[i]:C.row_ptr[i + 1]], i)]
+                     for i in range(C.nrows)])
+    assert (diag == 20).sum() == 62 * 62 and (diag == 19).sum() == 4 * 62 and (diag == 18).sum() == 4
+
+
+def closed_form_27pt_square_row(g, p):
+    """Row p of (27I - J)^2 = 729I - 54J + K^2 (x) K^2 (x) K^2, K = tridiag(1,1,1).
+
+    K^2(x,y) on a line of g points: deg1(x) (2 or 3) on the diagonal, 2 at
+    distance 1, 1 at distance 2.
+    """
+    x, y, z = p % g, (p // g) % g, p // (g * g)
+
+    def k2(a, b):
+        d = abs(a - b)
+        if d == 0:
+            return 1 + (a > 0) + (a < g - 1)
+        return {1: 2, 2: 1}.get(d, 0)
+
+    out = []
+    for dz in range(-2, 3):
+        for dy in range(-2, 3):
+            for dx in range(-2, 3):
+                qx, qy, qz = x + dx, y + dy, z + dz
+                if not (0 <= qx < g and 0 <= qy < g and 0 <= qz < g):
+                    continue
+                q = qz * g * g + qy * g + qx
+                jv = 1 if max(abs(dx), abs(dy), abs(dz)) <= 1 else 0
+                v = 729 * (q == p) - 54 * jv + k2(x, qx) * k2(y, qy) * k2(z, qz)
+                out.append((q, float(v)))
+    return out
+
+
+@pytest.mark.parametrize("g", [1, 2, 3, 6])
+def test_27pt_square_closed_form_small(g):
+    A = synth.stencil27(g)
+    C = oracle.spgemm(A, A)
+    assert_rows_equal(C, [closed_form_27pt_square_row(g, p) for p in range(g ** 3)])
+    if g >= 2:
+        fm, maxrf, _ = oracle.flops(A, A)
+        assert fm == (9 * g - 10) ** 3 or g < 2
+        assert C.nnz == (5 * g - 6) ** 3
+
+
+@pytest.mark.slow
+def test_27pt_square_100cubed():
+    """Full config: nnz = 494^3, f_m = 890^3, maxrs 125, maxrf 729; sampled rows exact."""
+    g = 100
+    A = synth.stencil27(g)
+    assert A.nnz == 26463592
+    fm, maxrf, _ = oracle.flops(A, A)
+    assert fm == 890 ** 3 == 704969000 and maxrf == 729
+    C = oracle.spgemm(A, A)
+    assert C.nnz == 494 ** 3 == 120553784
+    assert np.diff(C.row_ptr).max() == 125
+    assert C.values.min() == -46.0 and C.values.max() == 702.0 and not (C.values == 0).any()
+    rng = np.random.default_rng(5)
+    for p in list(rng.integers(0, g ** 3, 300)) + [0, g ** 3 - 1, 505050]:
+        s, e = C.row_ptr[p], C.row_ptr[p + 1]
+        ref = closed_form_27pt_square_row(g, int(p))
+        assert list(C.col_idx[s:e]) == [q for q, _ in ref]
+        assert list(C.values[s:e]) == [v for _, v in ref]
+
+
+def galerkin_coarse_closed_form(h):
+    """P^T A P for the 27-point operator and 2x2x2 aggregation on (2h)^3.
+
+    Sum over fine pairs factorises per dimension: aggregate pair (a,b) on one
+    axis contributes 4 fine neighbour pairs if a == b, 1 if |a-b| == 1, else 0;
+    so the coarse entry is 27*8*[I==J] - prod_d s_d = 152 / -16 / -4 / -1.
+    """
+    rows = []
+    for p in range(h ** 3):
+        x, y, z = p % h, (p // h) % h, p // (h * h)
+        r = []
+        for dz in (-1, 0, 1):
+            for dy in (-1, 0, 1):
+                for dx in (-1, 0, 1):
+                    qx, qy, qz = x + dx, y + dy, z + dz
+                    if not (0 <= qx < h and 0 <= qy < h and 0 <= qz < h):
+                        continue
+                    s = 1
+                    for d in (dx, dy, dz):
+                        s *= 4 if d == 0 else 1
+                    v = 27 * 8 * ((dx, dy, dz) == (0, 0, 0)) - s
+                    r.append((qz * h * h + qy * h + qx, float(v)))
+        rows.append(r)
+    return rows
+
+
+@pytest.mark.parametrize("g", [2, 4, 8])
+def test_galerkin_closed_form_and_association(g):
+    A = synth.stencil27(g)
+    P, Pt = synth.aggregation_2x2x2(g)
+    AP = oracle.spgemm(A, P)
+    assert AP.nnz == (2 * g - 2) ** 3  # per axis: 2 aggregates reached, 1 at the two ends
+    fm_ap, _, _ = oracle.flops(A, P)
+    assert fm_ap == A.nnz  # P has one entry per row
+    R = oracle.spgemm(Pt, AP)
+    assert_rows_equal(R, galerkin_coarse_closed_form(g // 2))
+    # association: (P^T A) P has the identical pattern and values
+    PtA = oracle.spgemm(Pt, A)
+    R2 = oracle.spgemm(PtA, P)
+    assert np.array_equal(R.row_ptr, R2.row_ptr)
+    assert np.array_equal(R.col_idx, R2.col_idx)
+    assert np.array_equal(R.values, R2.values)
+    # f_m(R*A) == f_m(A*P) for symmetric A, R = P^T (paired multigrid rows of Table 3)
+    assert oracle.flops(Pt, A)[0] == oracle.flops(A, P)[0]
+
+
+@pytest.mark.slow
+def test_galerkin_100cubed_counts():
+    g = 100
+    A = synth.stencil27(g)
+    P, Pt = synth.aggregation_2x2x2(g)
+    AP = oracle.spgemm(A, P)
+    assert AP.nnz == 198 ** 3 == 7762392
+    R = oracle.spgemm(Pt, AP)
+    assert R.nnz == 148 ** 3 == 3241792
+    vals = set(np.unique(R.values).tolist())
+    assert vals == {152.0, -16.0, -4.0, -1.0}
+    rs = np.add.reduceat(R.values, R.row_ptr[:-1])
+    h = 50
+    c = np.arange(h ** 3)
+    cx, cy, cz = c % h, (c // h) % h, c // (h * h)
+    interior = (cx > 0) & (cx < h - 1) & (cy > 0) & (cy < h - 1) & (cz > 0) & (cz < h - 1)
+    assert interior.sum() == 110592 and np.all(rs[interior] == 0)
+
+
+# ---------------------------------------------------------------- brute force
+def _cases():
+    rng = np.random.default_rng(1234)
+    out = []
+    for t in range(160):
+        m, n, k = (int(v) for v in rng.integers(0, 41, 3))
+        if t % 17 == 0:
+            k = 1
+        dA, dB = float(rng.uniform(0, 0.6)), float(rng.uniform(0, 0.6))
+        out.append((m, n, k, dA, dB, t))
+    out += [(0, 0, 0, 0.5, 0.5, 1001), (5, 0, 7, 0.5, 0.5, 1002), (0, 4, 3, 0.5, 0.5, 1003),
+            (6, 6, 6, 0.0, 0.5, 1004), (6, 6, 6, 1.0, 1.0, 1005), (40, 40, 40, 1.0, 1.0, 1006)]
+    return out
+
+
+@pytest.mark.parametrize("m,n,k,dA,dB,seed", _cases())
+def test_bruteforce_dense(m, n, k, dA, dB, seed):
+    A = synth.shuffle_columns(synth.tiny_random(m, n, dA, seed, "int", zero_frac=0.2), seed)
+    B = synth.shuffle_columns(synth.tiny_random(n, k, dB, seed + 7, "int", zero_frac=0.2), seed + 1)
+    C = oracle.spgemm(A, B)
+    pat = (synth.pattern_dense(A) @ synth.pattern_dense(B)) > 0
+    assert C.nnz == int(pat.sum())
+    assert np.array_equal(synth.pattern_dense(C).astype(bool), pat)
+    for i in range(C.nrows):  # strictly increasing columns
+        assert np.all(np.diff(C.col_idx[C.row_ptr[i]:C.row_ptr[i + 1]]) > 0)
+    # small integers: every partial sum is exact, so dense equality is exact
+    assert np.array_equal(synth.to_dense(C), synth.to_dense(A) @ synth.to_dense(B))
+    fm, maxrf, rf = oracle.flops(A, B)
+    # f_m counted column-wise: B(j,:) is read once per stored A(:,j)
+    colcnt = np.bincount(A.col_idx, minlength=n) if A.nnz else np.zeros(n, np.int64)
+    assert fm == int((colcnt * B.row_lengths()).sum()) if n else fm == 0
+    assert C.nnz <= fm
+    assert np.array_equal(np.diff(oracle.symbolic(A, B)), C.row_lengths())
+
+
+def test_structural_zeros_kept():
+    # A = [1 1], B = [[1],[-1]] -> C = [0] stored
+    A = synth.Csr(1, 2, np.array([0, 2]), np.array([0, 1], np.int32), np.array([1.0, 1.0]))
+    B = synth.Csr(2, 1, np.array([0, 1, 2]), np.array([0, 0], np.int32), np.array([1.0, -1.0]))
+    C = oracle.spgemm(A, B)
+    assert C.nnz == 1 and C.values[0] == 0.0
+
+
+def test_rows_with_nothing():
+    A = synth.tiny_random(30, 20, 0.3, 3)
+    B = synth.tiny_random(20, 25, 0.0, 4)  # B has no entries at all
+    C = oracle.spgemm(A, B)
+    assert C.nnz == 0 and np.all(C.row_ptr == 0)
+
+
+def test_row_sum_invariant_normal_values():
+    A = synth.random_csr(300, 200, np.random.default_rng(0).integers(0, 30, 300), 11)
+    B = synth.random_csr(200, 500, np.random.default_rng(1).integers(0, 30, 200), 12)
+    C, S = oracle.spgemm(A, B, with_abs=True)
+    ones = np.ones(500)
+    lhs = np.add.reduceat(np.append(C.values, 0), C.row_ptr[:-1])[:300] * (np.diff(C.row_ptr) > 0)
+    Bd = synth.to_dense(B)
+    rhs = synth.to_dense(A) @ (Bd @ ones)
+    scale = synth.to_dense(A.with_values(np.abs(A.values))) @ (np.abs(Bd) @ ones)
+    assert np.all(np.abs(lhs - rhs) <= 1e-12 * np.maximum(scale, 1e-300))
+    assert np.all(S >= np.abs(C.values))
+
+
+def test_transpose_pattern_identity():
+    A = synth.tiny_random(25, 30, 0.2, 8)
+    B = synth.tiny_random(30, 35, 0.2, 9)
+
+    def T(M):
+        D = synth.to_dense(M).T
+        pd = synth.pattern_dense(M).T
+        rows, cols = np.nonzero(pd)
+        rp = np.zeros(D.shape[0] + 1, np.int64)
+        np.cumsum(np.bincount(rows, minlength=D.shape[0]), out=rp[1:])
+        return synth.Csr(D.shape[0], D.shape[1], rp, cols.astype(np.int32), D[rows, cols])
+
+    C = oracle.spgemm(A, B)
+    Ct = oracle.spgemm(T(B), T(A))
+    assert np.array_equal(synth.pattern_dense(C).T, synth.pattern_dense(Ct))
+    assert np.array_equal(synth.to_dense(C).T, synth.to_dense(Ct))
+
+
+def test_block_counts():
+    B = synth.shuffle_columns(synth.tiny_random(40, 300, 0.1, 21), 2)
+    for w in (1, 8, 32, 64):
+        want = [len({int(c) // w for c in B.col_idx[B.row_ptr[r]:B.row_ptr[r + 1]]}) for r in range(40)]
+        assert list(oracle.block_counts(B, w)) == want
+    assert np.array_equal(oracle.block_counts(B, 1), B.row_lengths())
+
+
+def test_dimension_mismatch_raises():
+    A = synth.tiny_random(3, 4, 0.5, 1)
+    B = synth.tiny_random(5, 2, 0.5, 2)
+    with pytest.raises(ValueError):
+        oracle.spgemm(A, B)
+
+
+# ---------------------------------------------------------------- gradient
+@pytest.mark.parametrize("seed", range(12))
+def test_grad_matches_dense_formula(seed):
+    rng = np.random.default_rng(seed)
+    m, n, k = (int(v) for v in rng.integers(1, 30, 3))
+    A = synth.shuffle_columns(synth.tiny_random(m, n, 0.3, seed, "int"), seed)
+    B = synth.tiny_random(n, k, 0.3, seed + 50, "int")
+    C = oracle.spgemm(A, B)
+    G = rng.integers(-3, 4, C.nnz).astype(np.float64)
+    dA, dB = oracle.grad(A, B, C, G)
+    Gd = synth.to_dense(C.with_values(G))
+    ref_dA = Gd @ synth.to_dense(B).T
+    ref_dB = synth.to_dense(A).T @ Gd
+    ra = np.repeat(np.arange(m), A.row_lengths())
+    rb = np.repeat(np.arange(n), B.row_lengths())
+    assert np.array_equal(dA, ref_dA[ra, A.col_idx])
+    assert np.array_equal(dB, ref_dB[rb, B.col_idx])
+
+
+def test_grad_finite_difference():
+    """L(A,B) = sum(G*C) is bilinear, so central differences are exact up to rounding."""
+    rng = np.random.default_rng(3)
+    A = synth.random_csr(20, 15, rng.integers(1, 6, 20), 1)
+    B = synth.random_csr(15, 25, rng.integers(1, 6, 15), 2)
+    C = oracle.spgemm(A, B)
+    G = rng.standard_normal(C.nnz)
+    dA, dB = oracle.grad(A, B, C, G)
+
+    def L(Av, Bv):
+        Cv = oracle.spgemm(A.with_values(Av), B.with_values(Bv))
+        return float(np.dot(Cv.values, G))
+
+    h = 1e-6
+    for e in rng.integers(0, A.nnz, 10):
+        ap, am = A.values.copy(), A.values.copy()
+        ap[e] += h
+        am[e] -= h
+        assert abs((L(ap, B.values) - L(am, B.values)) / (2 * h) - dA[e]) < 1e-7
+    for f in rng.integers(0, B.nnz, 10):
+        bp, bm = B.values.copy(), B.values.copy()
+        bp[f] += h
+        bm[f] -= h
+        assert abs((L(A.values, bp) - L(A.values, bm)) / (2 * h) - dB[f]) < 1e-7
