@@ -1,0 +1,196 @@
+/*
+ * spgemm.h -- C ABI of the MI355X (gfx950) two-phase sparse matrix-matrix
+ * multiply C = A * B on CSR (Deveci, Trott, Rajamanickam, "Multi-threaded
+ * Sparse Matrix-Matrix Multiplication for Many-Core and GPU Architectures").
+ *
+ * The product is computed in the paper's two phases (Algorithms section,
+ * Algorithm 2):
+ *   1. spgemm_symbolic: compress B into column-set bit words (Compression
+ *      subsection), find the size of every row of C by a union of those words
+ *      (core kernel, Algorithm 3, symbolic branch), exclusive-scan the sizes
+ *      into C.row_ptr and return nnz(C) so the caller can allocate C.
+ *   2. spgemm_numeric: Gustavson row-by-row multiply-accumulate (Background
+ *      section, Algorithm 1; Algorithm 3, numeric branch) writing C.col_idx
+ *      (strictly increasing per row) and C.values.
+ * The symbolic result is kept in the handle, so spgemm_numeric can be called
+ * again with new values on the same structure (the reuse case the paper argues
+ * for in its Background section and measures as "Reuse" in Experiments).
+ *
+ * Conventions (every entry point):
+ *  - Pointers inside spg_csr / spg_csr_out are DEVICE pointers (memory the
+ *    caller allocated on the GPU the handle was created on) unless the
+ *    parameter says "host".
+ *  - Every call returns an spg_status; nothing is thrown across the ABI.
+ *    Arguments are validated before any launch.  HIP runtime failures map to
+ *    SPG_ERR_HIP; spg_last_error(h) gives the text of the last failure.
+ *  - All device work is enqueued on the handle's stream, in stream order.
+ *    Inputs are borrowed: they must stay valid until the stream has reached
+ *    the call.  spgemm_symbolic blocks the host twice (to read global flop
+ *    counts and nnz(C)); spgemm_numeric never blocks the host.
+ *  - The handle owns all scratch memory (compressed B, row bins, per-row
+ *    windows, spill arenas); the caller owns A, B and C.
+ *  - A handle is not thread-safe: use one handle per host thread / stream.
+ *  - Indices: col_idx is always int32.  row_ptr is int32 or int64
+ *    (spg_itype).  Input rows may hold columns in any order but no duplicate
+ *    column within a row.  Stored zeros are structure.
+ */
+#ifndef SPGEMM_MI355X_H
+#define SPGEMM_MI355X_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SPG_OK = 0,
+    SPG_ERR_INVALID_ARG = 1,        /* NULL pointer, negative size, bad enum, bad CSR */
+    SPG_ERR_DIM_MISMATCH = 2,       /* A.ncols != B.nrows, or C's shape is not m x k */
+    SPG_ERR_INDEX_OVERFLOW = 3,     /* nnz(C) does not fit the requested row_ptr type */
+    SPG_ERR_OUT_OF_MEMORY = 4,      /* device allocation failed, or a scratch limit */
+    SPG_ERR_NOT_READY = 5,          /* numeric called before a successful symbolic */
+    SPG_ERR_STRUCTURE_MISMATCH = 6, /* numeric inputs differ from the symbolic ones */
+    SPG_ERR_HIP = 7,                /* HIP runtime error (text in spg_last_error) */
+    SPG_ERR_UNSUPPORTED = 8,        /* valid input this build does not handle */
+    SPG_ERR_INTERNAL = 9
+} spg_status;
+
+typedef enum { SPG_F64 = 0, SPG_F32 = 1 } spg_dtype;
+typedef enum { SPG_I32 = 0, SPG_I64 = 1 } spg_itype;
+
+/* Accumulator selection for every row of C (Accumulators subsection). */
+typedef enum {
+    SPG_ACC_AUTO = 0,   /* per-row choice by the library's selector */
+    SPG_ACC_DENSE = 1,  /* bit-window dense accumulator where it fits, else hash */
+    SPG_ACC_HASH = 2,   /* linear-probing hash (LDS level 1, HBM level 2) */
+    SPG_ACC_HASH_L2 = 3 /* two-level hash for every non-empty row (tests the spill path) */
+} spg_accumulator;
+
+/* Floating-point forms of the numeric phase for FP32 values. */
+typedef enum {
+    SPG_FP32_PLAIN = 0,       /* FP32 products, FP32 accumulation */
+    SPG_FP32_COMPENSATED = 1, /* FP32 with a compensated (TwoSum / TwoProduct) pair per entry */
+    SPG_FP32_WIDE = 2         /* FP32 inputs and outputs, FP64 accumulation */
+} spg_fp32_mode;
+
+/* Read-only CSR operand.  values may be NULL for the symbolic phase. */
+typedef struct {
+    int64_t nrows, ncols, nnz;
+    spg_itype rp_type;
+    const void *row_ptr;      /* nrows+1 entries of rp_type, row_ptr[0] == 0 */
+    const int32_t *col_idx;   /* nnz entries in [0, ncols) */
+    const void *values;       /* nnz entries of dtype */
+    spg_dtype dtype;
+} spg_csr;
+
+/* Output CSR: row_ptr holds the symbolic result (read), col_idx and values
+ * are written by the numeric phase; nnz must equal the symbolic nnz(C). */
+typedef struct {
+    int64_t nrows, ncols, nnz;
+    spg_itype rp_type;
+    const void *row_ptr;
+    int32_t *col_idx;
+    void *values;
+    spg_dtype dtype;
+} spg_csr_out;
+
+typedef struct {
+    /* Compression of B for the symbolic phase (Compression subsection):
+     * -1 = compress only if it removes more than (1 - cf_threshold) of the
+     * flops, 0 = never, 1 = always. */
+    int32_t compression;
+    double cf_threshold;          /* 0.85: the paper's "more than 15%" rule */
+    int32_t accumulator;          /* spg_accumulator */
+    int32_t fp32_mode;            /* spg_fp32_mode, FP32 values only */
+    int64_t fp64_heavy_row_flops; /* FP32: rows with at least this many flops
+                                     accumulate in FP64 (0 = never) */
+    int32_t l1_hash_slots;        /* cap on LDS hash slots for the two-level
+                                     hash (0 = sized by LDS); small values force
+                                     level-2 spills */
+    int32_t autotune;             /* 1 = time candidate kernels on sampled rows
+                                     during symbolic and keep the fastest */
+} spg_options;
+
+typedef struct {
+    int64_t flops;                  /* f_m: number of multiplications */
+    int64_t flops_compressed;       /* symbolic inserts after compression */
+    int64_t max_row_flops;          /* maxrf */
+    int64_t max_row_flops_compressed;
+    int64_t nnz_c;                  /* nnz(C) */
+    int64_t max_row_nnz;            /* maxrs */
+    int64_t nnz_b_compressed;       /* (column-set index, column-set) pairs */
+    int32_t compressed;             /* 1 if the symbolic phase used compressed B */
+    int32_t n_kinds;
+    int64_t rows_symbolic[8];       /* rows per symbolic kernel kind */
+    int64_t rows_numeric[8];        /* rows per numeric kernel kind */
+    int32_t l2_spill_rows;          /* rows that used the level-2 (HBM) hash */
+    int32_t reserved[7];
+} spg_stats;
+
+typedef struct spg_handle_s *spg_handle;
+
+/* Fill *opt with the defaults (compression -1, cf_threshold 0.85, AUTO,
+ * FP32_PLAIN, no FP64 heavy rows, LDS-sized hash, no autotune). */
+void spg_default_options(spg_options *opt);
+
+/* Create a handle on the current HIP device.  hip_stream is a hipStream_t
+ * (NULL = the legacy default stream).  opt may be NULL (defaults); it is
+ * copied.  Errors: INVALID_ARG (h NULL or bad option), HIP. */
+spg_status spg_create(spg_handle *h, void *hip_stream, const spg_options *opt);
+
+/* Release the handle and all scratch it owns (synchronises its stream). */
+spg_status spg_destroy(spg_handle h);
+
+/* Change the stream later calls enqueue on. */
+spg_status spg_set_stream(spg_handle h, void *hip_stream);
+
+/* Replace the options.  Takes effect at the next spgemm_symbolic. */
+spg_status spg_set_options(spg_handle h, const spg_options *opt);
+
+/* Symbolic phase (Algorithm 2, compress + symbolic lines; Algorithm 3).
+ * A: m x n, B: n x k (values are not read).  C_row_ptr: device array of m+1
+ * entries of c_rp_type, caller-allocated, written with the exclusive scan of
+ * the row sizes of C.  *nnz_c (host) receives nnz(C).  The handle keeps the
+ * plan for spgemm_numeric.  Errors: INVALID_ARG, DIM_MISMATCH,
+ * INDEX_OVERFLOW (nnz(C) > INT32_MAX with SPG_I32), OUT_OF_MEMORY,
+ * UNSUPPORTED, HIP. */
+spg_status spgemm_symbolic(spg_handle h, const spg_csr *A, const spg_csr *B,
+                           void *C_row_ptr, spg_itype c_rp_type, int64_t *nnz_c);
+
+/* Numeric phase (Algorithm 2, numeric line; Algorithm 3; Algorithm 1).
+ * A and B must have the structure (dims, nnz, row_ptr and col_idx pointers)
+ * given to the last spgemm_symbolic on this handle; values may change.
+ * C->row_ptr must be the array the symbolic phase wrote; C->col_idx (nnz_c
+ * int32) and C->values (nnz_c of C->dtype) are written.  A, B and C must share
+ * one dtype.  Columns come out strictly increasing per row.  Never blocks the
+ * host.  Errors: INVALID_ARG, NOT_READY, STRUCTURE_MISMATCH, UNSUPPORTED,
+ * OUT_OF_MEMORY, HIP. */
+spg_status spgemm_numeric(spg_handle h, const spg_csr *A, const spg_csr *B, spg_csr_out *C);
+
+/* Synchronise the handle's stream and report errors the device found since
+ * the last check: STRUCTURE_MISMATCH if a numeric call met a row whose size
+ * differs from the plan (the caller changed A or B's structure in place; that
+ * row was left unwritten), OUT_OF_MEMORY if a level-2 table did not fit its
+ * arena slice.  Clears the device flags.  spgemm_numeric itself never blocks,
+ * so this is how a caller confirms a numeric result. */
+spg_status spg_check_errors(spg_handle h);
+
+/* Statistics of the last symbolic phase (host struct). */
+spg_status spg_get_stats(spg_handle h, spg_stats *out);
+
+/* Static text for a status code. */
+const char *spg_status_string(spg_status s);
+
+/* Text of the last error on this handle ("" if none).  Valid until the next
+ * call on the handle. */
+const char *spg_last_error(spg_handle h);
+
+/* Library version string. */
+const char *spg_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SPGEMM_MI355X_H */

@@ -1,0 +1,275 @@
+"""Python binding of the gfx950 two-phase SpGEMM library (libspgemm_mi355x.so).
+
+Argument marshalling only: every step of the product runs in the HIP kernels
+behind the C ABI declared in include/spgemm.h.  PyTorch supplies device memory
+(tensors) and the stream.  If the compiled library is missing, the first call
+into it raises ImportError: there is no CPU fallback.
+
+    h = Handle()                                   # spg_create
+    rp, nnz = spgemm_symbolic(h, A, B)             # C.row_ptr (device), nnz(C)
+    C = spgemm_numeric(h, A, B, rp, nnz)           # DeviceCsr with sorted columns
+    spgemm_numeric(h, A2, B2, rp, nnz, out=C)      # reuse: new values, same structure
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import torch  # imported first so the library binds to torch's HIP runtime
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libspgemm_mi355x.so")
+
+_lib = None
+
+
+def lib():
+    """The loaded C library; raises if it was not built (no CPU fallback exists)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1801_03065_amd.build` "
+                              "(there is no CPU fallback)")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _sigs.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+# ----------------------------------------------------------------- C types
+SPG_OK, SPG_ERR_INVALID_ARG, SPG_ERR_DIM_MISMATCH, SPG_ERR_INDEX_OVERFLOW = 0, 1, 2, 3
+SPG_ERR_OUT_OF_MEMORY, SPG_ERR_NOT_READY, SPG_ERR_STRUCTURE_MISMATCH = 4, 5, 6
+SPG_ERR_HIP, SPG_ERR_UNSUPPORTED, SPG_ERR_INTERNAL = 7, 8, 9
+SPG_F64, SPG_F32 = 0, 1
+SPG_I32, SPG_I64 = 0, 1
+ACC_AUTO, ACC_DENSE, ACC_HASH, ACC_HASH_L2 = 0, 1, 2, 3
+FP32_PLAIN, FP32_COMPENSATED, FP32_WIDE = 0, 1, 2
+KIND_NAMES = ("empty", "dense_wave", "hash_wave", "dense_wg", "hash_two_level")
+
+
+class spg_csr(ctypes.Structure):
+    _fields_ = [("nrows", ctypes.c_int64), ("ncols", ctypes.c_int64), ("nnz", ctypes.c_int64),
+                ("rp_type", ctypes.c_int), ("row_ptr", ctypes.c_void_p), ("col_idx", ctypes.c_void_p),
+                ("values", ctypes.c_void_p), ("dtype", ctypes.c_int)]
+
+
+class spg_csr_out(ctypes.Structure):
+    _fields_ = spg_csr._fields_
+
+
+class spg_options(ctypes.Structure):
+    _fields_ = [("compression", ctypes.c_int32), ("cf_threshold", ctypes.c_double),
+                ("accumulator", ctypes.c_int32), ("fp32_mode", ctypes.c_int32),
+                ("fp64_heavy_row_flops", ctypes.c_int64), ("l1_hash_slots", ctypes.c_int32),
+                ("autotune", ctypes.c_int32)]
+
+
+class spg_stats(ctypes.Structure):
+    _fields_ = [("flops", ctypes.c_int64), ("flops_compressed", ctypes.c_int64),
+                ("max_row_flops", ctypes.c_int64), ("max_row_flops_compressed", ctypes.c_int64),
+                ("nnz_c", ctypes.c_int64), ("max_row_nnz", ctypes.c_int64),
+                ("nnz_b_compressed", ctypes.c_int64), ("compressed", ctypes.c_int32),
+                ("n_kinds", ctypes.c_int32), ("rows_symbolic", ctypes.c_int64 * 8),
+                ("rows_numeric", ctypes.c_int64 * 8), ("l2_spill_rows", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 7)]
+
+
+_P = ctypes.c_void_p
+_S = ctypes.c_int
+_sigs = {
+    "spg_default_options": (None, [ctypes.POINTER(spg_options)]),
+    "spg_create": (_S, [ctypes.POINTER(_P), _P, ctypes.POINTER(spg_options)]),
+    "spg_destroy": (_S, [_P]),
+    "spg_set_stream": (_S, [_P, _P]),
+    "spg_set_options": (_S, [_P, ctypes.POINTER(spg_options)]),
+    "spgemm_symbolic": (_S, [_P, ctypes.POINTER(spg_csr), ctypes.POINTER(spg_csr), _P, _S,
+                             ctypes.POINTER(ctypes.c_int64)]),
+    "spgemm_numeric": (_S, [_P, ctypes.POINTER(spg_csr), ctypes.POINTER(spg_csr), ctypes.POINTER(spg_csr_out)]),
+    "spg_check_errors": (_S, [_P]),
+    "spg_get_stats": (_S, [_P, ctypes.POINTER(spg_stats)]),
+    "spg_status_string": (ctypes.c_char_p, [_S]),
+    "spg_last_error": (ctypes.c_char_p, [_P]),
+    "spg_version": (ctypes.c_char_p, []),
+}
+
+
+class SpgemmError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{lib().spg_status_string(status).decode()} ({status}): {msg}")
+        self.status = status
+
+
+def version() -> str:
+    return lib().spg_version().decode()
+
+
+# ----------------------------------------------------------------- operands
+@dataclass
+class DeviceCsr:
+    """CSR on the GPU: row_ptr int32/int64, col_idx int32, values float64/float32."""
+
+    nrows: int
+    ncols: int
+    row_ptr: torch.Tensor
+    col_idx: torch.Tensor
+    values: torch.Tensor | None
+
+    @property
+    def nnz(self) -> int:
+        return int(self.col_idx.numel())
+
+    @staticmethod
+    def from_arrays(nrows, ncols, row_ptr, col_idx, values, device="cuda", rp_dtype=torch.int32,
+                    dtype=torch.float64) -> "DeviceCsr":
+        rp = torch.as_tensor(row_ptr).to(device=device, dtype=rp_dtype)
+        ci = torch.as_tensor(col_idx).to(device=device, dtype=torch.int32)
+        va = None if values is None else torch.as_tensor(values).to(device=device, dtype=dtype)
+        return DeviceCsr(int(nrows), int(ncols), rp.contiguous(), ci.contiguous(),
+                         None if va is None else va.contiguous())
+
+    def with_values(self, values: torch.Tensor) -> "DeviceCsr":
+        return DeviceCsr(self.nrows, self.ncols, self.row_ptr, self.col_idx, values.contiguous())
+
+
+def _itype(t: torch.Tensor) -> int:
+    if t.dtype == torch.int32:
+        return SPG_I32
+    if t.dtype == torch.int64:
+        return SPG_I64
+    raise TypeError(f"row_ptr must be int32 or int64, got {t.dtype}")
+
+
+def _dtype(t: torch.Tensor | None) -> int:
+    if t is None:
+        return SPG_F64
+    if t.dtype == torch.float64:
+        return SPG_F64
+    if t.dtype == torch.float32:
+        return SPG_F32
+    raise TypeError(f"values must be float64 or float32, got {t.dtype}")
+
+
+def _check_dev(t: torch.Tensor | None, what: str):
+    if t is not None and (not t.is_cuda or not t.is_contiguous()):
+        raise ValueError(f"{what} must be a contiguous GPU tensor")
+
+
+def _csr(M: DeviceCsr) -> spg_csr:
+    _check_dev(M.row_ptr, "row_ptr")
+    _check_dev(M.col_idx, "col_idx")
+    _check_dev(M.values, "values")
+    if M.col_idx.dtype != torch.int32:
+        raise TypeError("col_idx must be int32")
+    return spg_csr(M.nrows, M.ncols, M.nnz, _itype(M.row_ptr), M.row_ptr.data_ptr(),
+                   M.col_idx.data_ptr() if M.nnz else None,
+                   M.values.data_ptr() if (M.values is not None and M.nnz) else None, _dtype(M.values))
+
+
+def options(**kw) -> spg_options:
+    o = spg_options()
+    lib().spg_default_options(ctypes.byref(o))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise KeyError(k)
+        setattr(o, k, v)
+    return o
+
+
+# ----------------------------------------------------------------- handle
+class Handle:
+    """spg_create / spg_destroy; holds the symbolic plan for reuse."""
+
+    def __init__(self, stream: torch.cuda.Stream | None = None, **opts):
+        torch.cuda.init()
+        s = (stream or torch.cuda.current_stream()).cuda_stream
+        self._h = _P()
+        o = options(**opts)
+        rc = lib().spg_create(ctypes.byref(self._h), _P(s), ctypes.byref(o))
+        if rc != SPG_OK:
+            raise SpgemmError(rc, "spg_create")
+
+    def _raise(self, rc: int):
+        raise SpgemmError(rc, lib().spg_last_error(self._h).decode())
+
+    @property
+    def ptr(self):
+        return self._h
+
+    def set_options(self, **opts):
+        o = options(**opts)
+        rc = lib().spg_set_options(self._h, ctypes.byref(o))
+        if rc != SPG_OK:
+            self._raise(rc)
+
+    def set_stream(self, stream: torch.cuda.Stream):
+        rc = lib().spg_set_stream(self._h, _P(stream.cuda_stream))
+        if rc != SPG_OK:
+            self._raise(rc)
+
+    def stats(self) -> dict:
+        st = spg_stats()
+        rc = lib().spg_get_stats(self._h, ctypes.byref(st))
+        if rc != SPG_OK:
+            self._raise(rc)
+        d = {k: getattr(st, k) for k, _ in spg_stats._fields_ if k not in ("reserved",)}
+        d["rows_symbolic"] = dict(zip(KIND_NAMES, list(st.rows_symbolic)[:st.n_kinds]))
+        d["rows_numeric"] = dict(zip(KIND_NAMES, list(st.rows_numeric)[:st.n_kinds]))
+        return d
+
+    def check_errors(self):
+        rc = lib().spg_check_errors(self._h)
+        if rc != SPG_OK:
+            self._raise(rc)
+
+    def close(self):
+        if self._h:
+            lib().spg_destroy(self._h)
+            self._h = _P()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def spgemm_symbolic(h: Handle, A: DeviceCsr, B: DeviceCsr, rp_dtype=torch.int32):
+    """spgemm_symbolic: returns (C.row_ptr device tensor of rp_dtype, nnz(C))."""
+    rp = torch.empty(A.nrows + 1, dtype=rp_dtype, device=A.row_ptr.device)
+    nnz = ctypes.c_int64(0)
+    a, b = _csr(A), _csr(B)
+    rc = lib().spgemm_symbolic(h.ptr, ctypes.byref(a), ctypes.byref(b), _P(rp.data_ptr()), _itype(rp),
+                              ctypes.byref(nnz))
+    if rc != SPG_OK:
+        h._raise(rc)
+    return rp, int(nnz.value)
+
+
+def spgemm_numeric(h: Handle, A: DeviceCsr, B: DeviceCsr, C_row_ptr: torch.Tensor, nnz: int,
+                   out: DeviceCsr | None = None) -> DeviceCsr:
+    """spgemm_numeric: writes (or allocates) C's columns and values; never blocks the host."""
+    if A.values is None or B.values is None:
+        raise ValueError("numeric phase needs values")
+    if out is None:
+        ci = torch.empty(nnz, dtype=torch.int32, device=A.values.device)
+        va = torch.empty(nnz, dtype=A.values.dtype, device=A.values.device)
+        out = DeviceCsr(A.nrows, B.ncols, C_row_ptr, ci, va)
+    c = spg_csr_out(out.nrows, out.ncols, out.nnz, _itype(out.row_ptr), out.row_ptr.data_ptr(),
+                    out.col_idx.data_ptr() if out.nnz else None,
+                    out.values.data_ptr() if out.nnz else None, _dtype(out.values))
+    a, b = _csr(A), _csr(B)
+    rc = lib().spgemm_numeric(h.ptr, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c))
+    if rc != SPG_OK:
+        h._raise(rc)
+    return out
+
+
+def spgemm(A: DeviceCsr, B: DeviceCsr, handle: Handle | None = None, rp_dtype=torch.int32) -> DeviceCsr:
+    """Both phases; the product with sorted columns."""
+    h = handle or Handle()
+    rp, nnz = spgemm_symbolic(h, A, B, rp_dtype)
+    return spgemm_numeric(h, A, B, rp, nnz)

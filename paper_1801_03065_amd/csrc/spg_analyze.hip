@@ -1,0 +1,579 @@
+// Analysis kernels of the symbolic phase: B row statistics and compression
+// of B into column-set words (Compression subsection), per-row flop counts
+// and column windows of C (memory-pool sizing by max row flops, Accumulators
+// subsection), row classification into kernel kinds, stable partition of the
+// rows by kind, and the exclusive scans that turn row sizes into C.row_ptr
+// (Algorithm 2).
+#include "spg_internal.hpp"
+
+namespace spg {
+
+namespace {
+
+constexpr int BLK = 256;
+
+__device__ __forceinline__ unsigned long long ull(long long v) { return (unsigned long long)v; }
+
+// ------------------------------------------------------------------ row ptrs
+template <typename T>
+__global__ __launch_bounds__(BLK) void k_copy_rp(int64_t n1, const T *src, int64_t nnz, int64_t *dst, int *bad) {
+    for (int64_t i = (int64_t)blockIdx.x * BLK + threadIdx.x; i < n1; i += (int64_t)gridDim.x * BLK) {
+        int64_t v = (int64_t)src[i];
+        dst[i] = v;
+        if ((i == 0 && v != 0) || (i > 0 && v < (int64_t)src[i - 1]) || (i == n1 - 1 && v != nnz))
+            atomicOr(bad, 1);
+    }
+}
+
+__global__ __launch_bounds__(BLK) void k_check_cols(int64_t nnz, const int32_t *ci, int64_t ncols, int *bad) {
+    int b = 0;
+    for (int64_t i = (int64_t)blockIdx.x * BLK + threadIdx.x; i < nnz; i += (int64_t)gridDim.x * BLK) {
+        const int32_t c = ci[i];
+        b |= (c < 0) | ((int64_t)c >= ncols);
+    }
+    if (__ballot(b) && lane_id() == 0) atomicOr(bad, 1);
+}
+
+// ------------------------------------------------------------------ B rows
+// One group of 16 lanes per row of B.  For rows whose columns are strictly
+// increasing, the number of distinct words col >> 5 is the number of word
+// changes along the row; other rows are queued for the LDS-bitmap kernel.
+constexpr int BR_GS = 16;
+
+__global__ __launch_bounds__(BLK) void k_brow(int64_t n, const int64_t *brp, const int32_t *bci, BRow *out,
+                                               int32_t *ulist, DevStats *st) {
+    const int q = threadIdx.x & (BR_GS - 1);
+    const int64_t g0 = ((int64_t)blockIdx.x * BLK + threadIdx.x) / BR_GS;
+    const int64_t ng = (int64_t)gridDim.x * BLK / BR_GS;
+    for (int64_t r = g0; r < n; r += ng) {
+        const int64_t b = brp[r], e = brp[r + 1];
+        int cmin = INT_MAX, cmax = -1, heads = 0, unsorted = 0, prev_last = -1;
+        for (int64_t c0 = b; c0 < e; c0 += BR_GS) {
+            const int64_t idx = c0 + q;
+            const bool v = idx < e;
+            const int col = v ? bci[idx] : INT_MAX;
+            int prevc = __shfl_up(col, 1, BR_GS);
+            if (q == 0) prevc = prev_last;
+            if (v) {
+                cmin = min(cmin, col);
+                cmax = max(cmax, col);
+                unsorted |= (prevc >= col);
+                heads += ((col >> 5) != (prevc >> 5));
+            }
+            prev_last = __shfl(col, BR_GS - 1, BR_GS);
+        }
+#pragma unroll
+        for (int d = BR_GS / 2; d >= 1; d >>= 1) {
+            cmin = min(cmin, __shfl_xor(cmin, d, BR_GS));
+            cmax = max(cmax, __shfl_xor(cmax, d, BR_GS));
+            heads += __shfl_xor(heads, d, BR_GS);
+            unsorted |= __shfl_xor(unsorted, d, BR_GS);
+        }
+        if (q == 0) {
+            BRow o;
+            o.len = (int32_t)(e - b);
+            o.lenc = heads;
+            o.wmin = (e > b) ? (cmin >> 5) : INT_MAX;
+            o.wmax = (e > b) ? (cmax >> 5) : -1;
+            out[r] = o;
+            if (unsorted) ulist[atomicAdd(&st->unsorted, 1)] = (int32_t)r;
+        }
+    }
+}
+
+// One wavefront per listed row: OR every column bit into an LDS bitmap over
+// the row's word window; distinct words = nonzero bitmap words.  mode 0
+// writes the count, mode 1 writes the (word, bits) pairs in word order.
+constexpr int UB_WORDS = 16384;
+
+__global__ __launch_bounds__(WAVE) void k_brow_unsorted(const int32_t *list, const int *count_p, const int64_t *brp,
+                                                         const int32_t *bci, BRow *bi, const int64_t *bcrp,
+                                                         int32_t *bcsi, uint32_t *bcs, int mode, DevStats *st) {
+    __shared__ uint32_t bits[UB_WORDS];
+    const int l = lane_id();
+    const int count = *count_p;
+    if ((int)blockIdx.x >= count) return;
+    for (int w = l; w < UB_WORDS; w += WAVE) bits[w] = 0;
+    __syncthreads();
+    for (int t = blockIdx.x; t < count; t += gridDim.x) {
+        const int64_t r = list[t];
+        const int64_t b = brp[r], e = brp[r + 1];
+        const BRow br = bi[r];
+        const int64_t nw = (int64_t)br.wmax - br.wmin + 1;
+        if (e == b) continue;
+        if (nw > UB_WORDS) {
+            if (l == 0 && st) atomicAdd(&st->bad_window, 1);
+            continue;
+        }
+        for (int64_t idx = b + l; idx < e; idx += WAVE) {
+            const int col = bci[idx];
+            atomicOr(&bits[(col >> 5) - br.wmin], 1u << (col & 31));
+        }
+        __syncthreads();
+        int run = 0;
+        const int64_t out0 = mode ? bcrp[r] : 0;
+        for (int w0 = 0; w0 < nw; w0 += WAVE) {
+            const int w = w0 + l;
+            const uint32_t m = (w < nw) ? bits[w] : 0u;
+            const unsigned long long bal = __ballot(m != 0u);
+            if (mode && m) {
+                const int64_t pos = out0 + run + mbcnt(bal);
+                bcsi[pos] = br.wmin + w;
+                bcs[pos] = m;
+            }
+            if (w < nw) bits[w] = 0;
+            run += __popcll(bal);
+        }
+        if (mode == 0 && l == 0) bi[r].lenc = run;
+        __syncthreads();
+    }
+}
+
+// Compressed B for rows with sorted columns: a 16-lane group per row; the
+// first lane of each word run writes the word index, every run tail ORs its
+// partial bit set in (a run may straddle two 16-column chunks).
+__global__ __launch_bounds__(BLK) void k_compress_sorted(int64_t n, const int64_t *brp, const int32_t *bci,
+                                                          const BRow *bi, const uint8_t *unsorted,
+                                                          const int64_t *bcrp, int32_t *bcsi, uint32_t *bcs) {
+    const int q = threadIdx.x & (BR_GS - 1);
+    const int64_t g0 = ((int64_t)blockIdx.x * BLK + threadIdx.x) / BR_GS;
+    const int64_t ng = (int64_t)gridDim.x * BLK / BR_GS;
+    for (int64_t r = g0; r < n; r += ng) {
+        if (unsorted[r]) continue;
+        const int64_t b = brp[r], e = brp[r + 1];
+        const int64_t o0 = bcrp[r];
+        int heads_before = 0, prev_last = -1;
+        for (int64_t c0 = b; c0 < e; c0 += BR_GS) {
+            const int64_t idx = c0 + q;
+            const bool v = idx < e;
+            const int col = v ? bci[idx] : INT_MAX;
+            int prevc = __shfl_up(col, 1, BR_GS);
+            if (q == 0) prevc = prev_last;
+            const int head = v && ((col >> 5) != (prevc >> 5));
+            // inclusive count of heads in this chunk = run id (0 = run from previous chunk)
+            int seg = head;
+#pragma unroll
+            for (int d = 1; d < BR_GS; d <<= 1) {
+                int t = __shfl_up(seg, d, BR_GS);
+                if (q >= d) seg += t;
+            }
+            uint32_t acc = v ? (1u << (col & 31)) : 0u;
+#pragma unroll
+            for (int d = 1; d < BR_GS; d <<= 1) {
+                uint32_t t = __shfl_up(acc, d, BR_GS);
+                int ts = __shfl_up(seg, d, BR_GS);
+                if (q >= d && ts == seg) acc |= t;
+            }
+            const int nseg = __shfl_down(seg, 1, BR_GS);
+            const bool nvalid = (q + 1 < BR_GS) && (idx + 1 < e);
+            const bool tail = v && (!nvalid || nseg != seg);
+            const int64_t pos = o0 + heads_before + seg - 1;
+            if (head) bcsi[pos] = col >> 5;
+            if (tail) atomicOr(&bcs[pos], acc);
+            heads_before += __shfl(seg, BR_GS - 1, BR_GS);
+            prev_last = __shfl(col, BR_GS - 1, BR_GS);
+        }
+    }
+}
+
+__global__ __launch_bounds__(BLK) void k_mark_unsorted(const int32_t *list, const int *count_p, uint8_t *flag) {
+    const int count = *count_p;
+    for (int t = blockIdx.x * BLK + threadIdx.x; t < count; t += gridDim.x * BLK) flag[list[t]] = 1;
+}
+
+// ------------------------------------------------------------------ A rows
+// 16 lanes per row of A: f_m(i) = sum |B(j,:)|, the same over compressed B,
+// and the word window [min wmin, max wmax] of the B rows it reads.
+constexpr int RI_GS = 16;
+
+__global__ __launch_bounds__(BLK) void k_rowinfo(int64_t m, const int64_t *arp, const int32_t *aci,
+                                                  const BRow *bi, int64_t *rflops, int64_t *rflopsc,
+                                                  int2 *rwin, DevStats *st) {
+    const int q = threadIdx.x & (RI_GS - 1);
+    const int64_t g0 = ((int64_t)blockIdx.x * BLK + threadIdx.x) / RI_GS;
+    const int64_t ng = (int64_t)gridDim.x * BLK / RI_GS;
+    long long s_fm = 0, s_fmc = 0, s_mx = 0, s_mxc = 0;
+    for (int64_t i = g0; i < m; i += ng) {
+        const int64_t b = arp[i], e = arp[i + 1];
+        long long f = 0, fc = 0;
+        int wlo = INT_MAX, whi = -1;
+        for (int64_t idx = b + q; idx < e; idx += RI_GS) {
+            const BRow br = bi[aci[idx]];
+            f += br.len;
+            fc += br.lenc;
+            wlo = min(wlo, br.wmin);
+            whi = max(whi, br.wmax);
+        }
+#pragma unroll
+        for (int d = RI_GS / 2; d >= 1; d >>= 1) {
+            f += __shfl_xor(f, d, RI_GS);
+            fc += __shfl_xor(fc, d, RI_GS);
+            wlo = min(wlo, __shfl_xor(wlo, d, RI_GS));
+            whi = max(whi, __shfl_xor(whi, d, RI_GS));
+        }
+        if (q == 0) {
+            rflops[i] = f;
+            rflopsc[i] = fc;
+            rwin[i] = make_int2(wlo, whi);
+            s_fm += f;
+            s_fmc += fc;
+            s_mx = max(s_mx, f);
+            s_mxc = max(s_mxc, fc);
+        }
+    }
+    s_fm = wave_sum64(s_fm);
+    s_fmc = wave_sum64(s_fmc);
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) {
+        s_mx = max(s_mx, (long long)__shfl_xor(s_mx, d));
+        s_mxc = max(s_mxc, (long long)__shfl_xor(s_mxc, d));
+    }
+    if (lane_id() == 0) {
+        if (s_fm) atomicAdd(&st->fm, ull(s_fm));
+        if (s_fmc) atomicAdd(&st->fmc, ull(s_fmc));
+        atomicMax(&st->maxrf, ull(s_mx));
+        atomicMax(&st->maxrfc, ull(s_mxc));
+    }
+}
+
+__global__ __launch_bounds__(BLK) void k_brow_lens(int64_t n, const BRow *bi, int which, int64_t *out) {
+    for (int64_t i = (int64_t)blockIdx.x * BLK + threadIdx.x; i < n; i += (int64_t)gridDim.x * BLK)
+        out[i] = which ? bi[i].lenc : bi[i].len;
+}
+
+// ------------------------------------------------------------------ classify
+__global__ __launch_bounds__(BLK) void k_classify(int64_t m, const int64_t *rflops, const int64_t *rflopsc,
+                                                   const int2 *rwin, const int32_t *row_nnz, ClassParams p,
+                                                   uint8_t *kind, int32_t *row_nnz_out, DevStats *st) {
+    __shared__ int smax[NK][2];
+    __shared__ long long scnt[NK];
+    if (threadIdx.x < NK) {
+        smax[threadIdx.x][0] = 0;
+        smax[threadIdx.x][1] = 0;
+        scnt[threadIdx.x] = 0;
+    }
+    __syncthreads();
+    for (int64_t i = (int64_t)blockIdx.x * BLK + threadIdx.x; i < m; i += (int64_t)gridDim.x * BLK) {
+        const long long f = rflops[i];
+        const int2 w = rwin[i];
+        int k = K_EMPTY, a = 0, bnd = 0;
+        if (f > 0) {
+            const long long nw = (long long)w.y - w.x + 1;
+            long long bound;
+            if (p.phase == 0) {
+                bound = p.compressed ? min((long long)rflopsc[i], nw) : min(f, 32 * nw);
+            } else {
+                bound = row_nnz[i];
+            }
+            const bool dw_fit = nw <= p.dw_nw_max && (p.phase == 0 || bound <= p.dw_r_max);
+            const bool hw_fit = bound <= p.hw_keys_max;
+            const bool dg_fit = nw <= p.dg_nw_max;
+            switch (p.accumulator) {
+                case 2:  // hash
+                    k = hw_fit ? K_HW : K_HL;
+                    break;
+                case 3:  // two-level hash everywhere
+                    k = K_HL;
+                    break;
+                default:  // auto / dense
+                    k = dw_fit ? K_DW : (hw_fit ? K_HW : (dg_fit ? K_DG : K_HL));
+            }
+            a = (int)min(nw, (long long)INT_MAX);
+            bnd = (int)min(bound, (long long)INT_MAX);
+        } else if (p.phase == 0) {
+            row_nnz_out[i] = 0;
+        }
+        kind[i] = (uint8_t)k;
+        atomicMax(&smax[k][0], a);
+        atomicMax(&smax[k][1], bnd);
+        atomicAdd((unsigned long long *)&scnt[k], 1ull);
+    }
+    __syncthreads();
+    if (threadIdx.x < NK) {
+        int *gm = p.phase == 0 ? &st->kmax_sym[threadIdx.x][0] : &st->kmax_num[threadIdx.x][0];
+        atomicMax(gm, smax[threadIdx.x][0]);
+        atomicMax(gm + 1, smax[threadIdx.x][1]);
+        long long *gc = p.phase == 0 ? &st->kcount_sym[threadIdx.x] : &st->kcount_num[threadIdx.x];
+        if (scnt[threadIdx.x]) atomicAdd((unsigned long long *)gc, (unsigned long long)scnt[threadIdx.x]);
+    }
+}
+
+// ------------------------------------------------------------------ partition
+// Stable partition of rows by kind: per-block counts, a scan over blocks per
+// kind, then an in-order scatter using wavefront ballots.
+constexpr int PB = 1024;  // rows per block
+
+__global__ __launch_bounds__(PB) void k_part_count(int64_t m, const uint8_t *kind, int64_t *blk) {
+    __shared__ int cnt[NK];
+    if (threadIdx.x < NK) cnt[threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t i = (int64_t)blockIdx.x * PB + threadIdx.x;
+    if (i < m) atomicAdd(&cnt[kind[i]], 1);
+    __syncthreads();
+    if (threadIdx.x < NK) blk[(int64_t)blockIdx.x * NK + threadIdx.x] = cnt[threadIdx.x];
+}
+
+__global__ __launch_bounds__(PB) void k_part_scan(int64_t nb, int64_t *blk, int64_t *koff) {
+    // one block: kind by kind, exclusive scan over the nb block counts
+    __shared__ long long wsum[PB / WAVE];
+    __shared__ long long carry;
+    const int t = threadIdx.x, l = lane_id(), wv = t / WAVE;
+    if (t == 0) carry = 0;
+    __syncthreads();
+    for (int k = 0; k < NK; ++k) {
+        if (t == 0) koff[k] = carry;
+        __syncthreads();
+        for (int64_t c0 = 0; c0 < nb; c0 += PB) {
+            const int64_t b = c0 + t;
+            const long long v = b < nb ? blk[b * NK + k] : 0;
+            long long inc = wave_incl_scan64(v);
+            if (l == WAVE - 1) wsum[wv] = inc;
+            __syncthreads();
+            long long off = 0, tot = 0;
+            for (int u = 0; u < PB / WAVE; ++u) {
+                if (u < wv) off += wsum[u];
+                tot += wsum[u];
+            }
+            if (b < nb) blk[b * NK + k] = carry + off + inc - v;
+            __syncthreads();
+            if (t == 0) carry += tot;
+            __syncthreads();
+        }
+    }
+    if (t == 0) koff[NK] = carry;
+}
+
+__global__ __launch_bounds__(PB) void k_part_scatter(int64_t m, const uint8_t *kind, const int64_t *blk,
+                                                      int32_t *perm) {
+    __shared__ int wcnt[PB / WAVE][NK];
+    const int t = threadIdx.x, l = lane_id(), wv = t / WAVE;
+    const int64_t i = (int64_t)blockIdx.x * PB + t;
+    const int k = i < m ? kind[i] : -1;
+    int rank = 0;
+    for (int kk = 0; kk < NK; ++kk) {
+        const unsigned long long bal = __ballot(k == kk);
+        if (kk == k) rank = mbcnt(bal);
+        if (l == 0) wcnt[wv][kk] = __popcll(bal);
+    }
+    __syncthreads();
+    if (i < m) {
+        int off = 0;
+        for (int u = 0; u < wv; ++u) off += wcnt[u][k];
+        perm[blk[(int64_t)blockIdx.x * NK + k] + off + rank] = (int32_t)i;
+    }
+}
+
+// ------------------------------------------------------------------ scans
+constexpr int SC_T = 256, SC_E = 8, SC_B = SC_T * SC_E;
+
+template <typename T>
+__global__ __launch_bounds__(SC_T) void k_scan_local(int64_t n, const T *in, int64_t *out, int64_t *bsum) {
+    __shared__ long long wsum[SC_T / WAVE];
+    const int t = threadIdx.x, l = lane_id(), wv = t / WAVE;
+    const int64_t base = (int64_t)blockIdx.x * SC_B + (int64_t)t * SC_E;
+    long long v[SC_E];
+    long long s = 0;
+#pragma unroll
+    for (int e = 0; e < SC_E; ++e) {
+        v[e] = (base + e < n) ? (long long)in[base + e] : 0;
+        s += v[e];
+    }
+    const long long inc = wave_incl_scan64(s);
+    if (l == WAVE - 1) wsum[wv] = inc;
+    __syncthreads();
+    long long off = 0;
+    for (int u = 0; u < wv; ++u) off += wsum[u];
+    long long run = off + inc - s;
+#pragma unroll
+    for (int e = 0; e < SC_E; ++e) {
+        if (base + e < n) out[base + e] = run;
+        run += v[e];
+    }
+    if (t == SC_T - 1) bsum[blockIdx.x] = off + inc;
+}
+
+__global__ __launch_bounds__(SC_T) void k_scan_top(int64_t nb, int64_t *bsum, int64_t *total_out) {
+    __shared__ long long wsum[SC_T / WAVE];
+    __shared__ long long carry;
+    const int t = threadIdx.x, l = lane_id(), wv = t / WAVE;
+    if (t == 0) carry = 0;
+    __syncthreads();
+    for (int64_t c0 = 0; c0 < nb; c0 += SC_T) {
+        const int64_t b = c0 + t;
+        const long long v = b < nb ? bsum[b] : 0;
+        const long long inc = wave_incl_scan64(v);
+        if (l == WAVE - 1) wsum[wv] = inc;
+        __syncthreads();
+        long long off = 0, tot = 0;
+        for (int u = 0; u < SC_T / WAVE; ++u) {
+            if (u < wv) off += wsum[u];
+            tot += wsum[u];
+        }
+        if (b < nb) bsum[b] = carry + off + inc - v;
+        __syncthreads();
+        if (t == 0) carry += tot;
+        __syncthreads();
+    }
+    if (t == 0) *total_out = carry;
+}
+
+__global__ __launch_bounds__(SC_T) void k_scan_add(int64_t n, int64_t *out, const int64_t *bsum) {
+    const int64_t base = (int64_t)blockIdx.x * SC_B;
+    const long long add = bsum[blockIdx.x];
+    for (int e = threadIdx.x; e < SC_B; e += SC_T)
+        if (base + e < n) out[base + e] += add;
+}
+
+__global__ __launch_bounds__(BLK) void k_store_rp32(int64_t n1, const int64_t *src, int32_t *dst) {
+    for (int64_t i = (int64_t)blockIdx.x * BLK + threadIdx.x; i < n1; i += (int64_t)gridDim.x * BLK)
+        dst[i] = (int32_t)src[i];
+}
+__global__ __launch_bounds__(BLK) void k_store_rp64(int64_t n1, const int64_t *src, int64_t *dst) {
+    for (int64_t i = (int64_t)blockIdx.x * BLK + threadIdx.x; i < n1; i += (int64_t)gridDim.x * BLK)
+        dst[i] = src[i];
+}
+__global__ __launch_bounds__(BLK) void k_fill_i32(int32_t *p, int64_t n, int32_t v) {
+    for (int64_t i = (int64_t)blockIdx.x * BLK + threadIdx.x; i < n; i += (int64_t)gridDim.x * BLK) p[i] = v;
+}
+
+inline int grid_for(int64_t work, int per_block, int cap = 65536) {
+    int64_t g = (work + per_block - 1) / per_block;
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return (int)g;
+}
+
+}  // namespace
+
+hipError_t launch_copy_rp(int64_t n1, const void *src, int is64, int64_t nnz, int64_t *dst, int *bad,
+                          hipStream_t s) {
+    const int g = grid_for(n1, BLK);
+    if (is64)
+        hipLaunchKernelGGL(k_copy_rp<int64_t>, dim3(g), dim3(BLK), 0, s, n1, (const int64_t *)src, nnz, dst, bad);
+    else
+        hipLaunchKernelGGL(k_copy_rp<int32_t>, dim3(g), dim3(BLK), 0, s, n1, (const int32_t *)src, nnz, dst, bad);
+    return hipGetLastError();
+}
+
+hipError_t launch_check_cols(int64_t nnz, const int32_t *ci, int64_t ncols, int *bad, hipStream_t s) {
+    if (nnz == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_check_cols, dim3(grid_for(nnz, BLK * 8, 8192)), dim3(BLK), 0, s, nnz, ci, ncols, bad);
+    return hipGetLastError();
+}
+
+hipError_t launch_brow(int64_t n, const int64_t *brp, const int32_t *bci, BRow *out, int32_t *ulist,
+                       DevStats *st, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_brow, dim3(grid_for(n * BR_GS, BLK)), dim3(BLK), 0, s, n, brp, bci, out, ulist, st);
+    return hipGetLastError();
+}
+
+// The unsorted-row kernels read their row count from device memory, so they
+// are enqueued without a host round trip; surplus workgroups exit at once.
+constexpr int UB_GRID = 1024;
+
+hipError_t launch_brow_unsorted(const int32_t *list, const int *count, const int64_t *brp, const int32_t *bci,
+                                BRow *out, DevStats *st, hipStream_t s) {
+    hipLaunchKernelGGL(k_brow_unsorted, dim3(UB_GRID), dim3(WAVE), 0, s, list, count, brp, bci, out,
+                       (const int64_t *)nullptr, (int32_t *)nullptr, (uint32_t *)nullptr, 0, st);
+    return hipGetLastError();
+}
+
+hipError_t launch_compress_unsorted(const int32_t *list, const int *count, const int64_t *brp,
+                                    const int32_t *bci, const BRow *bi, const int64_t *bcrp, int32_t *bcsi,
+                                    uint32_t *bcs, hipStream_t s) {
+    hipLaunchKernelGGL(k_brow_unsorted, dim3(UB_GRID), dim3(WAVE), 0, s, list, count, brp, bci, (BRow *)bi, bcrp,
+                       bcsi, bcs, 1, (DevStats *)nullptr);
+    return hipGetLastError();
+}
+
+hipError_t launch_mark_unsorted(const int32_t *list, const int *count, uint8_t *flag, hipStream_t s) {
+    hipLaunchKernelGGL(k_mark_unsorted, dim3(64), dim3(BLK), 0, s, list, count, flag);
+    return hipGetLastError();
+}
+
+hipError_t launch_compress_sorted_flags(int64_t n, const int64_t *brp, const int32_t *bci, const BRow *bi,
+                                        const uint8_t *unsorted, const int64_t *bcrp, int32_t *bcsi,
+                                        uint32_t *bcs, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_compress_sorted, dim3(grid_for(n * BR_GS, BLK)), dim3(BLK), 0, s, n, brp, bci, bi,
+                       unsorted, bcrp, bcsi, bcs);
+    return hipGetLastError();
+}
+
+hipError_t launch_rowinfo(int64_t m, const int64_t *arp, const int32_t *aci, const BRow *bi, int64_t *rflops,
+                          int64_t *rflopsc, int2 *rwin, DevStats *st, hipStream_t s) {
+    if (m == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_rowinfo, dim3(grid_for(m * RI_GS, BLK)), dim3(BLK), 0, s, m, arp, aci, bi, rflops,
+                       rflopsc, rwin, st);
+    return hipGetLastError();
+}
+
+hipError_t launch_brow_lens(int64_t n, const BRow *bi, int which, int64_t *out, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_brow_lens, dim3(grid_for(n, BLK)), dim3(BLK), 0, s, n, bi, which, out);
+    return hipGetLastError();
+}
+
+int64_t scan_tmp_elems(int64_t n) { return (n + SC_B - 1) / SC_B + 1; }
+
+template <typename T>
+static hipError_t scan_impl(int64_t n, const T *in, int64_t *out, int64_t *tmp, hipStream_t s) {
+    const int64_t nb = (n + SC_B - 1) / SC_B;
+    if (nb > 0) {
+        hipLaunchKernelGGL(k_scan_local<T>, dim3((unsigned)nb), dim3(SC_T), 0, s, n, in, out, tmp);
+        hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(SC_T), 0, s, nb, tmp, out + n);
+        hipLaunchKernelGGL(k_scan_add, dim3((unsigned)nb), dim3(SC_T), 0, s, n, out, tmp);
+    } else {
+        hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(BLK), 0, s, (int32_t *)out, (int64_t)2, 0);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_scan_i64(int64_t n, const int64_t *in, int64_t *out, int64_t *tmp, hipStream_t s) {
+    return scan_impl<int64_t>(n, in, out, tmp, s);
+}
+hipError_t launch_scan_i32(int64_t n, const int32_t *in, int64_t *out, int64_t *tmp, hipStream_t s) {
+    return scan_impl<int32_t>(n, in, out, tmp, s);
+}
+
+hipError_t launch_store_rp(int64_t n1, const int64_t *src, void *dst, int is64, hipStream_t s) {
+    const int g = grid_for(n1, BLK);
+    if (is64)
+        hipLaunchKernelGGL(k_store_rp64, dim3(g), dim3(BLK), 0, s, n1, src, (int64_t *)dst);
+    else
+        hipLaunchKernelGGL(k_store_rp32, dim3(g), dim3(BLK), 0, s, n1, src, (int32_t *)dst);
+    return hipGetLastError();
+}
+
+hipError_t launch_classify(int64_t m, const int64_t *rflops, const int64_t *rflopsc, const int2 *rwin,
+                           const int32_t *row_nnz, ClassParams p, uint8_t *kind, int32_t *row_nnz_out,
+                           DevStats *st, hipStream_t s) {
+    if (m == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_classify, dim3(grid_for(m, BLK, 4096)), dim3(BLK), 0, s, m, rflops, rflopsc, rwin,
+                       row_nnz, p, kind, row_nnz_out, st);
+    return hipGetLastError();
+}
+
+int64_t part_tmp_elems(int64_t m) { return ((m + PB - 1) / PB) * NK + 1; }
+
+hipError_t launch_partition(int64_t m, const uint8_t *kind, int32_t *perm, int64_t *koff, int64_t *tmp,
+                            hipStream_t s) {
+    const int64_t nb = (m + PB - 1) / PB;
+    if (nb == 0) {
+        hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(BLK), 0, s, (int32_t *)koff, (int64_t)(2 * (NK + 1)), 0);
+        return hipGetLastError();
+    }
+    hipLaunchKernelGGL(k_part_count, dim3((unsigned)nb), dim3(PB), 0, s, m, kind, tmp);
+    hipLaunchKernelGGL(k_part_scan, dim3(1), dim3(PB), 0, s, nb, tmp, koff);
+    hipLaunchKernelGGL(k_part_scatter, dim3((unsigned)nb), dim3(PB), 0, s, m, kind, tmp, perm);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(n, BLK, 4096)), dim3(BLK), 0, s, p, n, v);
+    return hipGetLastError();
+}
+
+}  // namespace spg

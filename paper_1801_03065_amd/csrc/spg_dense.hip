@@ -1,0 +1,565 @@
+// Bit-window dense accumulator kernels (the "dense accumulator" of the
+// Accumulators subsection, re-cut for gfx950 LDS).
+//
+// A row i of C only touches columns inside a window of words
+// [wlo, whi] (word = column >> 5), known from the analysis pass.  The
+// structure of row i is the union of the column-set words of the B rows it
+// reads (Compression subsection): OR-ing them into an LDS bit array over the
+// window gives the row's pattern; a second-level summary bit per word marks
+// the touched words, so counting, ordering and resetting cost the touched
+// words only, never the whole window.
+//
+//  symbolic: row size = sum of popcounts of the touched words (Algorithm 3,
+//            symbolic branch).
+//  numeric:  the touched words in increasing order get prefix popcounts; the
+//            rank of column c in the row is then pre[word] + popcount of the
+//            lower bits of its word.  Products are added into vals[rank]
+//            (LDS, Algorithm 1's accumulation), and the sorted row is written
+//            with coalesced stores.  Output columns come out sorted for free.
+//
+// K_DW: one 64-lane wavefront per row, Thread-Parallel lane groups (a group
+//       of 2^lg_gs lanes walks one B row, several groups per wavefront),
+//       window up to 2048 words, row up to 1024 entries.
+// K_DG: one 256-lane workgroup per row, Thread-Flat-Parallel (each lane takes
+//       one multiplication of the flattened row; Partitioning Schemes
+//       subsection), window up to 32768 words in LDS, values in an HBM array
+//       over the window (one slice per resident workgroup: the memory pool of
+//       the Accumulators subsection in one-to-one mode).
+#include "spg_accum.hpp"
+#include "spg_internal.hpp"
+
+namespace spg {
+
+namespace {
+
+// ============================================================ wavefront / row
+
+struct DwLayout {
+    size_t bits, summ, pre, wlist, vals, colbuf, st_bs, st_len, st_a, total;
+};
+
+__host__ __device__ inline DwLayout dw_layout(int nwm, int rm, int acc_bytes, bool numeric) {
+    DwLayout L{};
+    const int nsm = (nwm + 31) >> 5;
+    size_t o = 0;
+    L.bits = o;
+    o += align16(4 * (size_t)nwm);
+    L.summ = o;
+    o += align16(4 * (size_t)nsm);
+    L.st_bs = o;
+    o += 8 * WAVE;
+    L.st_len = o;
+    o += 4 * WAVE;
+    L.st_a = o;
+    o += 8 * WAVE;
+    if (numeric) {
+        L.pre = o;
+        o += align16(2 * (size_t)nwm);
+        L.wlist = o;
+        o += align16(2 * (size_t)rm);
+        L.vals = o;
+        o += align16((size_t)acc_bytes * rm);
+        L.colbuf = o;
+        o += align16(4 * (size_t)rm);
+    }
+    L.total = o;
+    return L;
+}
+
+// Stage up to 64 entries of A's row: B row start/length (from `rp`) and the
+// A value.  Returns the number staged.
+template <typename VT>
+__device__ __forceinline__ int stage_chunk(int64_t cb, int64_t ae, const int32_t *aci, const VT *aval,
+                                           const int64_t *rp, int64_t *st_bs, int32_t *st_len, double *st_a) {
+    const int l = lane_id();
+    const int cn = (int)min((int64_t)WAVE, ae - cb);
+    if (l < cn) {
+        const int j = aci[cb + l];
+        const int64_t s0 = rp[j], s1 = rp[j + 1];
+        st_bs[l] = s0;
+        st_len[l] = (int32_t)(s1 - s0);
+        if (aval) st_a[l] = (double)aval[cb + l];
+    }
+    return cn;
+}
+
+// OR the row's column-set words into bits[] / summ[] (window-relative).
+__device__ __forceinline__ void dw_or_pass(int i, int wlo, const int64_t *arp, const int32_t *aci,
+                                           const int64_t *brp, const int32_t *bci, const int64_t *bcrp,
+                                           const int32_t *bcsi, const uint32_t *bcs, int lg_gs, uint32_t *bits,
+                                           uint32_t *summ, int64_t *st_bs, int32_t *st_len, double *st_a) {
+    const int l = lane_id();
+    const int gs = 1 << lg_gs, g = l >> lg_gs, q = l & (gs - 1), ng = WAVE >> lg_gs;
+    const bool comp = bcrp != nullptr;
+    const int64_t ab = arp[i], ae = arp[i + 1];
+    for (int64_t cb = ab; cb < ae; cb += WAVE) {
+        const int cn = stage_chunk<double>(cb, ae, aci, nullptr, comp ? bcrp : brp, st_bs, st_len, st_a);
+        __syncthreads();
+        for (int t = g; t < cn; t += ng) {
+            const int64_t bs = st_bs[t];
+            const int len = st_len[t];
+            for (int p = q; p < len; p += gs) {
+                uint32_t d, cs;
+                if (comp) {
+                    d = (uint32_t)(bcsi[bs + p] - wlo);
+                    cs = bcs[bs + p];
+                } else {
+                    const int c = bci[bs + p];
+                    d = (uint32_t)((c >> 5) - wlo);
+                    cs = 1u << (c & 31);
+                }
+                atomicOr(&bits[d], cs);
+                atomicOr(&summ[d >> 5], 1u << (d & 31));
+            }
+        }
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(WAVE) void k_sym_dw(SymArgs a) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const DwLayout L = dw_layout(a.nw_max, 0, 0, false);
+    uint32_t *bits = (uint32_t *)(smem + L.bits);
+    uint32_t *summ = (uint32_t *)(smem + L.summ);
+    int64_t *st_bs = (int64_t *)(smem + L.st_bs);
+    int32_t *st_len = (int32_t *)(smem + L.st_len);
+    double *st_a = (double *)(smem + L.st_a);
+    const int l = lane_id();
+    const int nsm = (a.nw_max + 31) >> 5;
+    for (int w = l; w < a.nw_max; w += WAVE) bits[w] = 0;
+    for (int w = l; w < nsm; w += WAVE) summ[w] = 0;
+    __syncthreads();
+    const int64_t lo = a.rs.koff[a.rs.kind], hi = a.rs.koff[a.rs.kind + 1];
+    const Slice sl = xcd_slice(lo, hi);
+    for (int64_t r = sl.idx; r < sl.end; r += sl.step) {
+        const int i = a.rs.rows[r];
+        const int2 win = a.rwin[i];
+        const int ns = (win.y - win.x + 1 + 31) >> 5;
+        dw_or_pass(i, win.x, a.arp, a.aci, a.brp, a.bci, a.bcrp, a.bcsi, a.bcs, a.lg_gs, bits, summ, st_bs,
+                   st_len, st_a);
+        int cnt = 0;
+        for (int s = l; s < ns; s += WAVE) {
+            uint32_t m = summ[s];
+            summ[s] = 0;
+            while (m) {
+                const int d = (s << 5) + __ffs(m) - 1;
+                m &= m - 1;
+                cnt += __popc(bits[d]);
+                bits[d] = 0;
+            }
+        }
+        cnt = wave_sum(cnt);
+        if (l == 0) a.row_nnz[i] = cnt;
+        __syncthreads();
+    }
+}
+
+template <typename VT, int ACC>
+__global__ __launch_bounds__(WAVE) void k_num_dw(NumArgs<VT> a) {
+    using A = Accum<VT, ACC>;
+    using S = typename A::store_t;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const DwLayout L = dw_layout(a.nw_max, a.r_max, sizeof(S), true);
+    uint32_t *bits = (uint32_t *)(smem + L.bits);
+    uint32_t *summ = (uint32_t *)(smem + L.summ);
+    uint16_t *pre = (uint16_t *)(smem + L.pre);
+    uint16_t *wlist = (uint16_t *)(smem + L.wlist);
+    S *vals = (S *)(smem + L.vals);
+    int32_t *colbuf = (int32_t *)(smem + L.colbuf);
+    int64_t *st_bs = (int64_t *)(smem + L.st_bs);
+    int32_t *st_len = (int32_t *)(smem + L.st_len);
+    double *st_a = (double *)(smem + L.st_a);
+    const int l = lane_id();
+    const int nsm = (a.nw_max + 31) >> 5;
+    for (int w = l; w < a.nw_max; w += WAVE) bits[w] = 0;
+    for (int w = l; w < nsm; w += WAVE) summ[w] = 0;
+    __syncthreads();
+    const int gs = 1 << a.lg_gs, g = l >> a.lg_gs, q = l & (gs - 1), ng = WAVE >> a.lg_gs;
+    const int64_t lo = a.rs.koff[a.rs.kind], hi = a.rs.koff[a.rs.kind + 1];
+    const Slice sl = xcd_slice(lo, hi);
+    for (int64_t r = sl.idx; r < sl.end; r += sl.step) {
+        const int i = a.rs.rows[r];
+        const int2 win = a.rwin[i];
+        const int wlo = win.x;
+        const int ns = (win.y - win.x + 1 + 31) >> 5;
+        // 1. structure of the row
+        dw_or_pass(i, wlo, a.arp, a.aci, a.brp, a.bci, a.bcrp, a.bcsi, a.bcs, a.lg_gs_or, bits, summ, st_bs,
+                   st_len, st_a);
+        // 2. touched words in increasing order
+        int T = 0;
+        for (int s0 = 0; s0 < ns; s0 += WAVE) {
+            const int s = s0 + l;
+            uint32_t m = (s < ns) ? summ[s] : 0u;
+            const int c = __popc(m);
+            const int inc = wave_incl_scan(c);
+            int idx = T + inc - c;
+            while (m) {
+                if (idx < a.r_max) wlist[idx] = (uint16_t)((s << 5) + __ffs(m) - 1);
+                ++idx;
+                m &= m - 1;
+            }
+            if (s < ns) summ[s] = 0;
+            T += __shfl(inc, WAVE - 1);
+        }
+        __syncthreads();
+        if (T > a.r_max) {  // structure differs from the plan: flag, reset the window, skip the row
+            if (l == 0) atomicAdd(&a.st->mismatch, 1);
+            for (int w = l; w < ns * 32; w += WAVE) bits[w] = 0;
+            __syncthreads();
+            continue;
+        }
+        // 3. prefix popcounts of the touched words
+        int run = 0;
+        for (int r0 = 0; r0 < T; r0 += WAVE) {
+            const int rr = r0 + l;
+            const int d = rr < T ? wlist[rr] : 0;
+            const int c = rr < T ? __popc(bits[d]) : 0;
+            const int inc = wave_incl_scan(c);
+            if (rr < T) pre[d] = (uint16_t)(run + inc - c);
+            run += __shfl(inc, WAVE - 1);
+        }
+        const int rnnz = run;
+        const int64_t cb = a.coff[i];
+        const bool ok = (a.coff[i + 1] - cb == rnnz);
+        if (l == 0 && !ok) atomicAdd(&a.st->mismatch, 1);
+        for (int t = l; t < rnnz; t += WAVE) vals[t] = A::zero();
+        __syncthreads();
+        // 4. products into vals[rank]
+        const int64_t ab = a.arp[i], ae = a.arp[i + 1];
+        for (int64_t c0 = ab; c0 < ae; c0 += WAVE) {
+            const int cn = stage_chunk<VT>(c0, ae, a.aci, a.aval, a.brp, st_bs, st_len, st_a);
+            __syncthreads();
+            for (int t = g; t < cn; t += ng) {
+                const int64_t bs = st_bs[t];
+                const int len = st_len[t];
+                const VT av = (VT)st_a[t];
+                for (int p = q; p < len; p += gs) {
+                    const int c = a.bci[bs + p];
+                    const VT bv = a.bval[bs + p];
+                    const int d = (c >> 5) - wlo;
+                    const uint32_t w = bits[d];
+                    const int rk = pre[d] + __popc(w & ((1u << (c & 31)) - 1u));
+                    A::add(&vals[rk], av, bv);
+                }
+            }
+            __syncthreads();
+        }
+        // 5. sorted columns, reset of the touched words
+        for (int t = l; t < T; t += WAVE) {
+            const int d = wlist[t];
+            uint32_t w = bits[d];
+            int p = pre[d];
+            const int base = (wlo + d) << 5;
+            while (w) {
+                colbuf[p++] = base + __ffs(w) - 1;
+                w &= w - 1;
+            }
+            bits[d] = 0;
+        }
+        __syncthreads();
+        if (ok) {
+            for (int t = l; t < rnnz; t += WAVE) {
+                a.cci[cb + t] = colbuf[t];
+                a.cval[cb + t] = A::fin(vals[t]);
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// ============================================================ workgroup / row
+
+struct DgLayout {
+    size_t bits, summ, st_off, st_bs, st_a, red, total;
+};
+
+__host__ __device__ inline DgLayout dg_layout(int nwm) {
+    DgLayout L{};
+    const int nsm = (nwm + 31) >> 5;
+    size_t o = 0;
+    L.bits = o;
+    o += align16(4 * (size_t)nwm);
+    L.summ = o;
+    o += align16(4 * (size_t)nsm);
+    L.st_off = o;
+    o += 8 * WG_BIG;
+    L.st_bs = o;
+    o += 8 * WG_BIG;
+    L.st_a = o;
+    o += 8 * WG_BIG;
+    L.red = o;
+    o += 8 * (WG_BIG / WAVE + 2);
+    L.total = o;
+    return L;
+}
+
+// Block-wide exclusive scan of v; *total receives the sum.  red holds
+// WG_BIG/WAVE + 2 longs.
+__device__ __forceinline__ long long block_excl_scan(long long v, long long *red, long long *total) {
+    const int t = threadIdx.x, l = lane_id(), wv = t / WAVE;
+    const long long inc = wave_incl_scan64(v);
+    __syncthreads();
+    if (l == WAVE - 1) red[wv] = inc;
+    __syncthreads();
+    long long off = 0, tot = 0;
+#pragma unroll
+    for (int u = 0; u < WG_BIG / WAVE; ++u) {
+        const long long x = red[u];
+        if (u < wv) off += x;
+        tot += x;
+    }
+    *total = tot;
+    return off + inc - v;
+}
+
+// Flat-parallel walk over the row's multiplications in chunks of 256 A
+// entries: lane f of the chunk's flattened range finds its A entry by binary
+// search in the inclusive prefix st_off[] of the B row lengths.
+template <typename F>
+__device__ __forceinline__ void dg_flat(int64_t ab, int64_t ae, const int32_t *aci, const int64_t *rp,
+                                        int64_t *st_off, int64_t *st_bs, long long *red, F &&body) {
+    const int t = threadIdx.x;
+    for (int64_t cb = ab; cb < ae; cb += WG_BIG) {
+        const int cn = (int)min((int64_t)WG_BIG, ae - cb);
+        long long len = 0;
+        if (t < cn) {
+            const int j = aci[cb + t];
+            const int64_t s0 = rp[j], s1 = rp[j + 1];
+            st_bs[t] = s0;
+            len = s1 - s0;
+        }
+        long long tot;
+        const long long ex = block_excl_scan(len, red, &tot);
+        if (t < cn) st_off[t] = ex + len;
+        __syncthreads();
+        for (long long f = t; f < tot; f += WG_BIG) {
+            int lo = 0, hi = cn - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (st_off[mid] > f) hi = mid; else lo = mid + 1;
+            }
+            const long long before = lo ? st_off[lo - 1] : 0;
+            body(lo, st_bs[lo] + (f - before), cb);
+        }
+        __syncthreads();
+    }
+}
+
+__device__ __forceinline__ int dg_next_row(const RowSet &rs, int64_t lo, int64_t hi, int &x, long long *red) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int64_t t = xcd_grab(rs.queue, lo, hi, x);
+        red[WG_BIG / WAVE] = t < 0 ? -1 : rs.rows[t];
+        red[WG_BIG / WAVE + 1] = x;
+    }
+    __syncthreads();
+    x = (int)red[WG_BIG / WAVE + 1];
+    return (int)red[WG_BIG / WAVE];
+}
+
+__device__ __forceinline__ void dg_or_pass(int i, int wlo, const int64_t *arp, const int32_t *aci,
+                                           const int64_t *brp, const int32_t *bci, const int64_t *bcrp,
+                                           const int32_t *bcsi, const uint32_t *bcs, uint32_t *bits,
+                                           uint32_t *summ, int64_t *st_off, int64_t *st_bs, long long *red) {
+    const bool comp = bcrp != nullptr;
+    dg_flat(arp[i], arp[i + 1], aci, comp ? bcrp : brp, st_off, st_bs, red,
+            [&](int, int64_t e, int64_t) {
+                uint32_t d, cs;
+                if (comp) {
+                    d = (uint32_t)(bcsi[e] - wlo);
+                    cs = bcs[e];
+                } else {
+                    const int c = bci[e];
+                    d = (uint32_t)((c >> 5) - wlo);
+                    cs = 1u << (c & 31);
+                }
+                atomicOr(&bits[d], cs);
+                atomicOr(&summ[d >> 5], 1u << (d & 31));
+            });
+}
+
+__global__ __launch_bounds__(WG_BIG) void k_sym_dg(SymArgs a) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const DgLayout L = dg_layout(a.nw_max);
+    uint32_t *bits = (uint32_t *)(smem + L.bits);
+    uint32_t *summ = (uint32_t *)(smem + L.summ);
+    int64_t *st_off = (int64_t *)(smem + L.st_off);
+    int64_t *st_bs = (int64_t *)(smem + L.st_bs);
+    long long *red = (long long *)(smem + L.red);
+    const int t = threadIdx.x;
+    const int nsm = (a.nw_max + 31) >> 5;
+    for (int w = t; w < a.nw_max; w += WG_BIG) bits[w] = 0;
+    for (int w = t; w < nsm; w += WG_BIG) summ[w] = 0;
+    const int64_t lo = a.rs.koff[a.rs.kind], hi = a.rs.koff[a.rs.kind + 1];
+    int x = blockIdx.x % XCDS;
+    for (;;) {
+        const int i = dg_next_row(a.rs, lo, hi, x, red);
+        if (i < 0) break;
+        const int2 win = a.rwin[i];
+        const int ns = (win.y - win.x + 1 + 31) >> 5;
+        dg_or_pass(i, win.x, a.arp, a.aci, a.brp, a.bci, a.bcrp, a.bcsi, a.bcs, bits, summ, st_off, st_bs, red);
+        long long cnt = 0;
+        for (int s = t; s < ns; s += WG_BIG) {
+            uint32_t m = summ[s];
+            summ[s] = 0;
+            while (m) {
+                const int d = (s << 5) + __ffs(m) - 1;
+                m &= m - 1;
+                cnt += __popc(bits[d]);
+                bits[d] = 0;
+            }
+        }
+        long long tot;
+        block_excl_scan(cnt, red, &tot);
+        if (t == 0) a.row_nnz[i] = (int32_t)tot;
+    }
+}
+
+template <typename VT, int ACC>
+__global__ __launch_bounds__(WG_BIG) void k_num_dg(NumArgs<VT> a) {
+    using A = Accum<VT, ACC>;
+    using S = typename A::store_t;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const DgLayout L = dg_layout(a.nw_max);
+    uint32_t *bits = (uint32_t *)(smem + L.bits);
+    uint32_t *summ = (uint32_t *)(smem + L.summ);
+    int64_t *st_off = (int64_t *)(smem + L.st_off);
+    int64_t *st_bs = (int64_t *)(smem + L.st_bs);
+    long long *red = (long long *)(smem + L.red);
+    S *gv = (S *)a.arena + (int64_t)blockIdx.x * a.arena_cap;  // this workgroup's window of values
+    const int t = threadIdx.x;
+    const int nsm = (a.nw_max + 31) >> 5;
+    for (int w = t; w < a.nw_max; w += WG_BIG) bits[w] = 0;
+    for (int w = t; w < nsm; w += WG_BIG) summ[w] = 0;
+    const int64_t lo = a.rs.koff[a.rs.kind], hi = a.rs.koff[a.rs.kind + 1];
+    int x = blockIdx.x % XCDS;
+    for (;;) {
+        const int i = dg_next_row(a.rs, lo, hi, x, red);
+        if (i < 0) break;
+        const int2 win = a.rwin[i];
+        const int wlo = win.x;
+        const int ns = (win.y - win.x + 1 + 31) >> 5;
+        const int64_t cbase = (int64_t)wlo << 5;
+        dg_or_pass(i, wlo, a.arp, a.aci, a.brp, a.bci, a.bcrp, a.bcsi, a.bcs, bits, summ, st_off, st_bs, red);
+        const int64_t ab = a.arp[i], ae = a.arp[i + 1];
+        dg_flat(ab, ae, a.aci, a.brp, st_off, st_bs, red, [&](int k, int64_t e, int64_t cb) {
+            const VT av = a.aval[cb + k];
+            A::add(&gv[a.bci[e] - cbase], av, a.bval[e]);
+        });
+        __threadfence();  // the HBM atomics above complete before any lane reads a slot
+        __syncthreads();
+        // sorted write-out: summary words in chunks of 256
+        const int64_t c0 = a.coff[i];
+        const int64_t cend = a.coff[i + 1];
+        long long run = 0;
+        for (int s0 = 0; s0 < ns; s0 += WG_BIG) {
+            const int s = s0 + t;
+            const uint32_t m = (s < ns) ? summ[s] : 0u;
+            long long cnt = 0;
+            for (uint32_t mm = m; mm; mm &= mm - 1) cnt += __popc(bits[(s << 5) + __ffs(mm) - 1]);
+            long long tot;
+            const long long ex = block_excl_scan(cnt, red, &tot);
+            int64_t pos = c0 + run + ex;
+            for (uint32_t mm = m; mm; mm &= mm - 1) {
+                const int d = (s << 5) + __ffs(mm) - 1;
+                uint32_t w = bits[d];
+                const int base = (wlo + d) << 5;
+                while (w) {
+                    const int col = base + __ffs(w) - 1;
+                    w &= w - 1;
+                    S *slot = &gv[col - cbase];
+                    const S v = __hip_atomic_load(slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    __hip_atomic_store(slot, A::zero(), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    if (pos < cend) {
+                        a.cci[pos] = col;
+                        a.cval[pos] = A::fin(v);
+                    }
+                    ++pos;
+                }
+                bits[d] = 0;
+            }
+            if (s < ns) summ[s] = 0;
+            run += tot;
+        }
+        if (t == 0 && cend - c0 != run) atomicAdd(&a.st->mismatch, 1);
+        __threadfence();
+    }
+}
+
+template <typename K>
+inline int resident_grid(K kernel, int block, size_t lds, int cus) {
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, block, lds) != hipSuccess || per_cu < 1)
+        per_cu = 1;
+    int g = per_cu * cus;
+    g = (g / XCDS) * XCDS;
+    return g < XCDS ? XCDS : g;
+}
+
+}  // namespace
+
+size_t lds_sym_dw(int nw_max) { return dw_layout(nw_max, 0, 0, false).total; }
+size_t lds_num_dw(int nw_max, int r_max, int acc_bytes, int) { return dw_layout(nw_max, r_max, acc_bytes, true).total; }
+size_t lds_sym_dg(int nw_max) { return dg_layout(nw_max).total; }
+size_t lds_num_dg(int nw_max) { return dg_layout(nw_max).total; }
+
+hipError_t launch_sym_dw(const SymArgs &a, const LaunchCfg &c) {
+    const size_t lds = lds_sym_dw(a.nw_max);
+    const int grid = c.grid > 0 ? c.grid : resident_grid(k_sym_dw, WAVE, lds, c.cus);
+    hipLaunchKernelGGL(k_sym_dw, dim3(grid), dim3(WAVE), lds, c.stream, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_sym_dg(const SymArgs &a, const LaunchCfg &c) {
+    const size_t lds = lds_sym_dg(a.nw_max);
+    const int grid = c.grid > 0 ? c.grid : resident_grid(k_sym_dg, WG_BIG, lds, c.cus);
+    hipLaunchKernelGGL(k_sym_dg, dim3(grid), dim3(WG_BIG), lds, c.stream, a);
+    return hipGetLastError();
+}
+
+template <typename VT, int ACC>
+static hipError_t num_dw_impl(const NumArgs<VT> &a, const LaunchCfg &c) {
+    const size_t lds = lds_num_dw(a.nw_max, a.r_max, sizeof(typename Accum<VT, ACC>::store_t), sizeof(VT));
+    const int grid = c.grid > 0 ? c.grid : resident_grid(k_num_dw<VT, ACC>, WAVE, lds, c.cus);
+    hipLaunchKernelGGL((k_num_dw<VT, ACC>), dim3(grid), dim3(WAVE), lds, c.stream, a);
+    return hipGetLastError();
+}
+
+template <typename VT, int ACC>
+static hipError_t num_dg_impl(const NumArgs<VT> &a, const LaunchCfg &c) {
+    const size_t lds = lds_num_dg(a.nw_max);
+    const int grid = c.grid > 0 ? c.grid : resident_grid(k_num_dg<VT, ACC>, WG_BIG, lds, c.cus);
+    hipLaunchKernelGGL((k_num_dg<VT, ACC>), dim3(grid), dim3(WG_BIG), lds, c.stream, a);
+    return hipGetLastError();
+}
+
+template <>
+hipError_t launch_num_dw<double>(const NumArgs<double> &a, int, const LaunchCfg &c) {
+    return num_dw_impl<double, ACC_NATIVE>(a, c);
+}
+template <>
+hipError_t launch_num_dw<float>(const NumArgs<float> &a, int acc, const LaunchCfg &c) {
+    if (acc == ACC_COMP) return num_dw_impl<float, ACC_COMP>(a, c);
+    if (acc == ACC_WIDE) return num_dw_impl<float, ACC_WIDE>(a, c);
+    return num_dw_impl<float, ACC_NATIVE>(a, c);
+}
+template <>
+hipError_t launch_num_dg<double>(const NumArgs<double> &a, int, const LaunchCfg &c) {
+    return num_dg_impl<double, ACC_NATIVE>(a, c);
+}
+template <>
+hipError_t launch_num_dg<float>(const NumArgs<float> &a, int acc, const LaunchCfg &c) {
+    if (acc == ACC_COMP) return num_dg_impl<float, ACC_COMP>(a, c);
+    if (acc == ACC_WIDE) return num_dg_impl<float, ACC_WIDE>(a, c);
+    return num_dg_impl<float, ACC_NATIVE>(a, c);
+}
+
+// Grid of the persistent kernels: resident workgroups of the concrete kernel.
+int dg_resident_grid(int acc, bool dbl, size_t lds, int cus) {
+    if (dbl) return resident_grid(k_num_dg<double, ACC_NATIVE>, WG_BIG, lds, cus);
+    if (acc == ACC_COMP) return resident_grid(k_num_dg<float, ACC_COMP>, WG_BIG, lds, cus);
+    if (acc == ACC_WIDE) return resident_grid(k_num_dg<float, ACC_WIDE>, WG_BIG, lds, cus);
+    return resident_grid(k_num_dg<float, ACC_NATIVE>, WG_BIG, lds, cus);
+}
+
+}  // namespace spg

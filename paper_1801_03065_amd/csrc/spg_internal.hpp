@@ -1,0 +1,267 @@
+// Internal declarations of the gfx950 SpGEMM library: argument blocks of the
+// kernels, 64-lane wavefront primitives and the host-side launch wrappers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <climits>
+#include <cstdint>
+
+namespace spg {
+
+constexpr int WAVE = 64;  // CDNA wavefront width
+constexpr int XCDS = 8;   // accelerator complex dies on the MI355X
+constexpr int WG_BIG = 256;
+
+// Per row of B: number of entries, number of distinct column-set words
+// (col >> 5) after compression, lowest and highest word touched.
+struct BRow {
+    int32_t len, lenc, wmin, wmax;
+};
+
+// Kernel kinds a row of C can be assigned to (one persistent launch each).
+enum Kind : int {
+    K_EMPTY = 0,  // no multiplications: row size 0
+    K_DW = 1,     // bit-window dense accumulator, one wavefront per row
+    K_HW = 2,     // LDS linear-probing hash, one wavefront per row
+    K_DG = 3,     // bit-window dense accumulator, one 256-lane workgroup per row, values in HBM
+    K_HL = 4,     // two-level hash: LDS level 1 + HBM level 2, one workgroup per row
+    NK = 5
+};
+
+// Global counters written by the analysis kernels (zeroed per symbolic call).
+struct DevStats {
+    unsigned long long fm, fmc, maxrf, maxrfc, nnzbc;
+    unsigned long long nnzc;
+    int bad_input;    // malformed CSR (row_ptr not monotone / not ending at nnz, column out of range)
+    int unsorted;     // B rows whose columns are not sorted
+    int bad_window;   // unsorted B rows too wide for the LDS window
+    int mismatch;     // numeric: row size differs from the plan
+    int overflow;     // level-2 arena exhausted
+    long long kcount_sym[NK];
+    long long kcount_num[NK];
+    int kmax_sym[NK][2];   // per kind: max window words, max bound
+    int kmax_num[NK][2];   // per kind: max window words, max row size
+};
+
+// Limits of the kernel kinds (entries, not bytes).
+constexpr int DW_NW_MAX = 2048;   // window words of the wavefront dense kernel (65536 columns)
+constexpr int DW_R_MAX = 1024;    // row size of the wavefront dense kernel
+constexpr int HW_KEYS_MAX = 1024; // distinct keys of the wavefront hash (table 2x)
+constexpr int DG_NW_MAX = 32768;  // window words of the workgroup dense kernel (2^20 columns)
+
+// ------------------------------------------------------------ argument blocks
+struct RowSet {
+    const int32_t *rows;   // permutation of row ids, grouped by kind
+    const int64_t *koff;   // koff[kind] .. koff[kind+1] is this kind's slice
+    int kind;
+    int32_t *queue;        // XCDS dynamic-schedule counters (zeroed before launch)
+};
+
+struct SymArgs {
+    const int64_t *arp;
+    const int32_t *aci;
+    const int64_t *brp;    // raw B structure
+    const int32_t *bci;
+    const int64_t *bcrp;   // compressed B (nullptr when not compressed)
+    const int32_t *bcsi;
+    const uint32_t *bcs;
+    const int2 *rwin;      // per row: lowest / highest column-set word
+    int32_t *row_nnz;
+    RowSet rs;
+    int nw_max;            // LDS window words for this launch
+    int ts;                // hash table slots (power of two) for hash kinds
+    int lg_gs;             // log2 lanes per B row (Thread-Parallel group)
+    int l1_slots;          // two-level hash: level-1 slots
+    uint32_t *l2_keys;     // two-level hash arena (keys / masks), per workgroup
+    uint32_t *l2_vals;
+    int64_t l2_cap;        // slots per workgroup in the arena
+    DevStats *st;
+};
+
+template <typename VT>
+struct NumArgs {
+    const int64_t *arp;
+    const int32_t *aci;
+    const VT *aval;
+    const int64_t *brp;
+    const int32_t *bci;
+    const VT *bval;
+    const int64_t *bcrp;
+    const int32_t *bcsi;
+    const uint32_t *bcs;
+    const int2 *rwin;
+    const int64_t *coff;   // C row offsets (plan copy, int64)
+    int32_t *cci;
+    VT *cval;
+    RowSet rs;
+    int nw_max;
+    int r_max;
+    int ts;
+    int lg_gs_or;          // lanes per compressed B row in the structure pass
+    int lg_gs;             // lanes per B row in the product pass
+    int l1_slots;
+    void *arena;           // HBM scratch: dense values (K_DG) or level-2 tables (K_HL)
+    int64_t arena_cap;     // entries per workgroup
+    DevStats *st;
+};
+
+// ------------------------------------------------------------ device helpers
+__device__ __forceinline__ int lane_id() { return threadIdx.x & (WAVE - 1); }
+
+__device__ __forceinline__ int wave_sum(int v) {
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d);
+    return v;
+}
+__device__ __forceinline__ long long wave_sum64(long long v) {
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d);
+    return v;
+}
+__device__ __forceinline__ int wave_max(int v) {
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) v = max(v, __shfl_xor(v, d));
+    return v;
+}
+__device__ __forceinline__ int wave_min(int v) {
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) v = min(v, __shfl_xor(v, d));
+    return v;
+}
+// Inclusive prefix sum over the 64 lanes.
+__device__ __forceinline__ int wave_incl_scan(int v) {
+    const int l = lane_id();
+#pragma unroll
+    for (int d = 1; d < WAVE; d <<= 1) {
+        int t = __shfl_up(v, d);
+        if (l >= d) v += t;
+    }
+    return v;
+}
+__device__ __forceinline__ long long wave_incl_scan64(long long v) {
+    const int l = lane_id();
+#pragma unroll
+    for (int d = 1; d < WAVE; d <<= 1) {
+        long long t = __shfl_up(v, d);
+        if (l >= d) v += t;
+    }
+    return v;
+}
+// Number of set bits of a 64-bit lane mask below this lane.
+__device__ __forceinline__ int mbcnt(unsigned long long m) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0));
+}
+__device__ __forceinline__ int read_first(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// Static, XCD-aware slice of [lo, hi) for this workgroup: the grid is a
+// multiple of 8 and workgroup b runs on die b % 8, so each die walks one
+// contiguous eighth of the rows (its L2 then holds that eighth's B rows),
+// and the workgroups of one die interleave row by row inside it.
+struct Slice {
+    int64_t idx, end, step;
+};
+__device__ __forceinline__ Slice xcd_slice(int64_t lo, int64_t hi, int per_wg = 1, int sub = 0) {
+    const int G = gridDim.x, b = blockIdx.x;
+    const int x = b % XCDS, slot = b / XCDS, S = G / XCDS;
+    const int64_t n = hi - lo;
+    Slice s;
+    const int64_t beg = lo + n * x / XCDS;
+    s.end = lo + n * (x + 1) / XCDS;
+    s.idx = beg + (int64_t)slot * per_wg + sub;
+    s.step = (int64_t)S * per_wg;
+    return s;
+}
+
+// Dynamic XCD-aware queue: a workgroup first drains its own die's eighth,
+// then the other dies' eighths.  Returns -1 when everything is taken.
+__device__ __forceinline__ int64_t xcd_grab(int32_t *queue, int64_t lo, int64_t hi, int &x) {
+    const int64_t n = hi - lo;
+    for (int k = 0; k < XCDS; ++k) {
+        const int64_t beg = lo + n * x / XCDS, end = lo + n * (x + 1) / XCDS;
+        if (beg < end) {
+            const int64_t t = beg + atomicAdd(&queue[x], 1);
+            if (t < end) return t;
+        }
+        x = (x + 1) % XCDS;
+    }
+    return -1;
+}
+
+// ------------------------------------------------------------ host launchers
+struct LaunchCfg {
+    hipStream_t stream;
+    int grid;  // persistent workgroups (multiple of 8); 0 = all resident workgroups
+    int cus;   // compute units of the device
+};
+
+hipError_t launch_brow(int64_t n, const int64_t *brp, const int32_t *bci, BRow *out,
+                       int32_t *unsorted_list, DevStats *st, hipStream_t s);
+hipError_t launch_brow_unsorted(const int32_t *list, const int *count, const int64_t *brp, const int32_t *bci,
+                                BRow *out, DevStats *st, hipStream_t s);
+hipError_t launch_compress_sorted_flags(int64_t n, const int64_t *brp, const int32_t *bci, const BRow *bi,
+                                        const uint8_t *unsorted, const int64_t *bcrp, int32_t *bcsi,
+                                        uint32_t *bcs, hipStream_t s);
+hipError_t launch_mark_unsorted(const int32_t *list, const int *count, uint8_t *flag, hipStream_t s);
+hipError_t launch_compress_unsorted(const int32_t *list, const int *count, const int64_t *brp,
+                                    const int32_t *bci, const BRow *bi, const int64_t *bcrp, int32_t *bcsi,
+                                    uint32_t *bcs, hipStream_t s);
+hipError_t launch_rowinfo(int64_t m, const int64_t *arp, const int32_t *aci, const BRow *bi,
+                          int64_t *rflops, int64_t *rflopsc, int2 *rwin, DevStats *st, hipStream_t s);
+hipError_t launch_copy_rp(int64_t n1, const void *src, int is64, int64_t nnz, int64_t *dst, int *bad,
+                          hipStream_t s);
+hipError_t launch_check_cols(int64_t nnz, const int32_t *ci, int64_t ncols, int *bad, hipStream_t s);
+hipError_t launch_brow_lens(int64_t n, const BRow *bi, int which, int64_t *out, hipStream_t s);
+
+// Exclusive scan: out[0..n] (n+1 entries) of in[0..n), int64 result.
+// tmp must hold scan_tmp_elems(n) int64.
+int64_t scan_tmp_elems(int64_t n);
+hipError_t launch_scan_i64(int64_t n, const int64_t *in, int64_t *out, int64_t *tmp, hipStream_t s);
+hipError_t launch_scan_i32(int64_t n, const int32_t *in, int64_t *out, int64_t *tmp, hipStream_t s);
+hipError_t launch_store_rp(int64_t n1, const int64_t *src, void *dst, int is64, hipStream_t s);
+
+// Classification parameters shared by host and device.
+struct ClassParams {
+    int phase;          // 0 symbolic, 1 numeric
+    int accumulator;    // spg_accumulator
+    int compressed;
+    int dw_nw_max, dw_r_max, hw_keys_max, dg_nw_max;
+};
+hipError_t launch_classify(int64_t m, const int64_t *rflops, const int64_t *rflopsc, const int2 *rwin,
+                           const int32_t *row_nnz, ClassParams p, uint8_t *kind, int32_t *row_nnz_out,
+                           DevStats *st, hipStream_t s);
+int64_t part_tmp_elems(int64_t m);
+hipError_t launch_partition(int64_t m, const uint8_t *kind, int32_t *perm, int64_t *koff, int64_t *tmp,
+                            hipStream_t s);
+hipError_t launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s);
+
+// Core kernels.
+hipError_t launch_sym_dw(const SymArgs &a, const LaunchCfg &c);
+hipError_t launch_sym_hw(const SymArgs &a, const LaunchCfg &c);
+hipError_t launch_sym_dg(const SymArgs &a, const LaunchCfg &c);
+hipError_t launch_sym_hl(const SymArgs &a, const LaunchCfg &c);
+
+// acc: 0 native, 1 compensated pair (FP32), 2 FP64 accumulation (FP32)
+template <typename VT>
+hipError_t launch_num_dw(const NumArgs<VT> &a, int acc, const LaunchCfg &c);
+template <typename VT>
+hipError_t launch_num_hw(const NumArgs<VT> &a, int acc, const LaunchCfg &c);
+template <typename VT>
+hipError_t launch_num_dg(const NumArgs<VT> &a, int acc, const LaunchCfg &c);
+template <typename VT>
+hipError_t launch_num_hl(const NumArgs<VT> &a, int acc, const LaunchCfg &c);
+
+// LDS bytes of the core kernels for given limits.
+size_t lds_sym_dw(int nw_max);
+size_t lds_sym_hw(int ts);
+size_t lds_sym_dg(int nw_max);
+size_t lds_sym_hl(int l1_slots);
+size_t lds_num_dw(int nw_max, int r_max, int acc_bytes, int val_bytes);
+size_t lds_num_hw(int ts, int acc_bytes);
+size_t lds_num_dg(int nw_max);
+size_t lds_num_hl(int l1_slots, int acc_bytes);
+
+int dg_resident_grid(int acc, bool dbl, size_t lds, int cus);
+int hl_resident_grid(int acc, bool dbl, size_t lds, int cus);
+
+}  // namespace spg

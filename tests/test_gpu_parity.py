@@ -1,0 +1,132 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle.
+
+Structure (row_ptr, col_idx) must match bit for bit; FP64 values within
+1e-12 * max(|c|, sum |a*b|) per entry (summation order differs); integer-valued
+stencil products are exact in any order, so there they must match exactly.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from helpers import check_f64, check_structure, oracle_ref, run
+
+pytestmark = pytest.mark.gpu
+
+
+def _exact(A, B, **kw):
+    ref = oracle.spgemm(A, B)
+    got, h = run(A, B, **kw)
+    check_structure(ref, got)
+    assert np.array_equal(got[2], ref.values)
+    return h
+
+
+def test_5pt_square_64x64():
+    A = synth.laplace2d_5pt(64, 64)
+    h = _exact(A, A)
+    st = h.stats()
+    assert st["flops"] == 100104 and st["nnz_c"] == 51972 and st["max_row_flops"] == 25
+
+
+@pytest.mark.parametrize("g", [2, 3, 7, 20])
+def test_27pt_square_small(g):
+    A = synth.stencil27(g)
+    _exact(A, A)
+
+
+@pytest.mark.parametrize("g", [4, 10])
+def test_galerkin_small(g):
+    A = synth.stencil27(g)
+    P, Pt = synth.aggregation_2x2x2(g)
+    AP = oracle.spgemm(A, P)
+    _exact(A, P)
+    _exact(Pt, AP)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_random_unsorted_rectangular(seed):
+    rng = np.random.default_rng(seed)
+    m, n, k = int(rng.integers(50, 700)), int(rng.integers(50, 700)), int(rng.integers(1, 5000))
+    A = synth.shuffle_columns(synth.random_csr(m, n, rng.integers(0, 20, m), seed), seed)
+    B = synth.shuffle_columns(synth.random_csr(n, k, rng.integers(0, 30, n), seed + 9), seed + 1)
+    ref, S = oracle_ref(A, B)
+    got, _ = run(A, B)
+    check_f64(ref, S, got)
+
+
+@pytest.mark.parametrize("acc", [0, 1, 2, 3])
+@pytest.mark.parametrize("comp", [-1, 0, 1])
+def test_forced_paths_agree(acc, comp):
+    rng = np.random.default_rng(7)
+    A = synth.shuffle_columns(synth.random_csr(400, 300, rng.integers(0, 25, 400), 1), 2)
+    B = synth.random_csr(300, 3000, rng.integers(0, 40, 300), 3)
+    ref, S = oracle_ref(A, B)
+    got, h = run(A, B, accumulator=acc, compression=comp,
+                 l1_hash_slots=64 if acc == 3 else 0)
+    check_f64(ref, S, got)
+    st = h.stats()
+    if acc == 3:
+        assert st["rows_numeric"]["hash_two_level"] > 0
+    if comp == 1:
+        assert st["compressed"] == 1
+    if comp == 0:
+        assert st["compressed"] == 0
+
+
+def test_heavy_rows_dense_workgroup():
+    """A few rows with tens of thousands of entries in C: workgroup-per-row kernels."""
+    rng = np.random.default_rng(11)
+    counts = rng.integers(0, 6, 500)
+    counts[[3, 77, 400]] = [1500, 900, 2500]
+    A = synth.random_csr(500, 2000, counts, 5)
+    B = synth.random_csr(2000, 200000, rng.integers(5, 60, 2000), 6)
+    ref, S = oracle_ref(A, B)
+    got, h = run(A, B)
+    check_f64(ref, S, got)
+    assert h.stats()["rows_numeric"]["dense_wg"] >= 3
+
+
+def test_wide_window_two_level_hash():
+    """Rows whose column window exceeds the LDS bit window and are large: level-2 hash."""
+    rng = np.random.default_rng(12)
+    counts = rng.integers(0, 4, 300)
+    counts[[5, 100]] = [400, 700]
+    A = synth.random_csr(300, 1000, counts, 8)
+    B = synth.random_csr(1000, 1 << 23, rng.integers(1, 12, 1000), 9)
+    ref, S = oracle_ref(A, B)
+    got, h = run(A, B)
+    check_f64(ref, S, got)
+    assert h.stats()["rows_numeric"]["hash_two_level"] >= 2
+
+
+@pytest.mark.parametrize("shape", [(0, 5, 7), (5, 0, 7), (5, 7, 0), (1, 1, 1), (64, 64, 1)])
+def test_degenerate_shapes(shape):
+    m, n, k = shape
+    A = synth.tiny_random(m, n, 0.5, 1)
+    B = synth.tiny_random(n, k, 0.5, 2)
+    ref, S = oracle_ref(A, B)
+    got, _ = run(A, B)
+    check_f64(ref, S, got)
+
+
+def test_empty_rows_and_structural_zeros():
+    A0 = synth.tiny_random(60, 50, 0.15, 3, zero_frac=0.3)
+    rows = np.repeat(np.arange(60), A0.row_lengths())
+    sel = (rows < 10) | (rows >= 20)
+    counts = np.bincount(rows[sel], minlength=60)
+    rp = np.zeros(61, np.int64)
+    np.cumsum(counts, out=rp[1:])
+    A = synth.Csr(60, 50, rp, A0.col_idx[sel], A0.values[sel])
+    B = synth.tiny_random(50, 40, 0.2, 4, zero_frac=0.3)
+    ref, S = oracle_ref(A, B)
+    got, _ = run(A, B)
+    check_f64(ref, S, got)
+
+
+def test_int64_row_ptrs():
+    A = synth.stencil27(6)
+    ref = oracle.spgemm(A, A)
+    got, _ = run(A, A, rp="i64", crp="i64")
+    check_structure(ref, got)
+    assert np.array_equal(got[2], ref.values)
