@@ -1,0 +1,245 @@
+"""Benchmark of the two-phase SpGEMM on one MI355X.
+
+Workload (one step = both phases of every product, NoReuse): the multigrid
+setup shapes on a 100^3 grid, FP64 values, int32 indices:
+    C  = A * A          A = 27-point operator (diag 26, off -1), n = 1e6
+    AP = A * P          P = 2x2x2 piecewise-constant aggregation (1e6 x 125000)
+    R  = P^T * (A P)    the Galerkin coarse operator
+Reported `value`: whole-step GFLOP/s = 2 * sum f_m / step time (a multiply and
+an add per multiplication).  Symbolic and numeric phases are also reported
+separately per product, with achieved HBM GB/s from algorithmic bytes, and
+the numeric-only (Reuse) rate.  The `roofline` object covers the dominant
+kernel, the numeric kernel of A*A, timed with HIP events on its own stream.
+
+    python bench.py [--gpus 1] [--steps 5] [--warmup 1] [--no-cpu]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def csr_bytes(M, vbytes=8, rp_bytes=4):
+    return rp_bytes * (M.nrows + 1) + (4 + vbytes) * M.nnz
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--grid", type=int, default=100)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--forms", default="", help="comma list of extra forms: precision,batch,backward")
+    ap.add_argument("--rmat-scale", type=int, default=16)
+    ap.add_argument("--batch-count", type=int, default=64)
+    ap.add_argument("--diff-grid", type=int, default=64)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); "
+              "the path is single-GPU, see the sharding notes in DESIGN.md", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_1801_03065_amd as spg
+    import synth
+
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda:0")
+    g = args.grid
+    log(f"[bench] building inputs, grid {g}^3")
+    A = synth.stencil27(g)
+    P, Pt = synth.aggregation_2x2x2(g)
+
+    def to_dev(M):
+        return spg.DeviceCsr.from_arrays(M.nrows, M.ncols, M.row_ptr, M.col_idx, M.values)
+
+    dA, dP, dPt = to_dev(A), to_dev(P), to_dev(Pt)
+    stream = torch.cuda.Stream()
+    torch.cuda.synchronize()
+
+    # device copy bandwidth (for context beside the published peak)
+    x = torch.empty(1 << 28, dtype=torch.float64, device=dev)  # 2 GiB
+    y = torch.empty_like(x)
+    for _ in range(2):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(5):
+        y.copy_(x)
+    e1.record()
+    torch.cuda.synchronize()
+    copy_gbps = 5 * 2 * x.numel() * 8 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del x, y
+    torch.cuda.empty_cache()
+
+    names = ["AxA", "AxP", "PtxAP"]
+    handles = {k: spg.Handle(stream=stream) for k in names}
+
+    def events():
+        return torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    rec = {k: {"sym": [], "num": []} for k in names}
+    last = {}
+
+    def product(name, L, R, timing):
+        h = handles[name]
+        es, ee = events()
+        es.record(stream)
+        rp, nnz = spg.spgemm_symbolic(h, L, R)
+        ee.record(stream)
+        ns, ne = events()
+        with torch.cuda.stream(stream):
+            ci = torch.empty(nnz, dtype=torch.int32, device=dev)
+            va = torch.empty(nnz, dtype=torch.float64, device=dev)
+        C = spg.DeviceCsr(L.nrows, R.ncols, rp, ci, va)
+        ns.record(stream)
+        spg.spgemm_numeric(h, L, R, rp, nnz, out=C)
+        ne.record(stream)
+        if timing:
+            rec[name]["sym"].append((es, ee))
+            rec[name]["num"].append((ns, ne))
+        last[name] = (L, R, rp, nnz, C)
+        return C
+
+    def step(timing):
+        product("AxA", dA, dA, timing)
+        AP = product("AxP", dA, dP, timing)
+        product("PtxAP", dPt, AP, timing)
+
+    log(f"[bench] warmup {args.warmup}")
+    for _ in range(args.warmup):
+        step(False)
+    torch.cuda.synchronize()
+    for k in names:
+        handles[k].check_errors()
+
+    log(f"[bench] timing {args.steps} steps")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step(True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for k in names:
+        handles[k].check_errors()
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+
+    # Reuse case: numeric phase only, same structure (timed separately)
+    reuse_ms = {}
+    for k in names:
+        L, R, rp, nnz, C = last[k]
+        h = handles[k]
+        ts = []
+        for _ in range(args.steps):
+            a, b = events()
+            a.record(stream)
+            spg.spgemm_numeric(h, L, R, rp, nnz, out=C)
+            b.record(stream)
+            ts.append((a, b))
+        torch.cuda.synchronize()
+        h.check_errors()
+        reuse_ms[k] = float(np.mean([a.elapsed_time(b) for a, b in ts]))
+
+    stats = {k: handles[k].stats() for k in names}
+    fm = {k: stats[k]["flops"] for k in names}
+    total_fm = sum(fm.values())
+
+    shapes = {
+        "AxA": (A, A, stats["AxA"]["nnz_c"], A.nrows),
+        "AxP": (A, P, stats["AxP"]["nnz_c"], A.nrows),
+        "PtxAP": (Pt, None, stats["PtxAP"]["nnz_c"], Pt.nrows),
+    }
+    nnz_ap = stats["AxP"]["nnz_c"]
+    ap_bytes = 4 * (P.nrows + 1) + 12 * nnz_ap
+    phases = {}
+    for k in names:
+        L, R, nnzc, m = shapes[k]
+        rb = csr_bytes(R) if R is not None else ap_bytes
+        rstruct = (4 * (R.nrows + 1) + 4 * R.nnz) if R is not None else (4 * (P.nrows + 1) + 4 * nnz_ap)
+        num_bytes = csr_bytes(L) + rb + 4 * (m + 1) + 12 * nnzc
+        nnzbc = stats[k]["flops_compressed"]
+        sym_bytes = (4 * (L.nrows + 1) + 4 * L.nnz) + rstruct + 4 * (m + 1)
+        tsym = float(np.mean([a.elapsed_time(b) for a, b in rec[k]["sym"]]))
+        tnum = float(np.mean([a.elapsed_time(b) for a, b in rec[k]["num"]]))
+        phases[k] = {
+            "flops_m": fm[k], "nnz_c": nnzc, "compressed": bool(stats[k]["compressed"]),
+            "symbolic_ms": round(tsym, 4), "numeric_ms": round(tnum, 4), "reuse_numeric_ms": round(reuse_ms[k], 4),
+            "symbolic_gflops": round(2 * fm[k] / (tsym * 1e-3) / 1e9, 2),
+            "numeric_gflops": round(2 * fm[k] / (tnum * 1e-3) / 1e9, 2),
+            "numeric_hbm_gbps": round(num_bytes / (tnum * 1e-3) / 1e9, 1),
+            "numeric_alg_bytes": int(num_bytes),
+            "symbolic_hbm_gbps": round(sym_bytes / (tsym * 1e-3) / 1e9, 1),
+            "rows_numeric": {kk: v for kk, v in stats[k]["rows_numeric"].items() if v},
+        }
+
+    # roofline: numeric kernel of A*A (one launch on `stream`), HIP events per launch
+    dom = phases["AxA"]
+    t_dom = dom["numeric_ms"] * 1e-3
+    achieved = dom["numeric_alg_bytes"] / t_dom / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": None,
+                "kernel": "k_num_dw<double> (27-point A*A, FP64)",
+                "frac_of_measured_copy": round(achieved / copy_gbps, 4)}
+
+    cpu = None
+    if not args.no_cpu:
+        import oracle
+
+        log("[bench] CPU oracle baseline (full step, sequential C)")
+        reps = 2
+        t = time.perf_counter()
+        for _ in range(reps):
+            oracle.spgemm(A, A)
+            APo = oracle.spgemm(A, P)
+            oracle.spgemm(Pt, APo)
+        tc = (time.perf_counter() - t) / reps
+        cpu = {"value": round(2 * total_fm / tc / 1e9, 3), "unit": "GFLOP/s", "cores": 1, "kind": "oracle",
+               "sample": f"the full step (A*A, A*P, P^T*(AP) on 100^3, both phases), {reps} repetitions, "
+                         f"{tc:.2f} s each on one host core"}
+
+    value = 2 * total_fm / (ms_per_step * 1e-3) / 1e9
+    out = {
+        "metric": "SpGEMM GFLOP/s (two-phase, symbolic+numeric, FP64), with per-phase GFLOP/s and HBM GB/s",
+        "value": round(value, 2), "unit": "GFLOP/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"27-point stencil squared on {g}^3 plus Galerkin P^T(AP) with 2x2x2 aggregation",
+                   "n": A.nrows, "nnz_A": A.nnz, "flops_m_total": total_fm, "index": "int32",
+                   "parallelism": "single GPU"},
+        "phases": phases,
+        "device_copy_gbps": round(copy_gbps, 1),
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    for k in names:
+        handles[k].close()
+    forms = [f for f in args.forms.split(",") if f]
+    if forms:
+        import bench_forms
+
+        out["forms"] = {}
+        for f in forms:
+            log(f"[bench] form {f}")
+            out["forms"][f] = getattr(bench_forms, f)(args, log)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

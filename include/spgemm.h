@@ -125,7 +125,9 @@ typedef struct {
     int64_t rows_symbolic[8];       /* rows per symbolic kernel kind */
     int64_t rows_numeric[8];        /* rows per numeric kernel kind */
     int32_t l2_spill_rows;          /* rows that used the level-2 (HBM) hash */
-    int32_t reserved[7];
+    int32_t tuned_policy;           /* autotune: 0 selector, 1 bit window first, 2 hash first */
+    int32_t tuned_lanes;            /* autotune: lanes per B row in the numeric phase (0 = not tuned) */
+    int32_t reserved[5];
 } spg_stats;
 
 typedef struct spg_handle_s *spg_handle;
@@ -167,6 +169,41 @@ spg_status spgemm_symbolic(spg_handle h, const spg_csr *A, const spg_csr *B,
  * host.  Errors: INVALID_ARG, NOT_READY, STRUCTURE_MISMATCH, UNSUPPORTED,
  * OUT_OF_MEMORY, HIP. */
 spg_status spgemm_numeric(spg_handle h, const spg_csr *A, const spg_csr *B, spg_csr_out *C);
+
+/* Batched symbolic phase of `count` independent products C_i = A_i * B_i
+ * (host arrays A[count], B[count] of device operands; C_row_ptr[count] of
+ * device arrays of A_i.nrows+1 entries of c_rp_type; nnz_c[count] on the
+ * host).  The batch runs as one block-diagonal product: one persistent launch
+ * per row kind serves the rows of every product, in a work list binned by
+ * flops.  The handle's plan then belongs to the batch (spgemm_numeric on it
+ * returns STRUCTURE_MISMATCH).  Errors as spgemm_symbolic. */
+spg_status spgemm_batch_symbolic(spg_handle h, int32_t count, const spg_csr *A, const spg_csr *B,
+                                 void *const *C_row_ptr, spg_itype c_rp_type, int64_t *nnz_c);
+
+/* Batched numeric phase on the plan of the last spgemm_batch_symbolic (same
+ * operands' structure, new values allowed; C[i].nnz = nnz_c[i]).  When the
+ * values of all A_i (and of all B_i, and the columns and values of all C_i)
+ * lie back to back in one allocation, in batch order, nothing is copied and
+ * the call never blocks the host (so it can be captured in a HIP graph);
+ * otherwise the values are gathered / scattered through handle-owned staging
+ * buffers and the call synchronises the stream to upload the pointer tables.
+ * Errors as spgemm_numeric. */
+spg_status spgemm_batch_numeric(spg_handle h, int32_t count, const spg_csr *A, const spg_csr *B,
+                                spg_csr_out *C);
+
+/* Backward of C = A * B restricted to the stored entries (differentiation
+ * of the numeric phase: each multiplication A(i,k)*B(k,j) of Algorithm 1
+ * contributes G(i,j)*B(k,j) to dA(i,k) and A(i,k)*G(i,j) to dB(k,j)):
+ *   dA = (G * B^T) on pattern(A),   dB = (A^T * G) on pattern(B).
+ * A and B: the operands of the last spgemm_symbolic (same structure, current
+ * values).  G: m x k with C's structure -- row_ptr and col_idx of the C the
+ * numeric phase wrote (sorted columns), values = dL/dC.  dA_values (nnz(A))
+ * and dB_values (nnz(B)) are device arrays of the common dtype, overwritten;
+ * either may be NULL to skip it.  Never blocks the host.  Errors: INVALID_ARG,
+ * NOT_READY, STRUCTURE_MISMATCH, HIP (a G column missing from C's row is
+ * reported by spg_check_errors as STRUCTURE_MISMATCH). */
+spg_status spgemm_backward(spg_handle h, const spg_csr *A, const spg_csr *B, const spg_csr *G,
+                           void *dA_values, void *dB_values);
 
 /* Synchronise the handle's stream and report errors the device found since
  * the last check: STRUCTURE_MISMATCH if a numeric call met a row whose size

@@ -9,6 +9,7 @@ Functions (each cites the passage of the paper it follows in the C source):
   block_counts(B, width)  -> distinct col//width per row of B    Compression subsection
   symbolic(A, B)          -> C.row_ptr                          Algorithm 2, line "symbolic"
   spgemm(A, B, with_abs)  -> C (sorted columns) [, S]           Algorithm 1
+  rows(A, B, rows)        -> selected rows of C (+ S) by the same definition
   grad(A, B, C, G)        -> (dA on pattern(A), dB on pattern(B))
 """
 from __future__ import annotations
@@ -52,6 +53,8 @@ def _load():
         lib.spo_symbolic.argtypes = [I, I, I, P, P, P, P, P]
         lib.spo_numeric.restype = ctypes.c_int
         lib.spo_numeric.argtypes = [I, I, I, P, P, P, P, P, P, P, P, P, P]
+        lib.spo_rows.restype = ctypes.c_int
+        lib.spo_rows.argtypes = [I, I, I, P, P, P, P, P, P, I, P, P, P, P, P]
         lib.spo_grad.restype = ctypes.c_int
         lib.spo_grad.argtypes = [I, I, I, P, P, P, P, P, P, P, P, P, P, P]
         _lib = lib
@@ -139,3 +142,26 @@ def grad(A: Csr, B: Csr, C: Csr, G: np.ndarray):
     if rc:
         raise ValueError(f"spo_grad rc={rc}")
     return dA[: A.nnz], dB[: B.nnz]
+
+
+def rows(A: Csr, B: Csr, sel):
+    """Rows `sel` of C = A*B: (row_ptr over the selection, col_idx, values, S)."""
+    _check_dims(A, B)
+    arp, aci, ava = _norm(A)
+    brp, bci, bva = _norm(B)
+    sel = np.ascontiguousarray(sel, dtype=np.int64)
+    rp = np.zeros(sel.shape[0] + 1, dtype=np.int64)
+    L = _load()
+    rc = L.spo_rows(A.nrows, A.ncols, B.ncols, _p(arp), _p(aci), _p(ava), _p(brp), _p(bci), _p(bva),
+                    sel.shape[0], _p(sel), _p(rp), None, None, None)
+    if rc:
+        raise ValueError(f"spo_rows rc={rc}")
+    nnz = int(rp[-1])
+    ci = np.zeros(max(nnz, 1), dtype=np.int32)
+    va = np.zeros(max(nnz, 1))
+    ab = np.zeros(max(nnz, 1))
+    rc = L.spo_rows(A.nrows, A.ncols, B.ncols, _p(arp), _p(aci), _p(ava), _p(brp), _p(bci), _p(bva),
+                    sel.shape[0], _p(sel), _p(rp), _p(ci), _p(va), _p(ab))
+    if rc:
+        raise ValueError(f"spo_rows rc={rc}")
+    return rp, ci[:nnz], va[:nnz], ab[:nnz]

@@ -197,3 +197,61 @@ int spo_grad(int64_t m, int64_t n, int64_t k,
     }
     return 0;
 }
+
+/* Selected rows of C = A * B by the same definition (for products too large
+ * to form whole): rows[0..nsel) are row indices of A; out_rp (nsel+1) gets
+ * the offsets of the selected rows in the compact output.  Call with
+ * out_ci == NULL to get the sizes only (out_rp filled), then again with the
+ * arrays of out_rp[nsel] entries.  Columns sorted per row. */
+int spo_rows(int64_t m, int64_t n, int64_t k,
+             const int64_t *arp, const int32_t *aci, const double *aval,
+             const int64_t *brp, const int32_t *bci, const double *bval,
+             int64_t nsel, const int64_t *rows,
+             int64_t *out_rp, int32_t *out_ci, double *out_val, double *out_abs) {
+    if (check_csr(m, n, arp, aci) || check_csr(n, k, brp, bci)) return -1;
+    size_t kk = (size_t)(k > 0 ? k : 1);
+    int64_t *mark = (int64_t *)malloc(kk * sizeof(int64_t));
+    double *acc = (double *)malloc(kk * sizeof(double));
+    double *aab = (double *)malloc(kk * sizeof(double));
+    int32_t *touched = (int32_t *)malloc(kk * sizeof(int32_t));
+    if (!mark || !acc || !aab || !touched) {
+        free(mark); free(acc); free(aab); free(touched);
+        return -3;
+    }
+    for (int64_t j = 0; j < k; ++j) mark[j] = -1;
+    if (!out_ci) out_rp[0] = 0;
+    for (int64_t s = 0; s < nsel; ++s) {
+        int64_t i = rows[s];
+        if (i < 0 || i >= m) { free(mark); free(acc); free(aab); free(touched); return -1; }
+        int64_t nt = 0;
+        for (int64_t e = arp[i]; e < arp[i + 1]; ++e) {
+            int64_t r = aci[e];
+            double a = aval ? aval[e] : 0.0;
+            for (int64_t f = brp[r]; f < brp[r + 1]; ++f) {
+                int32_t j = bci[f];
+                if (mark[j] != s) {
+                    mark[j] = s;
+                    acc[j] = 0.0;
+                    aab[j] = 0.0;
+                    touched[nt++] = j;
+                }
+                if (out_ci) {
+                    double p = a * bval[f];
+                    acc[j] = acc[j] + p;
+                    aab[j] = aab[j] + (p < 0 ? -p : p);
+                }
+            }
+        }
+        if (!out_ci) { out_rp[s + 1] = out_rp[s] + nt; continue; }
+        if (out_rp[s + 1] - out_rp[s] != nt) { free(mark); free(acc); free(aab); free(touched); return -2; }
+        qsort(touched, (size_t)nt, sizeof(int32_t), cmp_i32);
+        for (int64_t t = 0; t < nt; ++t) {
+            int32_t j = touched[t];
+            out_ci[out_rp[s] + t] = j;
+            out_val[out_rp[s] + t] = acc[j];
+            if (out_abs) out_abs[out_rp[s] + t] = aab[j];
+        }
+    }
+    free(mark); free(acc); free(aab); free(touched);
+    return 0;
+}

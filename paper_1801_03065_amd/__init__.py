@@ -48,7 +48,7 @@ SPG_F64, SPG_F32 = 0, 1
 SPG_I32, SPG_I64 = 0, 1
 ACC_AUTO, ACC_DENSE, ACC_HASH, ACC_HASH_L2 = 0, 1, 2, 3
 FP32_PLAIN, FP32_COMPENSATED, FP32_WIDE = 0, 1, 2
-KIND_NAMES = ("empty", "dense_wave", "hash_wave", "dense_wg", "hash_two_level")
+KIND_NAMES = ("empty", "dense_wave", "hash_wave", "dense_wg", "hash_two_level", "word_hash_wave")
 
 
 class spg_csr(ctypes.Structure):
@@ -75,7 +75,8 @@ class spg_stats(ctypes.Structure):
                 ("nnz_b_compressed", ctypes.c_int64), ("compressed", ctypes.c_int32),
                 ("n_kinds", ctypes.c_int32), ("rows_symbolic", ctypes.c_int64 * 8),
                 ("rows_numeric", ctypes.c_int64 * 8), ("l2_spill_rows", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 7)]
+                ("tuned_policy", ctypes.c_int32), ("tuned_lanes", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 5)]
 
 
 _P = ctypes.c_void_p
@@ -90,6 +91,11 @@ _sigs = {
                              ctypes.POINTER(ctypes.c_int64)]),
     "spgemm_numeric": (_S, [_P, ctypes.POINTER(spg_csr), ctypes.POINTER(spg_csr), ctypes.POINTER(spg_csr_out)]),
     "spg_check_errors": (_S, [_P]),
+    "spgemm_batch_symbolic": (_S, [_P, ctypes.c_int32, ctypes.POINTER(spg_csr), ctypes.POINTER(spg_csr),
+                                   ctypes.POINTER(_P), _S, ctypes.POINTER(ctypes.c_int64)]),
+    "spgemm_batch_numeric": (_S, [_P, ctypes.c_int32, ctypes.POINTER(spg_csr), ctypes.POINTER(spg_csr),
+                                  ctypes.POINTER(spg_csr_out)]),
+    "spgemm_backward": (_S, [_P, ctypes.POINTER(spg_csr), ctypes.POINTER(spg_csr), ctypes.POINTER(spg_csr), _P, _P]),
     "spg_get_stats": (_S, [_P, ctypes.POINTER(spg_stats)]),
     "spg_status_string": (ctypes.c_char_p, [_S]),
     "spg_last_error": (ctypes.c_char_p, [_P]),
@@ -273,3 +279,126 @@ def spgemm(A: DeviceCsr, B: DeviceCsr, handle: Handle | None = None, rp_dtype=to
     h = handle or Handle()
     rp, nnz = spgemm_symbolic(h, A, B, rp_dtype)
     return spgemm_numeric(h, A, B, rp, nnz)
+
+
+def spgemm_backward(h: Handle, A: DeviceCsr, B: DeviceCsr, G: DeviceCsr, need_dA: bool = True,
+                    need_dB: bool = True):
+    """spgemm_backward: (dA on pattern(A), dB on pattern(B)) for dL/dC = G (C's structure)."""
+    dA = torch.empty_like(A.values) if need_dA else None
+    dB = torch.empty_like(B.values) if need_dB else None
+    a, b, g = _csr(A), _csr(B), _csr(G)
+    rc = lib().spgemm_backward(h.ptr, ctypes.byref(a), ctypes.byref(b), ctypes.byref(g),
+                               _P(dA.data_ptr()) if (dA is not None and A.nnz) else None,
+                               _P(dB.data_ptr()) if (dB is not None and B.nnz) else None)
+    if rc != SPG_OK:
+        h._raise(rc)
+    return dA, dB
+
+
+class _SpGEMMFunction(torch.autograd.Function):
+    """C.values = numeric(A.values, B.values) on a fixed symbolic plan."""
+
+    @staticmethod
+    def forward(ctx, a_values, b_values, prod):
+        A = prod.A.with_values(a_values)
+        B = prod.B.with_values(b_values)
+        C = spgemm_numeric(prod.handle, A, B, prod.row_ptr, prod.nnz)
+        ctx.prod = prod
+        ctx.save_for_backward(a_values, b_values, C.col_idx)
+        return C.values
+
+    @staticmethod
+    def backward(ctx, grad_c):
+        a_values, b_values, c_col = ctx.saved_tensors
+        prod = ctx.prod
+        A = prod.A.with_values(a_values)
+        B = prod.B.with_values(b_values)
+        G = DeviceCsr(A.nrows, B.ncols, prod.row_ptr, c_col, grad_c.contiguous())
+        dA, dB = spgemm_backward(prod.handle, A, B, G, ctx.needs_input_grad[0], ctx.needs_input_grad[1])
+        return dA, dB, None
+
+
+class SparseProduct:
+    """A differentiable C = A * B on a fixed structure.
+
+    The symbolic phase runs once at construction; calling the object runs the
+    numeric phase on new values (the reuse case) and returns C's values as an
+    autograd-tracked tensor; C's row_ptr / col_idx are in .row_ptr / .col_idx
+    after the first call.
+    """
+
+    def __init__(self, A: DeviceCsr, B: DeviceCsr, handle: Handle | None = None, rp_dtype=torch.int32):
+        self.A, self.B = A, B
+        self.handle = handle or Handle()
+        self.row_ptr, self.nnz = spgemm_symbolic(self.handle, A, B, rp_dtype)
+        self.col_idx = None
+
+    def __call__(self, a_values: torch.Tensor, b_values: torch.Tensor) -> torch.Tensor:
+        out = _SpGEMMFunction.apply(a_values, b_values, self)
+        return out
+
+    def structure(self) -> DeviceCsr:
+        """C's structure (runs one numeric pass on the stored values if needed)."""
+        C = spgemm_numeric(self.handle, self.A, self.B, self.row_ptr, self.nnz)
+        self.col_idx = C.col_idx
+        return C
+
+
+# ----------------------------------------------------------------- batch
+def spgemm_batch_symbolic(h: Handle, As: list, Bs: list, rp_dtype=torch.int32):
+    """spgemm_batch_symbolic: returns ([C_i.row_ptr], [nnz(C_i)])."""
+    n = len(As)
+    if n != len(Bs) or n == 0:
+        raise ValueError("need equal, non-empty lists")
+    a = (spg_csr * n)(*[_csr(M) for M in As])
+    b = (spg_csr * n)(*[_csr(M) for M in Bs])
+    rps = [torch.empty(M.nrows + 1, dtype=rp_dtype, device=M.row_ptr.device) for M in As]
+    ptrs = (_P * n)(*[r.data_ptr() for r in rps])
+    nnz = (ctypes.c_int64 * n)()
+    rc = lib().spgemm_batch_symbolic(h.ptr, n, a, b, ptrs, _itype(rps[0]), nnz)
+    if rc != SPG_OK:
+        h._raise(rc)
+    return rps, [int(v) for v in nnz]
+
+
+def batch_outputs(As, Bs, rps, nnzs, dtype):
+    """C_i laid out back to back in one allocation (the zero-copy layout)."""
+    dev = rps[0].device
+    tot = sum(nnzs)
+    ci = torch.empty(max(tot, 1), dtype=torch.int32, device=dev)
+    va = torch.empty(max(tot, 1), dtype=dtype, device=dev)
+    out, off = [], 0
+    for A, B, rp, nz in zip(As, Bs, rps, nnzs):
+        out.append(DeviceCsr(A.nrows, B.ncols, rp, ci[off:off + nz], va[off:off + nz]))
+        off += nz
+    return out
+
+
+def spgemm_batch_numeric(h: Handle, As: list, Bs: list, Cs: list):
+    """spgemm_batch_numeric into the given outputs (see batch_outputs)."""
+    n = len(As)
+    a = (spg_csr * n)(*[_csr(M) for M in As])
+    b = (spg_csr * n)(*[_csr(M) for M in Bs])
+    c = (spg_csr_out * n)(*[spg_csr_out(C.nrows, C.ncols, C.nnz, _itype(C.row_ptr), C.row_ptr.data_ptr(),
+                                        C.col_idx.data_ptr() if C.nnz else None,
+                                        C.values.data_ptr() if C.nnz else None, _dtype(C.values))
+                            for C in Cs])
+    rc = lib().spgemm_batch_numeric(h.ptr, n, a, b, c)
+    if rc != SPG_OK:
+        h._raise(rc)
+    return Cs
+
+
+def pack_batch(mats, device="cuda", dtype=torch.float64, rp_dtype=torch.int32):
+    """Device operands with all values (and column indices) back to back in one allocation each."""
+    import numpy as np
+
+    ci = torch.as_tensor(np.concatenate([M.col_idx for M in mats]) if mats else np.zeros(0, np.int32)).to(device)
+    va = torch.as_tensor(np.concatenate([M.values for M in mats])).to(device=device, dtype=dtype)
+    out, off = [], 0
+    for M in mats:
+        nz = int(M.row_ptr[-1])
+        rp = torch.as_tensor(M.row_ptr).to(device=device, dtype=rp_dtype)
+        out.append(DeviceCsr(M.nrows, M.ncols, rp, ci[off:off + nz], va[off:off + nz]))
+        off += nz
+    return out

@@ -221,6 +221,8 @@ __global__ __launch_bounds__(BLK) void k_rowinfo(int64_t m, const int64_t *arp, 
             s_mxc = max(s_mxc, fc);
         }
     }
+    // one set of global atomics per block (same-address atomics serialise in L2)
+    __shared__ long long red[4][BLK / WAVE];
     s_fm = wave_sum64(s_fm);
     s_fmc = wave_sum64(s_fmc);
 #pragma unroll
@@ -228,11 +230,26 @@ __global__ __launch_bounds__(BLK) void k_rowinfo(int64_t m, const int64_t *arp, 
         s_mx = max(s_mx, (long long)__shfl_xor(s_mx, d));
         s_mxc = max(s_mxc, (long long)__shfl_xor(s_mxc, d));
     }
+    const int wv = threadIdx.x / WAVE;
     if (lane_id() == 0) {
-        if (s_fm) atomicAdd(&st->fm, ull(s_fm));
-        if (s_fmc) atomicAdd(&st->fmc, ull(s_fmc));
-        atomicMax(&st->maxrf, ull(s_mx));
-        atomicMax(&st->maxrfc, ull(s_mxc));
+        red[0][wv] = s_fm;
+        red[1][wv] = s_fmc;
+        red[2][wv] = s_mx;
+        red[3][wv] = s_mxc;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        long long a = 0, b = 0, c = 0, d = 0;
+        for (int u = 0; u < BLK / WAVE; ++u) {
+            a += red[0][u];
+            b += red[1][u];
+            c = max(c, red[2][u]);
+            d = max(d, red[3][u]);
+        }
+        if (a) atomicAdd(&st->fm, ull(a));
+        if (b) atomicAdd(&st->fmc, ull(b));
+        if (c) atomicMax(&st->maxrf, ull(c));
+        if (d) atomicMax(&st->maxrfc, ull(d));
     }
 }
 
@@ -243,56 +260,85 @@ __global__ __launch_bounds__(BLK) void k_brow_lens(int64_t n, const BRow *bi, in
 
 // ------------------------------------------------------------------ classify
 __global__ __launch_bounds__(BLK) void k_classify(int64_t m, const int64_t *rflops, const int64_t *rflopsc,
-                                                   const int2 *rwin, const int32_t *row_nnz, ClassParams p,
-                                                   uint8_t *kind, int32_t *row_nnz_out, DevStats *st) {
-    __shared__ int smax[NK][2];
+                                                   const int2 *rwin, const int32_t *row_nnz,
+                                                   const int32_t *row_words, ClassParams p, uint8_t *kind,
+                                                   int32_t *row_nnz_out, DevStats *st) {
+    __shared__ int smax[NK][3];
     __shared__ long long scnt[NK];
     if (threadIdx.x < NK) {
         smax[threadIdx.x][0] = 0;
         smax[threadIdx.x][1] = 0;
+        smax[threadIdx.x][2] = 0;
         scnt[threadIdx.x] = 0;
     }
     __syncthreads();
-    for (int64_t i = (int64_t)blockIdx.x * BLK + threadIdx.x; i < m; i += (int64_t)gridDim.x * BLK) {
-        const long long f = rflops[i];
-        const int2 w = rwin[i];
-        int k = K_EMPTY, a = 0, bnd = 0;
+    // every lane runs the same trip count so the wavefront reductions below
+    // see all 64 lanes active
+    const int64_t stride = (int64_t)gridDim.x * BLK;
+    for (int64_t i0 = (int64_t)blockIdx.x * BLK; i0 < m; i0 += stride) {
+        const int64_t i = i0 + threadIdx.x;
+        const bool valid = i < m;
+        const bool sampled = p.sample_stride <= 1 || (i % p.sample_stride) == 0;
+        const long long f = (valid && sampled) ? rflops[i] : 0;
+        const int2 w = valid ? rwin[i] : make_int2(0, -1);
+        int k = valid ? K_EMPTY : -1, a = 0, bnd = 0, tw = 0;
         if (f > 0) {
             const long long nw = (long long)w.y - w.x + 1;
-            long long bound;
+            long long bound, words;
             if (p.phase == 0) {
                 bound = p.compressed ? min((long long)rflopsc[i], nw) : min(f, 32 * nw);
+                words = min(bound, nw);
             } else {
                 bound = row_nnz[i];
+                words = row_words[i];
             }
             const bool dw_fit = nw <= p.dw_nw_max && (p.phase == 0 || bound <= p.dw_r_max);
+            const bool wh_fit = p.phase == 1 && nw <= p.wh_nw_max && bound <= p.wh_r_max && words <= p.wh_t_max;
             const bool hw_fit = bound <= p.hw_keys_max;
             const bool dg_fit = nw <= p.dg_nw_max;
             switch (p.accumulator) {
+                case 1:  // bit-window dense wherever it fits
+                    k = dw_fit ? K_DW : (dg_fit ? K_DG : (hw_fit ? K_HW : K_HL));
+                    break;
                 case 2:  // hash
                     k = hw_fit ? K_HW : K_HL;
                     break;
                 case 3:  // two-level hash everywhere
                     k = K_HL;
                     break;
-                default:  // auto / dense
-                    k = dw_fit ? K_DW : (hw_fit ? K_HW : (dg_fit ? K_DG : K_HL));
+                default:  // selector
+                    if (p.phase == 0)
+                        k = dw_fit ? K_DW : (hw_fit ? K_HW : (dg_fit ? K_DG : K_HL));
+                    else
+                        k = wh_fit ? K_WH : (hw_fit ? K_HW : (dg_fit ? K_DG : K_HL));
             }
             a = (int)min(nw, (long long)INT_MAX);
             bnd = (int)min(bound, (long long)INT_MAX);
-        } else if (p.phase == 0) {
+            tw = (int)min(words, (long long)INT_MAX);
+        } else if (valid && p.phase == 0) {
             row_nnz_out[i] = 0;
         }
-        kind[i] = (uint8_t)k;
-        atomicMax(&smax[k][0], a);
-        atomicMax(&smax[k][1], bnd);
-        atomicAdd((unsigned long long *)&scnt[k], 1ull);
+        if (valid) kind[i] = (uint8_t)k;
+        // aggregate over the wavefront per kind, then one LDS atomic per kind
+        for (int kk = 0; kk < NK; ++kk) {
+            const unsigned long long bal = __ballot(k == kk);
+            if (!bal) continue;
+            const int ma = wave_max(k == kk ? a : 0), mb = wave_max(k == kk ? bnd : 0);
+            const int mc = wave_max(k == kk ? tw : 0);
+            if (lane_id() == 0) {
+                atomicMax(&smax[kk][0], ma);
+                atomicMax(&smax[kk][1], mb);
+                atomicMax(&smax[kk][2], mc);
+                atomicAdd((unsigned long long *)&scnt[kk], (unsigned long long)__popcll(bal));
+            }
+        }
     }
     __syncthreads();
     if (threadIdx.x < NK) {
         int *gm = p.phase == 0 ? &st->kmax_sym[threadIdx.x][0] : &st->kmax_num[threadIdx.x][0];
         atomicMax(gm, smax[threadIdx.x][0]);
         atomicMax(gm + 1, smax[threadIdx.x][1]);
+        atomicMax(gm + 2, smax[threadIdx.x][2]);
         long long *gc = p.phase == 0 ? &st->kcount_sym[threadIdx.x] : &st->kcount_num[threadIdx.x];
         if (scnt[threadIdx.x]) atomicAdd((unsigned long long *)gc, (unsigned long long)scnt[threadIdx.x]);
     }
@@ -504,7 +550,7 @@ hipError_t launch_compress_sorted_flags(int64_t n, const int64_t *brp, const int
 hipError_t launch_rowinfo(int64_t m, const int64_t *arp, const int32_t *aci, const BRow *bi, int64_t *rflops,
                           int64_t *rflopsc, int2 *rwin, DevStats *st, hipStream_t s) {
     if (m == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_rowinfo, dim3(grid_for(m * RI_GS, BLK)), dim3(BLK), 0, s, m, arp, aci, bi, rflops,
+    hipLaunchKernelGGL(k_rowinfo, dim3(grid_for(m * RI_GS, BLK, 4096)), dim3(BLK), 0, s, m, arp, aci, bi, rflops,
                        rflopsc, rwin, st);
     return hipGetLastError();
 }
@@ -547,11 +593,11 @@ hipError_t launch_store_rp(int64_t n1, const int64_t *src, void *dst, int is64, 
 }
 
 hipError_t launch_classify(int64_t m, const int64_t *rflops, const int64_t *rflopsc, const int2 *rwin,
-                           const int32_t *row_nnz, ClassParams p, uint8_t *kind, int32_t *row_nnz_out,
-                           DevStats *st, hipStream_t s) {
+                           const int32_t *row_nnz, const int32_t *row_words, ClassParams p, uint8_t *kind,
+                           int32_t *row_nnz_out, DevStats *st, hipStream_t s) {
     if (m == 0) return hipSuccess;
     hipLaunchKernelGGL(k_classify, dim3(grid_for(m, BLK, 4096)), dim3(BLK), 0, s, m, rflops, rflopsc, rwin,
-                       row_nnz, p, kind, row_nnz_out, st);
+                       row_nnz, row_words, p, kind, row_nnz_out, st);
     return hipGetLastError();
 }
 

@@ -10,6 +10,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <vector>
 
 #include "spg_accum.hpp"
 #include "spg_internal.hpp"
@@ -54,8 +55,21 @@ struct spg_handle_s {
     spg_stats stats{};
 
     DevBuf arp64, brp64, binfo, ulist, uflag, bcrp, bcsi, bcs, rflops, rflopsc, rwin, row_nnz, coff, kind_sym,
-        kind_num, perm_sym, perm_num, koff_sym, koff_num, tmp, dstats, queue, arena, l2k, l2v, blens;
+        kind_num, perm_sym, perm_num, koff_sym, koff_num, tmp, dstats, queue, arena, l2k, l2v, blens, row_words;
     size_t arena_bytes_zeroed = 0;
+    const int32_t *aci_used = nullptr, *bci_used = nullptr;  // column arrays the kernels read
+    ClassParams cparams{};                                   // classification of the last symbolic phase
+    int lg_num = 4;                                          // log2 lanes per B row, numeric phase
+    bool tuned = false;
+    DevBuf kind_tmp, perm_tmp, koff_tmp;
+
+    struct Batch {
+        int count = 0;
+        std::vector<BatchDesc> a, b, c;    // host copies (c: row_ptr outputs of C_i)
+        std::vector<int64_t> c_off, c_nnz; // C_i's entries in the concatenation
+        int64_t rows = 0, nnza = 0, nnzb = 0, max_rows = 0, max_nnza = 0, max_nnzb = 0, max_nnzc = 0;
+        DevBuf aci, bci, desc, astage, bstage, cci, cval;
+    } batch;
 };
 
 namespace {
@@ -230,7 +244,7 @@ spg_status spg_destroy(spg_handle h) {
     DevBuf *bufs[] = {&h->arp64, &h->brp64, &h->binfo, &h->ulist, &h->uflag, &h->bcrp, &h->bcsi, &h->bcs,
                       &h->rflops, &h->rflopsc, &h->rwin, &h->row_nnz, &h->coff, &h->kind_sym, &h->kind_num,
                       &h->perm_sym, &h->perm_num, &h->koff_sym, &h->koff_num, &h->tmp, &h->dstats, &h->queue,
-                      &h->arena, &h->l2k, &h->l2v, &h->blens};
+                      &h->arena, &h->l2k, &h->l2v, &h->blens, &h->row_words, &h->kind_tmp, &h->perm_tmp, &h->koff_tmp};
     for (DevBuf *b : bufs) release(*b);
     if (h->hst) (void)hipHostFree(h->hst);
     if (h->hkoff) (void)hipHostFree(h->hkoff);
@@ -274,24 +288,8 @@ spg_status spg_check_errors(spg_handle h) {
 }
 
 // ------------------------------------------------------------------ symbolic
-spg_status spgemm_symbolic(spg_handle h, const spg_csr *A, const spg_csr *B, void *C_row_ptr,
-                           spg_itype c_rpt, int64_t *nnz_c) {
-    if (!h) return SPG_ERR_INVALID_ARG;
-    h->err.clear();
-    spg_status s;
-    if ((s = check_csr(h, A, "A", false)) != SPG_OK) return s;
-    if ((s = check_csr(h, B, "B", false)) != SPG_OK) return s;
-    if (!C_row_ptr || !nnz_c) return fail(h, SPG_ERR_INVALID_ARG, "C_row_ptr / nnz_c is NULL");
-    if (c_rpt != SPG_I32 && c_rpt != SPG_I64) return fail(h, SPG_ERR_INVALID_ARG, "bad C rp_type");
-    if (A->ncols != B->nrows) return fail(h, SPG_ERR_DIM_MISMATCH, "A.ncols != B.nrows");
-    h->ready = false;
-    const int64_t m = A->nrows, n = B->nrows, k = B->ncols;
-    hipStream_t st = h->stream;
-    Fingerprint fp;
-    fp.m = m; fp.n = n; fp.k = k; fp.nnza = A->nnz; fp.nnzb = B->nnz;
-    fp.arp = A->row_ptr; fp.brp = B->row_ptr; fp.aci = A->col_idx; fp.bci = B->col_idx;
-    fp.arpt = A->rp_type; fp.brpt = B->rp_type;
-
+// Plan buffers for an m x n times n x k product (grow-only).
+static spg_status plan_buffers(spg_handle h, int64_t m, int64_t n, int64_t nnzb) {
     HIPCHK(ensure(h->arp64, 8 * (m + 1)));
     HIPCHK(ensure(h->brp64, 8 * (n + 1)));
     HIPCHK(ensure(h->binfo, sizeof(BRow) * std::max<int64_t>(n, 1)));
@@ -302,6 +300,7 @@ spg_status spgemm_symbolic(spg_handle h, const spg_csr *A, const spg_csr *B, voi
     HIPCHK(ensure(h->rflopsc, 8 * std::max<int64_t>(m, 1)));
     HIPCHK(ensure(h->rwin, 8 * std::max<int64_t>(m, 1)));
     HIPCHK(ensure(h->row_nnz, 4 * std::max<int64_t>(m, 1)));
+    HIPCHK(ensure(h->row_words, 4 * std::max<int64_t>(m, 1)));
     HIPCHK(ensure(h->coff, 8 * (m + 1)));
     HIPCHK(ensure(h->kind_sym, std::max<int64_t>(m, 1)));
     HIPCHK(ensure(h->kind_num, std::max<int64_t>(m, 1)));
@@ -312,23 +311,22 @@ spg_status spgemm_symbolic(spg_handle h, const spg_csr *A, const spg_csr *B, voi
     const int64_t tmp_elems = std::max({scan_tmp_elems(m), scan_tmp_elems(n), part_tmp_elems(m)});
     HIPCHK(ensure(h->tmp, 8 * tmp_elems));
 
-    DevStats *dst = h->dstats.as<DevStats>();
-    HIPCHK(hipMemsetAsync(dst, 0, sizeof(DevStats), st));
-    int *bad = &dst->bad_input;
-    HIPCHK(launch_copy_rp(m + 1, A->row_ptr, A->rp_type == SPG_I64, A->nnz, h->arp64.as<int64_t>(), bad, st));
-    HIPCHK(launch_copy_rp(n + 1, B->row_ptr, B->rp_type == SPG_I64, B->nnz, h->brp64.as<int64_t>(), bad, st));
-    HIPCHK(launch_check_cols(A->nnz, A->col_idx, n, bad, st));
-    HIPCHK(launch_check_cols(B->nnz, B->col_idx, k, bad, st));
-    // The structure kernels below index B by A's columns: they run only on
-    // validated input, so a malformed operand is rejected before any of them.
-    if ((s = pull_stats(h)) != SPG_OK) return s;
-    if (h->hst->bad_input) return fail(h, SPG_ERR_INVALID_ARG, "malformed CSR: row_ptr or col_idx out of range");
+    return SPG_OK;
+}
 
+// The symbolic phase on validated, device-resident structure: h->arp64 (m+1),
+// h->brp64 (n+1) as int64, A's columns aci (row indices of B) and B's columns
+// bci.  Leaves the plan in the handle and C's int64 row offsets in h->coff.
+static spg_status symbolic_core(spg_handle h, int64_t m, int64_t n, int64_t nnza, int64_t nnzb,
+                                const int32_t *aci, const int32_t *bci, int64_t *nnzc_out) {
+    spg_status s;
+    hipStream_t st = h->stream;
+    DevStats *dst = h->dstats.as<DevStats>();
     const int64_t *arp = h->arp64.as<int64_t>(), *brp = h->brp64.as<int64_t>();
     BRow *bi = h->binfo.as<BRow>();
-    HIPCHK(launch_brow(n, brp, B->col_idx, bi, h->ulist.as<int32_t>(), dst, st));
-    HIPCHK(launch_brow_unsorted(h->ulist.as<int32_t>(), &dst->unsorted, brp, B->col_idx, bi, dst, st));
-    HIPCHK(launch_rowinfo(m, arp, A->col_idx, bi, h->rflops.as<int64_t>(), h->rflopsc.as<int64_t>(),
+    HIPCHK(launch_brow(n, brp, bci, bi, h->ulist.as<int32_t>(), dst, st));
+    HIPCHK(launch_brow_unsorted(h->ulist.as<int32_t>(), &dst->unsorted, brp, bci, bi, dst, st));
+    HIPCHK(launch_rowinfo(m, arp, aci, bi, h->rflops.as<int64_t>(), h->rflopsc.as<int64_t>(),
                           h->rwin.as<int2>(), dst, st));
     if ((s = pull_stats(h)) != SPG_OK) return s;  // host sync 1: flop counts
     const DevStats hs1 = *h->hst;
@@ -339,22 +337,22 @@ spg_status spgemm_symbolic(spg_handle h, const spg_csr *A, const spg_csr *B, voi
     bool comp = false;
     if (h->opt.compression == 1) comp = true;
     else if (h->opt.compression == -1) comp = hs1.fm > 0 && fmc < h->opt.cf_threshold * fm;
-    h->avg_len = A->nnz ? std::max(1.0, fm / (double)A->nnz) : 1.0;
-    h->avg_len_c = A->nnz ? std::max(1.0, (comp ? fmc : fm) / (double)A->nnz) : 1.0;
+    h->avg_len = nnza ? std::max(1.0, fm / (double)nnza) : 1.0;
+    h->avg_len_c = nnza ? std::max(1.0, (comp ? fmc : fm) / (double)nnza) : 1.0;
 
     if (comp) {
         // compressed B (Compression subsection): lengths -> offsets -> (word, bits) pairs
         HIPCHK(ensure(h->blens, 8 * std::max<int64_t>(n, 1)));
         HIPCHK(launch_brow_lens(n, bi, 1, h->blens.as<int64_t>(), st));
         HIPCHK(launch_scan_i64(n, h->blens.as<int64_t>(), h->bcrp.as<int64_t>(), h->tmp.as<int64_t>(), st));
-        HIPCHK(ensure(h->bcsi, 4 * std::max<int64_t>(B->nnz, 1)));
-        HIPCHK(ensure(h->bcs, 4 * std::max<int64_t>(B->nnz, 1)));
-        HIPCHK(hipMemsetAsync(h->bcs.p, 0, 4 * std::max<int64_t>(B->nnz, 1), st));
+        HIPCHK(ensure(h->bcsi, 4 * std::max<int64_t>(nnzb, 1)));
+        HIPCHK(ensure(h->bcs, 4 * std::max<int64_t>(nnzb, 1)));
+        HIPCHK(hipMemsetAsync(h->bcs.p, 0, 4 * std::max<int64_t>(nnzb, 1), st));
         HIPCHK(hipMemsetAsync(h->uflag.p, 0, std::max<int64_t>(n, 1), st));
         HIPCHK(launch_mark_unsorted(h->ulist.as<int32_t>(), &dst->unsorted, h->uflag.as<uint8_t>(), st));
-        HIPCHK(launch_compress_sorted_flags(n, brp, B->col_idx, bi, h->uflag.as<uint8_t>(), h->bcrp.as<int64_t>(),
+        HIPCHK(launch_compress_sorted_flags(n, brp, bci, bi, h->uflag.as<uint8_t>(), h->bcrp.as<int64_t>(),
                                             h->bcsi.as<int32_t>(), h->bcs.as<uint32_t>(), st));
-        HIPCHK(launch_compress_unsorted(h->ulist.as<int32_t>(), &dst->unsorted, brp, B->col_idx, bi,
+        HIPCHK(launch_compress_unsorted(h->ulist.as<int32_t>(), &dst->unsorted, brp, bci, bi,
                                         h->bcrp.as<int64_t>(), h->bcsi.as<int32_t>(), h->bcs.as<uint32_t>(), st));
     }
 
@@ -366,8 +364,13 @@ spg_status spgemm_symbolic(spg_handle h, const spg_csr *A, const spg_csr *B, voi
     cp.dw_r_max = DW_R_MAX;
     cp.hw_keys_max = HW_KEYS_MAX;
     cp.dg_nw_max = h->dg_nw_max;
-    HIPCHK(launch_classify(m, h->rflops.as<int64_t>(), h->rflopsc.as<int64_t>(), h->rwin.as<int2>(), nullptr, cp,
-                           h->kind_sym.as<uint8_t>(), h->row_nnz.as<int32_t>(), dst, st));
+    cp.wh_nw_max = WH_NW_MAX;
+    cp.wh_r_max = WH_R_MAX;
+    cp.wh_t_max = WH_T_MAX;
+    cp.sample_stride = 1;
+    HIPCHK(hipMemsetAsync(h->row_words.p, 0, 4 * std::max<int64_t>(m, 1), st));
+    HIPCHK(launch_classify(m, h->rflops.as<int64_t>(), h->rflopsc.as<int64_t>(), h->rwin.as<int2>(), nullptr,
+                           nullptr, cp, h->kind_sym.as<uint8_t>(), h->row_nnz.as<int32_t>(), dst, st));
     HIPCHK(launch_partition(m, h->kind_sym.as<uint8_t>(), h->perm_sym.as<int32_t>(), h->koff_sym.as<int64_t>(),
                             h->tmp.as<int64_t>(), st));
     if ((s = pull_stats(h)) != SPG_OK) return s;  // host sync 2: per-kind sizes
@@ -375,9 +378,9 @@ spg_status spgemm_symbolic(spg_handle h, const spg_csr *A, const spg_csr *B, voi
 
     SymArgs sa{};
     sa.arp = arp;
-    sa.aci = A->col_idx;
+    sa.aci = aci;
     sa.brp = brp;
-    sa.bci = B->col_idx;
+    sa.bci = bci;
     if (comp) {
         sa.bcrp = h->bcrp.as<int64_t>();
         sa.bcsi = h->bcsi.as<int32_t>();
@@ -385,6 +388,7 @@ spg_status spgemm_symbolic(spg_handle h, const spg_csr *A, const spg_csr *B, voi
     }
     sa.rwin = h->rwin.as<int2>();
     sa.row_nnz = h->row_nnz.as<int32_t>();
+    sa.row_words = h->row_words.as<int32_t>();
     sa.rs.rows = h->perm_sym.as<int32_t>();
     sa.rs.koff = h->koff_sym.as<int64_t>();
     sa.st = dst;
@@ -434,7 +438,8 @@ spg_status spgemm_symbolic(spg_handle h, const spg_csr *A, const spg_csr *B, voi
     HIPCHK(launch_scan_i32(m, h->row_nnz.as<int32_t>(), h->coff.as<int64_t>(), h->tmp.as<int64_t>(), st));
     cp.phase = 1;
     HIPCHK(launch_classify(m, h->rflops.as<int64_t>(), h->rflopsc.as<int64_t>(), h->rwin.as<int2>(),
-                           h->row_nnz.as<int32_t>(), cp, h->kind_num.as<uint8_t>(), nullptr, dst, st));
+                           h->row_nnz.as<int32_t>(), h->row_words.as<int32_t>(), cp, h->kind_num.as<uint8_t>(),
+                           nullptr, dst, st));
     HIPCHK(launch_partition(m, h->kind_num.as<uint8_t>(), h->perm_num.as<int32_t>(), h->koff_num.as<int64_t>(),
                             h->tmp.as<int64_t>(), st));
     HIPCHK(hipMemcpyAsync(h->hkoff, h->coff.as<int64_t>() + m, sizeof(int64_t), hipMemcpyDeviceToHost, st));
@@ -442,12 +447,6 @@ spg_status spgemm_symbolic(spg_handle h, const spg_csr *A, const spg_csr *B, voi
     const DevStats hs3 = *h->hst;
     if (hs3.overflow) return fail(h, SPG_ERR_OUT_OF_MEMORY, "level-2 hash arena too small in the symbolic phase");
     const int64_t nnzc = h->hkoff[0];
-    if (c_rpt == SPG_I32 && nnzc > INT32_MAX)
-        return fail(h, SPG_ERR_INDEX_OVERFLOW, "nnz(C) exceeds an int32 row_ptr; ask for SPG_I64");
-    HIPCHK(launch_store_rp(m + 1, h->coff.as<int64_t>(), C_row_ptr, c_rpt == SPG_I64, st));
-
-    h->fp = fp;
-    h->nnzc = nnzc;
     h->compressed = comp;
     *h->hst = hs3;
     spg_stats &o = h->stats;
@@ -467,6 +466,52 @@ spg_status spgemm_symbolic(spg_handle h, const spg_csr *A, const spg_csr *B, voi
     }
     o.max_row_nnz = maxrs;
     o.l2_spill_rows = (int32_t)hs3.kcount_num[K_HL];
+    h->aci_used = aci;
+    h->bci_used = bci;
+    h->cparams = cp;
+    h->lg_num = lg_group(h->avg_len);
+    h->tuned = false;
+    *nnzc_out = nnzc;
+    return SPG_OK;
+}
+
+spg_status spgemm_symbolic(spg_handle h, const spg_csr *A, const spg_csr *B, void *C_row_ptr,
+                           spg_itype c_rpt, int64_t *nnz_c) {
+    if (!h) return SPG_ERR_INVALID_ARG;
+    h->err.clear();
+    spg_status s;
+    if ((s = check_csr(h, A, "A", false)) != SPG_OK) return s;
+    if ((s = check_csr(h, B, "B", false)) != SPG_OK) return s;
+    if (!C_row_ptr || !nnz_c) return fail(h, SPG_ERR_INVALID_ARG, "C_row_ptr / nnz_c is NULL");
+    if (c_rpt != SPG_I32 && c_rpt != SPG_I64) return fail(h, SPG_ERR_INVALID_ARG, "bad C rp_type");
+    if (A->ncols != B->nrows) return fail(h, SPG_ERR_DIM_MISMATCH, "A.ncols != B.nrows");
+    h->ready = false;
+    h->batch.count = 0;
+    const int64_t m = A->nrows, n = B->nrows, k = B->ncols;
+    hipStream_t st = h->stream;
+    if ((s = plan_buffers(h, m, n, B->nnz)) != SPG_OK) return s;
+    DevStats *dst = h->dstats.as<DevStats>();
+    HIPCHK(hipMemsetAsync(dst, 0, sizeof(DevStats), st));
+    int *bad = &dst->bad_input;
+    HIPCHK(launch_copy_rp(m + 1, A->row_ptr, A->rp_type == SPG_I64, A->nnz, h->arp64.as<int64_t>(), bad, st));
+    HIPCHK(launch_copy_rp(n + 1, B->row_ptr, B->rp_type == SPG_I64, B->nnz, h->brp64.as<int64_t>(), bad, st));
+    HIPCHK(launch_check_cols(A->nnz, A->col_idx, n, bad, st));
+    HIPCHK(launch_check_cols(B->nnz, B->col_idx, k, bad, st));
+    // The structure kernels index B by A's columns: they run only on validated
+    // input, so a malformed operand is rejected before any of them.
+    if ((s = pull_stats(h)) != SPG_OK) return s;
+    if (h->hst->bad_input) return fail(h, SPG_ERR_INVALID_ARG, "malformed CSR: row_ptr or col_idx out of range");
+    HIPCHK(hipMemsetAsync(dst, 0, sizeof(DevStats), st));
+    int64_t nnzc = 0;
+    if ((s = symbolic_core(h, m, n, A->nnz, B->nnz, A->col_idx, B->col_idx, &nnzc)) != SPG_OK) return s;
+    if (c_rpt == SPG_I32 && nnzc > INT32_MAX)
+        return fail(h, SPG_ERR_INDEX_OVERFLOW, "nnz(C) exceeds an int32 row_ptr; ask for SPG_I64");
+    HIPCHK(launch_store_rp(m + 1, h->coff.as<int64_t>(), C_row_ptr, c_rpt == SPG_I64, st));
+    Fingerprint &fp = h->fp;
+    fp.m = m; fp.n = n; fp.k = k; fp.nnza = A->nnz; fp.nnzb = B->nnz;
+    fp.arp = A->row_ptr; fp.brp = B->row_ptr; fp.aci = A->col_idx; fp.bci = B->col_idx;
+    fp.arpt = A->rp_type; fp.brpt = B->rp_type;
+    h->nnzc = nnzc;
     *nnz_c = nnzc;
     h->ready = true;
     return SPG_OK;
@@ -475,51 +520,47 @@ spg_status spgemm_symbolic(spg_handle h, const spg_csr *A, const spg_csr *B, voi
 }  // extern "C"
 
 // ------------------------------------------------------------------ numeric
+static int fp32_acc(spg_handle h) {
+    return h->opt.fp32_mode == SPG_FP32_COMPENSATED ? ACC_COMP
+           : h->opt.fp32_mode == SPG_FP32_WIDE      ? ACC_WIDE
+                                                    : ACC_NATIVE;
+}
+
+// The numeric phase on the plan: A's values aval, B's values bval (entry order
+// of the structure the symbolic phase saw), C's columns / values written at the
+// plan's row offsets.
+// One persistent launch per non-empty kind, sized by the kind's maxima.
 template <typename VT>
-static spg_status numeric_impl(spg_handle h, const spg_csr *A, const spg_csr *B, spg_csr_out *C, int acc) {
+static spg_status launch_kinds(spg_handle h, NumArgs<VT> na, const long long *kcount, const int (*kmax)[3],
+                               int acc) {
     hipStream_t st = h->stream;
-    const DevStats &hs = *h->hst;
-    NumArgs<VT> na{};
-    na.arp = h->arp64.as<int64_t>();
-    na.aci = A->col_idx;
-    na.aval = (const VT *)A->values;
-    na.brp = h->brp64.as<int64_t>();
-    na.bci = B->col_idx;
-    na.bval = (const VT *)B->values;
-    if (h->compressed) {
-        na.bcrp = h->bcrp.as<int64_t>();
-        na.bcsi = h->bcsi.as<int32_t>();
-        na.bcs = h->bcs.as<uint32_t>();
-    }
-    na.rwin = h->rwin.as<int2>();
-    na.coff = h->coff.as<int64_t>();
-    na.cci = C->col_idx;
-    na.cval = (VT *)C->values;
-    na.rs.rows = h->perm_num.as<int32_t>();
-    na.rs.koff = h->koff_num.as<int64_t>();
-    na.st = h->dstats.as<DevStats>();
-    na.lg_gs_or = lg_group(h->avg_len_c);
-    na.lg_gs = lg_group(h->avg_len);
     const size_t sbytes = (sizeof(VT) == 8 || acc != ACC_NATIVE) ? 8 : 4;
     LaunchCfg lc{st, 0, h->cus};
     auto grid_cap = [&](int64_t rows) { return (int)std::min<int64_t>(2048 * 8, ((rows + 7) / 8) * 8); };
 
-    if (hs.kcount_num[K_DW] > 0) {
+    if (kcount[K_DW] > 0) {
         na.rs.kind = K_DW;
-        na.nw_max = ((hs.kmax_num[K_DW][0] + 31) / 32) * 32;
-        na.r_max = std::max(hs.kmax_num[K_DW][1], 1);
+        na.nw_max = ((kmax[K_DW][0] + 31) / 32) * 32;
+        na.r_max = std::max(kmax[K_DW][1], 1);
         HIPCHK(launch_num_dw<VT>(na, acc, lc));
     }
-    if (hs.kcount_num[K_HW] > 0) {
+    if (kcount[K_WH] > 0) {
+        na.rs.kind = K_WH;
+        na.nw_max = ((kmax[K_WH][0] + 31) / 32) * 32;
+        na.r_max = std::max(kmax[K_WH][1], 1);
+        na.ts = pow2_at_least(2 * (int64_t)std::max(kmax[K_WH][2], 1), 16);
+        HIPCHK(launch_num_wh<VT>(na, acc, lc));
+    }
+    if (kcount[K_HW] > 0) {
         na.rs.kind = K_HW;
-        na.ts = pow2_at_least(2 * (int64_t)hs.kmax_num[K_HW][1], 64);
+        na.ts = pow2_at_least(2 * (int64_t)kmax[K_HW][1], 64);
         HIPCHK(launch_num_hw<VT>(na, acc, lc));
     }
-    if (hs.kcount_num[K_DG] > 0) {
+    if (kcount[K_DG] > 0) {
         na.rs.kind = K_DG;
         na.rs.queue = h->queue.as<int32_t>() + XCDS * K_DG;
-        na.nw_max = ((hs.kmax_num[K_DG][0] + 31) / 32) * 32;
-        const int grid = std::min(grid_cap(hs.kcount_num[K_DG]),
+        na.nw_max = ((kmax[K_DG][0] + 31) / 32) * 32;
+        const int grid = std::min(grid_cap(kcount[K_DG]),
                                   dg_resident_grid(acc, sizeof(VT) == 8, lds_num_dg(na.nw_max), h->cus));
         na.arena_cap = (int64_t)na.nw_max * 32;
         const size_t bytes = (size_t)na.arena_cap * grid * sbytes;
@@ -534,13 +575,13 @@ static spg_status numeric_impl(spg_handle h, const spg_csr *A, const spg_csr *B,
         HIPCHK(launch_num_dg<VT>(na, acc, lc));
         lc.grid = 0;
     }
-    if (hs.kcount_num[K_HL] > 0) {
+    if (kcount[K_HL] > 0) {
         na.rs.kind = K_HL;
         na.rs.queue = h->queue.as<int32_t>() + XCDS * K_HL;
         na.l1_slots = h->opt.l1_hash_slots ? h->opt.l1_hash_slots : (sbytes == 8 ? 4096 : 8192);
-        const int grid = std::min(grid_cap(hs.kcount_num[K_HL]),
+        const int grid = std::min(grid_cap(kcount[K_HL]),
                                   hl_resident_grid(acc, sizeof(VT) == 8, lds_num_hl(na.l1_slots, (int)sbytes), h->cus));
-        na.arena_cap = pow2_at_least(2 * (int64_t)std::max(1, hs.kmax_num[K_HL][1]), 64);
+        na.arena_cap = pow2_at_least(2 * (int64_t)std::max(1, kmax[K_HL][1]), 64);
         const size_t bytes = (size_t)na.arena_cap * grid * (8 + 2 * sbytes);
         if (h->l2k.cap < bytes) HIPCHK(ensure(h->l2k, bytes));
         na.arena = h->l2k.p;
@@ -552,6 +593,117 @@ static spg_status numeric_impl(spg_handle h, const spg_csr *A, const spg_csr *B,
     return SPG_OK;
 }
 
+
+// Measured selection (replaces a fixed heuristic): on a strided sample of the
+// rows, time each accumulator policy (selector / bit window first / column
+// hash first) with lane groups of 2^(base-1), 2^base, 2^(base+1) lanes per B
+// row, keep the fastest, and classify every row with it.  Runs once per plan,
+// at the first numeric call (values and C are available then); blocks the host.
+template <typename VT>
+static spg_status autotune(spg_handle h, NumArgs<VT> na, int acc) {
+    hipStream_t st = h->stream;
+    const int64_t m = h->fp.m;
+    DevStats *dst = h->dstats.as<DevStats>();
+    HIPCHK(ensure(h->kind_tmp, std::max<int64_t>(m, 1)));
+    HIPCHK(ensure(h->perm_tmp, 4 * std::max<int64_t>(m, 1)));
+    HIPCHK(ensure(h->koff_tmp, 8 * (NK + 1)));
+    const int stride = (int)std::max<int64_t>(1, std::min<int64_t>(16, m / 16384));
+    ClassParams cp = h->cparams;
+    cp.phase = 1;
+    cp.sample_stride = stride;
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    float best = 3.4e38f;
+    int best_pol = cp.accumulator, best_lg = h->lg_num;
+    const int base = lg_group(h->avg_len);
+    spg_status s = SPG_OK;
+    const size_t koff_bytes = offsetof(DevStats, kcount_num);
+    for (int pol = 0; pol < 3 && s == SPG_OK; ++pol) {
+        cp.accumulator = pol;
+        HIPCHK(hipMemsetAsync((char *)dst + koff_bytes, 0, sizeof(long long) * NK, st));
+        HIPCHK(hipMemsetAsync(&dst->kmax_num[0][0], 0, sizeof(dst->kmax_num), st));
+        HIPCHK(launch_classify(m, h->rflops.as<int64_t>(), h->rflopsc.as<int64_t>(), h->rwin.as<int2>(),
+                               h->row_nnz.as<int32_t>(), h->row_words.as<int32_t>(), cp, h->kind_tmp.as<uint8_t>(),
+                               nullptr, dst, st));
+        HIPCHK(launch_partition(m, h->kind_tmp.as<uint8_t>(), h->perm_tmp.as<int32_t>(), h->koff_tmp.as<int64_t>(),
+                                h->tmp.as<int64_t>(), st));
+        if ((s = pull_stats(h)) != SPG_OK) break;
+        const DevStats hs = *h->hst;
+        na.rs.rows = h->perm_tmp.as<int32_t>();
+        na.rs.koff = h->koff_tmp.as<int64_t>();
+        for (int lg = std::max(2, base - 1); lg <= std::min(6, base + 1); ++lg) {
+            na.lg_gs = lg;
+            if ((s = launch_kinds<VT>(h, na, hs.kcount_num, hs.kmax_num, acc)) != SPG_OK) break;  // warm-up
+            HIPCHK(hipEventRecord(e0, st));
+            if ((s = launch_kinds<VT>(h, na, hs.kcount_num, hs.kmax_num, acc)) != SPG_OK) break;
+            HIPCHK(hipEventRecord(e1, st));
+            HIPCHK(hipEventSynchronize(e1));
+            float ms = 0;
+            HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+            if (ms < best) {
+                best = ms;
+                best_pol = pol;
+                best_lg = lg;
+            }
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (s != SPG_OK) return s;
+    // final classification of every row with the winner
+    cp.accumulator = best_pol;
+    cp.sample_stride = 1;
+    HIPCHK(hipMemsetAsync((char *)dst + koff_bytes, 0, sizeof(long long) * NK, st));
+    HIPCHK(hipMemsetAsync(&dst->kmax_num[0][0], 0, sizeof(dst->kmax_num), st));
+    HIPCHK(launch_classify(m, h->rflops.as<int64_t>(), h->rflopsc.as<int64_t>(), h->rwin.as<int2>(),
+                           h->row_nnz.as<int32_t>(), h->row_words.as<int32_t>(), cp, h->kind_num.as<uint8_t>(),
+                           nullptr, dst, st));
+    HIPCHK(launch_partition(m, h->kind_num.as<uint8_t>(), h->perm_num.as<int32_t>(), h->koff_num.as<int64_t>(),
+                            h->tmp.as<int64_t>(), st));
+    if ((s = pull_stats(h)) != SPG_OK) return s;
+    h->lg_num = best_lg;
+    h->tuned = true;
+    h->stats.tuned_policy = best_pol;
+    h->stats.tuned_lanes = 1 << best_lg;
+    for (int kk = 0; kk < NK; ++kk) h->stats.rows_numeric[kk] = h->hst->kcount_num[kk];
+    return SPG_OK;
+}
+
+template <typename VT>
+static spg_status numeric_impl(spg_handle h, const VT *aval, const VT *bval, int32_t *cci, VT *cval, int acc) {
+    hipStream_t st = h->stream;
+    DevStats &hs = *h->hst;
+    NumArgs<VT> na{};
+    na.arp = h->arp64.as<int64_t>();
+    na.aci = h->aci_used;
+    na.aval = aval;
+    na.brp = h->brp64.as<int64_t>();
+    na.bci = h->bci_used;
+    na.bval = bval;
+    if (h->compressed) {
+        na.bcrp = h->bcrp.as<int64_t>();
+        na.bcsi = h->bcsi.as<int32_t>();
+        na.bcs = h->bcs.as<uint32_t>();
+    }
+    na.rwin = h->rwin.as<int2>();
+    na.coff = h->coff.as<int64_t>();
+    na.cci = cci;
+    na.cval = cval;
+    na.rs.rows = h->perm_num.as<int32_t>();
+    na.rs.koff = h->koff_num.as<int64_t>();
+    na.st = h->dstats.as<DevStats>();
+    na.lg_gs_or = lg_group(h->avg_len_c);
+    na.lg_gs = h->lg_num;
+    if (h->opt.autotune && !h->tuned) {
+        spg_status s = autotune<VT>(h, na, acc);
+        if (s != SPG_OK) return s;
+        na.lg_gs = h->lg_num;
+    }
+    na.rs.rows = h->perm_num.as<int32_t>();
+    na.rs.koff = h->koff_num.as<int64_t>();
+    return launch_kinds<VT>(h, na, hs.kcount_num, hs.kmax_num, acc);
+}
 extern "C" spg_status spgemm_numeric(spg_handle h, const spg_csr *A, const spg_csr *B, spg_csr_out *C) {
     if (!h) return SPG_ERR_INVALID_ARG;
     h->err.clear();
@@ -570,12 +722,247 @@ extern "C" spg_status spgemm_numeric(spg_handle h, const spg_csr *A, const spg_c
     if (h->nnzc > 0 && (!C->col_idx || !C->values)) return fail(h, SPG_ERR_INVALID_ARG, "C arrays are NULL");
     if (A->dtype != B->dtype || A->dtype != C->dtype)
         return fail(h, SPG_ERR_INVALID_ARG, "A, B and C must share one dtype");
+    if (h->batch.count) return fail(h, SPG_ERR_STRUCTURE_MISMATCH, "the plan is a batch: use spgemm_batch_numeric");
     if (h->nnzc == 0) return SPG_OK;
-    if (A->dtype == SPG_F64) return numeric_impl<double>(h, A, B, C, ACC_NATIVE);
-    const int acc = h->opt.fp32_mode == SPG_FP32_COMPENSATED ? ACC_COMP
-                    : h->opt.fp32_mode == SPG_FP32_WIDE      ? ACC_WIDE
-                                                             : ACC_NATIVE;
-    return numeric_impl<float>(h, A, B, C, acc);
+    if (A->dtype == SPG_F64)
+        return numeric_impl<double>(h, (const double *)A->values, (const double *)B->values, C->col_idx,
+                                    (double *)C->values, ACC_NATIVE);
+    return numeric_impl<float>(h, (const float *)A->values, (const float *)B->values, C->col_idx,
+                               (float *)C->values, fp32_acc(h));
 }
 
 
+
+// ------------------------------------------------------------------ backward
+template <typename VT>
+static spg_status backward_impl(spg_handle h, const spg_csr *A, const spg_csr *B, const spg_csr *G, void *dA,
+                                void *dB) {
+    BwdArgs<VT> ba{};
+    ba.m = h->fp.m;
+    ba.nnza = A->nnz;
+    ba.nnzb = B->nnz;
+    ba.arp = h->arp64.as<int64_t>();
+    ba.aci = A->col_idx;
+    ba.aval = (const VT *)A->values;
+    ba.brp = h->brp64.as<int64_t>();
+    ba.bci = B->col_idx;
+    ba.bval = (const VT *)B->values;
+    ba.coff = h->coff.as<int64_t>();
+    ba.gci = G->col_idx;
+    ba.gval = (const VT *)G->values;
+    ba.dA = (VT *)dA;
+    ba.dB = (VT *)dB;
+    ba.lg_gs = lg_group(h->avg_len);
+    ba.st = h->dstats.as<DevStats>();
+    LaunchCfg lc{h->stream, 0, h->cus};
+    HIPCHK(launch_backward<VT>(ba, lc));
+    return SPG_OK;
+}
+
+extern "C" spg_status spgemm_backward(spg_handle h, const spg_csr *A, const spg_csr *B, const spg_csr *G,
+                                      void *dA, void *dB) {
+    if (!h) return SPG_ERR_INVALID_ARG;
+    h->err.clear();
+    if (!h->ready) return fail(h, SPG_ERR_NOT_READY, "spgemm_backward before a successful spgemm_symbolic");
+    if (h->batch.count) return fail(h, SPG_ERR_UNSUPPORTED, "backward of a batch plan");
+    spg_status s;
+    if ((s = check_csr(h, A, "A", true)) != SPG_OK) return s;
+    if ((s = check_csr(h, B, "B", true)) != SPG_OK) return s;
+    if ((s = check_csr(h, G, "G", true)) != SPG_OK) return s;
+    const Fingerprint &f = h->fp;
+    if (A->nrows != f.m || A->ncols != f.n || B->ncols != f.k || A->nnz != f.nnza || B->nnz != f.nnzb ||
+        A->row_ptr != f.arp || B->row_ptr != f.brp || A->col_idx != f.aci || B->col_idx != f.bci ||
+        (int)A->rp_type != f.arpt || (int)B->rp_type != f.brpt)
+        return fail(h, SPG_ERR_STRUCTURE_MISMATCH, "A or B differs from the operands of the symbolic phase");
+    if (G->nrows != f.m || G->ncols != f.k || G->nnz != h->nnzc)
+        return fail(h, SPG_ERR_STRUCTURE_MISMATCH, "G must have the structure of C");
+    if (A->dtype != B->dtype || A->dtype != G->dtype)
+        return fail(h, SPG_ERR_INVALID_ARG, "A, B and G must share one dtype");
+    if (A->dtype == SPG_F64) return backward_impl<double>(h, A, B, G, dA, dB);
+    return backward_impl<float>(h, A, B, G, dA, dB);
+}
+
+// ------------------------------------------------------------------ batch
+static spg_status upload_desc(spg_handle h, const std::vector<BatchDesc> &d, BatchDesc **out) {
+    HIPCHK(ensure(h->batch.desc, sizeof(BatchDesc) * d.size() * 4 + 16));
+    // four regions: A, B, C row pointers, scratch for gather/scatter descriptors
+    *out = h->batch.desc.as<BatchDesc>();
+    HIPCHK(hipMemcpyAsync(*out, d.data(), sizeof(BatchDesc) * d.size(), hipMemcpyHostToDevice, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    return SPG_OK;
+}
+
+extern "C" spg_status spgemm_batch_symbolic(spg_handle h, int32_t count, const spg_csr *A, const spg_csr *B,
+                                            void *const *C_row_ptr, spg_itype c_rpt, int64_t *nnz_c) {
+    if (!h) return SPG_ERR_INVALID_ARG;
+    h->err.clear();
+    if (count <= 0 || !A || !B || !C_row_ptr || !nnz_c) return fail(h, SPG_ERR_INVALID_ARG, "bad batch arguments");
+    if (c_rpt != SPG_I32 && c_rpt != SPG_I64) return fail(h, SPG_ERR_INVALID_ARG, "bad C rp_type");
+    spg_status s;
+    auto &bt = h->batch;
+    h->ready = false;
+    bt.count = 0;
+    bt.a.assign(count, BatchDesc{});
+    bt.b.assign(count, BatchDesc{});
+    bt.c.assign(count, BatchDesc{});
+    int64_t R = 0, N = 0, NA = 0, NB = 0, K = 0;
+    bt.max_rows = bt.max_nnza = bt.max_nnzb = 0;
+    for (int i = 0; i < count; ++i) {
+        if ((s = check_csr(h, &A[i], "A[i]", false)) != SPG_OK) return s;
+        if ((s = check_csr(h, &B[i], "B[i]", false)) != SPG_OK) return s;
+        if (A[i].ncols != B[i].nrows) return fail(h, SPG_ERR_DIM_MISMATCH, "A[i].ncols != B[i].nrows");
+        if (!C_row_ptr[i]) return fail(h, SPG_ERR_INVALID_ARG, "C_row_ptr[i] is NULL");
+        BatchDesc &a = bt.a[i], &b = bt.b[i], &c = bt.c[i];
+        a.rp = A[i].row_ptr; a.ci = A[i].col_idx; a.nrows = A[i].nrows; a.ncols = A[i].ncols; a.nnz = A[i].nnz;
+        a.row_off = R; a.nnz_off = NA; a.col_add = (int32_t)N; a.rp64 = A[i].rp_type == SPG_I64;
+        b.rp = B[i].row_ptr; b.ci = B[i].col_idx; b.nrows = B[i].nrows; b.ncols = B[i].ncols; b.nnz = B[i].nnz;
+        b.row_off = N; b.nnz_off = NB; b.col_add = 0; b.rp64 = B[i].rp_type == SPG_I64;
+        c.rp = C_row_ptr[i]; c.nrows = A[i].nrows; c.ncols = B[i].ncols; c.row_off = R; c.rp64 = c_rpt == SPG_I64;
+        R += A[i].nrows;
+        N += B[i].nrows;
+        NA += A[i].nnz;
+        NB += B[i].nnz;
+        K = std::max<int64_t>(K, B[i].ncols);
+        bt.max_rows = std::max<int64_t>(bt.max_rows, std::max(A[i].nrows, B[i].nrows));
+        bt.max_nnza = std::max<int64_t>(bt.max_nnza, A[i].nnz);
+        bt.max_nnzb = std::max<int64_t>(bt.max_nnzb, B[i].nnz);
+        if (N > INT32_MAX || R > INT32_MAX - 1)
+            return fail(h, SPG_ERR_UNSUPPORTED, "a batch with more than 2^31-1 rows of A or B");
+    }
+    bt.rows = R;
+    bt.nnza = NA;
+    bt.nnzb = NB;
+    hipStream_t st = h->stream;
+    if ((s = plan_buffers(h, R, N, NB)) != SPG_OK) return s;
+    HIPCHK(ensure(bt.aci, 4 * std::max<int64_t>(NA, 1)));
+    HIPCHK(ensure(bt.bci, 4 * std::max<int64_t>(NB, 1)));
+    DevStats *dst = h->dstats.as<DevStats>();
+    HIPCHK(hipMemsetAsync(dst, 0, sizeof(DevStats), st));
+    BatchDesc *dev = nullptr;
+    if ((s = upload_desc(h, bt.a, &dev)) != SPG_OK) return s;
+    HIPCHK(launch_batch_struct(dev, count, std::max(bt.max_rows + 1, bt.max_nnza), h->arp64.as<int64_t>(),
+                               bt.aci.as<int32_t>(), &dst->bad_input, st));
+    // B: the same kernel, column bound = k_i, no offset
+    if ((s = upload_desc(h, bt.b, &dev)) != SPG_OK) return s;
+    HIPCHK(launch_batch_struct(dev, count, std::max(bt.max_rows + 1, bt.max_nnzb), h->brp64.as<int64_t>(),
+                               bt.bci.as<int32_t>(), &dst->bad_input, st));
+    if ((s = pull_stats(h)) != SPG_OK) return s;
+    if (h->hst->bad_input) return fail(h, SPG_ERR_INVALID_ARG, "malformed CSR in the batch");
+    HIPCHK(hipMemsetAsync(dst, 0, sizeof(DevStats), st));
+    int64_t nnzc = 0;
+    if ((s = symbolic_core(h, R, N, NA, NB, bt.aci.as<int32_t>(), bt.bci.as<int32_t>(), &nnzc)) != SPG_OK)
+        return s;
+    // per-product entries of C, then each C_i.row_ptr
+    if ((s = upload_desc(h, bt.c, &dev)) != SPG_OK) return s;
+    HIPCHK(ensure(h->blens, 16 * (size_t)count));
+    HIPCHK(launch_batch_bounds(dev, count, h->coff.as<int64_t>(), h->blens.as<int64_t>(), st));
+    std::vector<int64_t> bnd(2 * (size_t)count);
+    HIPCHK(hipMemcpyAsync(bnd.data(), h->blens.p, 16 * (size_t)count, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    bt.c_off.assign(count, 0);
+    bt.c_nnz.assign(count, 0);
+    bt.max_nnzc = 0;
+    for (int i = 0; i < count; ++i) {
+        bt.c_off[i] = bnd[2 * i];
+        bt.c_nnz[i] = bnd[2 * i + 1] - bnd[2 * i];
+        bt.c[i].nnz = bt.c_nnz[i];
+        bt.c[i].nnz_off = bt.c_off[i];
+        bt.max_nnzc = std::max(bt.max_nnzc, bt.c_nnz[i]);
+        if (c_rpt == SPG_I32 && bt.c_nnz[i] > INT32_MAX)
+            return fail(h, SPG_ERR_INDEX_OVERFLOW, "nnz(C_i) exceeds an int32 row_ptr; ask for SPG_I64");
+        nnz_c[i] = bt.c_nnz[i];
+    }
+    HIPCHK(launch_batch_rp_out(dev, count, bt.max_rows, h->coff.as<int64_t>(), st));
+    h->nnzc = nnzc;
+    Fingerprint &fp = h->fp;
+    fp = Fingerprint{};
+    fp.m = R; fp.n = N; fp.k = K; fp.nnza = NA; fp.nnzb = NB;
+    bt.count = count;
+    h->ready = true;
+    return SPG_OK;
+}
+
+template <typename VT>
+static spg_status batch_numeric_impl(spg_handle h, int32_t count, const spg_csr *A, const spg_csr *B,
+                                     spg_csr_out *C, int acc) {
+    auto &bt = h->batch;
+    hipStream_t st = h->stream;
+    const size_t vb = sizeof(VT);
+    // values of A / B: zero-copy when the batch is laid out back to back,
+    // otherwise gathered into a staging buffer
+    bool a_contig = true, b_contig = true, c_contig = true;
+    for (int i = 0; i < count; ++i) {
+        a_contig &= A[i].nnz == 0 || (const char *)A[i].values == (const char *)A[0].values + vb * bt.a[i].nnz_off;
+        b_contig &= B[i].nnz == 0 || (const char *)B[i].values == (const char *)B[0].values + vb * bt.b[i].nnz_off;
+        c_contig &= C[i].nnz == 0 || (C[i].col_idx == C[0].col_idx + bt.c_off[i] &&
+                                      (const char *)C[i].values == (const char *)C[0].values + vb * bt.c_off[i]);
+    }
+    const VT *aval = (const VT *)A[0].values, *bval = (const VT *)B[0].values;
+    int32_t *cci = C[0].col_idx;
+    VT *cval = (VT *)C[0].values;
+    spg_status s;
+    BatchDesc *dev = nullptr;
+    if (!a_contig) {
+        std::vector<BatchDesc> d = bt.a;
+        for (int i = 0; i < count; ++i) d[i].vals = A[i].values;
+        HIPCHK(ensure(bt.astage, vb * std::max<int64_t>(bt.nnza, 1)));
+        if ((s = upload_desc(h, d, &dev)) != SPG_OK) return s;
+        HIPCHK(launch_batch_gather(dev, count, bt.max_nnza, bt.astage.p, (int)vb, st));
+        aval = bt.astage.as<VT>();
+    }
+    if (!b_contig) {
+        std::vector<BatchDesc> d = bt.b;
+        for (int i = 0; i < count; ++i) d[i].vals = B[i].values;
+        HIPCHK(ensure(bt.bstage, vb * std::max<int64_t>(bt.nnzb, 1)));
+        if ((s = upload_desc(h, d, &dev)) != SPG_OK) return s;
+        HIPCHK(launch_batch_gather(dev, count, bt.max_nnzb, bt.bstage.p, (int)vb, st));
+        bval = bt.bstage.as<VT>();
+    }
+    if (!c_contig) {
+        HIPCHK(ensure(bt.cci, 4 * std::max<int64_t>(h->nnzc, 1)));
+        HIPCHK(ensure(bt.cval, vb * std::max<int64_t>(h->nnzc, 1)));
+        cci = bt.cci.as<int32_t>();
+        cval = bt.cval.as<VT>();
+    }
+    if (h->nnzc > 0) {
+        if ((s = numeric_impl<VT>(h, aval, bval, cci, cval, acc)) != SPG_OK) return s;
+    }
+    if (!c_contig) {
+        std::vector<BatchDesc> d = bt.c;
+        for (int i = 0; i < count; ++i) d[i].vals = C[i].col_idx;
+        if ((s = upload_desc(h, d, &dev)) != SPG_OK) return s;
+        HIPCHK(launch_batch_scatter(dev, count, bt.max_nnzc, cci, 4, st));
+        for (int i = 0; i < count; ++i) d[i].vals = C[i].values;
+        HIPCHK(hipStreamSynchronize(st));
+        if ((s = upload_desc(h, d, &dev)) != SPG_OK) return s;
+        HIPCHK(launch_batch_scatter(dev, count, bt.max_nnzc, cval, (int)vb, st));
+    }
+    return SPG_OK;
+}
+
+extern "C" spg_status spgemm_batch_numeric(spg_handle h, int32_t count, const spg_csr *A, const spg_csr *B,
+                                           spg_csr_out *C) {
+    if (!h) return SPG_ERR_INVALID_ARG;
+    h->err.clear();
+    auto &bt = h->batch;
+    if (!h->ready || bt.count == 0) return fail(h, SPG_ERR_NOT_READY, "spgemm_batch_numeric before spgemm_batch_symbolic");
+    if (count != bt.count || !A || !B || !C) return fail(h, SPG_ERR_STRUCTURE_MISMATCH, "batch size differs from the plan");
+    spg_status s;
+    const int dt = A[0].dtype;
+    for (int i = 0; i < count; ++i) {
+        if ((s = check_csr(h, &A[i], "A[i]", true)) != SPG_OK) return s;
+        if ((s = check_csr(h, &B[i], "B[i]", true)) != SPG_OK) return s;
+        const BatchDesc &a = bt.a[i], &b = bt.b[i];
+        if (A[i].row_ptr != a.rp || A[i].col_idx != a.ci || A[i].nnz != a.nnz || A[i].nrows != a.nrows ||
+            B[i].row_ptr != b.rp || B[i].col_idx != b.ci || B[i].nnz != b.nnz || B[i].nrows != b.nrows ||
+            B[i].ncols != b.ncols)
+            return fail(h, SPG_ERR_STRUCTURE_MISMATCH, "A[i] or B[i] differs from the symbolic batch");
+        if (C[i].nrows != a.nrows || C[i].ncols != b.ncols || C[i].nnz != bt.c_nnz[i])
+            return fail(h, SPG_ERR_STRUCTURE_MISMATCH, "C[i] shape or nnz differs from the symbolic batch");
+        if (C[i].nnz > 0 && (!C[i].col_idx || !C[i].values)) return fail(h, SPG_ERR_INVALID_ARG, "C[i] arrays are NULL");
+        if ((int)A[i].dtype != dt || (int)B[i].dtype != dt || (int)C[i].dtype != dt)
+            return fail(h, SPG_ERR_INVALID_ARG, "one dtype for the whole batch");
+    }
+    if (dt == SPG_F64) return batch_numeric_impl<double>(h, count, A, B, C, ACC_NATIVE);
+    return batch_numeric_impl<float>(h, count, A, B, C, fp32_acc(h));
+}

@@ -35,7 +35,7 @@ namespace {
 // ============================================================ wavefront / row
 
 struct DwLayout {
-    size_t bits, summ, pre, wlist, vals, colbuf, st_bs, st_len, st_a, total;
+    size_t bits, summ, pre, wlist, vals, colbuf, st_bs, st_len, st_cbs, st_clen, st_a, total;
 };
 
 __host__ __device__ inline DwLayout dw_layout(int nwm, int rm, int acc_bytes, bool numeric) {
@@ -46,13 +46,17 @@ __host__ __device__ inline DwLayout dw_layout(int nwm, int rm, int acc_bytes, bo
     o += align16(4 * (size_t)nwm);
     L.summ = o;
     o += align16(4 * (size_t)nsm);
-    L.st_bs = o;
+    L.st_cbs = o;
     o += 8 * WAVE;
-    L.st_len = o;
+    L.st_clen = o;
     o += 4 * WAVE;
-    L.st_a = o;
-    o += 8 * WAVE;
     if (numeric) {
+        L.st_bs = o;
+        o += 8 * WAVE;
+        L.st_len = o;
+        o += 4 * WAVE;
+        L.st_a = o;
+        o += 8 * WAVE;
         L.pre = o;
         o += align16(2 * (size_t)nwm);
         L.wlist = o;
@@ -66,54 +70,117 @@ __host__ __device__ inline DwLayout dw_layout(int nwm, int rm, int acc_bytes, bo
     return L;
 }
 
-// Stage up to 64 entries of A's row: B row start/length (from `rp`) and the
-// A value.  Returns the number staged.
+constexpr int DW_U = 8;  // B rows per lane group kept in flight
+
+// Stage up to 64 entries of A's row: per entry the extent of B(j,:) in the
+// structure source (compressed B when present) and, for the numeric phase,
+// in raw B plus the A value.  All extents load in one dependent step.
 template <typename VT>
-__device__ __forceinline__ int stage_chunk(int64_t cb, int64_t ae, const int32_t *aci, const VT *aval,
-                                           const int64_t *rp, int64_t *st_bs, int32_t *st_len, double *st_a) {
+__device__ __forceinline__ int dw_stage(int64_t cb, int64_t ae, const int32_t *aci, const VT *aval,
+                                        const int64_t *srp, const int64_t *brp, int64_t *st_cbs,
+                                        int32_t *st_clen, int64_t *st_bs, int32_t *st_len, double *st_a) {
     const int l = lane_id();
     const int cn = (int)min((int64_t)WAVE, ae - cb);
     if (l < cn) {
         const int j = aci[cb + l];
-        const int64_t s0 = rp[j], s1 = rp[j + 1];
-        st_bs[l] = s0;
-        st_len[l] = (int32_t)(s1 - s0);
-        if (aval) st_a[l] = (double)aval[cb + l];
+        const int64_t c0 = srp[j], c1 = srp[j + 1];
+        if (st_bs) {
+            const int64_t b0 = brp[j], b1 = brp[j + 1];
+            st_bs[l] = b0;
+            st_len[l] = (int32_t)(b1 - b0);
+            st_a[l] = (double)aval[cb + l];
+        }
+        st_cbs[l] = c0;
+        st_clen[l] = (int32_t)(c1 - c0);
     }
     return cn;
 }
 
-// OR the row's column-set words into bits[] / summ[] (window-relative).
-__device__ __forceinline__ void dw_or_pass(int i, int wlo, const int64_t *arp, const int32_t *aci,
-                                           const int64_t *brp, const int32_t *bci, const int64_t *bcrp,
-                                           const int32_t *bcsi, const uint32_t *bcs, int lg_gs, uint32_t *bits,
-                                           uint32_t *summ, int64_t *st_bs, int32_t *st_len, double *st_a) {
+// One column-set word of the structure source: window-relative word index
+// and its bits.  COMP is a template parameter so that the batched loads of
+// dw_or_staged stay branch-free and all issue before the first use.
+template <bool COMP>
+__device__ __forceinline__ void dw_word(int64_t e, int wlo, const int32_t *bci, const int32_t *bcsi,
+                                        const uint32_t *bcs, uint32_t &d, uint32_t &cs) {
+    if constexpr (COMP) {
+        d = (uint32_t)(bcsi[e] - wlo);
+        cs = bcs[e];
+    } else {
+        const int c = bci[e];
+        d = (uint32_t)((c >> 5) - wlo);
+        cs = 1u << (c & 31);
+    }
+}
+
+__device__ __forceinline__ void dw_or(uint32_t *bits, uint32_t *summ, uint32_t d, uint32_t cs) {
+    atomicOr(&bits[d], cs);
+    atomicOr(&summ[d >> 5], 1u << (d & 31));
+}
+
+// OR the staged entries' column-set words into bits[] / summ[].  Lane group g
+// (2^lg_gs lanes) takes entries g, g+ng, ...; DW_U entries per group are
+// loaded before any is used, so each lane keeps DW_U loads in flight.
+template <bool COMP>
+__device__ __forceinline__ void dw_or_batched(int cn, int wlo, const int32_t *bci, const int32_t *bcsi,
+                                              const uint32_t *bcs, int lg_gs, const int64_t *st_cbs,
+                                              const int32_t *st_clen, uint32_t *bits, uint32_t *summ) {
     const int l = lane_id();
     const int gs = 1 << lg_gs, g = l >> lg_gs, q = l & (gs - 1), ng = WAVE >> lg_gs;
-    const bool comp = bcrp != nullptr;
-    const int64_t ab = arp[i], ae = arp[i + 1];
-    for (int64_t cb = ab; cb < ae; cb += WAVE) {
-        const int cn = stage_chunk<double>(cb, ae, aci, nullptr, comp ? bcrp : brp, st_bs, st_len, st_a);
-        __syncthreads();
-        for (int t = g; t < cn; t += ng) {
-            const int64_t bs = st_bs[t];
-            const int len = st_len[t];
-            for (int p = q; p < len; p += gs) {
-                uint32_t d, cs;
-                if (comp) {
-                    d = (uint32_t)(bcsi[bs + p] - wlo);
-                    cs = bcs[bs + p];
-                } else {
-                    const int c = bci[bs + p];
-                    d = (uint32_t)((c >> 5) - wlo);
-                    cs = 1u << (c & 31);
-                }
-                atomicOr(&bits[d], cs);
-                atomicOr(&summ[d >> 5], 1u << (d & 31));
+    for (int t0 = g; t0 < cn; t0 += ng * DW_U) {
+        uint32_t d[DW_U], cs[DW_U];
+        int len[DW_U];
+        int64_t bs[DW_U];
+        unsigned okm = 0;
+#pragma unroll
+        for (int u = 0; u < DW_U; ++u) {  // staging reads first (LDS, group-uniform)
+            const int t = min(t0 + u * ng, cn - 1);
+            len[u] = st_clen[t];
+            bs[u] = st_cbs[t];
+        }
+#pragma unroll
+        for (int u = 0; u < DW_U; ++u) {  // then every global load of the batch
+            const bool ok = t0 + u * ng < cn && q < len[u];
+            okm |= (unsigned)ok << u;
+            dw_word<COMP>(ok ? bs[u] + q : 0, wlo, bci, bcsi, bcs, d[u], cs[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < DW_U; ++u)
+            if (okm & (1u << u)) dw_or(bits, summ, d[u], cs[u]);
+        for (int u = 0; u < DW_U; ++u) {  // rows of B longer than the group
+            const int t = t0 + u * ng;
+            if (t >= cn) break;
+            const int len = st_clen[t];
+            for (int p = q + gs; p < len; p += gs) {
+                uint32_t dd, cc;
+                dw_word<COMP>(st_cbs[t] + p, wlo, bci, bcsi, bcs, dd, cc);
+                dw_or(bits, summ, dd, cc);
             }
         }
-        __syncthreads();
     }
+}
+
+__device__ __forceinline__ void dw_or_staged(int cn, int wlo, bool comp, const int32_t *bci, const int32_t *bcsi,
+                                             const uint32_t *bcs, int lg_gs, const int64_t *st_cbs,
+                                             const int32_t *st_clen, uint32_t *bits, uint32_t *summ) {
+    if (comp)
+        dw_or_batched<true>(cn, wlo, bci, bcsi, bcs, lg_gs, st_cbs, st_clen, bits, summ);
+    else
+        dw_or_batched<false>(cn, wlo, bci, bcsi, bcs, lg_gs, st_cbs, st_clen, bits, summ);
+}
+
+struct RowDesc {
+    int64_t ab, ae;
+    int wlo, ns;
+};
+
+__device__ __forceinline__ RowDesc row_desc(int i, const int64_t *arp, const int2 *rwin) {
+    RowDesc d;
+    d.ab = arp[i];
+    d.ae = arp[i + 1];
+    const int2 w = rwin[i];
+    d.wlo = w.x;
+    d.ns = (w.y - w.x + 1 + 31) >> 5;
+    return d;
 }
 
 __global__ __launch_bounds__(WAVE) void k_sym_dw(SymArgs a) {
@@ -121,35 +188,53 @@ __global__ __launch_bounds__(WAVE) void k_sym_dw(SymArgs a) {
     const DwLayout L = dw_layout(a.nw_max, 0, 0, false);
     uint32_t *bits = (uint32_t *)(smem + L.bits);
     uint32_t *summ = (uint32_t *)(smem + L.summ);
-    int64_t *st_bs = (int64_t *)(smem + L.st_bs);
-    int32_t *st_len = (int32_t *)(smem + L.st_len);
-    double *st_a = (double *)(smem + L.st_a);
+    int64_t *st_cbs = (int64_t *)(smem + L.st_cbs);
+    int32_t *st_clen = (int32_t *)(smem + L.st_clen);
     const int l = lane_id();
     const int nsm = (a.nw_max + 31) >> 5;
     for (int w = l; w < a.nw_max; w += WAVE) bits[w] = 0;
     for (int w = l; w < nsm; w += WAVE) summ[w] = 0;
     __syncthreads();
+    const bool comp = a.bcrp != nullptr;
+    const int64_t *srp = comp ? a.bcrp : a.brp;
     const int64_t lo = a.rs.koff[a.rs.kind], hi = a.rs.koff[a.rs.kind + 1];
     const Slice sl = xcd_slice(lo, hi);
-    for (int64_t r = sl.idx; r < sl.end; r += sl.step) {
-        const int i = a.rs.rows[r];
-        const int2 win = a.rwin[i];
-        const int ns = (win.y - win.x + 1 + 31) >> 5;
-        dw_or_pass(i, win.x, a.arp, a.aci, a.brp, a.bci, a.bcrp, a.bcsi, a.bcs, a.lg_gs, bits, summ, st_bs,
-                   st_len, st_a);
-        int cnt = 0;
-        for (int s = l; s < ns; s += WAVE) {
+    int64_t r = sl.idx;
+    int i_next = r < sl.end ? a.rs.rows[r] : 0;
+    RowDesc dn = r < sl.end ? row_desc(i_next, a.arp, a.rwin) : RowDesc{};
+    while (r < sl.end) {
+        const int i = i_next;
+        const RowDesc d = dn;
+        r += sl.step;
+        if (r < sl.end) {  // prefetch the next row's descriptor
+            i_next = a.rs.rows[r];
+            dn = row_desc(i_next, a.arp, a.rwin);
+        }
+        for (int64_t cb = d.ab; cb < d.ae; cb += WAVE) {
+            const int cn = dw_stage<double>(cb, d.ae, a.aci, nullptr, srp, nullptr, st_cbs, st_clen, nullptr,
+                                            nullptr, nullptr);
+            __syncthreads();
+            dw_or_staged(cn, d.wlo, comp, a.bci, a.bcsi, a.bcs, a.lg_gs, st_cbs, st_clen, bits, summ);
+            __syncthreads();
+        }
+        int cnt = 0, nwt = 0;
+        for (int s = l; s < d.ns; s += WAVE) {
             uint32_t m = summ[s];
             summ[s] = 0;
+            nwt += __popc(m);
             while (m) {
-                const int d = (s << 5) + __ffs(m) - 1;
+                const int w = (s << 5) + __ffs(m) - 1;
                 m &= m - 1;
-                cnt += __popc(bits[d]);
-                bits[d] = 0;
+                cnt += __popc(bits[w]);
+                bits[w] = 0;
             }
         }
         cnt = wave_sum(cnt);
-        if (l == 0) a.row_nnz[i] = cnt;
+        nwt = wave_sum(nwt);
+        if (l == 0) {
+            a.row_nnz[i] = cnt;
+            a.row_words[i] = nwt;
+        }
         __syncthreads();
     }
 }
@@ -168,23 +253,43 @@ __global__ __launch_bounds__(WAVE) void k_num_dw(NumArgs<VT> a) {
     int32_t *colbuf = (int32_t *)(smem + L.colbuf);
     int64_t *st_bs = (int64_t *)(smem + L.st_bs);
     int32_t *st_len = (int32_t *)(smem + L.st_len);
+    int64_t *st_cbs = (int64_t *)(smem + L.st_cbs);
+    int32_t *st_clen = (int32_t *)(smem + L.st_clen);
     double *st_a = (double *)(smem + L.st_a);
     const int l = lane_id();
     const int nsm = (a.nw_max + 31) >> 5;
     for (int w = l; w < a.nw_max; w += WAVE) bits[w] = 0;
     for (int w = l; w < nsm; w += WAVE) summ[w] = 0;
     __syncthreads();
+    const bool comp = a.bcrp != nullptr;
+    const int64_t *srp = comp ? a.bcrp : a.brp;
     const int gs = 1 << a.lg_gs, g = l >> a.lg_gs, q = l & (gs - 1), ng = WAVE >> a.lg_gs;
     const int64_t lo = a.rs.koff[a.rs.kind], hi = a.rs.koff[a.rs.kind + 1];
     const Slice sl = xcd_slice(lo, hi);
-    for (int64_t r = sl.idx; r < sl.end; r += sl.step) {
-        const int i = a.rs.rows[r];
-        const int2 win = a.rwin[i];
-        const int wlo = win.x;
-        const int ns = (win.y - win.x + 1 + 31) >> 5;
-        // 1. structure of the row
-        dw_or_pass(i, wlo, a.arp, a.aci, a.brp, a.bci, a.bcrp, a.bcsi, a.bcs, a.lg_gs_or, bits, summ, st_bs,
-                   st_len, st_a);
+    int64_t r = sl.idx;
+    int i_next = r < sl.end ? a.rs.rows[r] : 0;
+    RowDesc dn = r < sl.end ? row_desc(i_next, a.arp, a.rwin) : RowDesc{};
+    int64_t c0n = r < sl.end ? a.coff[i_next] : 0, c1n = r < sl.end ? a.coff[i_next + 1] : 0;
+    while (r < sl.end) {
+        const int i = i_next;
+        const RowDesc d = dn;
+        const int64_t cb = c0n, ce = c1n;
+        r += sl.step;
+        if (r < sl.end) {  // prefetch the next row's descriptor
+            i_next = a.rs.rows[r];
+            dn = row_desc(i_next, a.arp, a.rwin);
+            c0n = a.coff[i_next];
+            c1n = a.coff[i_next + 1];
+        }
+        const int wlo = d.wlo, ns = d.ns;
+        const bool one_chunk = d.ae - d.ab <= WAVE;
+        // 1. structure of the row (staging kept for step 4 when the row fits one chunk)
+        for (int64_t c0 = d.ab; c0 < d.ae; c0 += WAVE) {
+            const int cn = dw_stage<VT>(c0, d.ae, a.aci, a.aval, srp, a.brp, st_cbs, st_clen, st_bs, st_len, st_a);
+            __syncthreads();
+            dw_or_staged(cn, wlo, comp, a.bci, a.bcsi, a.bcs, a.lg_gs_or, st_cbs, st_clen, bits, summ);
+            __syncthreads();
+        }
         // 2. touched words in increasing order
         int T = 0;
         for (int s0 = 0; s0 < ns; s0 += WAVE) {
@@ -212,49 +317,82 @@ __global__ __launch_bounds__(WAVE) void k_num_dw(NumArgs<VT> a) {
         int run = 0;
         for (int r0 = 0; r0 < T; r0 += WAVE) {
             const int rr = r0 + l;
-            const int d = rr < T ? wlist[rr] : 0;
-            const int c = rr < T ? __popc(bits[d]) : 0;
+            const int w = rr < T ? wlist[rr] : 0;
+            const int c = rr < T ? __popc(bits[w]) : 0;
             const int inc = wave_incl_scan(c);
-            if (rr < T) pre[d] = (uint16_t)(run + inc - c);
+            if (rr < T) pre[w] = (uint16_t)(run + inc - c);
             run += __shfl(inc, WAVE - 1);
         }
         const int rnnz = run;
-        const int64_t cb = a.coff[i];
-        const bool ok = (a.coff[i + 1] - cb == rnnz);
+        const bool ok = (ce - cb == rnnz);
         if (l == 0 && !ok) atomicAdd(&a.st->mismatch, 1);
         for (int t = l; t < rnnz; t += WAVE) vals[t] = A::zero();
         __syncthreads();
         // 4. products into vals[rank]
-        const int64_t ab = a.arp[i], ae = a.arp[i + 1];
-        for (int64_t c0 = ab; c0 < ae; c0 += WAVE) {
-            const int cn = stage_chunk<VT>(c0, ae, a.aci, a.aval, a.brp, st_bs, st_len, st_a);
-            __syncthreads();
-            for (int t = g; t < cn; t += ng) {
-                const int64_t bs = st_bs[t];
-                const int len = st_len[t];
-                const VT av = (VT)st_a[t];
-                for (int p = q; p < len; p += gs) {
-                    const int c = a.bci[bs + p];
-                    const VT bv = a.bval[bs + p];
-                    const int d = (c >> 5) - wlo;
-                    const uint32_t w = bits[d];
-                    const int rk = pre[d] + __popc(w & ((1u << (c & 31)) - 1u));
-                    A::add(&vals[rk], av, bv);
+        for (int64_t c0 = d.ab; c0 < d.ae; c0 += WAVE) {
+            int cn;
+            if (one_chunk) {
+                cn = (int)(d.ae - d.ab);
+            } else {
+                cn = dw_stage<VT>(c0, d.ae, a.aci, a.aval, srp, a.brp, st_cbs, st_clen, st_bs, st_len, st_a);
+                __syncthreads();
+            }
+            for (int t0 = g; t0 < cn; t0 += ng * DW_U) {
+                int col[DW_U], len[DW_U];
+                int64_t bs[DW_U];
+                VT bv[DW_U];
+                unsigned okm = 0;
+#pragma unroll
+                for (int u = 0; u < DW_U; ++u) {  // staging reads first
+                    const int t = min(t0 + u * ng, cn - 1);
+                    len[u] = st_len[t];
+                    bs[u] = st_bs[t];
+                }
+#pragma unroll
+                for (int u = 0; u < DW_U; ++u) {  // then every global load of the batch
+                    const bool ok = t0 + u * ng < cn && q < len[u];
+                    okm |= (unsigned)ok << u;
+                    const int64_t e = ok ? bs[u] + q : 0;
+                    col[u] = a.bci[e];
+                    bv[u] = a.bval[e];
+                }
+#pragma unroll
+                for (int u = 0; u < DW_U; ++u) {
+                    if (okm & (1u << u)) {
+                        const VT av = (VT)st_a[t0 + u * ng];
+                        const int c = col[u];
+                        const int w = (c >> 5) - wlo;
+                        const int rk = pre[w] + __popc(bits[w] & ((1u << (c & 31)) - 1u));
+                        A::add(&vals[rk], av, bv[u]);
+                    }
+                }
+                for (int u = 0; u < DW_U; ++u) {  // rows of B longer than the group
+                    const int t = t0 + u * ng;
+                    if (t >= cn) break;
+                    const int len = st_len[t];
+                    const VT avt = (VT)st_a[t];
+                    for (int p = q + gs; p < len; p += gs) {
+                        const int64_t e = st_bs[t] + p;
+                        const int c = a.bci[e];
+                        const int w = (c >> 5) - wlo;
+                        const int rk = pre[w] + __popc(bits[w] & ((1u << (c & 31)) - 1u));
+                        A::add(&vals[rk], avt, a.bval[e]);
+                    }
                 }
             }
             __syncthreads();
         }
         // 5. sorted columns, reset of the touched words
         for (int t = l; t < T; t += WAVE) {
-            const int d = wlist[t];
-            uint32_t w = bits[d];
-            int p = pre[d];
-            const int base = (wlo + d) << 5;
-            while (w) {
-                colbuf[p++] = base + __ffs(w) - 1;
-                w &= w - 1;
+            const int w = wlist[t];
+            uint32_t m = bits[w];
+            int p = pre[w];
+            const int base = (wlo + w) << 5;
+            while (m) {
+                colbuf[p++] = base + __ffs(m) - 1;
+                m &= m - 1;
             }
-            bits[d] = 0;
+            bits[w] = 0;
         }
         __syncthreads();
         if (ok) {
@@ -402,6 +540,7 @@ __global__ __launch_bounds__(WG_BIG) void k_sym_dg(SymArgs a) {
         for (int s = t; s < ns; s += WG_BIG) {
             uint32_t m = summ[s];
             summ[s] = 0;
+            cnt += (long long)__popc(m) << 32;  // touched words in the high half
             while (m) {
                 const int d = (s << 5) + __ffs(m) - 1;
                 m &= m - 1;
@@ -411,7 +550,10 @@ __global__ __launch_bounds__(WG_BIG) void k_sym_dg(SymArgs a) {
         }
         long long tot;
         block_excl_scan(cnt, red, &tot);
-        if (t == 0) a.row_nnz[i] = (int32_t)tot;
+        if (t == 0) {
+            a.row_nnz[i] = (int32_t)(tot & 0xffffffffll);
+            a.row_words[i] = (int32_t)(tot >> 32);
+        }
     }
 }
 

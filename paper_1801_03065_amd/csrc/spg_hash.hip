@@ -151,16 +151,23 @@ __global__ __launch_bounds__(WAVE) void k_sym_hw(SymArgs a) {
             }
             __syncthreads();
         }
-        int cnt = 0;
+        int cnt = 0, occ = 0;
         for (int s = l; s < a.ts; s += WAVE) {
             if (keys[s] != -1) {
                 cnt += __popc(masks[s]);
+                ++occ;
                 keys[s] = -1;
                 masks[s] = 0;
             }
         }
         cnt = wave_sum(cnt);
-        if (l == 0) a.row_nnz[i] = cnt;
+        occ = wave_sum(occ);
+        if (l == 0) {
+            a.row_nnz[i] = cnt;
+            // compressed keys are the touched words; column keys bound them by the window
+            const int2 win = a.rwin[i];
+            a.row_words[i] = comp ? occ : min(cnt, win.y - win.x + 1);
+        }
         __syncthreads();
     }
 }
@@ -408,6 +415,7 @@ __global__ __launch_bounds__(WG_BIG) void k_sym_hl(SymArgs a) {
             if (t == 0) {
                 atomicAdd(&a.st->overflow, 1);
                 a.row_nnz[i] = 0;
+                a.row_words[i] = 0;
             }
             continue;
         }
@@ -448,11 +456,16 @@ __global__ __launch_bounds__(WG_BIG) void k_sym_hl(SymArgs a) {
         long long cnt = 0;
         for (int64_t s = t; s < cap2; s += WG_BIG) {
             if (__hip_atomic_load(&keys2[s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != -1)
-                cnt += __popc(__hip_atomic_load(&masks2[s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+                cnt += __popc(__hip_atomic_load(&masks2[s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) +
+                       (1ll << 32);
         }
         long long tot;
         hl_block_excl_scan(cnt, red, &tot);
-        if (t == 0) a.row_nnz[i] = (int32_t)tot;
+        if (t == 0) {
+            const int rn = (int32_t)(tot & 0xffffffffll), occ = (int32_t)(tot >> 32);
+            a.row_nnz[i] = rn;
+            a.row_words[i] = comp ? occ : (int)min((long long)rn, (long long)win.y - win.x + 1);
+        }
     }
 }
 

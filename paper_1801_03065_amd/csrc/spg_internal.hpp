@@ -26,7 +26,8 @@ enum Kind : int {
     K_HW = 2,     // LDS linear-probing hash, one wavefront per row
     K_DG = 3,     // bit-window dense accumulator, one 256-lane workgroup per row, values in HBM
     K_HL = 4,     // two-level hash: LDS level 1 + HBM level 2, one workgroup per row
-    NK = 5
+    K_WH = 5,     // word hash + ordered summary, one wavefront per row (numeric)
+    NK = 6
 };
 
 // Global counters written by the analysis kernels (zeroed per symbolic call).
@@ -40,8 +41,8 @@ struct DevStats {
     int overflow;     // level-2 arena exhausted
     long long kcount_sym[NK];
     long long kcount_num[NK];
-    int kmax_sym[NK][2];   // per kind: max window words, max bound
-    int kmax_num[NK][2];   // per kind: max window words, max row size
+    int kmax_sym[NK][3];   // per kind: max window words, max bound, max touched words
+    int kmax_num[NK][3];   // per kind: max window words, max row size, max touched words
 };
 
 // Limits of the kernel kinds (entries, not bytes).
@@ -49,6 +50,9 @@ constexpr int DW_NW_MAX = 2048;   // window words of the wavefront dense kernel 
 constexpr int DW_R_MAX = 1024;    // row size of the wavefront dense kernel
 constexpr int HW_KEYS_MAX = 1024; // distinct keys of the wavefront hash (table 2x)
 constexpr int DG_NW_MAX = 32768;  // window words of the workgroup dense kernel (2^20 columns)
+constexpr int WH_NW_MAX = 32768;  // window words of the word-hash kernel (summary of 1024 words)
+constexpr int WH_R_MAX = 1024;    // row size of the word-hash kernel
+constexpr int WH_T_MAX = 512;     // touched words of the word-hash kernel (table 2x)
 
 // ------------------------------------------------------------ argument blocks
 struct RowSet {
@@ -68,6 +72,7 @@ struct SymArgs {
     const uint32_t *bcs;
     const int2 *rwin;      // per row: lowest / highest column-set word
     int32_t *row_nnz;
+    int32_t *row_words;    // touched column-set words per row (exact, or a bound)
     RowSet rs;
     int nw_max;            // LDS window words for this launch
     int ts;                // hash table slots (power of two) for hash kinds
@@ -104,6 +109,37 @@ struct NumArgs {
     void *arena;           // HBM scratch: dense values (K_DG) or level-2 tables (K_HL)
     int64_t arena_cap;     // entries per workgroup
     DevStats *st;
+};
+
+template <typename VT>
+struct BwdArgs {
+    int64_t m, nnza, nnzb;
+    const int64_t *arp;
+    const int32_t *aci;
+    const VT *aval;
+    const int64_t *brp;
+    const int32_t *bci;
+    const VT *bval;
+    const int64_t *coff;   // C row offsets (plan)
+    const int32_t *gci;    // C's sorted columns (pattern of G)
+    const VT *gval;        // dL/dC on pattern(C)
+    VT *dA;                // nnz(A) or nullptr
+    VT *dB;                // nnz(B) or nullptr
+    int lg_gs;
+    DevStats *st;
+};
+
+// One matrix of a batch: where its structure / values live and where they go
+// in the concatenated (block-diagonal) product.
+struct BatchDesc {
+    const void *rp;        // row_ptr (input), or C_i.row_ptr (output)
+    const int32_t *ci;
+    const void *vals;      // values (gather source / scatter target)
+    int64_t nrows, ncols, nnz;
+    int64_t row_off;       // first row in the concatenation
+    int64_t nnz_off;       // first entry in the concatenation
+    int32_t col_add;       // added to column indices (A: B's row offset)
+    int32_t rp64;
 };
 
 // ------------------------------------------------------------ device helpers
@@ -225,11 +261,12 @@ struct ClassParams {
     int phase;          // 0 symbolic, 1 numeric
     int accumulator;    // spg_accumulator
     int compressed;
-    int dw_nw_max, dw_r_max, hw_keys_max, dg_nw_max;
+    int dw_nw_max, dw_r_max, hw_keys_max, dg_nw_max, wh_nw_max, wh_r_max, wh_t_max;
+    int sample_stride;  // numeric: only rows i with i % stride == 0 get a kind (others: empty)
 };
 hipError_t launch_classify(int64_t m, const int64_t *rflops, const int64_t *rflopsc, const int2 *rwin,
-                           const int32_t *row_nnz, ClassParams p, uint8_t *kind, int32_t *row_nnz_out,
-                           DevStats *st, hipStream_t s);
+                           const int32_t *row_nnz, const int32_t *row_words, ClassParams p, uint8_t *kind,
+                           int32_t *row_nnz_out, DevStats *st, hipStream_t s);
 int64_t part_tmp_elems(int64_t m);
 hipError_t launch_partition(int64_t m, const uint8_t *kind, int32_t *perm, int64_t *koff, int64_t *tmp,
                             hipStream_t s);
@@ -250,6 +287,21 @@ template <typename VT>
 hipError_t launch_num_dg(const NumArgs<VT> &a, int acc, const LaunchCfg &c);
 template <typename VT>
 hipError_t launch_num_hl(const NumArgs<VT> &a, int acc, const LaunchCfg &c);
+template <typename VT>
+hipError_t launch_num_wh(const NumArgs<VT> &a, int acc, const LaunchCfg &c);
+size_t lds_num_wh(int ts, int nw_max, int r_max, int acc_bytes);
+template <typename VT>
+hipError_t launch_backward(const BwdArgs<VT> &a, const LaunchCfg &c);
+
+hipError_t launch_batch_struct(const BatchDesc *d, int count, int64_t max_work, int64_t *dst_rp, int32_t *dst_ci,
+                               int *bad, hipStream_t s);
+hipError_t launch_batch_gather(const BatchDesc *d, int count, int64_t max_nnz, void *dst, int bytes,
+                               hipStream_t s);
+hipError_t launch_batch_scatter(const BatchDesc *d, int count, int64_t max_nnz, const void *src, int bytes,
+                                hipStream_t s);
+hipError_t launch_batch_rp_out(const BatchDesc *d, int count, int64_t max_rows, const int64_t *coff,
+                               hipStream_t s);
+hipError_t launch_batch_bounds(const BatchDesc *d, int count, const int64_t *coff, int64_t *out, hipStream_t s);
 
 // LDS bytes of the core kernels for given limits.
 size_t lds_sym_dw(int nw_max);

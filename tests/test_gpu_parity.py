@@ -29,10 +29,14 @@ def test_5pt_square_64x64():
     assert st["flops"] == 100104 and st["nnz_c"] == 51972 and st["max_row_flops"] == 25
 
 
+@pytest.mark.parametrize("acc", [0, 1, 2, 3])
 @pytest.mark.parametrize("g", [2, 3, 7, 20])
-def test_27pt_square_small(g):
+def test_27pt_square_small(g, acc):
     A = synth.stencil27(g)
-    _exact(A, A)
+    h = _exact(A, A, accumulator=acc, l1_hash_slots=64 if acc == 3 else 0)
+    used = {k for k, v in h.stats()["rows_numeric"].items() if v}
+    want = {0: "word_hash_wave", 1: "dense_wave", 2: "hash_wave", 3: "hash_two_level"}[acc]
+    assert used == {want}, used
 
 
 @pytest.mark.parametrize("g", [4, 10])

@@ -335,3 +335,18 @@ def test_grad_finite_difference():
         bp[f] += h
         bm[f] -= h
         assert abs((L(A.values, bp) - L(A.values, bm)) / (2 * h) - dB[f]) < 1e-7
+
+
+def test_rows_agree_with_the_whole_product():
+    """Selected rows by the sampled entry point equal the same rows of the full product."""
+    rng = np.random.default_rng(4)
+    A = synth.shuffle_columns(synth.random_csr(200, 150, rng.integers(0, 12, 200), 1), 3)
+    B = synth.random_csr(150, 400, rng.integers(0, 15, 150), 2)
+    C, S = oracle.spgemm(A, B, with_abs=True)
+    sel = np.array([0, 199, 5, 5, 77, 120], dtype=np.int64)
+    rp, ci, va, ab = oracle.rows(A, B, sel)
+    for t, i in enumerate(sel):
+        s, e = C.row_ptr[i], C.row_ptr[i + 1]
+        assert np.array_equal(ci[rp[t]:rp[t + 1]], C.col_idx[s:e])
+        assert np.array_equal(va[rp[t]:rp[t + 1]], C.values[s:e])
+        assert np.array_equal(ab[rp[t]:rp[t + 1]], S[s:e])
