@@ -213,6 +213,16 @@ spg_status spgemm_backward(spg_handle h, const spg_csr *A, const spg_csr *B, con
  * so this is how a caller confirms a numeric result. */
 spg_status spg_check_errors(spg_handle h);
 
+/* Numeric phase for the rows [row_begin, row_end) of C only (a row panel:
+ * for products whose C does not fit device memory at once, the caller
+ * computes C in panels into reused buffers).  Same plan and operands as
+ * spgemm_numeric; the panel's entries (C.row_ptr[row_end] - C.row_ptr[row_begin]
+ * of them, C.row_ptr from the symbolic phase) are written to C_col_idx[0..)
+ * and C_values[0..) (device arrays, dtype of A and B).  Never blocks the host.
+ * Errors as spgemm_numeric, INVALID_ARG for a bad row range. */
+spg_status spgemm_numeric_rows(spg_handle h, const spg_csr *A, const spg_csr *B, int64_t row_begin,
+                               int64_t row_end, int32_t *C_col_idx, void *C_values);
+
 /* Statistics of the last symbolic phase (host struct). */
 spg_status spg_get_stats(spg_handle h, spg_stats *out);
 

@@ -91,6 +91,8 @@ _sigs = {
                              ctypes.POINTER(ctypes.c_int64)]),
     "spgemm_numeric": (_S, [_P, ctypes.POINTER(spg_csr), ctypes.POINTER(spg_csr), ctypes.POINTER(spg_csr_out)]),
     "spg_check_errors": (_S, [_P]),
+    "spgemm_numeric_rows": (_S, [_P, ctypes.POINTER(spg_csr), ctypes.POINTER(spg_csr), ctypes.c_int64,
+                                 ctypes.c_int64, _P, _P]),
     "spgemm_batch_symbolic": (_S, [_P, ctypes.c_int32, ctypes.POINTER(spg_csr), ctypes.POINTER(spg_csr),
                                    ctypes.POINTER(_P), _S, ctypes.POINTER(ctypes.c_int64)]),
     "spgemm_batch_numeric": (_S, [_P, ctypes.c_int32, ctypes.POINTER(spg_csr), ctypes.POINTER(spg_csr),
@@ -402,3 +404,14 @@ def pack_batch(mats, device="cuda", dtype=torch.float64, rp_dtype=torch.int32):
         out.append(DeviceCsr(M.nrows, M.ncols, rp, ci[off:off + nz], va[off:off + nz]))
         off += nz
     return out
+
+
+def spgemm_numeric_rows(h: Handle, A: DeviceCsr, B: DeviceCsr, row_begin: int, row_end: int,
+                        col_panel: torch.Tensor, val_panel: torch.Tensor):
+    """spgemm_numeric_rows: rows [row_begin, row_end) of C into the panel buffers."""
+    a, b = _csr(A), _csr(B)
+    rc = lib().spgemm_numeric_rows(h.ptr, ctypes.byref(a), ctypes.byref(b), row_begin, row_end,
+                                   _P(col_panel.data_ptr()) if col_panel.numel() else None,
+                                   _P(val_panel.data_ptr()) if val_panel.numel() else None)
+    if rc != SPG_OK:
+        h._raise(rc)

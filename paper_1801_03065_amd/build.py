@@ -24,7 +24,7 @@ CXXFLAGS = [
     "-ffp-contract=off",        # products rounded before the add, as written
     # no packed FP32 instructions (v_pk_*_f32) anywhere
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-    "-Wall", "-Wno-unused-function", "-Wno-unused-variable",
+    "-Wall", "-Wshadow", "-Wno-unused-function", "-Wno-unused-variable",
     f"-I{os.path.join(ROOT, 'include')}", f"-I{CSRC}",
 ]
 

@@ -482,6 +482,27 @@ __global__ __launch_bounds__(BLK) void k_fill_i32(int32_t *p, int64_t n, int32_t
     for (int64_t i = (int64_t)blockIdx.x * BLK + threadIdx.x; i < n; i += (int64_t)gridDim.x * BLK) p[i] = v;
 }
 
+// Per kind, the slice of the (row-sorted) kind list holding rows in [rb, re).
+__global__ void k_kind_ranges(const int32_t *perm, const int64_t *koff, int64_t rb, int64_t re, int64_t *range) {
+    const int k = threadIdx.x;
+    if (k >= NK) return;
+    int64_t lo = koff[k], hi = koff[k + 1];
+    int64_t a = lo, b = hi;  // first index with perm >= rb
+    while (a < b) {
+        const int64_t m = (a + b) >> 1;
+        if (perm[m] < rb) a = m + 1; else b = m;
+    }
+    const int64_t first = a;
+    a = first;
+    b = hi;  // first index with perm >= re
+    while (a < b) {
+        const int64_t m = (a + b) >> 1;
+        if (perm[m] < re) a = m + 1; else b = m;
+    }
+    range[2 * k] = first;
+    range[2 * k + 1] = a;
+}
+
 inline int grid_for(int64_t work, int per_block, int cap = 65536) {
     int64_t g = (work + per_block - 1) / per_block;
     if (g < 1) g = 1;
@@ -613,6 +634,12 @@ hipError_t launch_partition(int64_t m, const uint8_t *kind, int32_t *perm, int64
     hipLaunchKernelGGL(k_part_count, dim3((unsigned)nb), dim3(PB), 0, s, m, kind, tmp);
     hipLaunchKernelGGL(k_part_scan, dim3(1), dim3(PB), 0, s, nb, tmp, koff);
     hipLaunchKernelGGL(k_part_scatter, dim3((unsigned)nb), dim3(PB), 0, s, m, kind, tmp, perm);
+    return hipGetLastError();
+}
+
+hipError_t launch_kind_ranges(const int32_t *perm, const int64_t *koff, int64_t rb, int64_t re, int64_t *range,
+                              hipStream_t s) {
+    hipLaunchKernelGGL(k_kind_ranges, dim3(1), dim3(64), 0, s, perm, koff, rb, re, range);
     return hipGetLastError();
 }
 

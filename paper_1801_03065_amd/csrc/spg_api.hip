@@ -61,7 +61,7 @@ struct spg_handle_s {
     ClassParams cparams{};                                   // classification of the last symbolic phase
     int lg_num = 4;                                          // log2 lanes per B row, numeric phase
     bool tuned = false;
-    DevBuf kind_tmp, perm_tmp, koff_tmp;
+    DevBuf kind_tmp, perm_tmp, koff_tmp, krange;
 
     struct Batch {
         int count = 0;
@@ -244,7 +244,7 @@ spg_status spg_destroy(spg_handle h) {
     DevBuf *bufs[] = {&h->arp64, &h->brp64, &h->binfo, &h->ulist, &h->uflag, &h->bcrp, &h->bcsi, &h->bcs,
                       &h->rflops, &h->rflopsc, &h->rwin, &h->row_nnz, &h->coff, &h->kind_sym, &h->kind_num,
                       &h->perm_sym, &h->perm_num, &h->koff_sym, &h->koff_num, &h->tmp, &h->dstats, &h->queue,
-                      &h->arena, &h->l2k, &h->l2v, &h->blens, &h->row_words, &h->kind_tmp, &h->perm_tmp, &h->koff_tmp};
+                      &h->arena, &h->l2k, &h->l2v, &h->blens, &h->row_words, &h->kind_tmp, &h->perm_tmp, &h->koff_tmp, &h->krange};
     for (DevBuf *b : bufs) release(*b);
     if (h->hst) (void)hipHostFree(h->hst);
     if (h->hkoff) (void)hipHostFree(h->hkoff);
@@ -671,7 +671,8 @@ static spg_status autotune(spg_handle h, NumArgs<VT> na, int acc) {
 }
 
 template <typename VT>
-static spg_status numeric_impl(spg_handle h, const VT *aval, const VT *bval, int32_t *cci, VT *cval, int acc) {
+static spg_status numeric_impl(spg_handle h, const VT *aval, const VT *bval, int32_t *cci, VT *cval, int acc,
+                               int64_t row_begin = -1, int64_t row_end = -1) {
     hipStream_t st = h->stream;
     DevStats &hs = *h->hst;
     NumArgs<VT> na{};
@@ -695,6 +696,17 @@ static spg_status numeric_impl(spg_handle h, const VT *aval, const VT *bval, int
     na.st = h->dstats.as<DevStats>();
     na.lg_gs_or = lg_group(h->avg_len_c);
     na.lg_gs = h->lg_num;
+    na.cbase_row = -1;
+    if (row_begin >= 0) {  // one panel of rows: per-kind slices, output relative to the panel
+        HIPCHK(ensure(h->krange, 16 * NK));
+        HIPCHK(launch_kind_ranges(h->perm_num.as<int32_t>(), h->koff_num.as<int64_t>(), row_begin, row_end,
+                                  h->krange.as<int64_t>(), h->stream));
+        na.rs.rows = h->perm_num.as<int32_t>();
+        na.rs.koff = h->koff_num.as<int64_t>();
+        na.rs.range = h->krange.as<int64_t>();
+        na.cbase_row = row_begin;
+        return launch_kinds<VT>(h, na, hs.kcount_num, hs.kmax_num, acc);
+    }
     if (h->opt.autotune && !h->tuned) {
         spg_status s = autotune<VT>(h, na, acc);
         if (s != SPG_OK) return s;
@@ -965,4 +977,30 @@ extern "C" spg_status spgemm_batch_numeric(spg_handle h, int32_t count, const sp
     }
     if (dt == SPG_F64) return batch_numeric_impl<double>(h, count, A, B, C, ACC_NATIVE);
     return batch_numeric_impl<float>(h, count, A, B, C, fp32_acc(h));
+}
+
+extern "C" spg_status spgemm_numeric_rows(spg_handle h, const spg_csr *A, const spg_csr *B, int64_t row_begin,
+                                          int64_t row_end, int32_t *C_col_idx, void *C_values) {
+    if (!h) return SPG_ERR_INVALID_ARG;
+    h->err.clear();
+    if (!h->ready) return fail(h, SPG_ERR_NOT_READY, "spgemm_numeric_rows before a successful spgemm_symbolic");
+    if (h->batch.count) return fail(h, SPG_ERR_STRUCTURE_MISMATCH, "the plan is a batch");
+    spg_status s;
+    if ((s = check_csr(h, A, "A", true)) != SPG_OK) return s;
+    if ((s = check_csr(h, B, "B", true)) != SPG_OK) return s;
+    const Fingerprint &f = h->fp;
+    if (A->nrows != f.m || A->ncols != f.n || B->ncols != f.k || A->nnz != f.nnza || B->nnz != f.nnzb ||
+        A->row_ptr != f.arp || B->row_ptr != f.brp || A->col_idx != f.aci || B->col_idx != f.bci ||
+        (int)A->rp_type != f.arpt || (int)B->rp_type != f.brpt)
+        return fail(h, SPG_ERR_STRUCTURE_MISMATCH, "A or B differs from the operands of the symbolic phase");
+    if (row_begin < 0 || row_end < row_begin || row_end > f.m)
+        return fail(h, SPG_ERR_INVALID_ARG, "need 0 <= row_begin <= row_end <= A.nrows");
+    if (A->dtype != B->dtype) return fail(h, SPG_ERR_INVALID_ARG, "A and B must share one dtype");
+    if (row_begin == row_end || h->nnzc == 0) return SPG_OK;
+    if (!C_col_idx || !C_values) return fail(h, SPG_ERR_INVALID_ARG, "panel arrays are NULL");
+    if (A->dtype == SPG_F64)
+        return numeric_impl<double>(h, (const double *)A->values, (const double *)B->values, C_col_idx,
+                                    (double *)C_values, ACC_NATIVE, row_begin, row_end);
+    return numeric_impl<float>(h, (const float *)A->values, (const float *)B->values, C_col_idx,
+                               (float *)C_values, fp32_acc(h), row_begin, row_end);
 }

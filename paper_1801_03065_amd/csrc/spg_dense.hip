@@ -149,8 +149,8 @@ __device__ __forceinline__ void dw_or_batched(int cn, int wlo, const int32_t *bc
         for (int u = 0; u < DW_U; ++u) {  // rows of B longer than the group
             const int t = t0 + u * ng;
             if (t >= cn) break;
-            const int len = st_clen[t];
-            for (int p = q + gs; p < len; p += gs) {
+            const int tl = st_clen[t];
+            for (int p = q + gs; p < tl; p += gs) {
                 uint32_t dd, cc;
                 dw_word<COMP>(st_cbs[t] + p, wlo, bci, bcsi, bcs, dd, cc);
                 dw_or(bits, summ, dd, cc);
@@ -197,25 +197,59 @@ __global__ __launch_bounds__(WAVE) void k_sym_dw(SymArgs a) {
     __syncthreads();
     const bool comp = a.bcrp != nullptr;
     const int64_t *srp = comp ? a.bcrp : a.brp;
-    const int64_t lo = a.rs.koff[a.rs.kind], hi = a.rs.koff[a.rs.kind + 1];
+    int64_t lo, hi;
+    rs_bounds(a.rs, lo, hi);
     const Slice sl = xcd_slice(lo, hi);
+    // Software pipeline across rows: the next row's A entries and B extents
+    // (first chunk) load while the current row's words are OR-ed and counted.
     int64_t r = sl.idx;
-    int i_next = r < sl.end ? a.rs.rows[r] : 0;
-    RowDesc dn = r < sl.end ? row_desc(i_next, a.arp, a.rwin) : RowDesc{};
+    int icur = r < sl.end ? a.rs.rows[r] : 0;
+    RowDesc dcur = r < sl.end ? row_desc(icur, a.arp, a.rwin) : RowDesc{};
+    int64_t sc0 = 0, sc1 = 0;
+    if (r < sl.end && l < min((int64_t)WAVE, dcur.ae - dcur.ab)) {
+        const int j = a.aci[dcur.ab + l];
+        sc0 = srp[j];
+        sc1 = srp[j + 1];
+    }
+    int inext = r + sl.step < sl.end ? a.rs.rows[r + sl.step] : 0;
+    RowDesc dn = r + sl.step < sl.end ? row_desc(inext, a.arp, a.rwin) : RowDesc{};
     while (r < sl.end) {
-        const int i = i_next;
-        const RowDesc d = dn;
+        const int i = icur;
+        const RowDesc d = dcur;
         r += sl.step;
-        if (r < sl.end) {  // prefetch the next row's descriptor
-            i_next = a.rs.rows[r];
-            dn = row_desc(i_next, a.arp, a.rwin);
-        }
+        const bool has_next = r < sl.end;
+        const int ncn = has_next ? (int)min((int64_t)WAVE, dn.ae - dn.ab) : 0;
         for (int64_t cb = d.ab; cb < d.ae; cb += WAVE) {
-            const int cn = dw_stage<double>(cb, d.ae, a.aci, nullptr, srp, nullptr, st_cbs, st_clen, nullptr,
-                                            nullptr, nullptr);
+            int cn;
+            if (cb == d.ab) {  // first chunk: from the prefetched registers
+                cn = (int)min((int64_t)WAVE, d.ae - d.ab);
+                if (l < cn) {
+                    st_cbs[l] = sc0;
+                    st_clen[l] = (int32_t)(sc1 - sc0);
+                }
+                // next row, first level
+                int nj = 0;
+                if (l < ncn) nj = a.aci[dn.ab + l];
+                __syncthreads();
+                dw_or_staged(cn, d.wlo, comp, a.bci, a.bcsi, a.bcs, a.lg_gs, st_cbs, st_clen, bits, summ);
+                // next row, second level
+                if (l < ncn) {
+                    sc0 = srp[nj];
+                    sc1 = srp[nj + 1];
+                }
+            } else {
+                cn = dw_stage<double>(cb, d.ae, a.aci, nullptr, srp, nullptr, st_cbs, st_clen, nullptr, nullptr,
+                                      nullptr);
+                __syncthreads();
+                dw_or_staged(cn, d.wlo, comp, a.bci, a.bcsi, a.bcs, a.lg_gs, st_cbs, st_clen, bits, summ);
+            }
             __syncthreads();
-            dw_or_staged(cn, d.wlo, comp, a.bci, a.bcsi, a.bcs, a.lg_gs, st_cbs, st_clen, bits, summ);
-            __syncthreads();
+        }
+        icur = inext;
+        dcur = dn;
+        if (r + sl.step < sl.end) {
+            inext = a.rs.rows[r + sl.step];
+            dn = row_desc(inext, a.arp, a.rwin);
         }
         int cnt = 0, nwt = 0;
         for (int s = l; s < d.ns; s += WAVE) {
@@ -264,7 +298,9 @@ __global__ __launch_bounds__(WAVE) void k_num_dw(NumArgs<VT> a) {
     const bool comp = a.bcrp != nullptr;
     const int64_t *srp = comp ? a.bcrp : a.brp;
     const int gs = 1 << a.lg_gs, g = l >> a.lg_gs, q = l & (gs - 1), ng = WAVE >> a.lg_gs;
-    const int64_t lo = a.rs.koff[a.rs.kind], hi = a.rs.koff[a.rs.kind + 1];
+    int64_t lo, hi;
+    rs_bounds(a.rs, lo, hi);
+    const int64_t cbase = a.cbase_row >= 0 ? a.coff[a.cbase_row] : 0;
     const Slice sl = xcd_slice(lo, hi);
     int64_t r = sl.idx;
     int i_next = r < sl.end ? a.rs.rows[r] : 0;
@@ -350,9 +386,9 @@ __global__ __launch_bounds__(WAVE) void k_num_dw(NumArgs<VT> a) {
                 }
 #pragma unroll
                 for (int u = 0; u < DW_U; ++u) {  // then every global load of the batch
-                    const bool ok = t0 + u * ng < cn && q < len[u];
-                    okm |= (unsigned)ok << u;
-                    const int64_t e = ok ? bs[u] + q : 0;
+                    const bool okp = t0 + u * ng < cn && q < len[u];
+                    okm |= (unsigned)okp << u;
+                    const int64_t e = okp ? bs[u] + q : 0;
                     col[u] = a.bci[e];
                     bv[u] = a.bval[e];
                 }
@@ -369,9 +405,9 @@ __global__ __launch_bounds__(WAVE) void k_num_dw(NumArgs<VT> a) {
                 for (int u = 0; u < DW_U; ++u) {  // rows of B longer than the group
                     const int t = t0 + u * ng;
                     if (t >= cn) break;
-                    const int len = st_len[t];
+                    const int tl = st_len[t];
                     const VT avt = (VT)st_a[t];
-                    for (int p = q + gs; p < len; p += gs) {
+                    for (int p = q + gs; p < tl; p += gs) {
                         const int64_t e = st_bs[t] + p;
                         const int c = a.bci[e];
                         const int w = (c >> 5) - wlo;
@@ -396,9 +432,10 @@ __global__ __launch_bounds__(WAVE) void k_num_dw(NumArgs<VT> a) {
         }
         __syncthreads();
         if (ok) {
+            const int64_t ob = cb - cbase;
             for (int t = l; t < rnnz; t += WAVE) {
-                a.cci[cb + t] = colbuf[t];
-                a.cval[cb + t] = A::fin(vals[t]);
+                a.cci[ob + t] = colbuf[t];
+                a.cval[ob + t] = A::fin(vals[t]);
             }
         }
         __syncthreads();
@@ -528,7 +565,8 @@ __global__ __launch_bounds__(WG_BIG) void k_sym_dg(SymArgs a) {
     const int nsm = (a.nw_max + 31) >> 5;
     for (int w = t; w < a.nw_max; w += WG_BIG) bits[w] = 0;
     for (int w = t; w < nsm; w += WG_BIG) summ[w] = 0;
-    const int64_t lo = a.rs.koff[a.rs.kind], hi = a.rs.koff[a.rs.kind + 1];
+    int64_t lo, hi;
+    rs_bounds(a.rs, lo, hi);
     int x = blockIdx.x % XCDS;
     for (;;) {
         const int i = dg_next_row(a.rs, lo, hi, x, red);
@@ -573,7 +611,9 @@ __global__ __launch_bounds__(WG_BIG) void k_num_dg(NumArgs<VT> a) {
     const int nsm = (a.nw_max + 31) >> 5;
     for (int w = t; w < a.nw_max; w += WG_BIG) bits[w] = 0;
     for (int w = t; w < nsm; w += WG_BIG) summ[w] = 0;
-    const int64_t lo = a.rs.koff[a.rs.kind], hi = a.rs.koff[a.rs.kind + 1];
+    int64_t lo, hi;
+    rs_bounds(a.rs, lo, hi);
+    const int64_t cbase = a.cbase_row >= 0 ? a.coff[a.cbase_row] : 0;
     int x = blockIdx.x % XCDS;
     for (;;) {
         const int i = dg_next_row(a.rs, lo, hi, x, red);
@@ -581,12 +621,12 @@ __global__ __launch_bounds__(WG_BIG) void k_num_dg(NumArgs<VT> a) {
         const int2 win = a.rwin[i];
         const int wlo = win.x;
         const int ns = (win.y - win.x + 1 + 31) >> 5;
-        const int64_t cbase = (int64_t)wlo << 5;
+        const int64_t colbase = (int64_t)wlo << 5;  // first column of the row's window
         dg_or_pass(i, wlo, a.arp, a.aci, a.brp, a.bci, a.bcrp, a.bcsi, a.bcs, bits, summ, st_off, st_bs, red);
         const int64_t ab = a.arp[i], ae = a.arp[i + 1];
         dg_flat(ab, ae, a.aci, a.brp, st_off, st_bs, red, [&](int k, int64_t e, int64_t cb) {
             const VT av = a.aval[cb + k];
-            A::add(&gv[a.bci[e] - cbase], av, a.bval[e]);
+            A::add(&gv[a.bci[e] - colbase], av, a.bval[e]);
         });
         __threadfence();  // the HBM atomics above complete before any lane reads a slot
         __syncthreads();
@@ -609,12 +649,12 @@ __global__ __launch_bounds__(WG_BIG) void k_num_dg(NumArgs<VT> a) {
                 while (w) {
                     const int col = base + __ffs(w) - 1;
                     w &= w - 1;
-                    S *slot = &gv[col - cbase];
+                    S *slot = &gv[col - colbase];
                     const S v = __hip_atomic_load(slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                     __hip_atomic_store(slot, A::zero(), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                     if (pos < cend) {
-                        a.cci[pos] = col;
-                        a.cval[pos] = A::fin(v);
+                        a.cci[pos - cbase] = col;
+                        a.cval[pos - cbase] = A::fin(v);
                     }
                     ++pos;
                 }

@@ -125,7 +125,8 @@ __global__ __launch_bounds__(WAVE) void k_sym_hw(SymArgs a) {
     __syncthreads();
     const bool comp = a.bcrp != nullptr;
     const int gs = 1 << a.lg_gs, g = l >> a.lg_gs, q = l & (gs - 1), ng = WAVE >> a.lg_gs;
-    const int64_t lo = a.rs.koff[a.rs.kind], hi = a.rs.koff[a.rs.kind + 1];
+    int64_t lo, hi;
+    rs_bounds(a.rs, lo, hi);
     const Slice sl = xcd_slice(lo, hi);
     for (int64_t r = sl.idx; r < sl.end; r += sl.step) {
         const int i = a.rs.rows[r];
@@ -193,7 +194,9 @@ __global__ __launch_bounds__(WAVE) void k_num_hw(NumArgs<VT> a) {
     }
     __syncthreads();
     const int gs = 1 << a.lg_gs, g = l >> a.lg_gs, q = l & (gs - 1), ng = WAVE >> a.lg_gs;
-    const int64_t lo = a.rs.koff[a.rs.kind], hi = a.rs.koff[a.rs.kind + 1];
+    int64_t lo, hi;
+    rs_bounds(a.rs, lo, hi);
+    const int64_t cbase = a.cbase_row >= 0 ? a.coff[a.cbase_row] : 0;
     const Slice sl = xcd_slice(lo, hi);
     for (int64_t r = sl.idx; r < sl.end; r += sl.step) {
         const int i = a.rs.rows[r];
@@ -241,8 +244,8 @@ __global__ __launch_bounds__(WAVE) void k_num_hw(NumArgs<VT> a) {
         if (ok) {
             bitonic_lds(sk, sv, np, WAVE);
             for (int t = l; t < n; t += WAVE) {
-                a.cci[cb + t] = sk[t];
-                a.cval[cb + t] = A::fin(sv[t]);
+                a.cci[cb - cbase + t] = sk[t];
+                a.cval[cb - cbase + t] = A::fin(sv[t]);
             }
         }
         __syncthreads();
@@ -389,7 +392,8 @@ __global__ __launch_bounds__(WG_BIG) void k_sym_hl(SymArgs a) {
         masks[s] = 0;
     }
     const bool comp = a.bcrp != nullptr;
-    const int64_t lo = a.rs.koff[a.rs.kind], hi = a.rs.koff[a.rs.kind + 1];
+    int64_t lo, hi;
+    rs_bounds(a.rs, lo, hi);
     int x = blockIdx.x % XCDS;
     for (;;) {
         const int i = hl_next_row(a.rs, lo, hi, x, red);
@@ -495,7 +499,9 @@ __global__ __launch_bounds__(WG_BIG) void k_num_hl(NumArgs<VT> a) {
         keys[s] = -1;
         vals[s] = A::zero();
     }
-    const int64_t lo = a.rs.koff[a.rs.kind], hi = a.rs.koff[a.rs.kind + 1];
+    int64_t lo, hi;
+    rs_bounds(a.rs, lo, hi);
+    const int64_t cbase = a.cbase_row >= 0 ? a.coff[a.cbase_row] : 0;
     int x = blockIdx.x % XCDS;
     for (;;) {
         const int i = hl_next_row(a.rs, lo, hi, x, red);
@@ -588,8 +594,8 @@ __global__ __launch_bounds__(WG_BIG) void k_num_hl(NumArgs<VT> a) {
                 }
             }
             for (int64_t p = t; p < rn; p += WG_BIG) {
-                a.cci[c0 + p] = sk[p];
-                a.cval[c0 + p] = A::fin(sv[p]);
+                a.cci[c0 - cbase + p] = sk[p];
+                a.cval[c0 - cbase + p] = A::fin(sv[p]);
             }
         }
         __threadfence();

@@ -58,9 +58,20 @@ constexpr int WH_T_MAX = 512;     // touched words of the word-hash kernel (tabl
 struct RowSet {
     const int32_t *rows;   // permutation of row ids, grouped by kind
     const int64_t *koff;   // koff[kind] .. koff[kind+1] is this kind's slice
+    const int64_t *range;  // when set: range[2*kind] .. range[2*kind+1] instead (row panels)
     int kind;
     int32_t *queue;        // XCDS dynamic-schedule counters (zeroed before launch)
 };
+
+__device__ __forceinline__ void rs_bounds(const RowSet &rs, int64_t &lo, int64_t &hi) {
+    if (rs.range) {
+        lo = rs.range[2 * rs.kind];
+        hi = rs.range[2 * rs.kind + 1];
+    } else {
+        lo = rs.koff[rs.kind];
+        hi = rs.koff[rs.kind + 1];
+    }
+}
 
 struct SymArgs {
     const int64_t *arp;
@@ -97,8 +108,9 @@ struct NumArgs {
     const uint32_t *bcs;
     const int2 *rwin;
     const int64_t *coff;   // C row offsets (plan copy, int64)
-    int32_t *cci;
+    int32_t *cci;          // written at coff[i] - coff[cbase_row] (0 when cbase_row < 0)
     VT *cval;
+    int64_t cbase_row;
     RowSet rs;
     int nw_max;
     int r_max;
@@ -271,6 +283,8 @@ int64_t part_tmp_elems(int64_t m);
 hipError_t launch_partition(int64_t m, const uint8_t *kind, int32_t *perm, int64_t *koff, int64_t *tmp,
                             hipStream_t s);
 hipError_t launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s);
+hipError_t launch_kind_ranges(const int32_t *perm, const int64_t *koff, int64_t rb, int64_t re, int64_t *range,
+                              hipStream_t s);
 
 // Core kernels.
 hipError_t launch_sym_dw(const SymArgs &a, const LaunchCfg &c);

@@ -107,7 +107,7 @@ __device__ __forceinline__ RowDescW row_desc_w(int i, const int64_t *arp, const 
 }
 
 template <typename VT, int ACC>
-__global__ __launch_bounds__(WAVE) void k_num_wh(NumArgs<VT> a) {
+__global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_num_wh(NumArgs<VT> a) {
     using A = Accum<VT, ACC>;
     using S = typename A::store_t;
     extern __shared__ __align__(16) unsigned char smem[];
@@ -133,41 +133,56 @@ __global__ __launch_bounds__(WAVE) void k_num_wh(NumArgs<VT> a) {
     for (int s = l; s < nsm; s += WAVE) summ[s] = 0;
     __syncthreads();
     const int gs = 1 << a.lg_gs, g = l >> a.lg_gs, q = l & (gs - 1), ng = WAVE >> a.lg_gs;
-    const int64_t lo = a.rs.koff[a.rs.kind], hi = a.rs.koff[a.rs.kind + 1];
+    int64_t lo, hi;
+    rs_bounds(a.rs, lo, hi);
+    const int64_t cbase = a.cbase_row >= 0 ? a.coff[a.cbase_row] : 0;
     const Slice sl = xcd_slice(lo, hi);
+    // Software pipeline across rows: while row r is processed, row r+1's A
+    // entries (first level) and B row extents (second level) are already in
+    // flight, and row r+2's descriptor; only the product loads of a row are
+    // exposed latency.
     int64_t r = sl.idx;
-    int i_next = r < sl.end ? a.rs.rows[r] : 0;
-    RowDescW dn = r < sl.end ? row_desc_w(i_next, a.arp, a.rwin, a.coff) : RowDescW{};
+    RowDescW dcur = r < sl.end ? row_desc_w(a.rs.rows[r], a.arp, a.rwin, a.coff) : RowDescW{};
+    int64_t sb0 = 0, sb1 = 0;  // staged extents / value of this lane's A entry (first chunk)
+    double sav = 0.0;
+    if (r < sl.end && l < min((int64_t)WAVE, dcur.ae - dcur.ab)) {
+        const int j = a.aci[dcur.ab + l];
+        sav = (double)a.aval[dcur.ab + l];
+        sb0 = a.brp[j];
+        sb1 = a.brp[j + 1];
+    }
+    RowDescW dn = r + sl.step < sl.end ? row_desc_w(a.rs.rows[r + sl.step], a.arp, a.rwin, a.coff) : RowDescW{};
     while (r < sl.end) {
-        const RowDescW d = dn;
+        const RowDescW d = dcur;
         r += sl.step;
-        if (r < sl.end) {  // prefetch the next row's descriptor
-            i_next = a.rs.rows[r];
-            dn = row_desc_w(i_next, a.arp, a.rwin, a.coff);
-        }
+        const bool has_next = r < sl.end;
         const int wlo = d.wlo;
         const int64_t na = d.ae - d.ab;
-        // ---- stage the first chunk of A's row (B row extents and A values)
+        // ---- stage the first chunk of A's row from the prefetched registers
         int cn = (int)min((int64_t)WAVE, na);
         int mylen = 0;
         if (l < cn) {
-            const int j = a.aci[d.ab + l];
-            const double av = (double)a.aval[d.ab + l];
-            const int64_t b0 = a.brp[j], b1 = a.brp[j + 1];
-            st_bs[l] = b0;
-            st_a[l] = av;
-            mylen = (int)(b1 - b0);
+            st_bs[l] = sb0;
+            st_a[l] = sav;
+            mylen = (int)(sb1 - sb0);
             st_len[l] = mylen;
         }
         const bool fast = na <= WAVE && cn <= ng * WH_U && wave_max(mylen) <= gs;
+        // next row, first level: its A entries
+        const int ncn = has_next ? (int)min((int64_t)WAVE, dn.ae - dn.ab) : 0;
+        int nj = 0;
+        if (l < ncn) {
+            nj = a.aci[dn.ab + l];
+            sav = (double)a.aval[dn.ab + l];
+        }
         __syncthreads();
 
         // ---- structure: insert every product's word, keep its slot / bit
         uint32_t pk[WH_U];  // slot << 5 | bit, or ~0u for no product
         VT pv[WH_U];
+        unsigned okm = 0;
         if (fast) {
             int col[WH_U];
-            unsigned okm = 0;
 #pragma unroll
             for (int u = 0; u < WH_U; ++u) {
                 const int t = g + u * ng;
@@ -175,9 +190,7 @@ __global__ __launch_bounds__(WAVE) void k_num_wh(NumArgs<VT> a) {
                 const int len = st_len[tt];
                 const bool ok = t < cn && q < len;
                 okm |= (unsigned)ok << u;
-                const int64_t e = ok ? st_bs[tt] + q : 0;
-                col[u] = a.bci[e];
-                pv[u] = a.bval[e];
+                col[u] = a.bci[ok ? st_bs[tt] + q : 0];
             }
 #pragma unroll
             for (int u = 0; u < WH_U; ++u) {
@@ -189,6 +202,13 @@ __global__ __launch_bounds__(WAVE) void k_num_wh(NumArgs<VT> a) {
                     atomicOr(&tbits[2 * h], 1u << (c & 31));
                     pk[u] = (h << 5) | (uint32_t)(c & 31);
                 }
+            }
+            // the values load now and arrive during the scans below
+#pragma unroll
+            for (int u = 0; u < WH_U; ++u) {
+                const int t = g + u * ng;
+                const int tt = t < cn ? t : 0;
+                pv[u] = a.bval[(okm & (1u << u)) ? st_bs[tt] + q : 0];
             }
         } else {
             for (int64_t c0 = d.ab; c0 < d.ae; c0 += WAVE) {
@@ -214,6 +234,13 @@ __global__ __launch_bounds__(WAVE) void k_num_wh(NumArgs<VT> a) {
                 }
             }
         }
+        // next row, second level: its B row extents; the row after: descriptor
+        if (l < ncn) {
+            sb0 = a.brp[nj];
+            sb1 = a.brp[nj + 1];
+        }
+        dcur = dn;
+        if (r + sl.step < sl.end) dn = row_desc_w(a.rs.rows[r + sl.step], a.arp, a.rwin, a.coff);
         __syncthreads();
 
         // ---- touched words in increasing order (summary), prefix counts per slot
@@ -315,9 +342,10 @@ __global__ __launch_bounds__(WAVE) void k_num_wh(NumArgs<VT> a) {
         }
         __syncthreads();
         if (ok) {
+            const int64_t ob = d.cb - cbase;
             for (int t = l; t < rnnz; t += WAVE) {
-                a.cci[d.cb + t] = colbuf[t];
-                a.cval[d.cb + t] = A::fin(vals[t]);
+                a.cci[ob + t] = colbuf[t];
+                a.cval[ob + t] = A::fin(vals[t]);
             }
         }
         __syncthreads();

@@ -66,3 +66,42 @@ def test_paper_constants_fixture():
     assert abs(o.cf_threshold - c["compression_flop_ratio_threshold"]["value"]) < 1e-15
     ex = c["linear_probing_example"]
     assert ex["key"] & (ex["table_size"] - 1) == ex["slot"]
+
+
+def test_create_without_device_fails_cleanly():
+    """With no GPU visible, spg_create reports a HIP error and leaves no handle."""
+    import torch
+
+    import paper_1801_03065_amd as spg
+
+    if torch.cuda.device_count() > 0:
+        pytest.skip("a GPU is present")
+    L = spg.lib()
+    h = ctypes.c_void_p(123)
+    rc = L.spg_create(ctypes.byref(h), None, None)
+    assert rc == spg.SPG_ERR_HIP
+    assert not h.value
+
+
+def test_create_rejects_bad_options():
+    """Options are validated before any device call."""
+    import paper_1801_03065_amd as spg
+
+    L = spg.lib()
+    for bad in (dict(compression=2), dict(cf_threshold=0.0), dict(cf_threshold=1.5), dict(accumulator=9),
+                dict(fp32_mode=3), dict(l1_hash_slots=100), dict(l1_hash_slots=4)):
+        o = spg.options(**bad)
+        h = ctypes.c_void_p(0)
+        assert L.spg_create(ctypes.byref(h), None, ctypes.byref(o)) == spg.SPG_ERR_INVALID_ARG, bad
+        assert not h.value
+
+
+def test_batch_and_panel_entry_points_reject_null_handle():
+    import paper_1801_03065_amd as spg
+
+    L = spg.lib()
+    assert L.spgemm_batch_symbolic(None, 1, None, None, None, 0, None) == spg.SPG_ERR_INVALID_ARG
+    assert L.spgemm_batch_numeric(None, 1, None, None, None) == spg.SPG_ERR_INVALID_ARG
+    assert L.spgemm_numeric_rows(None, None, None, 0, 0, None, None) == spg.SPG_ERR_INVALID_ARG
+    assert L.spgemm_backward(None, None, None, None, None, None) == spg.SPG_ERR_INVALID_ARG
+    assert L.spg_check_errors(None) == spg.SPG_ERR_INVALID_ARG

@@ -134,3 +134,50 @@ def test_int64_row_ptrs():
     got, _ = run(A, A, rp="i64", crp="i64")
     check_structure(ref, got)
     assert np.array_equal(got[2], ref.values)
+
+
+@pytest.mark.parametrize("acc", [0, 1, 2, 3])
+def test_row_panels_equal_whole_product(acc):
+    """spgemm_numeric_rows over panels reproduces the whole numeric result."""
+    import torch
+
+    import paper_1801_03065_amd as spg
+    from helpers import dev
+
+    rng = np.random.default_rng(21)
+    counts = rng.integers(0, 20, 700)
+    counts[[10, 400]] = [900, 1300]  # heavy rows land in the workgroup kinds
+    A = synth.random_csr(700, 2500, counts, 4)
+    B = synth.random_csr(2500, 60000, rng.integers(0, 30, 2500), 5)
+    ref, S = oracle_ref(A, B)
+    h = spg.Handle(accumulator=acc, l1_hash_slots=64 if acc == 3 else 0)
+    dA, dB = dev(A), dev(B)
+    rp, nnz = spg.spgemm_symbolic(h, dA, dB, torch.int64)
+    rph = rp.cpu().numpy()
+    cuts = [0, 1, 10, 11, 300, 401, 700]
+    ci = np.zeros(nnz, np.int32)
+    va = np.zeros(nnz)
+    for rb, re_ in zip(cuts[:-1], cuts[1:]):
+        n = int(rph[re_] - rph[rb])
+        pc = torch.full((max(n, 1),), -7, dtype=torch.int32, device="cuda")
+        pv = torch.zeros(max(n, 1), dtype=torch.float64, device="cuda")
+        spg.spgemm_numeric_rows(h, dA, dB, rb, re_, pc, pv)
+        h.check_errors()
+        torch.cuda.synchronize()
+        ci[rph[rb]:rph[re_]] = pc.cpu().numpy()[:n]
+        va[rph[rb]:rph[re_]] = pv.cpu().numpy()[:n]
+    check_f64(ref, S, (rph, ci, va))
+
+
+def test_heavy_rows_window_away_from_zero():
+    """Workgroup-kind rows whose column window starts far from column 0."""
+    rng = np.random.default_rng(13)
+    counts = rng.integers(0, 6, 300)
+    counts[[7, 150]] = [1200, 1700]
+    A = synth.random_csr(300, 1500, counts, 6)
+    B0 = synth.random_csr(1500, 90000, rng.integers(5, 40, 1500), 7)
+    B = synth.Csr(1500, 250000, B0.row_ptr, (B0.col_idx + 150000).astype(np.int32), B0.values)
+    ref, S = oracle_ref(A, B)
+    got, h = run(A, B)
+    check_f64(ref, S, got)
+    assert h.stats()["rows_numeric"]["dense_wg"] >= 2
