@@ -94,7 +94,7 @@ __global__ __launch_bounds__(WAVE) void k_brow_unsorted(const int32_t *list, con
     const int count = *count_p;
     if ((int)blockIdx.x >= count) return;
     for (int w = l; w < UB_WORDS; w += WAVE) bits[w] = 0;
-    __syncthreads();
+    wave_lds_sync();
     for (int t = blockIdx.x; t < count; t += gridDim.x) {
         const int64_t r = list[t];
         const int64_t b = brp[r], e = brp[r + 1];
@@ -109,7 +109,7 @@ __global__ __launch_bounds__(WAVE) void k_brow_unsorted(const int32_t *list, con
             const int col = bci[idx];
             atomicOr(&bits[(col >> 5) - br.wmin], 1u << (col & 31));
         }
-        __syncthreads();
+        wave_lds_sync();
         int run = 0;
         const int64_t out0 = mode ? bcrp[r] : 0;
         for (int w0 = 0; w0 < nw; w0 += WAVE) {
@@ -125,7 +125,7 @@ __global__ __launch_bounds__(WAVE) void k_brow_unsorted(const int32_t *list, con
             run += __popcll(bal);
         }
         if (mode == 0 && l == 0) bi[r].lenc = run;
-        __syncthreads();
+        wave_lds_sync();
     }
 }
 
@@ -184,7 +184,8 @@ __global__ __launch_bounds__(BLK) void k_mark_unsorted(const int32_t *list, cons
 // ------------------------------------------------------------------ A rows
 // 16 lanes per row of A: f_m(i) = sum |B(j,:)|, the same over compressed B,
 // and the word window [min wmin, max wmax] of the B rows it reads.
-constexpr int RI_GS = 16;
+constexpr int RI_GS = 8;
+constexpr int RI_U = 4;  // A entries per lane in flight
 
 __global__ __launch_bounds__(BLK) void k_rowinfo(int64_t m, const int64_t *arp, const int32_t *aci,
                                                   const BRow *bi, int64_t *rflops, int64_t *rflopsc,
@@ -197,12 +198,25 @@ __global__ __launch_bounds__(BLK) void k_rowinfo(int64_t m, const int64_t *arp, 
         const int64_t b = arp[i], e = arp[i + 1];
         long long f = 0, fc = 0;
         int wlo = INT_MAX, whi = -1;
-        for (int64_t idx = b + q; idx < e; idx += RI_GS) {
-            const BRow br = bi[aci[idx]];
-            f += br.len;
-            fc += br.lenc;
-            wlo = min(wlo, br.wmin);
-            whi = max(whi, br.wmax);
+        for (int64_t base = b; base < e; base += RI_GS * RI_U) {
+            int j[RI_U];
+#pragma unroll
+            for (int u = 0; u < RI_U; ++u) {
+                const int64_t idx = base + q + u * RI_GS;
+                j[u] = idx < e ? aci[idx] : -1;
+            }
+            BRow br[RI_U];
+#pragma unroll
+            for (int u = 0; u < RI_U; ++u) br[u] = bi[j[u] >= 0 ? j[u] : 0];
+#pragma unroll
+            for (int u = 0; u < RI_U; ++u) {
+                if (j[u] >= 0) {
+                    f += br[u].len;
+                    fc += br[u].lenc;
+                    wlo = min(wlo, br[u].wmin);
+                    whi = max(whi, br[u].wmax);
+                }
+            }
         }
 #pragma unroll
         for (int d = RI_GS / 2; d >= 1; d >>= 1) {
@@ -279,7 +293,8 @@ __global__ __launch_bounds__(BLK) void k_classify(int64_t m, const int64_t *rflo
         const int64_t i = i0 + threadIdx.x;
         const bool valid = i < m;
         const bool sampled = p.sample_stride <= 1 || (i % p.sample_stride) == 0;
-        const long long f = (valid && sampled) ? rflops[i] : 0;
+        long long f = (valid && sampled) ? rflops[i] : 0;
+        if (p.phase == 1 && (f < p.flops_lo || (p.flops_hi > 0 && f >= p.flops_hi))) f = 0;
         const int2 w = valid ? rwin[i] : make_int2(0, -1);
         int k = valid ? K_EMPTY : -1, a = 0, bnd = 0, tw = 0;
         if (f > 0) {
@@ -334,13 +349,18 @@ __global__ __launch_bounds__(BLK) void k_classify(int64_t m, const int64_t *rflo
         }
     }
     __syncthreads();
-    if (threadIdx.x < NK) {
-        int *gm = p.phase == 0 ? &st->kmax_sym[threadIdx.x][0] : &st->kmax_num[threadIdx.x][0];
+    // one global update per block and present kind (same-address atomics serialise in L2)
+    if (threadIdx.x < NK && scnt[threadIdx.x]) {
+        int *gm = p.phase == 0 ? &st->kmax_sym[threadIdx.x][0]
+                  : p.heavy     ? &st->kmax_heavy[threadIdx.x][0]
+                                : &st->kmax_num[threadIdx.x][0];
         atomicMax(gm, smax[threadIdx.x][0]);
         atomicMax(gm + 1, smax[threadIdx.x][1]);
         atomicMax(gm + 2, smax[threadIdx.x][2]);
-        long long *gc = p.phase == 0 ? &st->kcount_sym[threadIdx.x] : &st->kcount_num[threadIdx.x];
-        if (scnt[threadIdx.x]) atomicAdd((unsigned long long *)gc, (unsigned long long)scnt[threadIdx.x]);
+        long long *gc = p.phase == 0 ? &st->kcount_sym[threadIdx.x]
+                        : p.heavy    ? &st->kcount_heavy[threadIdx.x]
+                                     : &st->kcount_num[threadIdx.x];
+        atomicAdd((unsigned long long *)gc, (unsigned long long)scnt[threadIdx.x]);
     }
 }
 
@@ -571,7 +591,7 @@ hipError_t launch_compress_sorted_flags(int64_t n, const int64_t *brp, const int
 hipError_t launch_rowinfo(int64_t m, const int64_t *arp, const int32_t *aci, const BRow *bi, int64_t *rflops,
                           int64_t *rflopsc, int2 *rwin, DevStats *st, hipStream_t s) {
     if (m == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_rowinfo, dim3(grid_for(m * RI_GS, BLK, 4096)), dim3(BLK), 0, s, m, arp, aci, bi, rflops,
+    hipLaunchKernelGGL(k_rowinfo, dim3(grid_for(m * RI_GS, BLK, 2048)), dim3(BLK), 0, s, m, arp, aci, bi, rflops,
                        rflopsc, rwin, st);
     return hipGetLastError();
 }
@@ -617,7 +637,7 @@ hipError_t launch_classify(int64_t m, const int64_t *rflops, const int64_t *rflo
                            const int32_t *row_nnz, const int32_t *row_words, ClassParams p, uint8_t *kind,
                            int32_t *row_nnz_out, DevStats *st, hipStream_t s) {
     if (m == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_classify, dim3(grid_for(m, BLK, 4096)), dim3(BLK), 0, s, m, rflops, rflopsc, rwin,
+    hipLaunchKernelGGL(k_classify, dim3(grid_for(m, BLK, 512)), dim3(BLK), 0, s, m, rflops, rflopsc, rwin,
                        row_nnz, row_words, p, kind, row_nnz_out, st);
     return hipGetLastError();
 }

@@ -61,7 +61,8 @@ struct spg_handle_s {
     ClassParams cparams{};                                   // classification of the last symbolic phase
     int lg_num = 4;                                          // log2 lanes per B row, numeric phase
     bool tuned = false;
-    DevBuf kind_tmp, perm_tmp, koff_tmp, krange;
+    DevBuf kind_tmp, perm_tmp, koff_tmp, krange, kind_heavy, perm_heavy, koff_heavy, krange_heavy;
+    long long heavy_thr = 0;  // FP64-accumulated rows of the plan (flops at or above), 0 = none
 
     struct Batch {
         int count = 0;
@@ -244,7 +245,7 @@ spg_status spg_destroy(spg_handle h) {
     DevBuf *bufs[] = {&h->arp64, &h->brp64, &h->binfo, &h->ulist, &h->uflag, &h->bcrp, &h->bcsi, &h->bcs,
                       &h->rflops, &h->rflopsc, &h->rwin, &h->row_nnz, &h->coff, &h->kind_sym, &h->kind_num,
                       &h->perm_sym, &h->perm_num, &h->koff_sym, &h->koff_num, &h->tmp, &h->dstats, &h->queue,
-                      &h->arena, &h->l2k, &h->l2v, &h->blens, &h->row_words, &h->kind_tmp, &h->perm_tmp, &h->koff_tmp, &h->krange};
+                      &h->arena, &h->l2k, &h->l2v, &h->blens, &h->row_words, &h->kind_tmp, &h->perm_tmp, &h->koff_tmp, &h->krange, &h->kind_heavy, &h->perm_heavy, &h->koff_heavy, &h->krange_heavy};
     for (DevBuf *b : bufs) release(*b);
     if (h->hst) (void)hipHostFree(h->hst);
     if (h->hkoff) (void)hipHostFree(h->hkoff);
@@ -437,11 +438,28 @@ static spg_status symbolic_core(spg_handle h, int64_t m, int64_t n, int64_t nnza
     // scan -> C row offsets (int64 plan copy), then the numeric classification
     HIPCHK(launch_scan_i32(m, h->row_nnz.as<int32_t>(), h->coff.as<int64_t>(), h->tmp.as<int64_t>(), st));
     cp.phase = 1;
+    const long long thr = h->opt.fp64_heavy_row_flops;
+    cp.flops_lo = 0;
+    cp.flops_hi = thr > 0 ? thr : 0;
     HIPCHK(launch_classify(m, h->rflops.as<int64_t>(), h->rflopsc.as<int64_t>(), h->rwin.as<int2>(),
                            h->row_nnz.as<int32_t>(), h->row_words.as<int32_t>(), cp, h->kind_num.as<uint8_t>(),
                            nullptr, dst, st));
     HIPCHK(launch_partition(m, h->kind_num.as<uint8_t>(), h->perm_num.as<int32_t>(), h->koff_num.as<int64_t>(),
                             h->tmp.as<int64_t>(), st));
+    if (thr > 0) {  // rows at or above the threshold: their own kind lists (FP64 accumulation in FP32 mode)
+        HIPCHK(ensure(h->kind_heavy, std::max<int64_t>(m, 1)));
+        HIPCHK(ensure(h->perm_heavy, 4 * std::max<int64_t>(m, 1)));
+        HIPCHK(ensure(h->koff_heavy, 8 * (NK + 1)));
+        ClassParams ch = cp;
+        ch.flops_lo = thr;
+        ch.flops_hi = 0;
+        ch.heavy = 1;
+        HIPCHK(launch_classify(m, h->rflops.as<int64_t>(), h->rflopsc.as<int64_t>(), h->rwin.as<int2>(),
+                               h->row_nnz.as<int32_t>(), h->row_words.as<int32_t>(), ch,
+                               h->kind_heavy.as<uint8_t>(), nullptr, dst, st));
+        HIPCHK(launch_partition(m, h->kind_heavy.as<uint8_t>(), h->perm_heavy.as<int32_t>(),
+                                h->koff_heavy.as<int64_t>(), h->tmp.as<int64_t>(), st));
+    }
     HIPCHK(hipMemcpyAsync(h->hkoff, h->coff.as<int64_t>() + m, sizeof(int64_t), hipMemcpyDeviceToHost, st));
     if ((s = pull_stats(h)) != SPG_OK) return s;  // host sync 3: nnz(C), numeric kinds
     const DevStats hs3 = *h->hst;
@@ -469,6 +487,7 @@ static spg_status symbolic_core(spg_handle h, int64_t m, int64_t n, int64_t nnza
     h->aci_used = aci;
     h->bci_used = bci;
     h->cparams = cp;
+    h->heavy_thr = thr;
     h->lg_num = lg_group(h->avg_len);
     h->tuned = false;
     *nnzc_out = nnzc;
@@ -705,7 +724,15 @@ static spg_status numeric_impl(spg_handle h, const VT *aval, const VT *bval, int
         na.rs.koff = h->koff_num.as<int64_t>();
         na.rs.range = h->krange.as<int64_t>();
         na.cbase_row = row_begin;
-        return launch_kinds<VT>(h, na, hs.kcount_num, hs.kmax_num, acc);
+        spg_status s = launch_kinds<VT>(h, na, hs.kcount_num, hs.kmax_num, acc);
+        if (s != SPG_OK || h->heavy_thr <= 0) return s;
+        HIPCHK(ensure(h->krange_heavy, 16 * NK));
+        HIPCHK(launch_kind_ranges(h->perm_heavy.as<int32_t>(), h->koff_heavy.as<int64_t>(), row_begin, row_end,
+                                  h->krange_heavy.as<int64_t>(), h->stream));
+        na.rs.rows = h->perm_heavy.as<int32_t>();
+        na.rs.koff = h->koff_heavy.as<int64_t>();
+        na.rs.range = h->krange_heavy.as<int64_t>();
+        return launch_kinds<VT>(h, na, hs.kcount_heavy, hs.kmax_heavy, sizeof(VT) == 4 ? ACC_WIDE : acc);
     }
     if (h->opt.autotune && !h->tuned) {
         spg_status s = autotune<VT>(h, na, acc);
@@ -714,7 +741,12 @@ static spg_status numeric_impl(spg_handle h, const VT *aval, const VT *bval, int
     }
     na.rs.rows = h->perm_num.as<int32_t>();
     na.rs.koff = h->koff_num.as<int64_t>();
-    return launch_kinds<VT>(h, na, hs.kcount_num, hs.kmax_num, acc);
+    spg_status s = launch_kinds<VT>(h, na, hs.kcount_num, hs.kmax_num, acc);
+    if (s != SPG_OK || h->heavy_thr <= 0) return s;
+    // heaviest rows: FP64 accumulation for FP32 values (FP64 values: the same kernels)
+    na.rs.rows = h->perm_heavy.as<int32_t>();
+    na.rs.koff = h->koff_heavy.as<int64_t>();
+    return launch_kinds<VT>(h, na, hs.kcount_heavy, hs.kmax_heavy, sizeof(VT) == 4 ? ACC_WIDE : acc);
 }
 extern "C" spg_status spgemm_numeric(spg_handle h, const spg_csr *A, const spg_csr *B, spg_csr_out *C) {
     if (!h) return SPG_ERR_INVALID_ARG;

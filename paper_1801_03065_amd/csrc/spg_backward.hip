@@ -46,7 +46,7 @@ __global__ __launch_bounds__(WAVE) void k_bwd(BwdArgs<VT> a) {
                 st_len[l] = (int32_t)(b1 - b0);
                 st_a[l] = (double)a.aval[c0 + l];
             }
-            __syncthreads();
+            wave_lds_sync();
             // every group runs the same number of rounds, so the group-wide
             // reduction below always sees all its lanes
             const int rounds = (cn + ng - 1) / ng;
@@ -75,7 +75,7 @@ __global__ __launch_bounds__(WAVE) void k_bwd(BwdArgs<VT> a) {
                 for (int d = gs >> 1; d >= 1; d >>= 1) s += __shfl_xor(s, d, gs);
                 if (have && q == 0 && a.dA) a.dA[c0 + t] = s;
             }
-            __syncthreads();
+            wave_lds_sync();
         }
     }
 }

@@ -194,7 +194,7 @@ __global__ __launch_bounds__(WAVE) void k_sym_dw(SymArgs a) {
     const int nsm = (a.nw_max + 31) >> 5;
     for (int w = l; w < a.nw_max; w += WAVE) bits[w] = 0;
     for (int w = l; w < nsm; w += WAVE) summ[w] = 0;
-    __syncthreads();
+    wave_lds_sync();
     const bool comp = a.bcrp != nullptr;
     const int64_t *srp = comp ? a.bcrp : a.brp;
     int64_t lo, hi;
@@ -230,7 +230,7 @@ __global__ __launch_bounds__(WAVE) void k_sym_dw(SymArgs a) {
                 // next row, first level
                 int nj = 0;
                 if (l < ncn) nj = a.aci[dn.ab + l];
-                __syncthreads();
+                wave_lds_sync();
                 dw_or_staged(cn, d.wlo, comp, a.bci, a.bcsi, a.bcs, a.lg_gs, st_cbs, st_clen, bits, summ);
                 // next row, second level
                 if (l < ncn) {
@@ -240,10 +240,10 @@ __global__ __launch_bounds__(WAVE) void k_sym_dw(SymArgs a) {
             } else {
                 cn = dw_stage<double>(cb, d.ae, a.aci, nullptr, srp, nullptr, st_cbs, st_clen, nullptr, nullptr,
                                       nullptr);
-                __syncthreads();
+                wave_lds_sync();
                 dw_or_staged(cn, d.wlo, comp, a.bci, a.bcsi, a.bcs, a.lg_gs, st_cbs, st_clen, bits, summ);
             }
-            __syncthreads();
+            wave_lds_sync();
         }
         icur = inext;
         dcur = dn;
@@ -269,7 +269,7 @@ __global__ __launch_bounds__(WAVE) void k_sym_dw(SymArgs a) {
             a.row_nnz[i] = cnt;
             a.row_words[i] = nwt;
         }
-        __syncthreads();
+        wave_lds_sync();
     }
 }
 
@@ -294,7 +294,7 @@ __global__ __launch_bounds__(WAVE) void k_num_dw(NumArgs<VT> a) {
     const int nsm = (a.nw_max + 31) >> 5;
     for (int w = l; w < a.nw_max; w += WAVE) bits[w] = 0;
     for (int w = l; w < nsm; w += WAVE) summ[w] = 0;
-    __syncthreads();
+    wave_lds_sync();
     const bool comp = a.bcrp != nullptr;
     const int64_t *srp = comp ? a.bcrp : a.brp;
     const int gs = 1 << a.lg_gs, g = l >> a.lg_gs, q = l & (gs - 1), ng = WAVE >> a.lg_gs;
@@ -322,9 +322,9 @@ __global__ __launch_bounds__(WAVE) void k_num_dw(NumArgs<VT> a) {
         // 1. structure of the row (staging kept for step 4 when the row fits one chunk)
         for (int64_t c0 = d.ab; c0 < d.ae; c0 += WAVE) {
             const int cn = dw_stage<VT>(c0, d.ae, a.aci, a.aval, srp, a.brp, st_cbs, st_clen, st_bs, st_len, st_a);
-            __syncthreads();
+            wave_lds_sync();
             dw_or_staged(cn, wlo, comp, a.bci, a.bcsi, a.bcs, a.lg_gs_or, st_cbs, st_clen, bits, summ);
-            __syncthreads();
+            wave_lds_sync();
         }
         // 2. touched words in increasing order
         int T = 0;
@@ -342,11 +342,11 @@ __global__ __launch_bounds__(WAVE) void k_num_dw(NumArgs<VT> a) {
             if (s < ns) summ[s] = 0;
             T += __shfl(inc, WAVE - 1);
         }
-        __syncthreads();
+        wave_lds_sync();
         if (T > a.r_max) {  // structure differs from the plan: flag, reset the window, skip the row
             if (l == 0) atomicAdd(&a.st->mismatch, 1);
             for (int w = l; w < ns * 32; w += WAVE) bits[w] = 0;
-            __syncthreads();
+            wave_lds_sync();
             continue;
         }
         // 3. prefix popcounts of the touched words
@@ -363,7 +363,7 @@ __global__ __launch_bounds__(WAVE) void k_num_dw(NumArgs<VT> a) {
         const bool ok = (ce - cb == rnnz);
         if (l == 0 && !ok) atomicAdd(&a.st->mismatch, 1);
         for (int t = l; t < rnnz; t += WAVE) vals[t] = A::zero();
-        __syncthreads();
+        wave_lds_sync();
         // 4. products into vals[rank]
         for (int64_t c0 = d.ab; c0 < d.ae; c0 += WAVE) {
             int cn;
@@ -371,7 +371,7 @@ __global__ __launch_bounds__(WAVE) void k_num_dw(NumArgs<VT> a) {
                 cn = (int)(d.ae - d.ab);
             } else {
                 cn = dw_stage<VT>(c0, d.ae, a.aci, a.aval, srp, a.brp, st_cbs, st_clen, st_bs, st_len, st_a);
-                __syncthreads();
+                wave_lds_sync();
             }
             for (int t0 = g; t0 < cn; t0 += ng * DW_U) {
                 int col[DW_U], len[DW_U];
@@ -416,7 +416,7 @@ __global__ __launch_bounds__(WAVE) void k_num_dw(NumArgs<VT> a) {
                     }
                 }
             }
-            __syncthreads();
+            wave_lds_sync();
         }
         // 5. sorted columns, reset of the touched words
         for (int t = l; t < T; t += WAVE) {
@@ -430,7 +430,7 @@ __global__ __launch_bounds__(WAVE) void k_num_dw(NumArgs<VT> a) {
             }
             bits[w] = 0;
         }
-        __syncthreads();
+        wave_lds_sync();
         if (ok) {
             const int64_t ob = cb - cbase;
             for (int t = l; t < rnnz; t += WAVE) {
@@ -438,7 +438,7 @@ __global__ __launch_bounds__(WAVE) void k_num_dw(NumArgs<VT> a) {
                 a.cval[ob + t] = A::fin(vals[t]);
             }
         }
-        __syncthreads();
+        wave_lds_sync();
     }
 }
 

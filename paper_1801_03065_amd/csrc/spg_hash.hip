@@ -45,7 +45,7 @@ __device__ __forceinline__ void bitonic_lds(int32_t *key, S *val, int n, int nth
                     val[o] = vi;
                 }
             }
-            __syncthreads();
+            wave_lds_sync();
         }
     }
 }
@@ -122,7 +122,7 @@ __global__ __launch_bounds__(WAVE) void k_sym_hw(SymArgs a) {
         keys[s] = -1;
         masks[s] = 0;
     }
-    __syncthreads();
+    wave_lds_sync();
     const bool comp = a.bcrp != nullptr;
     const int gs = 1 << a.lg_gs, g = l >> a.lg_gs, q = l & (gs - 1), ng = WAVE >> a.lg_gs;
     int64_t lo, hi;
@@ -133,7 +133,7 @@ __global__ __launch_bounds__(WAVE) void k_sym_hw(SymArgs a) {
         const int64_t ab = a.arp[i], ae = a.arp[i + 1];
         for (int64_t cb = ab; cb < ae; cb += WAVE) {
             const int cn = hw_stage<double>(cb, ae, a.aci, nullptr, comp ? a.bcrp : a.brp, st_bs, st_len, st_a);
-            __syncthreads();
+            wave_lds_sync();
             for (int t = g; t < cn; t += ng) {
                 const int64_t bs = st_bs[t];
                 const int len = st_len[t];
@@ -150,7 +150,7 @@ __global__ __launch_bounds__(WAVE) void k_sym_hw(SymArgs a) {
                     atomicOr(&masks[lp_find_or_insert(keys, mask, key)], cs);
                 }
             }
-            __syncthreads();
+            wave_lds_sync();
         }
         int cnt = 0, occ = 0;
         for (int s = l; s < a.ts; s += WAVE) {
@@ -169,7 +169,7 @@ __global__ __launch_bounds__(WAVE) void k_sym_hw(SymArgs a) {
             const int2 win = a.rwin[i];
             a.row_words[i] = comp ? occ : min(cnt, win.y - win.x + 1);
         }
-        __syncthreads();
+        wave_lds_sync();
     }
 }
 
@@ -192,7 +192,7 @@ __global__ __launch_bounds__(WAVE) void k_num_hw(NumArgs<VT> a) {
         keys[s] = -1;
         vals[s] = A::zero();
     }
-    __syncthreads();
+    wave_lds_sync();
     const int gs = 1 << a.lg_gs, g = l >> a.lg_gs, q = l & (gs - 1), ng = WAVE >> a.lg_gs;
     int64_t lo, hi;
     rs_bounds(a.rs, lo, hi);
@@ -203,7 +203,7 @@ __global__ __launch_bounds__(WAVE) void k_num_hw(NumArgs<VT> a) {
         const int64_t ab = a.arp[i], ae = a.arp[i + 1];
         for (int64_t cb = ab; cb < ae; cb += WAVE) {
             const int cn = hw_stage<VT>(cb, ae, a.aci, a.aval, a.brp, st_bs, st_len, st_a);
-            __syncthreads();
+            wave_lds_sync();
             for (int t = g; t < cn; t += ng) {
                 const int64_t bs = st_bs[t];
                 const int len = st_len[t];
@@ -214,7 +214,7 @@ __global__ __launch_bounds__(WAVE) void k_num_hw(NumArgs<VT> a) {
                     A::add(&vals[lp_find_or_insert(keys, mask, c)], av, bv);
                 }
             }
-            __syncthreads();
+            wave_lds_sync();
         }
         // compact the occupied slots (in slot order), reset the table
         int n = 0;
@@ -240,7 +240,7 @@ __global__ __launch_bounds__(WAVE) void k_num_hw(NumArgs<VT> a) {
         while (np < n) np <<= 1;
         if (np > a.ts / 2) np = a.ts / 2;
         for (int p = n + l; p < np; p += WAVE) sk[p] = INT_MAX;
-        __syncthreads();
+        wave_lds_sync();
         if (ok) {
             bitonic_lds(sk, sv, np, WAVE);
             for (int t = l; t < n; t += WAVE) {
@@ -248,7 +248,7 @@ __global__ __launch_bounds__(WAVE) void k_num_hw(NumArgs<VT> a) {
                 a.cval[cb - cbase + t] = A::fin(sv[t]);
             }
         }
-        __syncthreads();
+        wave_lds_sync();
     }
 }
 

@@ -41,8 +41,10 @@ struct DevStats {
     int overflow;     // level-2 arena exhausted
     long long kcount_sym[NK];
     long long kcount_num[NK];
+    long long kcount_heavy[NK];
     int kmax_sym[NK][3];   // per kind: max window words, max bound, max touched words
     int kmax_num[NK][3];   // per kind: max window words, max row size, max touched words
+    int kmax_heavy[NK][3]; // numeric, rows at or above the FP64 flop threshold
 };
 
 // Limits of the kernel kinds (entries, not bytes).
@@ -202,6 +204,18 @@ __device__ __forceinline__ int mbcnt(unsigned long long m) {
 }
 __device__ __forceinline__ int read_first(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
+// LDS hand-off between the lanes of a one-wavefront workgroup: wait for this
+// wavefront's outstanding LDS operations only (lgkmcnt(0); vector-memory loads
+// stay in flight) and keep the compiler from moving memory operations across.
+// A workgroup barrier would also wait for every outstanding global load,
+// including loads prefetched for the next row.
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_s_waitcnt(0xC07F);  // vmcnt = max, expcnt = max, lgkmcnt = 0
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Static, XCD-aware slice of [lo, hi) for this workgroup: the grid is a
 // multiple of 8 and workgroup b runs on die b % 8, so each die walks one
 // contiguous eighth of the rows (its L2 then holds that eighth's B rows),
@@ -275,6 +289,8 @@ struct ClassParams {
     int compressed;
     int dw_nw_max, dw_r_max, hw_keys_max, dg_nw_max, wh_nw_max, wh_r_max, wh_t_max;
     int sample_stride;  // numeric: only rows i with i % stride == 0 get a kind (others: empty)
+    long long flops_lo, flops_hi;  // numeric: only rows with flops in [lo, hi) get a kind (hi <= 0: no limit)
+    int heavy;          // numeric: counts / maxima go to the heavy-row set
 };
 hipError_t launch_classify(int64_t m, const int64_t *rflops, const int64_t *rflopsc, const int2 *rwin,
                            const int32_t *row_nnz, const int32_t *row_words, ClassParams p, uint8_t *kind,

@@ -131,7 +131,7 @@ __global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(4, 8))) vo
         tbp[s] = 0ull;
     }
     for (int s = l; s < nsm; s += WAVE) summ[s] = 0;
-    __syncthreads();
+    wave_lds_sync();
     const int gs = 1 << a.lg_gs, g = l >> a.lg_gs, q = l & (gs - 1), ng = WAVE >> a.lg_gs;
     int64_t lo, hi;
     rs_bounds(a.rs, lo, hi);
@@ -175,7 +175,7 @@ __global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(4, 8))) vo
             nj = a.aci[dn.ab + l];
             sav = (double)a.aval[dn.ab + l];
         }
-        __syncthreads();
+        wave_lds_sync();
 
         // ---- structure: insert every product's word, keep its slot / bit
         uint32_t pk[WH_U];  // slot << 5 | bit, or ~0u for no product
@@ -213,7 +213,7 @@ __global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(4, 8))) vo
         } else {
             for (int64_t c0 = d.ab; c0 < d.ae; c0 += WAVE) {
                 if (c0 != d.ab) {
-                    __syncthreads();
+                    wave_lds_sync();
                     cn = (int)min((int64_t)WAVE, d.ae - c0);
                     if (l < cn) {
                         const int j = a.aci[c0 + l];
@@ -221,7 +221,7 @@ __global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(4, 8))) vo
                         st_bs[l] = b0;
                         st_len[l] = (int)(b1 - b0);
                     }
-                    __syncthreads();
+                    wave_lds_sync();
                 }
                 for (int t = g; t < cn; t += ng) {
                     const int64_t bs = st_bs[t];
@@ -241,7 +241,7 @@ __global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(4, 8))) vo
         }
         dcur = dn;
         if (r + sl.step < sl.end) dn = row_desc_w(a.rs.rows[r + sl.step], a.arp, a.rwin, a.coff);
-        __syncthreads();
+        wave_lds_sync();
 
         // ---- touched words in increasing order (summary), prefix counts per slot
         int T = 0;
@@ -260,7 +260,7 @@ __global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(4, 8))) vo
             if (s < d.ns) summ[s] = 0;
             T += __shfl(inc, WAVE - 1);
         }
-        __syncthreads();
+        wave_lds_sync();
         int run = 0;
         for (int r0 = 0; r0 < T; r0 += WAVE) {
             const int rr = r0 + l;
@@ -274,7 +274,7 @@ __global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(4, 8))) vo
         const bool ok = (d.ce - d.cb == rnnz) && rnnz <= a.r_max && T <= tm;
         if (l == 0 && !ok) atomicAdd(&a.st->mismatch, 1);
         for (int t = l; t < min(rnnz, a.r_max); t += WAVE) vals[t] = A::zero();
-        __syncthreads();
+        wave_lds_sync();
 
         // ---- products into vals[rank]
         if (ok) {
@@ -290,7 +290,7 @@ __global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(4, 8))) vo
                 }
             } else {
                 for (int64_t c0 = d.ab; c0 < d.ae; c0 += WAVE) {
-                    __syncthreads();
+                    wave_lds_sync();
                     cn = (int)min((int64_t)WAVE, d.ae - c0);
                     if (l < cn) {
                         const int j = a.aci[c0 + l];
@@ -299,7 +299,7 @@ __global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(4, 8))) vo
                         st_len[l] = (int)(b1 - b0);
                         st_a[l] = (double)a.aval[c0 + l];
                     }
-                    __syncthreads();
+                    wave_lds_sync();
                     for (int t = g; t < cn; t += ng) {
                         const int64_t bs = st_bs[t];
                         const int len = st_len[t];
@@ -315,7 +315,7 @@ __global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(4, 8))) vo
                 }
             }
         }
-        __syncthreads();
+        wave_lds_sync();
 
         // ---- sorted columns, table reset
         for (int t = l; t < min(T, tm); t += WAVE) {
@@ -340,7 +340,7 @@ __global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(4, 8))) vo
                 tbp[s] = 0ull;
             }
         }
-        __syncthreads();
+        wave_lds_sync();
         if (ok) {
             const int64_t ob = d.cb - cbase;
             for (int t = l; t < rnnz; t += WAVE) {
@@ -348,7 +348,7 @@ __global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(4, 8))) vo
                 a.cval[ob + t] = A::fin(vals[t]);
             }
         }
-        __syncthreads();
+        wave_lds_sync();
     }
 }
 

@@ -156,3 +156,25 @@ def test_backward_finite_differences_and_autograd():
     rdA, rdB = oracle.grad(A, B, C, G.cpu().numpy())
     assert np.allclose(a.grad.cpu().numpy(), rdA, rtol=1e-12, atol=1e-12)
     assert np.allclose(b.grad.cpu().numpy(), rdB, rtol=1e-12, atol=1e-12)
+
+
+def test_fp32_heaviest_rows_in_fp64():
+    """Rows at or above the flop threshold accumulate in FP64 (error about one rounding of the
+    result); the rest keep plain FP32 accumulation."""
+    rng = np.random.default_rng(17)
+    counts = rng.integers(1, 8, 400)
+    counts[[3, 200, 399]] = [300, 250, 400]
+    A = synth.random_csr(400, 500, counts, 2)
+    B = synth.random_csr(500, 800, rng.integers(1, 25, 500), 3)
+    A32, B32 = f32_inputs(A), f32_inputs(B)
+    ref, S = oracle_ref(A32, B32)
+    thr = 2000
+    got, h = run(A, B, dtype="f32", fp32_mode=0, fp64_heavy_row_flops=thr)
+    check_f32(ref, S, got)
+    fl = oracle.flops(A32, B32)[2]
+    heavy = np.nonzero(fl >= thr)[0]
+    assert heavy.size >= 3
+    err = np.abs(got[2].astype(np.float64) - ref.values)
+    for i in heavy:
+        s, e = ref.row_ptr[i], ref.row_ptr[i + 1]
+        assert np.all(err[s:e] <= U32 * np.abs(ref.values[s:e]) + 1e-12 * S[s:e])
