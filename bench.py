@@ -29,6 +29,11 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBPS = 8000.0
 
 
+# numeric kernel that processes each row kind
+KERNEL_OF_KIND = {"empty": "none", "dense_wave": "k_num_dw", "hash_wave": "k_num_hw", "dense_wg": "k_num_dg",
+                  "hash_two_level": "k_num_hl", "word_hash_wave": "k_num_wh", "short_rows": "k_sr"}
+
+
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
@@ -191,11 +196,12 @@ def main():
 
     # roofline: numeric kernel of A*A (one launch on `stream`), HIP events per launch
     dom = phases["AxA"]
+    dom_kind = max(dom["rows_numeric"].items(), key=lambda kv: kv[1])[0]
     t_dom = dom["numeric_ms"] * 1e-3
     achieved = dom["numeric_alg_bytes"] / t_dom / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": None,
-                "kernel": "k_num_dw<double> (27-point A*A, FP64)",
+                "kernel": f"{KERNEL_OF_KIND[dom_kind]}<double> (27-point A*A, FP64)",
                 "frac_of_measured_copy": round(achieved / copy_gbps, 4)}
 
     cpu = None
@@ -203,7 +209,7 @@ def main():
         import oracle
 
         log("[bench] CPU oracle baseline (full step, sequential C)")
-        reps = 2
+        reps = 5
         t = time.perf_counter()
         for _ in range(reps):
             oracle.spgemm(A, A)

@@ -121,7 +121,10 @@ typedef struct {
     int64_t max_row_nnz;            /* maxrs */
     int64_t nnz_b_compressed;       /* (column-set index, column-set) pairs */
     int32_t compressed;             /* 1 if the symbolic phase used compressed B */
-    int32_t n_kinds;
+    int32_t n_kinds;                /* kinds in use: 0 empty, 1 bit window (wavefront),
+                                       2 hash (wavefront), 3 bit window (workgroup),
+                                       4 two-level hash, 5 word hash (numeric),
+                                       6 short rows (a team of lanes per row) */
     int64_t rows_symbolic[8];       /* rows per symbolic kernel kind */
     int64_t rows_numeric[8];        /* rows per numeric kernel kind */
     int32_t l2_spill_rows;          /* rows that used the level-2 (HBM) hash */

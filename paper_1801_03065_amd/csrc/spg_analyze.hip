@@ -11,6 +11,7 @@ namespace spg {
 namespace {
 
 constexpr int BLK = 256;
+constexpr int CL_GRID = 512;  // classify workgroups (rows per lane grow beyond)
 
 __device__ __forceinline__ unsigned long long ull(long long v) { return (unsigned long long)v; }
 
@@ -130,8 +131,9 @@ __global__ __launch_bounds__(WAVE) void k_brow_unsorted(const int32_t *list, con
 }
 
 // Compressed B for rows with sorted columns: a 16-lane group per row; the
-// first lane of each word run writes the word index, every run tail ORs its
-// partial bit set in (a run may straddle two 16-column chunks).
+// first lane of each word run writes the word index and the last lane of the
+// run its bit set (plain stores).  A run that crosses into the next 16-column
+// chunk carries its partial bits there.
 __global__ __launch_bounds__(BLK) void k_compress_sorted(int64_t n, const int64_t *brp, const int32_t *bci,
                                                           const BRow *bi, const uint8_t *unsorted,
                                                           const int64_t *bcrp, int32_t *bcsi, uint32_t *bcs) {
@@ -143,12 +145,15 @@ __global__ __launch_bounds__(BLK) void k_compress_sorted(int64_t n, const int64_
         const int64_t b = brp[r], e = brp[r + 1];
         const int64_t o0 = bcrp[r];
         int heads_before = 0, prev_last = -1;
+        uint32_t carry = 0;
         for (int64_t c0 = b; c0 < e; c0 += BR_GS) {
             const int64_t idx = c0 + q;
             const bool v = idx < e;
             const int col = v ? bci[idx] : INT_MAX;
             int prevc = __shfl_up(col, 1, BR_GS);
             if (q == 0) prevc = prev_last;
+            int nextc = __shfl_down(col, 1, BR_GS);
+            if (q == BR_GS - 1) nextc = idx + 1 < e ? bci[idx + 1] : INT_MAX;
             const int head = v && ((col >> 5) != (prevc >> 5));
             // inclusive count of heads in this chunk = run id (0 = run from previous chunk)
             int seg = head;
@@ -158,18 +163,20 @@ __global__ __launch_bounds__(BLK) void k_compress_sorted(int64_t n, const int64_
                 if (q >= d) seg += t;
             }
             uint32_t acc = v ? (1u << (col & 31)) : 0u;
+            if (seg == 0) acc |= carry;
 #pragma unroll
             for (int d = 1; d < BR_GS; d <<= 1) {
                 uint32_t t = __shfl_up(acc, d, BR_GS);
                 int ts = __shfl_up(seg, d, BR_GS);
                 if (q >= d && ts == seg) acc |= t;
             }
-            const int nseg = __shfl_down(seg, 1, BR_GS);
-            const bool nvalid = (q + 1 < BR_GS) && (idx + 1 < e);
-            const bool tail = v && (!nvalid || nseg != seg);
+            // the run ends here when the next column is in another word (or there is none)
+            const bool tail = v && (idx + 1 >= e || (nextc >> 5) != (col >> 5));
             const int64_t pos = o0 + heads_before + seg - 1;
             if (head) bcsi[pos] = col >> 5;
-            if (tail) atomicOr(&bcs[pos], acc);
+            if (tail) bcs[pos] = acc;
+            const bool open = v && !tail && q == BR_GS - 1;  // run continues into the next chunk
+            carry = __shfl(open ? acc : 0u, BR_GS - 1, BR_GS);
             heads_before += __shfl(seg, BR_GS - 1, BR_GS);
             prev_last = __shfl(col, BR_GS - 1, BR_GS);
         }
@@ -186,10 +193,12 @@ __global__ __launch_bounds__(BLK) void k_mark_unsorted(const int32_t *list, cons
 // and the word window [min wmin, max wmax] of the B rows it reads.
 constexpr int RI_GS = 8;
 constexpr int RI_U = 4;  // A entries per lane in flight
+constexpr int RI_GRID = 2048;
+static_assert(4 * RI_GRID <= RED_ELEMS && 4 * NK * CL_GRID <= RED_ELEMS, "analysis partials exceed scratch");
 
 __global__ __launch_bounds__(BLK) void k_rowinfo(int64_t m, const int64_t *arp, const int32_t *aci,
                                                   const BRow *bi, int64_t *rflops, int64_t *rflopsc,
-                                                  int2 *rwin, DevStats *st) {
+                                                  int2 *rwin, long long *part) {
     const int q = threadIdx.x & (RI_GS - 1);
     const int64_t g0 = ((int64_t)blockIdx.x * BLK + threadIdx.x) / RI_GS;
     const int64_t ng = (int64_t)gridDim.x * BLK / RI_GS;
@@ -235,7 +244,8 @@ __global__ __launch_bounds__(BLK) void k_rowinfo(int64_t m, const int64_t *arp, 
             s_mxc = max(s_mxc, fc);
         }
     }
-    // one set of global atomics per block (same-address atomics serialise in L2)
+    // per-block partials; k_rowinfo_fin folds them (same-address global
+    // atomics from every block would serialise in L2)
     __shared__ long long red[4][BLK / WAVE];
     s_fm = wave_sum64(s_fm);
     s_fmc = wave_sum64(s_fmc);
@@ -260,6 +270,49 @@ __global__ __launch_bounds__(BLK) void k_rowinfo(int64_t m, const int64_t *arp, 
             c = max(c, red[2][u]);
             d = max(d, red[3][u]);
         }
+        long long *pp = part + 4 * (int64_t)blockIdx.x;
+        pp[0] = a;
+        pp[1] = b;
+        pp[2] = c;
+        pp[3] = d;
+    }
+}
+
+__device__ __forceinline__ long long wave_max64(long long v) {
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) v = max(v, (long long)__shfl_xor(v, d));
+    return v;
+}
+
+// One workgroup: fold the rowinfo partials of nb blocks into the statistics.
+__global__ __launch_bounds__(BLK) void k_rowinfo_fin(int nb, const long long *part, DevStats *st) {
+    long long a = 0, b = 0, c = 0, d = 0;
+    for (int k = threadIdx.x; k < nb; k += BLK) {
+        a += part[4 * k];
+        b += part[4 * k + 1];
+        c = max(c, part[4 * k + 2]);
+        d = max(d, part[4 * k + 3]);
+    }
+    a = wave_sum64(a);
+    b = wave_sum64(b);
+    c = wave_max64(c);
+    d = wave_max64(d);
+    __shared__ long long red[4][BLK / WAVE];
+    const int wv = threadIdx.x / WAVE;
+    if (lane_id() == 0) {
+        red[0][wv] = a;
+        red[1][wv] = b;
+        red[2][wv] = c;
+        red[3][wv] = d;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int u = 1; u < BLK / WAVE; ++u) {
+            a += red[0][u];
+            b += red[1][u];
+            c = max(c, red[2][u]);
+            d = max(d, red[3][u]);
+        }
         if (a) atomicAdd(&st->fm, ull(a));
         if (b) atomicAdd(&st->fmc, ull(b));
         if (c) atomicMax(&st->maxrf, ull(c));
@@ -276,7 +329,7 @@ __global__ __launch_bounds__(BLK) void k_brow_lens(int64_t n, const BRow *bi, in
 __global__ __launch_bounds__(BLK) void k_classify(int64_t m, const int64_t *rflops, const int64_t *rflopsc,
                                                    const int2 *rwin, const int32_t *row_nnz,
                                                    const int32_t *row_words, ClassParams p, uint8_t *kind,
-                                                   int32_t *row_nnz_out, DevStats *st) {
+                                                   int32_t *row_nnz_out, long long *part) {
     __shared__ int smax[NK][3];
     __shared__ long long scnt[NK];
     if (threadIdx.x < NK) {
@@ -322,11 +375,14 @@ __global__ __launch_bounds__(BLK) void k_classify(int64_t m, const int64_t *rflo
                     k = K_HL;
                     break;
                 default:  // selector
-                    if (p.phase == 0)
+                    if (f <= p.sr_f_max)
+                        k = K_SR;
+                    else if (p.phase == 0)
                         k = dw_fit ? K_DW : (hw_fit ? K_HW : (dg_fit ? K_DG : K_HL));
                     else
                         k = wh_fit ? K_WH : (hw_fit ? K_HW : (dg_fit ? K_DG : K_HL));
             }
+            if (k == K_SR) bound = f;  // a short row's team size follows its multiplications
             a = (int)min(nw, (long long)INT_MAX);
             bnd = (int)min(bound, (long long)INT_MAX);
             tw = (int)min(words, (long long)INT_MAX);
@@ -349,18 +405,49 @@ __global__ __launch_bounds__(BLK) void k_classify(int64_t m, const int64_t *rflo
         }
     }
     __syncthreads();
-    // one global update per block and present kind (same-address atomics serialise in L2)
-    if (threadIdx.x < NK && scnt[threadIdx.x]) {
-        int *gm = p.phase == 0 ? &st->kmax_sym[threadIdx.x][0]
-                  : p.heavy     ? &st->kmax_heavy[threadIdx.x][0]
-                                : &st->kmax_num[threadIdx.x][0];
-        atomicMax(gm, smax[threadIdx.x][0]);
-        atomicMax(gm + 1, smax[threadIdx.x][1]);
-        atomicMax(gm + 2, smax[threadIdx.x][2]);
-        long long *gc = p.phase == 0 ? &st->kcount_sym[threadIdx.x]
-                        : p.heavy    ? &st->kcount_heavy[threadIdx.x]
-                                     : &st->kcount_num[threadIdx.x];
-        atomicAdd((unsigned long long *)gc, (unsigned long long)scnt[threadIdx.x]);
+    // per-block partials, folded by k_classify_fin
+    if (threadIdx.x < NK) {
+        long long *pp = part + 4 * ((int64_t)blockIdx.x * NK + threadIdx.x);
+        pp[0] = smax[threadIdx.x][0];
+        pp[1] = smax[threadIdx.x][1];
+        pp[2] = smax[threadIdx.x][2];
+        pp[3] = scnt[threadIdx.x];
+    }
+}
+
+// One workgroup: fold the classify partials of nb blocks into the per-kind
+// counts and maxima of the phase (only kinds that have rows are touched).
+__global__ __launch_bounds__(BLK) void k_classify_fin(int nb, const long long *part, int phase, int heavy,
+                                                       DevStats *st) {
+    __shared__ long long red[NK * 4][BLK / WAVE];
+    const int wv = threadIdx.x / WAVE;
+    for (int f = 0; f < NK * 4; ++f) {
+        long long v = 0;
+        for (int k = threadIdx.x; k < nb; k += BLK) {
+            const long long x = part[4 * ((int64_t)k * NK) + f];
+            v = (f & 3) == 3 ? v + x : max(v, x);
+        }
+        v = (f & 3) == 3 ? wave_sum64(v) : wave_max64(v);
+        if (lane_id() == 0) red[f][wv] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < NK) {
+        const int kk = threadIdx.x;
+        long long m0 = 0, m1 = 0, m2 = 0, c = 0;
+        for (int u = 0; u < BLK / WAVE; ++u) {
+            m0 = max(m0, red[4 * kk][u]);
+            m1 = max(m1, red[4 * kk + 1][u]);
+            m2 = max(m2, red[4 * kk + 2][u]);
+            c += red[4 * kk + 3][u];
+        }
+        if (c) {
+            int *gm = phase == 0 ? &st->kmax_sym[kk][0] : heavy ? &st->kmax_heavy[kk][0] : &st->kmax_num[kk][0];
+            atomicMax(gm, (int)m0);
+            atomicMax(gm + 1, (int)m1);
+            atomicMax(gm + 2, (int)m2);
+            long long *gc = phase == 0 ? &st->kcount_sym[kk] : heavy ? &st->kcount_heavy[kk] : &st->kcount_num[kk];
+            atomicAdd((unsigned long long *)gc, (unsigned long long)c);
+        }
     }
 }
 
@@ -589,10 +676,11 @@ hipError_t launch_compress_sorted_flags(int64_t n, const int64_t *brp, const int
 }
 
 hipError_t launch_rowinfo(int64_t m, const int64_t *arp, const int32_t *aci, const BRow *bi, int64_t *rflops,
-                          int64_t *rflopsc, int2 *rwin, DevStats *st, hipStream_t s) {
+                          int64_t *rflopsc, int2 *rwin, DevStats *st, long long *part, hipStream_t s) {
     if (m == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_rowinfo, dim3(grid_for(m * RI_GS, BLK, 2048)), dim3(BLK), 0, s, m, arp, aci, bi, rflops,
-                       rflopsc, rwin, st);
+    const int g = grid_for(m * RI_GS, BLK, RI_GRID);
+    hipLaunchKernelGGL(k_rowinfo, dim3(g), dim3(BLK), 0, s, m, arp, aci, bi, rflops, rflopsc, rwin, part);
+    hipLaunchKernelGGL(k_rowinfo_fin, dim3(1), dim3(BLK), 0, s, g, (const long long *)part, st);
     return hipGetLastError();
 }
 
@@ -635,10 +723,12 @@ hipError_t launch_store_rp(int64_t n1, const int64_t *src, void *dst, int is64, 
 
 hipError_t launch_classify(int64_t m, const int64_t *rflops, const int64_t *rflopsc, const int2 *rwin,
                            const int32_t *row_nnz, const int32_t *row_words, ClassParams p, uint8_t *kind,
-                           int32_t *row_nnz_out, DevStats *st, hipStream_t s) {
+                           int32_t *row_nnz_out, DevStats *st, long long *part, hipStream_t s) {
     if (m == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_classify, dim3(grid_for(m, BLK, 512)), dim3(BLK), 0, s, m, rflops, rflopsc, rwin,
-                       row_nnz, row_words, p, kind, row_nnz_out, st);
+    const int g = grid_for(m, BLK, CL_GRID);
+    hipLaunchKernelGGL(k_classify, dim3(g), dim3(BLK), 0, s, m, rflops, rflopsc, rwin, row_nnz, row_words, p, kind,
+                       row_nnz_out, part);
+    hipLaunchKernelGGL(k_classify_fin, dim3(1), dim3(BLK), 0, s, g, (const long long *)part, p.phase, p.heavy, st);
     return hipGetLastError();
 }
 

@@ -55,7 +55,7 @@ struct spg_handle_s {
     spg_stats stats{};
 
     DevBuf arp64, brp64, binfo, ulist, uflag, bcrp, bcsi, bcs, rflops, rflopsc, rwin, row_nnz, coff, kind_sym,
-        kind_num, perm_sym, perm_num, koff_sym, koff_num, tmp, dstats, queue, arena, l2k, l2v, blens, row_words;
+        kind_num, perm_sym, perm_num, koff_sym, koff_num, tmp, dstats, red, queue, arena, l2k, l2v, blens, row_words;
     size_t arena_bytes_zeroed = 0;
     const int32_t *aci_used = nullptr, *bci_used = nullptr;  // column arrays the kernels read
     ClassParams cparams{};                                   // classification of the last symbolic phase
@@ -112,6 +112,14 @@ void release(DevBuf &b) {
     if (b.p) (void)hipFree(b.p);
     b.p = nullptr;
     b.cap = 0;
+}
+
+// Team size of the short-row kernel: the smallest power of two >= the largest
+// multiplication count among its rows, at least 8 lanes.
+static int sr_lg(int max_flops) {
+    int lg = 3;
+    while ((1 << lg) < max_flops && lg < 6) ++lg;
+    return lg;
 }
 
 int lg_group(double avg) {
@@ -223,6 +231,7 @@ spg_status spg_create(spg_handle *out, void *stream, const spg_options *opt) {
     if (e == hipSuccess) e = hipHostMalloc((void **)&h->hst, sizeof(DevStats), hipHostMallocDefault);
     if (e == hipSuccess) e = hipHostMalloc((void **)&h->hkoff, sizeof(int64_t) * (2 * (NK + 1) + 2), hipHostMallocDefault);
     if (e == hipSuccess) e = ensure(h->dstats, sizeof(DevStats));
+    if (e == hipSuccess) e = ensure(h->red, sizeof(long long) * RED_ELEMS);
     if (e == hipSuccess) e = ensure(h->queue, sizeof(int32_t) * XCDS * NK);
     if (e != hipSuccess) {
         spg_destroy(h);
@@ -244,7 +253,7 @@ spg_status spg_destroy(spg_handle h) {
     (void)hipStreamSynchronize(h->stream);
     DevBuf *bufs[] = {&h->arp64, &h->brp64, &h->binfo, &h->ulist, &h->uflag, &h->bcrp, &h->bcsi, &h->bcs,
                       &h->rflops, &h->rflopsc, &h->rwin, &h->row_nnz, &h->coff, &h->kind_sym, &h->kind_num,
-                      &h->perm_sym, &h->perm_num, &h->koff_sym, &h->koff_num, &h->tmp, &h->dstats, &h->queue,
+                      &h->perm_sym, &h->perm_num, &h->koff_sym, &h->koff_num, &h->tmp, &h->dstats, &h->red, &h->queue,
                       &h->arena, &h->l2k, &h->l2v, &h->blens, &h->row_words, &h->kind_tmp, &h->perm_tmp, &h->koff_tmp, &h->krange, &h->kind_heavy, &h->perm_heavy, &h->koff_heavy, &h->krange_heavy};
     for (DevBuf *b : bufs) release(*b);
     if (h->hst) (void)hipHostFree(h->hst);
@@ -328,7 +337,7 @@ static spg_status symbolic_core(spg_handle h, int64_t m, int64_t n, int64_t nnza
     HIPCHK(launch_brow(n, brp, bci, bi, h->ulist.as<int32_t>(), dst, st));
     HIPCHK(launch_brow_unsorted(h->ulist.as<int32_t>(), &dst->unsorted, brp, bci, bi, dst, st));
     HIPCHK(launch_rowinfo(m, arp, aci, bi, h->rflops.as<int64_t>(), h->rflopsc.as<int64_t>(),
-                          h->rwin.as<int2>(), dst, st));
+                          h->rwin.as<int2>(), dst, h->red.as<long long>(), st));
     if ((s = pull_stats(h)) != SPG_OK) return s;  // host sync 1: flop counts
     const DevStats hs1 = *h->hst;
     if (hs1.bad_window)
@@ -348,7 +357,6 @@ static spg_status symbolic_core(spg_handle h, int64_t m, int64_t n, int64_t nnza
         HIPCHK(launch_scan_i64(n, h->blens.as<int64_t>(), h->bcrp.as<int64_t>(), h->tmp.as<int64_t>(), st));
         HIPCHK(ensure(h->bcsi, 4 * std::max<int64_t>(nnzb, 1)));
         HIPCHK(ensure(h->bcs, 4 * std::max<int64_t>(nnzb, 1)));
-        HIPCHK(hipMemsetAsync(h->bcs.p, 0, 4 * std::max<int64_t>(nnzb, 1), st));
         HIPCHK(hipMemsetAsync(h->uflag.p, 0, std::max<int64_t>(n, 1), st));
         HIPCHK(launch_mark_unsorted(h->ulist.as<int32_t>(), &dst->unsorted, h->uflag.as<uint8_t>(), st));
         HIPCHK(launch_compress_sorted_flags(n, brp, bci, bi, h->uflag.as<uint8_t>(), h->bcrp.as<int64_t>(),
@@ -369,9 +377,10 @@ static spg_status symbolic_core(spg_handle h, int64_t m, int64_t n, int64_t nnza
     cp.wh_r_max = WH_R_MAX;
     cp.wh_t_max = WH_T_MAX;
     cp.sample_stride = 1;
+    cp.sr_f_max = SR_F_MAX;
     HIPCHK(hipMemsetAsync(h->row_words.p, 0, 4 * std::max<int64_t>(m, 1), st));
     HIPCHK(launch_classify(m, h->rflops.as<int64_t>(), h->rflopsc.as<int64_t>(), h->rwin.as<int2>(), nullptr,
-                           nullptr, cp, h->kind_sym.as<uint8_t>(), h->row_nnz.as<int32_t>(), dst, st));
+                           nullptr, cp, h->kind_sym.as<uint8_t>(), h->row_nnz.as<int32_t>(), dst, h->red.as<long long>(), st));
     HIPCHK(launch_partition(m, h->kind_sym.as<uint8_t>(), h->perm_sym.as<int32_t>(), h->koff_sym.as<int64_t>(),
                             h->tmp.as<int64_t>(), st));
     if ((s = pull_stats(h)) != SPG_OK) return s;  // host sync 2: per-kind sizes
@@ -397,6 +406,11 @@ static spg_status symbolic_core(spg_handle h, int64_t m, int64_t n, int64_t nnza
     LaunchCfg lc{st, 0, h->cus};
     auto grid_cap = [&](int64_t rows) { return (int)std::min<int64_t>(2048 * 8, ((rows + 7) / 8) * 8); };
 
+    if (hs2.kcount_sym[K_SR] > 0) {
+        sa.rs.kind = K_SR;
+        lc.grid = 0;
+        HIPCHK(launch_sym_sr(sa, sr_lg(hs2.kmax_sym[K_SR][1]), lc, hs2.kcount_sym[K_SR]));
+    }
     if (hs2.kcount_sym[K_DW] > 0) {
         sa.rs.kind = K_DW;
         sa.nw_max = ((hs2.kmax_sym[K_DW][0] + 31) / 32) * 32;
@@ -443,7 +457,7 @@ static spg_status symbolic_core(spg_handle h, int64_t m, int64_t n, int64_t nnza
     cp.flops_hi = thr > 0 ? thr : 0;
     HIPCHK(launch_classify(m, h->rflops.as<int64_t>(), h->rflopsc.as<int64_t>(), h->rwin.as<int2>(),
                            h->row_nnz.as<int32_t>(), h->row_words.as<int32_t>(), cp, h->kind_num.as<uint8_t>(),
-                           nullptr, dst, st));
+                           nullptr, dst, h->red.as<long long>(), st));
     HIPCHK(launch_partition(m, h->kind_num.as<uint8_t>(), h->perm_num.as<int32_t>(), h->koff_num.as<int64_t>(),
                             h->tmp.as<int64_t>(), st));
     if (thr > 0) {  // rows at or above the threshold: their own kind lists (FP64 accumulation in FP32 mode)
@@ -456,7 +470,7 @@ static spg_status symbolic_core(spg_handle h, int64_t m, int64_t n, int64_t nnza
         ch.heavy = 1;
         HIPCHK(launch_classify(m, h->rflops.as<int64_t>(), h->rflopsc.as<int64_t>(), h->rwin.as<int2>(),
                                h->row_nnz.as<int32_t>(), h->row_words.as<int32_t>(), ch,
-                               h->kind_heavy.as<uint8_t>(), nullptr, dst, st));
+                               h->kind_heavy.as<uint8_t>(), nullptr, dst, h->red.as<long long>(), st));
         HIPCHK(launch_partition(m, h->kind_heavy.as<uint8_t>(), h->perm_heavy.as<int32_t>(),
                                 h->koff_heavy.as<int64_t>(), h->tmp.as<int64_t>(), st));
     }
@@ -557,6 +571,10 @@ static spg_status launch_kinds(spg_handle h, NumArgs<VT> na, const long long *kc
     LaunchCfg lc{st, 0, h->cus};
     auto grid_cap = [&](int64_t rows) { return (int)std::min<int64_t>(2048 * 8, ((rows + 7) / 8) * 8); };
 
+    if (kcount[K_SR] > 0) {
+        na.rs.kind = K_SR;
+        HIPCHK(launch_num_sr<VT>(na, acc, sr_lg(kmax[K_SR][1]), lc, kcount[K_SR]));
+    }
     if (kcount[K_DW] > 0) {
         na.rs.kind = K_DW;
         na.nw_max = ((kmax[K_DW][0] + 31) / 32) * 32;
@@ -644,7 +662,7 @@ static spg_status autotune(spg_handle h, NumArgs<VT> na, int acc) {
         HIPCHK(hipMemsetAsync(&dst->kmax_num[0][0], 0, sizeof(dst->kmax_num), st));
         HIPCHK(launch_classify(m, h->rflops.as<int64_t>(), h->rflopsc.as<int64_t>(), h->rwin.as<int2>(),
                                h->row_nnz.as<int32_t>(), h->row_words.as<int32_t>(), cp, h->kind_tmp.as<uint8_t>(),
-                               nullptr, dst, st));
+                               nullptr, dst, h->red.as<long long>(), st));
         HIPCHK(launch_partition(m, h->kind_tmp.as<uint8_t>(), h->perm_tmp.as<int32_t>(), h->koff_tmp.as<int64_t>(),
                                 h->tmp.as<int64_t>(), st));
         if ((s = pull_stats(h)) != SPG_OK) break;
@@ -677,7 +695,7 @@ static spg_status autotune(spg_handle h, NumArgs<VT> na, int acc) {
     HIPCHK(hipMemsetAsync(&dst->kmax_num[0][0], 0, sizeof(dst->kmax_num), st));
     HIPCHK(launch_classify(m, h->rflops.as<int64_t>(), h->rflopsc.as<int64_t>(), h->rwin.as<int2>(),
                            h->row_nnz.as<int32_t>(), h->row_words.as<int32_t>(), cp, h->kind_num.as<uint8_t>(),
-                           nullptr, dst, st));
+                           nullptr, dst, h->red.as<long long>(), st));
     HIPCHK(launch_partition(m, h->kind_num.as<uint8_t>(), h->perm_num.as<int32_t>(), h->koff_num.as<int64_t>(),
                             h->tmp.as<int64_t>(), st));
     if ((s = pull_stats(h)) != SPG_OK) return s;

@@ -27,7 +27,8 @@ enum Kind : int {
     K_DG = 3,     // bit-window dense accumulator, one 256-lane workgroup per row, values in HBM
     K_HL = 4,     // two-level hash: LDS level 1 + HBM level 2, one workgroup per row
     K_WH = 5,     // word hash + ordered summary, one wavefront per row (numeric)
-    NK = 6
+    K_SR = 6,     // short rows: a team of T <= 64 lanes per row, several rows per wavefront
+    NK = 7
 };
 
 // Global counters written by the analysis kernels (zeroed per symbolic call).
@@ -55,6 +56,7 @@ constexpr int DG_NW_MAX = 32768;  // window words of the workgroup dense kernel 
 constexpr int WH_NW_MAX = 32768;  // window words of the word-hash kernel (summary of 1024 words)
 constexpr int WH_R_MAX = 1024;    // row size of the word-hash kernel
 constexpr int WH_T_MAX = 512;     // touched words of the word-hash kernel (table 2x)
+constexpr int SR_F_MAX = 64;      // multiplications of a short row (one per lane of its team)
 
 // ------------------------------------------------------------ argument blocks
 struct RowSet {
@@ -204,6 +206,14 @@ __device__ __forceinline__ int mbcnt(unsigned long long m) {
 }
 __device__ __forceinline__ int read_first(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
+// Load base[idx] with a 32-bit byte offset (idx * sizeof(T) < 2^32): the
+// compiler then addresses with the base in SGPRs plus one 32-bit VGPR offset
+// (one shift per gathered element instead of 64-bit address arithmetic).
+template <typename T>
+__device__ __forceinline__ T ld32(const T *base, uint32_t idx) {
+    return *(const T *)((const char *)base + (uint32_t)(idx * (uint32_t)sizeof(T)));
+}
+
 // LDS hand-off between the lanes of a one-wavefront workgroup: wait for this
 // wavefront's outstanding LDS operations only (lgkmcnt(0); vector-memory loads
 // stay in flight) and keep the compiler from moving memory operations across.
@@ -268,8 +278,12 @@ hipError_t launch_mark_unsorted(const int32_t *list, const int *count, uint8_t *
 hipError_t launch_compress_unsorted(const int32_t *list, const int *count, const int64_t *brp,
                                     const int32_t *bci, const BRow *bi, const int64_t *bcrp, int32_t *bcsi,
                                     uint32_t *bcs, hipStream_t s);
+// Per-block partials of the analysis reductions (rowinfo, classify), folded
+// by a one-workgroup kernel: RED_ELEMS int64 of device scratch.
+constexpr int RED_ELEMS = 16384;
 hipError_t launch_rowinfo(int64_t m, const int64_t *arp, const int32_t *aci, const BRow *bi,
-                          int64_t *rflops, int64_t *rflopsc, int2 *rwin, DevStats *st, hipStream_t s);
+                          int64_t *rflops, int64_t *rflopsc, int2 *rwin, DevStats *st, long long *part,
+                          hipStream_t s);
 hipError_t launch_copy_rp(int64_t n1, const void *src, int is64, int64_t nnz, int64_t *dst, int *bad,
                           hipStream_t s);
 hipError_t launch_check_cols(int64_t nnz, const int32_t *ci, int64_t ncols, int *bad, hipStream_t s);
@@ -291,10 +305,11 @@ struct ClassParams {
     int sample_stride;  // numeric: only rows i with i % stride == 0 get a kind (others: empty)
     long long flops_lo, flops_hi;  // numeric: only rows with flops in [lo, hi) get a kind (hi <= 0: no limit)
     int heavy;          // numeric: counts / maxima go to the heavy-row set
+    int sr_f_max;       // selector: rows with at most this many multiplications are short rows (0: off)
 };
 hipError_t launch_classify(int64_t m, const int64_t *rflops, const int64_t *rflopsc, const int2 *rwin,
                            const int32_t *row_nnz, const int32_t *row_words, ClassParams p, uint8_t *kind,
-                           int32_t *row_nnz_out, DevStats *st, hipStream_t s);
+                           int32_t *row_nnz_out, DevStats *st, long long *part, hipStream_t s);
 int64_t part_tmp_elems(int64_t m);
 hipError_t launch_partition(int64_t m, const uint8_t *kind, int32_t *perm, int64_t *koff, int64_t *tmp,
                             hipStream_t s);
@@ -307,6 +322,8 @@ hipError_t launch_sym_dw(const SymArgs &a, const LaunchCfg &c);
 hipError_t launch_sym_hw(const SymArgs &a, const LaunchCfg &c);
 hipError_t launch_sym_dg(const SymArgs &a, const LaunchCfg &c);
 hipError_t launch_sym_hl(const SymArgs &a, const LaunchCfg &c);
+// Short rows: teams of 2^lg_t lanes; rows = number of rows in the kind (grid sizing).
+hipError_t launch_sym_sr(const SymArgs &a, int lg_t, const LaunchCfg &c, int64_t rows);
 
 // acc: 0 native, 1 compensated pair (FP32), 2 FP64 accumulation (FP32)
 template <typename VT>
@@ -319,6 +336,8 @@ template <typename VT>
 hipError_t launch_num_hl(const NumArgs<VT> &a, int acc, const LaunchCfg &c);
 template <typename VT>
 hipError_t launch_num_wh(const NumArgs<VT> &a, int acc, const LaunchCfg &c);
+template <typename VT>
+hipError_t launch_num_sr(const NumArgs<VT> &a, int acc, int lg_t, const LaunchCfg &c, int64_t rows);
 size_t lds_num_wh(int ts, int nw_max, int r_max, int acc_bytes);
 template <typename VT>
 hipError_t launch_backward(const BwdArgs<VT> &a, const LaunchCfg &c);

@@ -9,7 +9,7 @@ import pytest
 
 import oracle
 import synth
-from helpers import check_f64, check_structure, oracle_ref, run
+from helpers import check_f32, check_f64, check_structure, f32_inputs, oracle_ref, run
 
 pytestmark = pytest.mark.gpu
 
@@ -35,8 +35,13 @@ def test_27pt_square_small(g, acc):
     A = synth.stencil27(g)
     h = _exact(A, A, accumulator=acc, l1_hash_slots=64 if acc == 3 else 0)
     used = {k for k, v in h.stats()["rows_numeric"].items() if v}
-    want = {0: "word_hash_wave", 1: "dense_wave", 2: "hash_wave", 3: "hash_two_level"}[acc]
-    assert used == {want}, used
+    if acc == 0:
+        # at g = 2 every row has 8 * 8 = 64 multiplications (short-row teams);
+        # from g = 3 on even a corner row has 125 (word hash)
+        assert used == ({"short_rows"} if g == 2 else {"word_hash_wave"}), used
+    else:
+        want = {1: "dense_wave", 2: "hash_wave", 3: "hash_two_level"}[acc]
+        assert used == {want}, used
 
 
 @pytest.mark.parametrize("g", [4, 10])
@@ -181,3 +186,58 @@ def test_heavy_rows_window_away_from_zero():
     got, h = run(A, B)
     check_f64(ref, S, got)
     assert h.stats()["rows_numeric"]["dense_wg"] >= 2
+
+
+@pytest.mark.parametrize("fmax", [4, 12, 30, 64])
+def test_short_rows_teams(fmax):
+    """Rows with at most 64 multiplications: several rows per wavefront, team
+    size the next power of two of the largest row (8 to 64 lanes)."""
+    rng = np.random.default_rng(fmax)
+    m, n, k = 3000, 900, 2500
+    nb = rng.integers(0, 5, n)
+    B = synth.shuffle_columns(synth.random_csr(n, k, nb, 31), 3)
+    A = synth.random_csr(m, n, rng.integers(0, 12, m), 32)
+    # keep entries of each row of A while its multiplications stay within fmax
+    lens = np.diff(B.row_ptr)
+    rp, ci, va = [0], [], []
+    for i in range(m):
+        tot = 0
+        for e in range(A.row_ptr[i], A.row_ptr[i + 1]):
+            if tot + lens[A.col_idx[e]] <= fmax:
+                ci.append(A.col_idx[e])
+                va.append(A.values[e])
+                tot += lens[A.col_idx[e]]
+        rp.append(len(ci))
+    A = synth.Csr(m, n, np.array(rp, np.int64), np.array(ci, np.int32), np.array(va))
+    ref, S = oracle_ref(A, B)
+    got, h = run(A, B)
+    check_f64(ref, S, got)
+    st = h.stats()
+    assert st["rows_numeric"]["short_rows"] > 0 and st["rows_symbolic"]["short_rows"] > 0
+    assert st["max_row_flops"] <= fmax
+
+
+def test_short_rows_many_empty_b_rows():
+    """Short rows whose A row is longer than the team (most B rows are empty):
+    the team walks its A row in chunks."""
+    rng = np.random.default_rng(5)
+    n, k = 4000, 700
+    nb = np.where(rng.random(n) < 0.1, rng.integers(1, 3, n), 0)
+    B = synth.random_csr(n, k, nb, 41)
+    A = synth.random_csr(400, n, rng.integers(60, 200, 400), 42)
+    fl = oracle.flops(A, B)[2]
+    ref, S = oracle_ref(A, B)
+    got, h = run(A, B)
+    check_f64(ref, S, got)
+    assert h.stats()["rows_numeric"]["short_rows"] == int(np.count_nonzero((fl > 0) & (fl <= 64)))
+
+
+@pytest.mark.parametrize("mode", [0, 1, 2])
+def test_short_rows_fp32(mode):
+    A = synth.stencil27(6)
+    P, _ = synth.aggregation_2x2x2(6)
+    A32, P32 = f32_inputs(A), f32_inputs(P)
+    ref, S = oracle_ref(A32, P32)
+    got, h = run(A, P, dtype="f32", fp32_mode=mode)
+    check_f32(ref, S, got)
+    assert set(k for k, v in h.stats()["rows_numeric"].items() if v) == {"short_rows"}
