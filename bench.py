@@ -31,7 +31,8 @@ HBM_PEAK_GBPS = 8000.0
 
 # numeric kernel that processes each row kind
 KERNEL_OF_KIND = {"empty": "none", "dense_wave": "k_num_dw", "hash_wave": "k_num_hw", "dense_wg": "k_num_dg",
-                  "hash_two_level": "k_num_hl", "word_hash_wave": "k_num_wh", "short_rows": "k_sr"}
+                  "hash_two_level": "k_num_hl", "word_hash_wave": "k_num_wh", "short_rows": "k_sr",
+                  "planned_wave": "k_num_pl"}
 
 
 def log(msg):

@@ -48,7 +48,8 @@ SPG_F64, SPG_F32 = 0, 1
 SPG_I32, SPG_I64 = 0, 1
 ACC_AUTO, ACC_DENSE, ACC_HASH, ACC_HASH_L2 = 0, 1, 2, 3
 FP32_PLAIN, FP32_COMPENSATED, FP32_WIDE = 0, 1, 2
-KIND_NAMES = ("empty", "dense_wave", "hash_wave", "dense_wg", "hash_two_level", "word_hash_wave", "short_rows")
+KIND_NAMES = ("empty", "dense_wave", "hash_wave", "dense_wg", "hash_two_level", "word_hash_wave", "short_rows",
+              "planned_wave")
 
 
 class spg_csr(ctypes.Structure):

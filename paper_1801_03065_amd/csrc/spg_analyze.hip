@@ -379,15 +379,20 @@ __global__ __launch_bounds__(BLK) void k_classify(int64_t m, const int64_t *rflo
                         k = K_SR;
                     else if (p.phase == 0)
                         k = dw_fit ? K_DW : (hw_fit ? K_HW : (dg_fit ? K_DG : K_HL));
+                    else if (p.plan_cap > 0 && p.sym_kind[i] == K_DW && words <= p.plan_len[i] &&
+                             nw <= PL_NW_MAX && bound <= PL_R_MAX)
+                        k = K_PL;  // the symbolic phase stored this row's structure
                     else
                         k = wh_fit ? K_WH : (hw_fit ? K_HW : (dg_fit ? K_DG : K_HL));
             }
+            if (p.phase == 0 && p.plan_len) p.plan_len[i] = k == K_DW ? (int)min(words, (long long)p.plan_cap) : 0;
             if (k == K_SR) bound = f;  // a short row's team size follows its multiplications
             a = (int)min(nw, (long long)INT_MAX);
             bnd = (int)min(bound, (long long)INT_MAX);
             tw = (int)min(words, (long long)INT_MAX);
         } else if (valid && p.phase == 0) {
             row_nnz_out[i] = 0;
+            if (p.plan_len) p.plan_len[i] = 0;
         }
         if (valid) kind[i] = (uint8_t)k;
         // aggregate over the wavefront per kind, then one LDS atomic per kind

@@ -51,11 +51,12 @@ struct spg_handle_s {
     bool compressed = false;
     double avg_len = 1, avg_len_c = 1;  // B entries (raw / compressed) read per A entry
     DevStats *hst = nullptr;            // pinned host copy of the device counters
-    int64_t *hkoff = nullptr;           // pinned: koff_sym[NK+1], koff_num[NK+1], nnzc
+    int64_t *hkoff = nullptr;           // pinned: [0] nnz(C), [1] stored-structure pairs
+    bool planned = false;               // the symbolic phase stored row structure (K_PL rows)
     spg_stats stats{};
 
     DevBuf arp64, brp64, binfo, ulist, uflag, bcrp, bcsi, bcs, rflops, rflopsc, rwin, row_nnz, coff, kind_sym,
-        kind_num, perm_sym, perm_num, koff_sym, koff_num, tmp, dstats, red, queue, arena, l2k, l2v, blens, row_words;
+        kind_num, perm_sym, perm_num, koff_sym, koff_num, tmp, dstats, red, queue, plan_len, plan_off, plan, arena, l2k, l2v, blens, row_words;
     size_t arena_bytes_zeroed = 0;
     const int32_t *aci_used = nullptr, *bci_used = nullptr;  // column arrays the kernels read
     ClassParams cparams{};                                   // classification of the last symbolic phase
@@ -253,7 +254,7 @@ spg_status spg_destroy(spg_handle h) {
     (void)hipStreamSynchronize(h->stream);
     DevBuf *bufs[] = {&h->arp64, &h->brp64, &h->binfo, &h->ulist, &h->uflag, &h->bcrp, &h->bcsi, &h->bcs,
                       &h->rflops, &h->rflopsc, &h->rwin, &h->row_nnz, &h->coff, &h->kind_sym, &h->kind_num,
-                      &h->perm_sym, &h->perm_num, &h->koff_sym, &h->koff_num, &h->tmp, &h->dstats, &h->red, &h->queue,
+                      &h->perm_sym, &h->perm_num, &h->koff_sym, &h->koff_num, &h->tmp, &h->dstats, &h->red, &h->queue, &h->plan_len, &h->plan_off, &h->plan,
                       &h->arena, &h->l2k, &h->l2v, &h->blens, &h->row_words, &h->kind_tmp, &h->perm_tmp, &h->koff_tmp, &h->krange, &h->kind_heavy, &h->perm_heavy, &h->koff_heavy, &h->krange_heavy};
     for (DevBuf *b : bufs) release(*b);
     if (h->hst) (void)hipHostFree(h->hst);
@@ -378,13 +379,34 @@ static spg_status symbolic_core(spg_handle h, int64_t m, int64_t n, int64_t nnza
     cp.wh_t_max = WH_T_MAX;
     cp.sample_stride = 1;
     cp.sr_f_max = SR_F_MAX;
+    // stored row structure: bit-window rows keep their (word, bits) pairs for
+    // the numeric phase (selector only)
+    const bool want_plan = h->opt.accumulator == SPG_ACC_AUTO;
+    if (want_plan) {
+        HIPCHK(ensure(h->plan_len, 4 * std::max<int64_t>(m, 1)));
+        HIPCHK(ensure(h->plan_off, 8 * (m + 1)));
+        cp.plan_cap = PL_CAP;
+        cp.plan_len = h->plan_len.as<int32_t>();
+    }
     HIPCHK(hipMemsetAsync(h->row_words.p, 0, 4 * std::max<int64_t>(m, 1), st));
     HIPCHK(launch_classify(m, h->rflops.as<int64_t>(), h->rflopsc.as<int64_t>(), h->rwin.as<int2>(), nullptr,
                            nullptr, cp, h->kind_sym.as<uint8_t>(), h->row_nnz.as<int32_t>(), dst, h->red.as<long long>(), st));
     HIPCHK(launch_partition(m, h->kind_sym.as<uint8_t>(), h->perm_sym.as<int32_t>(), h->koff_sym.as<int64_t>(),
                             h->tmp.as<int64_t>(), st));
-    if ((s = pull_stats(h)) != SPG_OK) return s;  // host sync 2: per-kind sizes
+    if (want_plan) {
+        HIPCHK(launch_scan_i32(m, h->plan_len.as<int32_t>(), h->plan_off.as<int64_t>(), h->tmp.as<int64_t>(), st));
+        HIPCHK(hipMemcpyAsync(h->hkoff + 1, h->plan_off.as<int64_t>() + m, sizeof(int64_t), hipMemcpyDeviceToHost,
+                              st));
+    }
+    if ((s = pull_stats(h)) != SPG_OK) return s;  // host sync 2: per-kind sizes, room for stored structure
     const DevStats hs2 = *h->hst;
+    h->planned = false;
+    if (want_plan && hs2.kcount_sym[K_DW] > 0 && h->hkoff[1] > 0) {
+        // the pairs are an optimisation: without room for them the numeric
+        // phase rebuilds the structure itself
+        h->planned = ensure(h->plan, 8 * (size_t)h->hkoff[1]) == hipSuccess;
+        (void)hipGetLastError();
+    }
 
     SymArgs sa{};
     sa.arp = arp;
@@ -403,6 +425,11 @@ static spg_status symbolic_core(spg_handle h, int64_t m, int64_t n, int64_t nnza
     sa.rs.koff = h->koff_sym.as<int64_t>();
     sa.st = dst;
     sa.lg_gs = lg_group(h->avg_len_c);
+    if (h->planned) {
+        sa.plan_off = h->plan_off.as<int64_t>();
+        sa.plan_len = h->plan_len.as<int32_t>();
+        sa.plan = h->plan.as<uint2>();
+    }
     LaunchCfg lc{st, 0, h->cus};
     auto grid_cap = [&](int64_t rows) { return (int)std::min<int64_t>(2048 * 8, ((rows + 7) / 8) * 8); };
 
@@ -452,6 +479,8 @@ static spg_status symbolic_core(spg_handle h, int64_t m, int64_t n, int64_t nnza
     // scan -> C row offsets (int64 plan copy), then the numeric classification
     HIPCHK(launch_scan_i32(m, h->row_nnz.as<int32_t>(), h->coff.as<int64_t>(), h->tmp.as<int64_t>(), st));
     cp.phase = 1;
+    cp.plan_cap = h->planned ? PL_CAP : 0;
+    cp.sym_kind = h->kind_sym.as<uint8_t>();
     const long long thr = h->opt.fp64_heavy_row_flops;
     cp.flops_lo = 0;
     cp.flops_hi = thr > 0 ? thr : 0;
@@ -571,6 +600,12 @@ static spg_status launch_kinds(spg_handle h, NumArgs<VT> na, const long long *kc
     LaunchCfg lc{st, 0, h->cus};
     auto grid_cap = [&](int64_t rows) { return (int)std::min<int64_t>(2048 * 8, ((rows + 7) / 8) * 8); };
 
+    if (kcount[K_PL] > 0) {
+        na.rs.kind = K_PL;
+        na.nw_max = ((kmax[K_PL][0] + 31) / 32) * 32;
+        na.r_max = std::max(kmax[K_PL][1], 1);
+        HIPCHK(launch_num_pl<VT>(na, acc, lc));
+    }
     if (kcount[K_SR] > 0) {
         na.rs.kind = K_SR;
         HIPCHK(launch_num_sr<VT>(na, acc, sr_lg(kmax[K_SR][1]), lc, kcount[K_SR]));
@@ -726,6 +761,12 @@ static spg_status numeric_impl(spg_handle h, const VT *aval, const VT *bval, int
     }
     na.rwin = h->rwin.as<int2>();
     na.coff = h->coff.as<int64_t>();
+    na.b32 = h->fp.nnzb < (int64_t(1) << 29);
+    if (h->planned) {
+        na.plan_off = h->plan_off.as<int64_t>();
+        na.plan = h->plan.as<uint2>();
+        na.row_words = h->row_words.as<int32_t>();
+    }
     na.cci = cci;
     na.cval = cval;
     na.rs.rows = h->perm_num.as<int32_t>();

@@ -219,6 +219,13 @@ __global__ __launch_bounds__(WAVE) void k_sym_dw(SymArgs a) {
         r += sl.step;
         const bool has_next = r < sl.end;
         const int ncn = has_next ? (int)min((int64_t)WAVE, dn.ae - dn.ab) : 0;
+        // room for this row's (word, bits) pairs (loaded early, used at the end)
+        int64_t poff = 0;
+        int plen = 0;
+        if (a.plan) {
+            poff = a.plan_off[i];
+            plen = a.plan_len[i];
+        }
         for (int64_t cb = d.ab; cb < d.ae; cb += WAVE) {
             int cn;
             if (cb == d.ab) {  // first chunk: from the prefetched registers
@@ -251,20 +258,28 @@ __global__ __launch_bounds__(WAVE) void k_sym_dw(SymArgs a) {
             inext = a.rs.rows[r + sl.step];
             dn = row_desc(inext, a.arp, a.rwin);
         }
+        // count the touched words in increasing order (summary word s, then
+        // bit order); with a plan, store each as (word, bits) at its position
         int cnt = 0, nwt = 0;
-        for (int s = l; s < d.ns; s += WAVE) {
-            uint32_t m = summ[s];
-            summ[s] = 0;
-            nwt += __popc(m);
+        for (int s0 = 0; s0 < d.ns; s0 += WAVE) {
+            const int s = s0 + l;
+            uint32_t m = s < d.ns ? summ[s] : 0u;
+            if (s < d.ns) summ[s] = 0;
+            const int c = __popc(m);
+            const int inc = wave_incl_scan(c);
+            int pos = nwt + inc - c;
             while (m) {
                 const int w = (s << 5) + __ffs(m) - 1;
                 m &= m - 1;
-                cnt += __popc(bits[w]);
+                const uint32_t bw = bits[w];
+                cnt += __popc(bw);
                 bits[w] = 0;
+                if (pos < plen) a.plan[poff + pos] = make_uint2((uint32_t)(d.wlo + w), bw);
+                ++pos;
             }
+            nwt += __shfl(inc, WAVE - 1);
         }
         cnt = wave_sum(cnt);
-        nwt = wave_sum(nwt);
         if (l == 0) {
             a.row_nnz[i] = cnt;
             a.row_words[i] = nwt;

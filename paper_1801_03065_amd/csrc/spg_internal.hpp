@@ -28,7 +28,8 @@ enum Kind : int {
     K_HL = 4,     // two-level hash: LDS level 1 + HBM level 2, one workgroup per row
     K_WH = 5,     // word hash + ordered summary, one wavefront per row (numeric)
     K_SR = 6,     // short rows: a team of T <= 64 lanes per row, several rows per wavefront
-    NK = 7
+    K_PL = 7,     // numeric on the symbolic phase's stored row structure, one wavefront per row
+    NK = 8
 };
 
 // Global counters written by the analysis kernels (zeroed per symbolic call).
@@ -57,6 +58,9 @@ constexpr int WH_NW_MAX = 32768;  // window words of the word-hash kernel (summa
 constexpr int WH_R_MAX = 1024;    // row size of the word-hash kernel
 constexpr int WH_T_MAX = 512;     // touched words of the word-hash kernel (table 2x)
 constexpr int SR_F_MAX = 64;      // multiplications of a short row (one per lane of its team)
+constexpr int PL_CAP = 64;        // stored (word, bits) pairs per row (one per lane)
+constexpr int PL_NW_MAX = 8192;   // window words of the stored-structure kernel (byte map in LDS)
+constexpr int PL_R_MAX = 2048;    // row size of the stored-structure kernel
 
 // ------------------------------------------------------------ argument blocks
 struct RowSet {
@@ -96,6 +100,9 @@ struct SymArgs {
     uint32_t *l2_keys;     // two-level hash arena (keys / masks), per workgroup
     uint32_t *l2_vals;
     int64_t l2_cap;        // slots per workgroup in the arena
+    const int64_t *plan_off;  // bit-window rows: where the row's (word, bits) pairs go
+    const int32_t *plan_len;  // room for pairs per row (0: none stored)
+    uint2 *plan;              // nullptr: no pairs stored
     DevStats *st;
 };
 
@@ -124,6 +131,10 @@ struct NumArgs {
     int l1_slots;
     void *arena;           // HBM scratch: dense values (K_DG) or level-2 tables (K_HL)
     int64_t arena_cap;     // entries per workgroup
+    const int64_t *plan_off;  // K_PL: the row's stored (word, bits) pairs
+    const uint2 *plan;
+    const int32_t *row_words; // K_PL: number of pairs of the row
+    int b32;               // nnz(B) * 8 < 2^32: B entries addressed with 32-bit offsets
     DevStats *st;
 };
 
@@ -205,6 +216,12 @@ __device__ __forceinline__ int mbcnt(unsigned long long m) {
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0));
 }
 __device__ __forceinline__ int read_first(int v) { return __builtin_amdgcn_readfirstlane(v); }
+// A wavefront-uniform 64-bit value moved to scalar registers.
+__device__ __forceinline__ int64_t uni64(int64_t v) {
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)v >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
 
 // Load base[idx] with a 32-bit byte offset (idx * sizeof(T) < 2^32): the
 // compiler then addresses with the base in SGPRs plus one 32-bit VGPR offset
@@ -306,6 +323,9 @@ struct ClassParams {
     long long flops_lo, flops_hi;  // numeric: only rows with flops in [lo, hi) get a kind (hi <= 0: no limit)
     int heavy;          // numeric: counts / maxima go to the heavy-row set
     int sr_f_max;       // selector: rows with at most this many multiplications are short rows (0: off)
+    int plan_cap;       // stored row structure: pairs per row (0: off)
+    int32_t *plan_len;  // symbolic: room for pairs per row (written); numeric: read
+    const uint8_t *sym_kind;  // numeric: kind of each row in the symbolic phase
 };
 hipError_t launch_classify(int64_t m, const int64_t *rflops, const int64_t *rflopsc, const int2 *rwin,
                            const int32_t *row_nnz, const int32_t *row_words, ClassParams p, uint8_t *kind,
@@ -336,6 +356,9 @@ template <typename VT>
 hipError_t launch_num_hl(const NumArgs<VT> &a, int acc, const LaunchCfg &c);
 template <typename VT>
 hipError_t launch_num_wh(const NumArgs<VT> &a, int acc, const LaunchCfg &c);
+template <typename VT>
+hipError_t launch_num_pl(const NumArgs<VT> &a, int acc, const LaunchCfg &c);
+size_t lds_num_pl(int nw_max, int r_max, int acc_bytes);
 template <typename VT>
 hipError_t launch_num_sr(const NumArgs<VT> &a, int acc, int lg_t, const LaunchCfg &c, int64_t rows);
 size_t lds_num_wh(int ts, int nw_max, int r_max, int acc_bytes);

@@ -37,8 +37,9 @@ def test_27pt_square_small(g, acc):
     used = {k for k, v in h.stats()["rows_numeric"].items() if v}
     if acc == 0:
         # at g = 2 every row has 8 * 8 = 64 multiplications (short-row teams);
-        # from g = 3 on even a corner row has 125 (word hash)
-        assert used == ({"short_rows"} if g == 2 else {"word_hash_wave"}), used
+        # from g = 3 on even a corner row has 125, and at most 50 touched
+        # words: the numeric phase runs on the stored structure
+        assert used == ({"short_rows"} if g == 2 else {"planned_wave"}), used
     else:
         want = {1: "dense_wave", 2: "hash_wave", 3: "hash_two_level"}[acc]
         assert used == {want}, used
@@ -241,3 +242,30 @@ def test_short_rows_fp32(mode):
     got, h = run(A, P, dtype="f32", fp32_mode=mode)
     check_f32(ref, S, got)
     assert set(k for k, v in h.stats()["rows_numeric"].items() if v) == {"short_rows"}
+
+
+def test_stored_structure_and_word_hash_mix():
+    """Rows with at most 64 touched words run on the structure the symbolic
+    phase stored; rows with more rebuild it with the word hash."""
+    rng = np.random.default_rng(21)
+    A = synth.shuffle_columns(synth.random_csr(2000, 3000, rng.integers(3, 40, 2000), 51), 4)
+    B = synth.random_csr(3000, 60000, rng.integers(1, 30, 3000), 52)
+    ref, S = oracle_ref(A, B)
+    got, h = run(A, B)
+    check_f64(ref, S, got)
+    st = h.stats()
+    assert st["rows_numeric"]["planned_wave"] > 0 and st["rows_numeric"]["word_hash_wave"] > 0, st
+    # Reuse: new values on the same plan
+    import torch
+
+    import paper_1801_03065_amd as spg
+    from helpers import dev
+
+    A2 = A.with_values(rng.standard_normal(A.nnz))
+    dA2, dB = dev(A2), dev(B)
+    rp = torch.as_tensor(got[0].astype(np.int32), device="cuda")
+    spg.spgemm_symbolic(h, dA2, dB)
+    C = spg.spgemm_numeric(h, dA2, dB, rp, int(got[0][-1]))
+    h.check_errors()
+    ref2, S2 = oracle_ref(A2, B)
+    check_f64(ref2, S2, (got[0], C.col_idx.cpu().numpy(), C.values.cpu().numpy()))
