@@ -311,7 +311,7 @@ static spg_status plan_buffers(spg_handle h, int64_t m, int64_t n, int64_t nnzb)
     HIPCHK(ensure(h->rflopsc, 8 * std::max<int64_t>(m, 1)));
     HIPCHK(ensure(h->rwin, 8 * std::max<int64_t>(m, 1)));
     HIPCHK(ensure(h->row_nnz, 4 * std::max<int64_t>(m, 1)));
-    HIPCHK(ensure(h->row_words, 4 * std::max<int64_t>(m, 1)));
+    HIPCHK(ensure(h->row_words, 4 * (m + 2)));  // one padding element (8-byte reads of the last row)
     HIPCHK(ensure(h->coff, 8 * (m + 1)));
     HIPCHK(ensure(h->kind_sym, std::max<int64_t>(m, 1)));
     HIPCHK(ensure(h->kind_num, std::max<int64_t>(m, 1)));

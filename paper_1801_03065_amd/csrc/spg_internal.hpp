@@ -202,6 +202,18 @@ __device__ __forceinline__ int wave_incl_scan(int v) {
     }
     return v;
 }
+// Inclusive prefix sum over the 64 lanes with DPP lane moves (row shifts
+// inside each 16-lane row, then row broadcasts of lane 15 and lane 31): no
+// address registers, unlike a shuffle through ds_bpermute.
+__device__ __forceinline__ int wave_scan_dpp(int v) {
+    v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xF, 0xF, false);  // row_shr:1
+    v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xF, 0xF, false);  // row_shr:2
+    v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xF, 0xF, false);  // row_shr:4
+    v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xF, 0xF, false);  // row_shr:8
+    v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xA, 0xF, false);  // row_bcast:15 into rows 1, 3
+    v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xC, 0xF, false);  // row_bcast:31 into rows 2, 3
+    return v;
+}
 __device__ __forceinline__ long long wave_incl_scan64(long long v) {
     const int l = lane_id();
 #pragma unroll

@@ -26,8 +26,12 @@ namespace {
 
 constexpr int PL_U = 16;  // products per lane held in registers (fast path)
 
+// LDS of one wavefront.  Staging, values and sorted columns are double
+// buffered: row p's results leave from one half while row p+1 is staged into
+// the other.  Half b starts at half0 + b * hsize; offsets inside a half are
+// the same for both.
 struct PlLayout {
-    size_t map, bp, vals, colbuf, st_bs, st_a, st_len, total;
+    size_t bp, map, half0, hsize, st_bs, st_a, st_len, st_pk, vals, colbuf, total;
 };
 
 __host__ __device__ inline PlLayout pl_layout(int nw_max, int r_max, int acc_bytes) {
@@ -35,16 +39,22 @@ __host__ __device__ inline PlLayout pl_layout(int nw_max, int r_max, int acc_byt
     size_t o = 0;
     L.bp = o;  // per plan pair: bits | pre << 32
     o += 8 * (size_t)PL_CAP;
-    L.st_bs = o;
-    o += 8 * WAVE;
-    L.st_a = o;
-    o += 8 * WAVE;
-    L.vals = o;
-    o += align16((size_t)acc_bytes * r_max);
-    L.colbuf = o;
-    o += align16(4 * (size_t)r_max);
-    L.st_len = o;
-    o += 4 * WAVE;
+    L.half0 = o;
+    size_t h = 0;
+    L.st_bs = h;
+    h += 8 * WAVE;
+    L.st_a = h;
+    h += 8 * WAVE;
+    L.vals = h;
+    h += align16((size_t)acc_bytes * r_max);
+    L.colbuf = h;
+    h += align16(4 * (size_t)r_max);
+    L.st_len = h;
+    h += 4 * WAVE;
+    L.st_pk = h;  // fast path: (32-bit B offset, length) per A entry
+    h += 8 * WAVE;
+    L.hsize = h;
+    o += 2 * h;
     L.map = o;  // window word -> pair index (uint8)
     o += align16((size_t)nw_max);
     L.total = o;
@@ -64,108 +74,191 @@ __global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(4, 8))) vo
     const PlLayout L = pl_layout(a.nw_max, a.r_max, sizeof(S));
     unsigned long long *bp = (unsigned long long *)(smem + L.bp);
     uint8_t *map = smem + L.map;
-    S *vals = (S *)(smem + L.vals);
-    int32_t *colbuf = (int32_t *)(smem + L.colbuf);
-    int64_t *st_bs = (int64_t *)(smem + L.st_bs);
-    double *st_a = (double *)(smem + L.st_a);
-    int32_t *st_len = (int32_t *)(smem + L.st_len);
     const int l = lane_id();
-    for (int t = l; t < a.r_max; t += WAVE) vals[t] = A::zero();
-    wave_lds_sync();
+    auto half = [&](int b) -> unsigned char * { return smem + L.half0 + (size_t)b * L.hsize; };
+    for (int b = 0; b < 2; ++b)
+        for (int t = l; t < a.r_max; t += WAVE) ((S *)(half(b) + L.vals))[t] = A::zero();
     const int gs = 1 << a.lg_gs, g = l >> a.lg_gs, q = l & (gs - 1), ng = WAVE >> a.lg_gs;
     int64_t lo, hi;
     rs_bounds(a.rs, lo, hi);
     const int64_t cbase = a.cbase_row >= 0 ? a.coff[a.cbase_row] : 0;
     const Slice sl = xcd_slice(lo, hi);
 
-    // row descriptor: wavefront-uniform, kept in scalar registers
-    auto desc = [&](int64_t rr) -> RowDescP {
-        const int i = read_first(a.rs.rows[rr]);
+    // Software pipeline over the wavefront's rows p, p+s, p+2s, ...: while
+    // row p is processed, row p+s's B extents (second level) and row p+2s's A
+    // entries and plan pairs (first level) load; lane k < 7 loads field k of
+    // row p+3s's descriptor (moved to scalar registers a row later) and the
+    // row index of p+4s loads a row before that.  Memory operations are
+    // issued in the order gathers of row p, pipeline loads, stores of row
+    // p-1: the vector-memory counter retires in order, so waiting for a load
+    // never waits for the previous row's stores.
+    auto load_desc = [&](int i) -> int64_t {
+        // lanes 0-4: arp[i], arp[i+1], coff[i], coff[i+1], plan_off[i] (64-bit);
+        // lane 5: the window's first word; lane 6: touched words (the row_words
+        // array has a padding element).  Two dword loads in every lane, no branch.
+        const uint32_t *src = (const uint32_t *)(a.arp + i + (l & 1));
+        if (l >= 2 && l < 4) src = (const uint32_t *)(a.coff + i + (l - 2));
+        if (l == 4) src = (const uint32_t *)(a.plan_off + i);
+        if (l == 5) src = (const uint32_t *)(a.rwin + i);
+        if (l == 6) src = (const uint32_t *)(a.row_words + i);
+        const uint32_t vlo = src[0], vhi = src[1];
+        return (int64_t)(((uint64_t)vhi << 32) | vlo);
+    };
+    auto lane64 = [](int64_t v, int k) -> int64_t {
+        const uint32_t vlo = __builtin_amdgcn_readlane((uint32_t)v, k);
+        const uint32_t vhi = __builtin_amdgcn_readlane((uint32_t)((uint64_t)v >> 32), k);
+        return (int64_t)(((uint64_t)vhi << 32) | vlo);
+    };
+    auto to_uni = [&](int64_t v) -> RowDescP {
         RowDescP d;
-        d.ab = uni64(a.arp[i]);
-        d.ae = uni64(a.arp[i + 1]);
-        d.cb = uni64(a.coff[i]);
-        d.ce = uni64(a.coff[i + 1]);
-        d.po = uni64(a.plan_off[i]);
-        d.wlo = read_first(a.rwin[i].x);
-        d.nw = read_first(a.row_words[i]);
+        d.ab = lane64(v, 0);
+        d.ae = lane64(v, 1);
+        d.cb = lane64(v, 2);
+        d.ce = lane64(v, 3);
+        d.po = lane64(v, 4);
+        d.wlo = (int)__builtin_amdgcn_readlane((uint32_t)v, 5);
+        d.nw = (int)__builtin_amdgcn_readlane((uint32_t)v, 6);
         return d;
     };
-
-    int64_t r = sl.idx;
-    RowDescP dcur = r < sl.end ? desc(r) : RowDescP{};
-    int64_t sb0 = 0, sb1 = 0;
-    double sav = 0.0;
-    uint2 pw = make_uint2(0u, 0u);
-    if (r < sl.end) {
-        if (l < min((int64_t)WAVE, dcur.ae - dcur.ab)) {
-            const int j = a.aci[dcur.ab + l];
-            sav = (double)a.aval[dcur.ab + l];
-            sb0 = a.brp[j];
-            sb1 = a.brp[j + 1];
-        }
-        if (l < dcur.nw) pw = a.plan[dcur.po + l];
-    }
-    RowDescP dn = r + sl.step < sl.end ? desc(r + sl.step) : RowDescP{};
-    while (r < sl.end) {
-        const RowDescP d = dcur;
-        r += sl.step;
-        const bool has_next = r < sl.end;
-        const int wlo = d.wlo;
-        const int64_t na = d.ae - d.ab;
-        // ---- stage the first chunk of A's row from the prefetched registers
-        int cn = (int)min((int64_t)WAVE, na);
-        int mylen = 0;
+    // stage up to 64 A entries of a row into half b; returns the fast-path test
+    auto stage = [&](int b, int cn, int64_t na, int64_t b0, int64_t b1, double av) -> bool {
+        const int len = (int)(b1 - b0);
         if (l < cn) {
-            st_bs[l] = sb0;
-            st_a[l] = sav;
-            mylen = (int)(sb1 - sb0);
-            st_len[l] = mylen;
+            unsigned char *hb = half(b);
+            ((int64_t *)(hb + L.st_bs))[l] = b0;
+            ((double *)(hb + L.st_a))[l] = av;
+            ((int32_t *)(hb + L.st_len))[l] = len;
+            ((int2 *)(hb + L.st_pk))[l] = make_int2((int)(uint32_t)b0, len);
         }
-        const bool fast = a.b32 && na <= WAVE && cn <= ng * PL_U && wave_max(mylen) <= gs;
+        return a.b32 && na <= WAVE && cn <= ng * PL_U && __ballot(l < cn && len > gs) == 0;
+    };
+    const int64_t step = sl.step;
+    const int64_t p0 = sl.idx, pend = sl.end;
+    auto row_at = [&](int64_t pp) -> int { return pp < pend ? read_first(a.rs.rows[pp]) : 0; };
+
+    // ---- prologue: fill the pipeline (waits here are once per kernel)
+    int64_t rn = p0 + step < pend ? load_desc(row_at(p0 + step)) : 0;    // raw, row p+s
+    int64_t r2 = p0 + 2 * step < pend ? load_desc(row_at(p0 + 2 * step)) : 0;  // raw, row p+2s
+    RowDescP d = p0 < pend ? to_uni(load_desc(row_at(p0))) : RowDescP{};   // row p
+    int64_t nan = p0 + step < pend ? lane64(rn, 1) - lane64(rn, 0) : 0;     // A entries of row p+s
+    int64_t f2ab = 0, f2na = 0, f2po = 0;                                    // row p+2s
+    int f2nw = 0;
+    if (p0 + 2 * step < pend) {
+        f2ab = lane64(r2, 0);
+        f2na = lane64(r2, 1) - f2ab;
+        f2po = lane64(r2, 4);
+        f2nw = (int)__builtin_amdgcn_readlane((uint32_t)r2, 6);
+    }
+    int i3u = row_at(p0 + 3 * step);  // uniform row index of row p+3s
+    bool fast_c = false;
+    uint2 cpw = make_uint2(0u, 0u);
+    if (p0 < pend) {  // row p: staged into half 0; its plan pair in a register
+        const int cn = (int)min((int64_t)WAVE, d.ae - d.ab);
+        int64_t b0 = 0, b1 = 0;
+        double av = 0.0;
+        if (l < cn) {
+            const int j = a.aci[d.ab + l];
+            av = (double)a.aval[d.ab + l];
+            b0 = a.brp[j];
+            b1 = a.brp[j + 1];
+        }
+        fast_c = stage(0, cn, d.ae - d.ab, b0, b1, av);
+        if (l < d.nw) cpw = a.plan[d.po + l];
+    }
+    int nj = 0;  // row p+s: A column, value, plan pair
+    double nav = 0.0;
+    uint2 npw = make_uint2(0u, 0u);
+    if (p0 + step < pend) {
+        const RowDescP dn = to_uni(rn);
+        if (l < min((int64_t)WAVE, nan)) {
+            nj = a.aci[dn.ab + l];
+            nav = (double)a.aval[dn.ab + l];
+        }
+        if (l < dn.nw) npw = a.plan[dn.po + l];
+    }
+    // the previous row's results, written out during the next row
+    bool prev_ok = false;
+    int64_t prev_ob = 0;
+    int prev_n = 0;
+    int b = 0;  // half of the current row
+    for (int64_t pp = p0; pp < pend; pp += step, b ^= 1) {
+        const bool has1 = pp + step < pend, has2 = pp + 2 * step < pend, has3 = pp + 3 * step < pend;
+        const int wlo = d.wlo;
+        unsigned char *hb = half(b);
+        int64_t *st_bs = (int64_t *)(hb + L.st_bs);
+        double *st_a = (double *)(hb + L.st_a);
+        int32_t *st_len = (int32_t *)(hb + L.st_len);
+        const int2 *st_pk = (const int2 *)(hb + L.st_pk);
+        S *vals = (S *)(hb + L.vals);
+        int32_t *colbuf = (int32_t *)(hb + L.colbuf);
+        const bool fast = fast_c;
+        int cn = (int)min((int64_t)WAVE, d.ae - d.ab);
         wave_lds_sync();
 
-        // ---- fast path: every product's column and value load now
+        // ---- 1. stores of row p-1 (other half)
+        if (prev_ok) {
+            S *pvals = (S *)(half(b ^ 1) + L.vals);
+            const int32_t *pcol = (const int32_t *)(half(b ^ 1) + L.colbuf);
+            for (int t = l; t < prev_n; t += WAVE) {
+                a.cci[prev_ob + t] = pcol[t];
+                a.cval[prev_ob + t] = A::fin(pvals[t]);
+                pvals[t] = A::zero();
+            }
+        }
+        // ---- 2. pipeline loads (addresses from values that landed a row ago):
+        //      row p+s B extents, row p+2s A entries and plan pairs, row p+3s
+        //      descriptor, row p+4s index
+        int64_t nb0 = 0, nb1 = 0;
+        if (has1 && l < min((int64_t)WAVE, nan)) {
+            nb0 = a.brp[nj];
+            nb1 = a.brp[nj + 1];
+        }
+        int nnj = 0;
+        double nnav = 0.0;
+        uint2 nnpw = make_uint2(0u, 0u);
+        if (has2) {
+            if (l < min((int64_t)WAVE, f2na)) {
+                nnj = a.aci[f2ab + l];
+                nnav = (double)a.aval[f2ab + l];
+            }
+            if (l < f2nw) nnpw = a.plan[f2po + l];
+        }
+        const int64_t raw3 = has3 ? load_desc(i3u) : 0;
+        const int i4 = pp + 4 * step < pend ? a.rs.rows[pp + 4 * step] : 0;
+
+        // ---- 3. gathers of row p: every product's column and value
         int col[PL_U];
         VT pv[PL_U];
         unsigned okm = 0;
         if (fast) {
+            int2 pk[PL_U];
+#pragma unroll
+            for (int u = 0; u < PL_U; ++u) pk[u] = st_pk[min(g + u * ng, cn - 1)];
 #pragma unroll
             for (int u = 0; u < PL_U; ++u) {
-                const int t = g + u * ng;
-                const int tt = t < cn ? t : 0;
-                const bool ok = t < cn && q < st_len[tt];
+                const bool ok = (g + u * ng < cn) & (q < pk[u].y);
                 okm |= (unsigned)ok << u;
-                const uint32_t e = ok ? (uint32_t)st_bs[tt] + q : 0u;  // nnz(B) * 8 < 2^32 on this path
+                const uint32_t e = ok ? (uint32_t)pk[u].x + q : 0u;  // nnz(B) * 8 < 2^32 on this path
                 col[u] = ld32(a.bci, e);
                 pv[u] = ld32(a.bval, e);
             }
         }
-        // ---- decode the plan while they are in flight: pre(word), word -> pair
+        // ---- 4. decode the plan of row p: pre(word), word -> pair
+        const uint2 mypw = cpw;
         const bool have = l < d.nw;
-        const int pc = have ? __popc(pw.y) : 0;
-        const int inc = wave_incl_scan(pc);
+        const int pc = have ? __popc(mypw.y) : 0;
+        const int inc = wave_scan_dpp(pc);
         const int pre = inc - pc;
-        const int rnnz = __shfl(inc, WAVE - 1);
-        const uint2 mypw = pw;
+        const int rnnz = __builtin_amdgcn_readlane(inc, WAVE - 1);
         if (have) {
             map[(int)mypw.x - wlo] = (uint8_t)l;
             bp[l] = (unsigned long long)mypw.y | ((unsigned long long)(uint32_t)pre << 32);
         }
         const bool ok = (d.ce - d.cb == rnnz) && rnnz <= a.r_max && d.nw <= PL_CAP;
         if (l == 0 && !ok) atomicAdd(&a.st->mismatch, 1);
-        // next row, first level: its A entries and plan pairs
-        const int ncn = has_next ? (int)min((int64_t)WAVE, dn.ae - dn.ab) : 0;
-        int nj = 0;
-        if (l < ncn) {
-            nj = a.aci[dn.ab + l];
-            sav = (double)a.aval[dn.ab + l];
-        }
-        pw = make_uint2(0u, 0u);
-        if (has_next && l < dn.nw) pw = a.plan[dn.po + l];
         wave_lds_sync();
 
-        // ---- products into vals[rank]
+        // ---- 5. products into vals[rank]
         if (ok) {
             if (fast) {
 #pragma unroll
@@ -208,7 +301,7 @@ __global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(4, 8))) vo
                 }
             }
         }
-        // sorted columns of the row from its pairs
+        // ---- 6. sorted columns of row p from its pairs
         if (ok && have) {
             uint32_t m = mypw.y;
             int p = pre;
@@ -218,23 +311,40 @@ __global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(4, 8))) vo
                 m &= m - 1;
             }
         }
-        // next row, second level: B extents; the row after next: descriptor
-        if (l < ncn) {
-            sb0 = a.brp[nj];
-            sb1 = a.brp[nj + 1];
+        // ---- 7. next row: every load issued above has landed (the products
+        //      waited for the gathers, issued last, and loads retire in order),
+        //      so its values move to scalar registers without a stall
+        prev_ok = ok;
+        prev_ob = d.cb - cbase;
+        prev_n = rnnz;
+        if (has1) {
+            fast_c = stage(b ^ 1, (int)min((int64_t)WAVE, nan), nan, nb0, nb1, nav);
+            d = to_uni(rn);
         }
-        dcur = dn;
-        if (r + sl.step < sl.end) dn = desc(r + sl.step);
-        wave_lds_sync();
-        if (ok) {
-            const int64_t ob = d.cb - cbase;
-            for (int t = l; t < rnnz; t += WAVE) {
-                a.cci[ob + t] = colbuf[t];
-                a.cval[ob + t] = A::fin(vals[t]);
-                vals[t] = A::zero();
-            }
+        if (has2) nan = lane64(r2, 1) - lane64(r2, 0);
+        if (has3) {
+            f2ab = lane64(raw3, 0);
+            f2na = lane64(raw3, 1) - f2ab;
+            f2po = lane64(raw3, 4);
+            f2nw = (int)__builtin_amdgcn_readlane((uint32_t)raw3, 6);
         }
-        wave_lds_sync();
+        i3u = read_first(i4);
+        rn = r2;
+        r2 = raw3;
+        cpw = npw;
+        nj = nnj;
+        nav = nnav;
+        npw = nnpw;
+    }
+    // the last row's stores
+    wave_lds_sync();
+    if (prev_ok) {
+        S *pvals = (S *)(half(b ^ 1) + L.vals);
+        const int32_t *pcol = (const int32_t *)(half(b ^ 1) + L.colbuf);
+        for (int t = l; t < prev_n; t += WAVE) {
+            a.cci[prev_ob + t] = pcol[t];
+            a.cval[prev_ob + t] = A::fin(pvals[t]);
+        }
     }
 }
 

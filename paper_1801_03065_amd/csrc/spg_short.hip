@@ -102,6 +102,7 @@ __global__ __launch_bounds__(WAVE) void k_sr(SrArgs<VT> a) {
         abn = a.arp[in];
         aen = a.arp[in + 1];
     }
+    int i2 = row_of(g + 2 * sl.step);  // row indices load two groups ahead
     while (g < sl.end) {
         // next row, first level: its A entries (first chunk)
         int jn = 0;
@@ -245,14 +246,15 @@ __global__ __launch_bounds__(WAVE) void k_sr(SrArgs<VT> a) {
             b0n = a.brp[jn];
             lenn = (int)(a.brp[jn + 1] - b0n);
         }
-        // the row after next: descriptor
+        // the row after next: its A extent (its index loaded a group ago)
         g += sl.step;
-        const int inn = row_of(g + sl.step);
+        const int inn = i2;
         int64_t abnn = 0, aenn = 0;
         if (inn >= 0) {
             abnn = a.arp[inn];
             aenn = a.arp[inn + 1];
         }
+        i2 = row_of(g + 2 * sl.step);
         ic = in;
         abc = abn;
         aec = aen;
