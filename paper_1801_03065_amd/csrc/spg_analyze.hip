@@ -191,10 +191,17 @@ __global__ __launch_bounds__(BLK) void k_mark_unsorted(const int32_t *list, cons
 // ------------------------------------------------------------------ A rows
 // 16 lanes per row of A: f_m(i) = sum |B(j,:)|, the same over compressed B,
 // and the word window [min wmin, max wmax] of the B rows it reads.
+__device__ __forceinline__ long long wave_max64(long long v) {
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) v = max(v, (long long)__shfl_xor(v, d));
+    return v;
+}
+
 constexpr int RI_GS = 8;
 constexpr int RI_U = 4;  // A entries per lane in flight
 constexpr int RI_GRID = 2048;
-static_assert(4 * RI_GRID <= RED_ELEMS && 4 * NK * CL_GRID <= RED_ELEMS, "analysis partials exceed scratch");
+constexpr int RI_F = 6;  // rowinfo partial fields: fm, fmc, max, max compressed, fm and fmc of long rows
+static_assert(RI_F * RI_GRID <= RED_ELEMS && 4 * NK * CL_GRID <= RED_ELEMS, "analysis partials exceed scratch");
 
 __global__ __launch_bounds__(BLK) void k_rowinfo(int64_t m, const int64_t *arp, const int32_t *aci,
                                                   const BRow *bi, int64_t *rflops, int64_t *rflopsc,
@@ -202,7 +209,7 @@ __global__ __launch_bounds__(BLK) void k_rowinfo(int64_t m, const int64_t *arp, 
     const int q = threadIdx.x & (RI_GS - 1);
     const int64_t g0 = ((int64_t)blockIdx.x * BLK + threadIdx.x) / RI_GS;
     const int64_t ng = (int64_t)gridDim.x * BLK / RI_GS;
-    long long s_fm = 0, s_fmc = 0, s_mx = 0, s_mxc = 0;
+    long long s_fm = 0, s_fmc = 0, s_mx = 0, s_mxc = 0, s_fmb = 0, s_fmcb = 0;
     for (int64_t i = g0; i < m; i += ng) {
         const int64_t b = arp[i], e = arp[i + 1];
         long long f = 0, fc = 0;
@@ -242,13 +249,19 @@ __global__ __launch_bounds__(BLK) void k_rowinfo(int64_t m, const int64_t *arp, 
             s_fmc += fc;
             s_mx = max(s_mx, f);
             s_mxc = max(s_mxc, fc);
+            if (f > SR_F_MAX) {  // rows that read B's structure word by word
+                s_fmb += f;
+                s_fmcb += fc;
+            }
         }
     }
     // per-block partials; k_rowinfo_fin folds them (same-address global
     // atomics from every block would serialise in L2)
-    __shared__ long long red[4][BLK / WAVE];
+    __shared__ long long red[RI_F][BLK / WAVE];
     s_fm = wave_sum64(s_fm);
     s_fmc = wave_sum64(s_fmc);
+    s_fmb = wave_sum64(s_fmb);
+    s_fmcb = wave_sum64(s_fmcb);
 #pragma unroll
     for (int d = 32; d >= 1; d >>= 1) {
         s_mx = max(s_mx, (long long)__shfl_xor(s_mx, d));
@@ -260,63 +273,49 @@ __global__ __launch_bounds__(BLK) void k_rowinfo(int64_t m, const int64_t *arp, 
         red[1][wv] = s_fmc;
         red[2][wv] = s_mx;
         red[3][wv] = s_mxc;
+        red[4][wv] = s_fmb;
+        red[5][wv] = s_fmcb;
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-        long long a = 0, b = 0, c = 0, d = 0;
-        for (int u = 0; u < BLK / WAVE; ++u) {
-            a += red[0][u];
-            b += red[1][u];
-            c = max(c, red[2][u]);
-            d = max(d, red[3][u]);
-        }
-        long long *pp = part + 4 * (int64_t)blockIdx.x;
-        pp[0] = a;
-        pp[1] = b;
-        pp[2] = c;
-        pp[3] = d;
+    if (threadIdx.x < RI_F) {
+        const int f = threadIdx.x;
+        long long v = 0;
+        for (int u = 0; u < BLK / WAVE; ++u) v = (f == 2 || f == 3) ? max(v, red[f][u]) : v + red[f][u];
+        part[RI_F * (int64_t)blockIdx.x + f] = v;
     }
-}
-
-__device__ __forceinline__ long long wave_max64(long long v) {
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) v = max(v, (long long)__shfl_xor(v, d));
-    return v;
 }
 
 // One workgroup: fold the rowinfo partials of nb blocks into the statistics.
 __global__ __launch_bounds__(BLK) void k_rowinfo_fin(int nb, const long long *part, DevStats *st) {
-    long long a = 0, b = 0, c = 0, d = 0;
-    for (int k = threadIdx.x; k < nb; k += BLK) {
-        a += part[4 * k];
-        b += part[4 * k + 1];
-        c = max(c, part[4 * k + 2]);
-        d = max(d, part[4 * k + 3]);
-    }
-    a = wave_sum64(a);
-    b = wave_sum64(b);
-    c = wave_max64(c);
-    d = wave_max64(d);
-    __shared__ long long red[4][BLK / WAVE];
+    long long v[RI_F];
+#pragma unroll
+    for (int f = 0; f < RI_F; ++f) v[f] = 0;
+    for (int k = threadIdx.x; k < nb; k += BLK)
+#pragma unroll
+        for (int f = 0; f < RI_F; ++f) {
+            const long long x = part[RI_F * (int64_t)k + f];
+            v[f] = (f == 2 || f == 3) ? max(v[f], x) : v[f] + x;
+        }
+    __shared__ long long red[RI_F][BLK / WAVE];
     const int wv = threadIdx.x / WAVE;
-    if (lane_id() == 0) {
-        red[0][wv] = a;
-        red[1][wv] = b;
-        red[2][wv] = c;
-        red[3][wv] = d;
+#pragma unroll
+    for (int f = 0; f < RI_F; ++f) {
+        const long long r = (f == 2 || f == 3) ? wave_max64(v[f]) : wave_sum64(v[f]);
+        if (lane_id() == 0) red[f][wv] = r;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        for (int u = 1; u < BLK / WAVE; ++u) {
-            a += red[0][u];
-            b += red[1][u];
-            c = max(c, red[2][u]);
-            d = max(d, red[3][u]);
+        long long a[RI_F];
+        for (int f = 0; f < RI_F; ++f) {
+            a[f] = 0;
+            for (int u = 0; u < BLK / WAVE; ++u) a[f] = (f == 2 || f == 3) ? max(a[f], red[f][u]) : a[f] + red[f][u];
         }
-        if (a) atomicAdd(&st->fm, ull(a));
-        if (b) atomicAdd(&st->fmc, ull(b));
-        if (c) atomicMax(&st->maxrf, ull(c));
-        if (d) atomicMax(&st->maxrfc, ull(d));
+        if (a[0]) atomicAdd(&st->fm, ull(a[0]));
+        if (a[1]) atomicAdd(&st->fmc, ull(a[1]));
+        if (a[2]) atomicMax(&st->maxrf, ull(a[2]));
+        if (a[3]) atomicMax(&st->maxrfc, ull(a[3]));
+        if (a[4]) atomicAdd(&st->fmb, ull(a[4]));
+        if (a[5]) atomicAdd(&st->fmcb, ull(a[5]));
     }
 }
 
@@ -422,17 +421,24 @@ __global__ __launch_bounds__(BLK) void k_classify(int64_t m, const int64_t *rflo
 
 // One workgroup: fold the classify partials of nb blocks into the per-kind
 // counts and maxima of the phase (only kinds that have rows are touched).
+// Each thread loads all fields of its blocks at once (the loads overlap).
 __global__ __launch_bounds__(BLK) void k_classify_fin(int nb, const long long *part, int phase, int heavy,
                                                        DevStats *st) {
     __shared__ long long red[NK * 4][BLK / WAVE];
     const int wv = threadIdx.x / WAVE;
+    long long acc[NK * 4];
+#pragma unroll
+    for (int f = 0; f < NK * 4; ++f) acc[f] = 0;
+    for (int k = threadIdx.x; k < nb; k += BLK) {
+        long long x[NK * 4];
+#pragma unroll
+        for (int f = 0; f < NK * 4; ++f) x[f] = part[4 * ((int64_t)k * NK) + f];
+#pragma unroll
+        for (int f = 0; f < NK * 4; ++f) acc[f] = (f & 3) == 3 ? acc[f] + x[f] : max(acc[f], x[f]);
+    }
+#pragma unroll
     for (int f = 0; f < NK * 4; ++f) {
-        long long v = 0;
-        for (int k = threadIdx.x; k < nb; k += BLK) {
-            const long long x = part[4 * ((int64_t)k * NK) + f];
-            v = (f & 3) == 3 ? v + x : max(v, x);
-        }
-        v = (f & 3) == 3 ? wave_sum64(v) : wave_max64(v);
+        const long long v = (f & 3) == 3 ? wave_sum64(acc[f]) : wave_max64(acc[f]);
         if (lane_id() == 0) red[f][wv] = v;
     }
     __syncthreads();
@@ -472,35 +478,62 @@ __global__ __launch_bounds__(PB) void k_part_count(int64_t m, const uint8_t *kin
 }
 
 __global__ __launch_bounds__(PB) void k_part_scan(int64_t nb, int64_t *blk, int64_t *koff) {
-    // one block: kind by kind, exclusive scan over the nb block counts
-    __shared__ long long wsum[PB / WAVE];
-    __shared__ long long carry;
+    // one block.  Pass 1: per-kind totals -> koff (kinds in order).  Pass 2:
+    // every thread loads all kinds of its block at once, then one scan per
+    // kind over the blocks (loads overlap instead of one round trip per kind).
+    __shared__ long long wsum[NK][PB / WAVE];
+    __shared__ long long base[NK];
     const int t = threadIdx.x, l = lane_id(), wv = t / WAVE;
-    if (t == 0) carry = 0;
-    __syncthreads();
+    long long tot[NK];
+#pragma unroll
+    for (int k = 0; k < NK; ++k) tot[k] = 0;
+    for (int64_t b = t; b < nb; b += PB)
+#pragma unroll
+        for (int k = 0; k < NK; ++k) tot[k] += blk[b * NK + k];
+#pragma unroll
     for (int k = 0; k < NK; ++k) {
-        if (t == 0) koff[k] = carry;
-        __syncthreads();
-        for (int64_t c0 = 0; c0 < nb; c0 += PB) {
-            const int64_t b = c0 + t;
-            const long long v = b < nb ? blk[b * NK + k] : 0;
-            long long inc = wave_incl_scan64(v);
-            if (l == WAVE - 1) wsum[wv] = inc;
-            __syncthreads();
-            long long off = 0, tot = 0;
-            for (int u = 0; u < PB / WAVE; ++u) {
-                if (u < wv) off += wsum[u];
-                tot += wsum[u];
-            }
-            if (b < nb) blk[b * NK + k] = carry + off + inc - v;
-            __syncthreads();
-            if (t == 0) carry += tot;
-            __syncthreads();
-        }
+        const long long v = wave_sum64(tot[k]);
+        if (l == 0) wsum[k][wv] = v;
     }
-    if (t == 0) koff[NK] = carry;
+    __syncthreads();
+    if (t == 0) {
+        long long run = 0;
+        for (int k = 0; k < NK; ++k) {
+            long long kt = 0;
+            for (int u = 0; u < PB / WAVE; ++u) kt += wsum[k][u];
+            koff[k] = run;
+            base[k] = run;
+            run += kt;
+        }
+        koff[NK] = run;
+    }
+    __syncthreads();
+    for (int64_t c0 = 0; c0 < nb; c0 += PB) {
+        const int64_t b = c0 + t;
+        long long v[NK], inc[NK];
+#pragma unroll
+        for (int k = 0; k < NK; ++k) v[k] = b < nb ? blk[b * NK + k] : 0;
+#pragma unroll
+        for (int k = 0; k < NK; ++k) {
+            inc[k] = wave_incl_scan64(v[k]);
+            if (l == WAVE - 1) wsum[k][wv] = inc[k];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < NK; ++k) {
+            long long off = 0;
+            for (int u = 0; u < wv; ++u) off += wsum[k][u];
+            if (b < nb) blk[b * NK + k] = base[k] + off + inc[k] - v[k];
+        }
+        __syncthreads();
+        if (t < NK) {
+            long long ct = 0;
+            for (int u = 0; u < PB / WAVE; ++u) ct += wsum[t][u];
+            base[t] += ct;
+        }
+        __syncthreads();
+    }
 }
-
 __global__ __launch_bounds__(PB) void k_part_scatter(int64_t m, const uint8_t *kind, const int64_t *blk,
                                                       int32_t *perm) {
     __shared__ int wcnt[PB / WAVE][NK];

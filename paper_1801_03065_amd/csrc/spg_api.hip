@@ -346,8 +346,15 @@ static spg_status symbolic_core(spg_handle h, int64_t m, int64_t n, int64_t nnza
 
     const double fm = (double)hs1.fm, fmc = (double)hs1.fmc;
     bool comp = false;
-    if (h->opt.compression == 1) comp = true;
-    else if (h->opt.compression == -1) comp = hs1.fm > 0 && fmc < h->opt.cf_threshold * fm;
+    if (h->opt.compression == 1) {
+        comp = true;
+    } else if (h->opt.compression == -1) {
+        // the 15% rule over the rows that read compressed B: with the selector,
+        // short rows (a team of lanes, raw B) do not
+        const bool sel = h->opt.accumulator == SPG_ACC_AUTO;
+        const double f0 = sel ? (double)hs1.fmb : fm, f1 = sel ? (double)hs1.fmcb : fmc;
+        comp = f0 > 0 && f1 < h->opt.cf_threshold * f0;
+    }
     h->avg_len = nnza ? std::max(1.0, fm / (double)nnza) : 1.0;
     h->avg_len_c = nnza ? std::max(1.0, (comp ? fmc : fm) / (double)nnza) : 1.0;
 

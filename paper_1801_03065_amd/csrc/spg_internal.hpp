@@ -35,6 +35,7 @@ enum Kind : int {
 // Global counters written by the analysis kernels (zeroed per symbolic call).
 struct DevStats {
     unsigned long long fm, fmc, maxrf, maxrfc, nnzbc;
+    unsigned long long fmb, fmcb;  // flops (raw / compressed) of rows beyond the short-row limit
     unsigned long long nnzc;
     int bad_input;    // malformed CSR (row_ptr not monotone / not ending at nnz, column out of range)
     int unsorted;     // B rows whose columns are not sorted
