@@ -28,6 +28,37 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0
 
+# HBM bytes per launch of the dominant kernel, from two rocprofv3 counter
+# passes (FETCH_SIZE, WRITE_SIZE) over `bench.py --steps 1 --warmup 0 --no-cpu`,
+# each scaled by what the counter reads for the bench's 2 GiB device copy
+# (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0).  Valid only for the kernel sources they
+# were taken on: reported as null once those sources change.
+TRAFFIC = {
+    "kernel": "k_num_pl",
+    "sources": ["paper_1801_03065_amd/csrc/spg_plan.hip", "paper_1801_03065_amd/csrc/spg_internal.hpp",
+                "paper_1801_03065_amd/csrc/spg_accum.hpp"],
+    "sha256": "c8e003ba37da6d24e9526fd8fc77ef383336eb3a19c08ac2088367c462c49d14",
+    "read_bytes": 3.8404e9,
+    "write_bytes": 1.5082e9,
+}
+
+
+def measured_traffic(kernel):
+    import hashlib
+
+    if not kernel.startswith(TRAFFIC["kernel"]):
+        return None
+    h = hashlib.sha256()
+    try:
+        for f in TRAFFIC["sources"]:
+            with open(os.path.join(ROOT, f), "rb") as fh:
+                h.update(fh.read())
+    except OSError:
+        return None
+    if h.hexdigest() != TRAFFIC["sha256"]:
+        return None
+    return TRAFFIC["read_bytes"] + TRAFFIC["write_bytes"]
+
 
 # numeric kernel that processes each row kind
 KERNEL_OF_KIND = {"empty": "none", "dense_wave": "k_num_dw", "hash_wave": "k_num_hw", "dense_wg": "k_num_dg",
@@ -200,9 +231,13 @@ def main():
     dom_kind = max(dom["rows_numeric"].items(), key=lambda kv: kv[1])[0]
     t_dom = dom["numeric_ms"] * 1e-3
     achieved = dom["numeric_alg_bytes"] / t_dom / 1e9
+    kname = f"{KERNEL_OF_KIND[dom_kind]}<double>"
+    traffic = measured_traffic(kname)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": None,
-                "kernel": f"{KERNEL_OF_KIND[dom_kind]}<double> (27-point A*A, FP64)",
+                "frac": round(achieved / HBM_PEAK_GBPS, 4),
+                "traffic": None if traffic is None else round(traffic / 1e9, 3),
+                "traffic_unit": "GB per launch", "algorithmic": round(dom["numeric_alg_bytes"] / 1e9, 3),
+                "kernel": f"{kname} (27-point A*A, FP64)",
                 "frac_of_measured_copy": round(achieved / copy_gbps, 4)}
 
     cpu = None
