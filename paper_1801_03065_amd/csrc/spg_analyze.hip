@@ -20,9 +20,12 @@ template <typename T>
 __global__ __launch_bounds__(BLK) void k_copy_rp(int64_t n1, const T *src, int64_t nnz, int64_t *dst, int *bad) {
     for (int64_t i = (int64_t)blockIdx.x * BLK + threadIdx.x; i < n1; i += (int64_t)gridDim.x * BLK) {
         int64_t v = (int64_t)src[i];
-        dst[i] = v;
         if ((i == 0 && v != 0) || (i > 0 && v < (int64_t)src[i - 1]) || (i == n1 - 1 && v != nnz))
             atomicOr(bad, 1);
+        // the copy is clamped to [0, nnz]: every row range read through it is
+        // empty or inside the arrays, so the analysis kernels that run before
+        // the host sees the flag cannot read out of bounds
+        dst[i] = min(max(v, (int64_t)0), nnz);
     }
 }
 
@@ -203,7 +206,7 @@ constexpr int RI_GRID = 2048;
 constexpr int RI_F = 6;  // rowinfo partial fields: fm, fmc, max, max compressed, fm and fmc of long rows
 static_assert(RI_F * RI_GRID <= RED_ELEMS && 4 * NK * CL_GRID <= RED_ELEMS, "analysis partials exceed scratch");
 
-__global__ __launch_bounds__(BLK) void k_rowinfo(int64_t m, const int64_t *arp, const int32_t *aci,
+__global__ __launch_bounds__(BLK) void k_rowinfo(int64_t m, int64_t n, const int64_t *arp, const int32_t *aci,
                                                   const BRow *bi, int64_t *rflops, int64_t *rflopsc,
                                                   int2 *rwin, long long *part) {
     const int q = threadIdx.x & (RI_GS - 1);
@@ -220,6 +223,7 @@ __global__ __launch_bounds__(BLK) void k_rowinfo(int64_t m, const int64_t *arp, 
             for (int u = 0; u < RI_U; ++u) {
                 const int64_t idx = base + q + u * RI_GS;
                 j[u] = idx < e ? aci[idx] : -1;
+                if ((uint64_t)(int64_t)j[u] >= (uint64_t)n) j[u] = -1;  // out of range (flagged): skipped
             }
             BRow br[RI_U];
 #pragma unroll
@@ -713,11 +717,11 @@ hipError_t launch_compress_sorted_flags(int64_t n, const int64_t *brp, const int
     return hipGetLastError();
 }
 
-hipError_t launch_rowinfo(int64_t m, const int64_t *arp, const int32_t *aci, const BRow *bi, int64_t *rflops,
+hipError_t launch_rowinfo(int64_t m, int64_t n, const int64_t *arp, const int32_t *aci, const BRow *bi, int64_t *rflops,
                           int64_t *rflopsc, int2 *rwin, DevStats *st, long long *part, hipStream_t s) {
     if (m == 0) return hipSuccess;
     const int g = grid_for(m * RI_GS, BLK, RI_GRID);
-    hipLaunchKernelGGL(k_rowinfo, dim3(g), dim3(BLK), 0, s, m, arp, aci, bi, rflops, rflopsc, rwin, part);
+    hipLaunchKernelGGL(k_rowinfo, dim3(g), dim3(BLK), 0, s, m, n, arp, aci, bi, rflops, rflopsc, rwin, part);
     hipLaunchKernelGGL(k_rowinfo_fin, dim3(1), dim3(BLK), 0, s, g, (const long long *)part, st);
     return hipGetLastError();
 }

@@ -305,7 +305,7 @@ static spg_status plan_buffers(spg_handle h, int64_t m, int64_t n, int64_t nnzb)
     HIPCHK(ensure(h->brp64, 8 * (n + 1)));
     HIPCHK(ensure(h->binfo, sizeof(BRow) * std::max<int64_t>(n, 1)));
     HIPCHK(ensure(h->ulist, 4 * std::max<int64_t>(n, 1)));
-    HIPCHK(ensure(h->uflag, std::max<int64_t>(n, 1)));
+    HIPCHK(ensure(h->uflag, 4 * ((std::max<int64_t>(n, 1) + 3) / 4)));
     HIPCHK(ensure(h->bcrp, 8 * (n + 1)));
     HIPCHK(ensure(h->rflops, 8 * std::max<int64_t>(m, 1)));
     HIPCHK(ensure(h->rflopsc, 8 * std::max<int64_t>(m, 1)));
@@ -337,10 +337,11 @@ static spg_status symbolic_core(spg_handle h, int64_t m, int64_t n, int64_t nnza
     BRow *bi = h->binfo.as<BRow>();
     HIPCHK(launch_brow(n, brp, bci, bi, h->ulist.as<int32_t>(), dst, st));
     HIPCHK(launch_brow_unsorted(h->ulist.as<int32_t>(), &dst->unsorted, brp, bci, bi, dst, st));
-    HIPCHK(launch_rowinfo(m, arp, aci, bi, h->rflops.as<int64_t>(), h->rflopsc.as<int64_t>(),
+    HIPCHK(launch_rowinfo(m, n, arp, aci, bi, h->rflops.as<int64_t>(), h->rflopsc.as<int64_t>(),
                           h->rwin.as<int2>(), dst, h->red.as<long long>(), st));
-    if ((s = pull_stats(h)) != SPG_OK) return s;  // host sync 1: flop counts
+    if ((s = pull_stats(h)) != SPG_OK) return s;  // host sync 1: input checks, flop counts
     const DevStats hs1 = *h->hst;
+    if (hs1.bad_input) return fail(h, SPG_ERR_INVALID_ARG, "malformed CSR: row_ptr or col_idx out of range");
     if (hs1.bad_window)
         return fail(h, SPG_ERR_UNSUPPORTED, "a row of B with unsorted columns spans more than 2^19 columns");
 
@@ -365,7 +366,7 @@ static spg_status symbolic_core(spg_handle h, int64_t m, int64_t n, int64_t nnza
         HIPCHK(launch_scan_i64(n, h->blens.as<int64_t>(), h->bcrp.as<int64_t>(), h->tmp.as<int64_t>(), st));
         HIPCHK(ensure(h->bcsi, 4 * std::max<int64_t>(nnzb, 1)));
         HIPCHK(ensure(h->bcs, 4 * std::max<int64_t>(nnzb, 1)));
-        HIPCHK(hipMemsetAsync(h->uflag.p, 0, std::max<int64_t>(n, 1), st));
+        HIPCHK(launch_fill_i32(h->uflag.as<int32_t>(), (std::max<int64_t>(n, 1) + 3) / 4, 0, st));
         HIPCHK(launch_mark_unsorted(h->ulist.as<int32_t>(), &dst->unsorted, h->uflag.as<uint8_t>(), st));
         HIPCHK(launch_compress_sorted_flags(n, brp, bci, bi, h->uflag.as<uint8_t>(), h->bcrp.as<int64_t>(),
                                             h->bcsi.as<int32_t>(), h->bcs.as<uint32_t>(), st));
@@ -395,7 +396,7 @@ static spg_status symbolic_core(spg_handle h, int64_t m, int64_t n, int64_t nnza
         cp.plan_cap = PL_CAP;
         cp.plan_len = h->plan_len.as<int32_t>();
     }
-    HIPCHK(hipMemsetAsync(h->row_words.p, 0, 4 * std::max<int64_t>(m, 1), st));
+    HIPCHK(launch_fill_i32(h->row_words.as<int32_t>(), std::max<int64_t>(m, 1), 0, st));
     HIPCHK(launch_classify(m, h->rflops.as<int64_t>(), h->rflopsc.as<int64_t>(), h->rwin.as<int2>(), nullptr,
                            nullptr, cp, h->kind_sym.as<uint8_t>(), h->row_nnz.as<int32_t>(), dst, h->red.as<long long>(), st));
     HIPCHK(launch_partition(m, h->kind_sym.as<uint8_t>(), h->perm_sym.as<int32_t>(), h->koff_sym.as<int64_t>(),
@@ -560,17 +561,16 @@ spg_status spgemm_symbolic(spg_handle h, const spg_csr *A, const spg_csr *B, voi
     hipStream_t st = h->stream;
     if ((s = plan_buffers(h, m, n, B->nnz)) != SPG_OK) return s;
     DevStats *dst = h->dstats.as<DevStats>();
-    HIPCHK(hipMemsetAsync(dst, 0, sizeof(DevStats), st));
+    HIPCHK(launch_fill_i32((int32_t *)dst, (int64_t)(sizeof(DevStats) / 4), 0, st));
     int *bad = &dst->bad_input;
+    // Row pointers are copied clamped to [0, nnz] and out-of-range columns of A
+    // are skipped by the analysis, so the kernels that run before the first
+    // host sync stay in bounds on malformed input; that sync rejects it before
+    // any structure kernel indexes B by A's columns.
     HIPCHK(launch_copy_rp(m + 1, A->row_ptr, A->rp_type == SPG_I64, A->nnz, h->arp64.as<int64_t>(), bad, st));
     HIPCHK(launch_copy_rp(n + 1, B->row_ptr, B->rp_type == SPG_I64, B->nnz, h->brp64.as<int64_t>(), bad, st));
     HIPCHK(launch_check_cols(A->nnz, A->col_idx, n, bad, st));
     HIPCHK(launch_check_cols(B->nnz, B->col_idx, k, bad, st));
-    // The structure kernels index B by A's columns: they run only on validated
-    // input, so a malformed operand is rejected before any of them.
-    if ((s = pull_stats(h)) != SPG_OK) return s;
-    if (h->hst->bad_input) return fail(h, SPG_ERR_INVALID_ARG, "malformed CSR: row_ptr or col_idx out of range");
-    HIPCHK(hipMemsetAsync(dst, 0, sizeof(DevStats), st));
     int64_t nnzc = 0;
     if ((s = symbolic_core(h, m, n, A->nnz, B->nnz, A->col_idx, B->col_idx, &nnzc)) != SPG_OK) return s;
     if (c_rpt == SPG_I32 && nnzc > INT32_MAX)

@@ -311,7 +311,7 @@ hipError_t launch_compress_unsorted(const int32_t *list, const int *count, const
 // Per-block partials of the analysis reductions (rowinfo, classify), folded
 // by a one-workgroup kernel: RED_ELEMS int64 of device scratch.
 constexpr int RED_ELEMS = 16384;
-hipError_t launch_rowinfo(int64_t m, const int64_t *arp, const int32_t *aci, const BRow *bi,
+hipError_t launch_rowinfo(int64_t m, int64_t n, const int64_t *arp, const int32_t *aci, const BRow *bi,
                           int64_t *rflops, int64_t *rflopsc, int2 *rwin, DevStats *st, long long *part,
                           hipStream_t s);
 hipError_t launch_copy_rp(int64_t n1, const void *src, int is64, int64_t nnz, int64_t *dst, int *bad,

@@ -269,3 +269,40 @@ def test_stored_structure_and_word_hash_mix():
     h.check_errors()
     ref2, S2 = oracle_ref(A2, B)
     check_f64(ref2, S2, (got[0], C.col_idx.cpu().numpy(), C.values.cpu().numpy()))
+
+
+def _malformed_cases():
+    """Operands a caller could pass by mistake; each must be rejected with
+    SPG_ERR_INVALID_ARG (the analysis before the check reads row ranges
+    clamped to the arrays and skips out-of-range columns)."""
+    A = synth.random_csr(40, 30, np.full(40, 3), 1)
+    B = synth.random_csr(30, 50, np.full(30, 4), 2)
+    cases = {}
+    rp = A.row_ptr.copy(); rp[5], rp[6] = rp[6], rp[5] + 100      # not monotone, past nnz
+    cases["row_ptr_not_monotone"] = (synth.Csr(A.nrows, A.ncols, rp, A.col_idx, A.values), B)
+    rp = A.row_ptr.copy(); rp[-1] = A.nnz - 2                      # last != nnz
+    cases["row_ptr_end"] = (synth.Csr(A.nrows, A.ncols, rp, A.col_idx, A.values), B)
+    ci = A.col_idx.copy(); ci[7] = 10 ** 6                         # column of A >= rows of B
+    cases["a_col_too_large"] = (synth.Csr(A.nrows, A.ncols, A.row_ptr, ci, A.values), B)
+    ci = A.col_idx.copy(); ci[3] = -5                              # negative column
+    cases["a_col_negative"] = (synth.Csr(A.nrows, A.ncols, A.row_ptr, ci, A.values), B)
+    ci = B.col_idx.copy(); ci[9] = 50                              # column of B >= its columns
+    cases["b_col_too_large"] = (A, synth.Csr(B.nrows, B.ncols, B.row_ptr, ci, B.values))
+    return A, B, cases
+
+
+@pytest.mark.parametrize("case", ["row_ptr_not_monotone", "row_ptr_end", "a_col_too_large", "a_col_negative",
+                                  "b_col_too_large"])
+def test_malformed_input_rejected_then_handle_reusable(case):
+    import paper_1801_03065_amd as spg
+    from helpers import dev
+
+    A, B, cases = _malformed_cases()
+    bA, bB = cases[case]
+    h = spg.Handle()
+    with pytest.raises(spg.SpgemmError) as ei:
+        spg.spgemm_symbolic(h, dev(bA), dev(bB))
+    assert ei.value.status == spg.SPG_ERR_INVALID_ARG
+    got, _ = run(A, B, handle=h)  # the same handle, valid operands
+    ref, S = oracle_ref(A, B)
+    check_f64(ref, S, got)
