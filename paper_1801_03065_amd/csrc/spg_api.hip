@@ -391,7 +391,7 @@ static spg_status symbolic_core(spg_handle h, int64_t m, int64_t n, int64_t nnza
     // the numeric phase (selector only)
     const bool want_plan = h->opt.accumulator == SPG_ACC_AUTO;
     if (want_plan) {
-        HIPCHK(ensure(h->plan_len, 4 * std::max<int64_t>(m, 1)));
+        HIPCHK(ensure(h->plan_len, 4 * (m + 2)));  // one padding element (8-byte reads of the last row)
         HIPCHK(ensure(h->plan_off, 8 * (m + 1)));
         cp.plan_cap = PL_CAP;
         cp.plan_len = h->plan_len.as<int32_t>();
@@ -433,6 +433,7 @@ static spg_status symbolic_core(spg_handle h, int64_t m, int64_t n, int64_t nnza
     sa.rs.koff = h->koff_sym.as<int64_t>();
     sa.st = dst;
     sa.lg_gs = lg_group(h->avg_len_c);
+    sa.b32 = nnzb < (int64_t(1) << 30);
     if (h->planned) {
         sa.plan_off = h->plan_off.as<int64_t>();
         sa.plan_len = h->plan_len.as<int32_t>();

@@ -183,108 +183,350 @@ __device__ __forceinline__ RowDesc row_desc(int i, const int64_t *arp, const int
     return d;
 }
 
+// LDS of the symbolic bit-window kernel: the window's bits and summary, and
+// two halves (row p, row p+1) of staging and of the row's (word, bits) list.
+struct SwLayout {
+    size_t bits, summ, half0, hsize, st_cbs, st_clen, pairs, total;
+};
+
+__host__ __device__ inline SwLayout sw_layout(int nwm) {
+    SwLayout L{};
+    const int nsm = (nwm + 31) >> 5;
+    size_t o = 0;
+    L.bits = o;
+    o += align16(4 * (size_t)nwm);
+    L.summ = o;
+    o += align16(4 * (size_t)nsm);
+    L.half0 = o;
+    size_t h = 0;
+    L.st_cbs = h;
+    h += 8 * WAVE;
+    L.st_clen = h;
+    h += 4 * WAVE;
+    L.pairs = h;
+    h += 8 * PL_CAP;
+    L.hsize = h;
+    o += 2 * h;
+    L.total = o;
+    return L;
+}
+
+constexpr int SW_SLOTS = 8;  // B rows per lane group held in registers (fast path)
+
+struct RowDescS {
+    int64_t ab, ae, poff;
+    int wlo, whi, plen, i;
+};
+
+// Symbolic phase, bit-window accumulator, one wavefront per row: the
+// compressed-B words of the row's B rows are ORed into an LDS bit array over
+// the row's column window, a summary bit per word marks the touched words;
+// row size = sum of their popcounts (Algorithm 3, symbolic branch).  The
+// touched words, in increasing order, are also kept as (word, bits) pairs
+// for the numeric phase.
+//
+// Software pipeline over the wavefront's rows p, p+s, ...: per row, first the
+// loads for later rows (row p+s's compressed extents, row p+2s's A entries,
+// row p+3s's descriptor, lane k < 5 holding field k, and row p+4s's index),
+// then row p's word gathers, then row p-s's stores (sizes and pairs, from the
+// other LDS half).  The memory counter retires in order, so waiting for the
+// gathers never waits for those stores, and the values for later rows have
+// landed by the time they are used.
+template <bool COMP>
 __global__ __launch_bounds__(WAVE) void k_sym_dw(SymArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
-    const DwLayout L = dw_layout(a.nw_max, 0, 0, false);
+    const SwLayout L = sw_layout(a.nw_max);
     uint32_t *bits = (uint32_t *)(smem + L.bits);
     uint32_t *summ = (uint32_t *)(smem + L.summ);
-    int64_t *st_cbs = (int64_t *)(smem + L.st_cbs);
-    int32_t *st_clen = (int32_t *)(smem + L.st_clen);
+    auto half = [&](int b) -> unsigned char * { return smem + L.half0 + (size_t)b * L.hsize; };
     const int l = lane_id();
     const int nsm = (a.nw_max + 31) >> 5;
     for (int w = l; w < a.nw_max; w += WAVE) bits[w] = 0;
     for (int w = l; w < nsm; w += WAVE) summ[w] = 0;
-    wave_lds_sync();
-    const bool comp = a.bcrp != nullptr;
-    const int64_t *srp = comp ? a.bcrp : a.brp;
+    // compression is a template parameter: a runtime branch between the two
+    // word sources inside the unrolled gathers makes the compiler wait for
+    // each load before issuing the next
+    const int64_t *srp = COMP ? a.bcrp : a.brp;
+    const int gs = 1 << a.lg_gs, g = l >> a.lg_gs, q = l & (gs - 1), ng = WAVE >> a.lg_gs;
     int64_t lo, hi;
     rs_bounds(a.rs, lo, hi);
     const Slice sl = xcd_slice(lo, hi);
-    // Software pipeline across rows: the next row's A entries and B extents
-    // (first chunk) load while the current row's words are OR-ed and counted.
-    int64_t r = sl.idx;
-    int icur = r < sl.end ? a.rs.rows[r] : 0;
-    RowDesc dcur = r < sl.end ? row_desc(icur, a.arp, a.rwin) : RowDesc{};
-    int64_t sc0 = 0, sc1 = 0;
-    if (r < sl.end && l < min((int64_t)WAVE, dcur.ae - dcur.ab)) {
-        const int j = a.aci[dcur.ab + l];
-        sc0 = srp[j];
-        sc1 = srp[j + 1];
+
+    // lanes 0-4: arp[i], arp[i+1], the window (first | last word), plan_off[i],
+    // plan_len[i] (its high word unused; the array has a padding element);
+    // two dword loads in every lane, no branch and no merge of the halves
+    // (either would wait for the loads)
+    auto load_desc = [&](int i) -> int64_t {
+        const uint32_t *src = (const uint32_t *)(a.arp + i + (l & 1));
+        if (l == 2) src = (const uint32_t *)(a.rwin + i);
+        if (l == 3 && a.plan) src = (const uint32_t *)(a.plan_off + i);
+        if (l == 4 && a.plan) src = (const uint32_t *)(a.plan_len + i);
+        const uint32_t vlo = src[0], vhi = src[1];
+        return (int64_t)(((uint64_t)vhi << 32) | vlo);
+    };
+    auto lane64 = [](int64_t v, int k) -> int64_t {
+        const uint32_t vlo = __builtin_amdgcn_readlane((uint32_t)v, k);
+        const uint32_t vhi = __builtin_amdgcn_readlane((uint32_t)((uint64_t)v >> 32), k);
+        return (int64_t)(((uint64_t)vhi << 32) | vlo);
+    };
+    auto to_uni = [&](int64_t v, int i) -> RowDescS {
+        RowDescS d;
+        d.ab = lane64(v, 0);
+        d.ae = lane64(v, 1);
+        const int64_t w = lane64(v, 2);
+        d.wlo = (int)(uint32_t)w;
+        d.whi = (int)(uint32_t)((uint64_t)w >> 32);
+        d.poff = a.plan ? lane64(v, 3) : 0;
+        d.plen = a.plan ? (int)__builtin_amdgcn_readlane((uint32_t)v, 4) : 0;
+        d.i = i;
+        return d;
+    };
+    // stage a row's first 64 A entries (compressed extent) into half b;
+    // returns 0 (slow path), 1 (fast path) or 2 (fast path, and some B row
+    // is longer than its lane group: an overflow pass follows)
+    auto stage = [&](int b, int64_t na, int64_t c0, uint32_t c1lo) -> int {
+        const int cn = (int)min((int64_t)WAVE, na);
+        const int len = (int)(c1lo - (uint32_t)c0);
+        if (l < cn) {
+            ((int64_t *)(half(b) + L.st_cbs))[l] = c0;
+            ((int32_t *)(half(b) + L.st_clen))[l] = len;
+        }
+        const bool fast = a.b32 && na <= WAVE && cn <= ng * SW_SLOTS;
+        return fast ? 1 + (__ballot(l < cn && len > gs) != 0) : 0;
+    };
+    const int64_t st1 = sl.step;
+    const int64_t p0 = sl.idx, pend = sl.end;
+    auto row_at = [&](int64_t pp) -> int { return pp < pend ? read_first(a.rs.rows[pp]) : 0; };
+
+    // ---- prologue (waits here are once per kernel)
+    const int i0 = row_at(p0), i1 = row_at(p0 + st1), i2 = row_at(p0 + 2 * st1);
+    RowDescS d = p0 < pend ? to_uni(load_desc(i0), i0) : RowDescS{};
+    int64_t rn = p0 + st1 < pend ? load_desc(i1) : 0;  // row p+s, raw
+    int in1 = i1;
+    int64_t r2 = p0 + 2 * st1 < pend ? load_desc(i2) : 0;  // row p+2s, raw
+    int in2 = i2;
+    int64_t nan = p0 + st1 < pend ? lane64(rn, 1) - lane64(rn, 0) : 0;
+    int64_t f2ab = 0, f2na = 0;
+    if (p0 + 2 * st1 < pend) {
+        f2ab = lane64(r2, 0);
+        f2na = lane64(r2, 1) - f2ab;
     }
-    int inext = r + sl.step < sl.end ? a.rs.rows[r + sl.step] : 0;
-    RowDesc dn = r + sl.step < sl.end ? row_desc(inext, a.arp, a.rwin) : RowDesc{};
-    while (r < sl.end) {
-        const int i = icur;
-        const RowDesc d = dcur;
-        r += sl.step;
-        const bool has_next = r < sl.end;
-        const int ncn = has_next ? (int)min((int64_t)WAVE, dn.ae - dn.ab) : 0;
-        // room for this row's (word, bits) pairs (loaded early, used at the end)
-        int64_t poff = 0;
-        int plen = 0;
-        if (a.plan) {
-            poff = a.plan_off[i];
-            plen = a.plan_len[i];
+    int i3u = row_at(p0 + 3 * st1);
+    int kc = 0;  // row p: slots per B row (0: slow path)
+    if (p0 < pend) {
+        const int cn = (int)min((int64_t)WAVE, d.ae - d.ab);
+        int64_t c0 = 0, c1 = 0;
+        if (l < cn) {
+            const int j = a.aci[d.ab + l];
+            c0 = srp[j];
+            c1 = srp[j + 1];
         }
-        for (int64_t cb = d.ab; cb < d.ae; cb += WAVE) {
-            int cn;
-            if (cb == d.ab) {  // first chunk: from the prefetched registers
-                cn = (int)min((int64_t)WAVE, d.ae - d.ab);
-                if (l < cn) {
-                    st_cbs[l] = sc0;
-                    st_clen[l] = (int32_t)(sc1 - sc0);
-                }
-                // next row, first level
-                int nj = 0;
-                if (l < ncn) nj = a.aci[dn.ab + l];
-                wave_lds_sync();
-                dw_or_staged(cn, d.wlo, comp, a.bci, a.bcsi, a.bcs, a.lg_gs, st_cbs, st_clen, bits, summ);
-                // next row, second level
-                if (l < ncn) {
-                    sc0 = srp[nj];
-                    sc1 = srp[nj + 1];
-                }
-            } else {
-                cn = dw_stage<double>(cb, d.ae, a.aci, nullptr, srp, nullptr, st_cbs, st_clen, nullptr, nullptr,
-                                      nullptr);
-                wave_lds_sync();
-                dw_or_staged(cn, d.wlo, comp, a.bci, a.bcsi, a.bcs, a.lg_gs, st_cbs, st_clen, bits, summ);
+        kc = stage(0, d.ae - d.ab, c0, (uint32_t)c1);
+    }
+    int nj = 0;  // row p+s: A column
+    if (p0 + st1 < pend && l < min((int64_t)WAVE, nan)) nj = a.aci[lane64(rn, 0) + l];
+    // the previous row's outputs, stored during the next row
+    int prev_i = -1, prev_cnt = 0, prev_nwt = 0, prev_plen = 0;
+    int64_t prev_poff = 0;
+    int b = 0;
+    wave_lds_sync();
+    for (int64_t pp = p0; pp < pend; pp += st1, b ^= 1) {
+        const bool has1 = pp + st1 < pend, has2 = pp + 2 * st1 < pend, has3 = pp + 3 * st1 < pend;
+        const int wlo = d.wlo;
+        const int64_t *st_cbs = (const int64_t *)(half(b) + L.st_cbs);
+        const int32_t *st_clen = (const int32_t *)(half(b) + L.st_clen);
+        uint2 *pairs = (uint2 *)(half(b) + L.pairs);
+        const int cn = (int)min((int64_t)WAVE, d.ae - d.ab);
+        const int kk = kc;
+
+        // ---- 1. loads for later rows
+        int64_t nc0 = 0;
+        uint32_t nc1 = 0;  // low word of srp[j+1]: only the length is needed
+        if (has1 && l < min((int64_t)WAVE, nan)) {
+            nc0 = srp[nj];
+            nc1 = ((const uint32_t *)srp)[2 * (nj + 1)];
+        }
+        int nnj = 0;
+        if (has2 && l < min((int64_t)WAVE, f2na)) nnj = a.aci[f2ab + l];
+        const int64_t raw3 = has3 ? load_desc(i3u) : 0;
+        const int in3 = i3u;
+        const int i4 = pp + 4 * st1 < pend ? a.rs.rows[pp + 4 * st1] : 0;
+
+        // ---- 2. gathers of row p: slot s2 covers B row t = g + s2 * ng, word q
+        uint32_t wd[SW_SLOTS], wc[SW_SLOTS];
+        unsigned okm = 0;
+        if (kk > 0) {
+            uint32_t cbv[SW_SLOTS];
+            int lenv[SW_SLOTS];
+#pragma unroll
+            for (int s2 = 0; s2 < SW_SLOTS; ++s2) {  // staging reads first: one LDS wait for all
+                const int tt = min(g + s2 * ng, cn - 1);
+                cbv[s2] = (uint32_t)st_cbs[tt];  // B entries < 2^30 on this path
+                lenv[s2] = st_clen[tt];
             }
-            wave_lds_sync();
-        }
-        icur = inext;
-        dcur = dn;
-        if (r + sl.step < sl.end) {
-            inext = a.rs.rows[r + sl.step];
-            dn = row_desc(inext, a.arp, a.rwin);
-        }
-        // count the touched words in increasing order (summary word s, then
-        // bit order); with a plan, store each as (word, bits) at its position
-        int cnt = 0, nwt = 0;
-        for (int s0 = 0; s0 < d.ns; s0 += WAVE) {
-            const int s = s0 + l;
-            uint32_t m = s < d.ns ? summ[s] : 0u;
-            if (s < d.ns) summ[s] = 0;
-            const int c = __popc(m);
-            const int inc = wave_incl_scan(c);
-            int pos = nwt + inc - c;
-            while (m) {
-                const int w = (s << 5) + __ffs(m) - 1;
-                m &= m - 1;
-                const uint32_t bw = bits[w];
-                cnt += __popc(bw);
-                bits[w] = 0;
-                if (pos < plen) a.plan[poff + pos] = make_uint2((uint32_t)(d.wlo + w), bw);
-                ++pos;
+#pragma unroll
+            for (int s2 = 0; s2 < SW_SLOTS; ++s2) {
+                const int t = g + s2 * ng;
+                const uint32_t cb = cbv[s2];
+                const int len = lenv[s2];
+                const bool ok = (t < cn) & (q < len);
+                okm |= (unsigned)ok << s2;
+                const uint32_t e = ok ? cb + (uint32_t)q : 0u;
+                if constexpr (COMP) {
+                    wd[s2] = (uint32_t)ld32(a.bcsi, e);
+                    wc[s2] = ld32(a.bcs, e);
+                } else {
+                    const int c = ld32(a.bci, e);
+                    wd[s2] = (uint32_t)(c >> 5);
+                    wc[s2] = 1u << (c & 31);
+                }
             }
-            nwt += __shfl(inc, WAVE - 1);
         }
-        cnt = wave_sum(cnt);
-        if (l == 0) {
-            a.row_nnz[i] = cnt;
-            a.row_words[i] = nwt;
+        // ---- 3. stores of row p-1 (its pairs from the other half)
+        if (prev_i >= 0) {
+            if (l == 0) {
+                a.row_nnz[prev_i] = prev_cnt;
+                a.row_words[prev_i] = prev_nwt;
+            }
+            const uint2 *pp2 = (const uint2 *)(half(b ^ 1) + L.pairs);
+            if (l < min(prev_nwt, prev_plen)) a.plan[prev_poff + l] = pp2[l];
+        }
+        // ---- 4. OR the words into the window
+        if (kk > 0) {
+#pragma unroll
+            for (int s2 = 0; s2 < SW_SLOTS; ++s2)
+                if (okm & (1u << s2)) dw_or(bits, summ, wd[s2] - (uint32_t)wlo, wc[s2]);
+            if (kk == 2) {  // words beyond the lane group of B rows longer than it
+                for (int t = g; t < cn; t += ng) {
+                    const int64_t cb = st_cbs[t];
+                    const int len = st_clen[t];
+                    for (int w = q + gs; w < len; w += gs) {
+                        uint32_t dd, cc;
+                        dw_word<COMP>(cb + w, wlo, a.bci, a.bcsi, a.bcs, dd, cc);
+                        dw_or(bits, summ, dd, cc);
+                    }
+                }
+            }
+        } else {
+            for (int64_t cb0 = d.ab; cb0 < d.ae; cb0 += WAVE) {
+                int ccn = cn;
+                const int64_t *scbs = st_cbs;
+                const int32_t *sclen = st_clen;
+                if (cb0 != d.ab) {  // later chunks: staged into the slow-path area of this half
+                    wave_lds_sync();
+                    int64_t *wcbs = (int64_t *)(half(b) + L.st_cbs);
+                    int32_t *wclen = (int32_t *)(half(b) + L.st_clen);
+                    ccn = dw_stage<double>(cb0, d.ae, a.aci, nullptr, srp, nullptr, wcbs, wclen, nullptr, nullptr,
+                                           nullptr);
+                    wave_lds_sync();
+                }
+                // rows beyond the fast path's registers: one word per lane at a
+                // time (kept light: the kernel's register budget is set by the
+                // fast path)
+                for (int t = g; t < ccn; t += ng) {
+                    const int64_t cb = scbs[t];
+                    const int len = sclen[t];
+                    for (int w = q; w < len; w += gs) {
+                        uint32_t dd, cc;
+                        dw_word<COMP>(cb + w, wlo, a.bci, a.bcsi, a.bcs, dd, cc);
+                        dw_or(bits, summ, dd, cc);
+                    }
+                }
+            }
         }
         wave_lds_sync();
+        // ---- 5. count the touched words in increasing order; keep (word, bits)
+        const int ns = (d.whi - wlo + 1 + 31) >> 5;
+        int cnt = 0, nwt = 0;
+        if (ns <= WAVE) {
+            // one summary word per lane: list the touched words (writes only),
+            // then, if they fit one pass, one word per lane in parallel
+            uint32_t m = l < ns ? summ[l] : 0u;
+            if (l < ns) summ[l] = 0;
+            const int c = __popc(m);
+            const int inc = wave_scan_dpp(c);
+            nwt = __builtin_amdgcn_readlane(inc, WAVE - 1);
+            uint32_t *list = (uint32_t *)pairs;  // word indices, then overwritten by the pairs
+            if (nwt <= WAVE) {
+                int pos = inc - c;
+                while (m) {
+                    list[pos++] = (uint32_t)((l << 5) + __ffs(m) - 1);
+                    m &= m - 1;
+                }
+                wave_lds_sync();
+                uint32_t w = 0, bw = 0;
+                if (l < nwt) {
+                    w = list[l];
+                    bw = bits[w];
+                    bits[w] = 0;
+                    cnt = __popc(bw);
+                }
+                wave_lds_sync();
+                if (l < nwt) pairs[l] = make_uint2((uint32_t)wlo + w, bw);
+            } else {
+                int pos = inc - c;
+                while (m) {
+                    const int w = (l << 5) + __ffs(m) - 1;
+                    m &= m - 1;
+                    const uint32_t bw = bits[w];
+                    cnt += __popc(bw);
+                    bits[w] = 0;
+                    if (pos < PL_CAP) pairs[pos] = make_uint2((uint32_t)(wlo + w), bw);
+                    ++pos;
+                }
+            }
+        } else {
+            for (int s0 = 0; s0 < ns; s0 += WAVE) {
+                const int s = s0 + l;
+                uint32_t m = s < ns ? summ[s] : 0u;
+                if (s < ns) summ[s] = 0;
+                const int c = __popc(m);
+                const int inc = wave_scan_dpp(c);
+                int pos = nwt + inc - c;
+                while (m) {
+                    const int w = (s << 5) + __ffs(m) - 1;
+                    m &= m - 1;
+                    const uint32_t bw = bits[w];
+                    cnt += __popc(bw);
+                    bits[w] = 0;
+                    if (pos < PL_CAP) pairs[pos] = make_uint2((uint32_t)(wlo + w), bw);
+                    ++pos;
+                }
+                nwt += __builtin_amdgcn_readlane(inc, WAVE - 1);
+            }
+        }
+        cnt = __builtin_amdgcn_readlane(wave_scan_dpp(cnt), WAVE - 1);
+        prev_i = d.i;
+        prev_cnt = cnt;
+        prev_nwt = nwt;
+        prev_poff = d.poff;
+        prev_plen = d.plen;
+        // ---- 6. next row: stage it, move the landed descriptors to scalars
+        if (has1) {
+            kc = stage(b ^ 1, nan, nc0, nc1);
+            d = to_uni(rn, in1);
+        }
+        if (has2) nan = lane64(r2, 1) - lane64(r2, 0);
+        if (has3) {
+            f2ab = lane64(raw3, 0);
+            f2na = lane64(raw3, 1) - f2ab;
+        }
+        i3u = read_first(i4);
+        rn = r2;
+        in1 = in2;
+        r2 = raw3;
+        in2 = in3;
+        nj = nnj;
+        wave_lds_sync();
+    }
+    // the last row's stores
+    if (prev_i >= 0) {
+        if (l == 0) {
+            a.row_nnz[prev_i] = prev_cnt;
+            a.row_words[prev_i] = prev_nwt;
+        }
+        const uint2 *pp2 = (const uint2 *)(half(b ^ 1) + L.pairs);
+        if (l < min(prev_nwt, prev_plen)) a.plan[prev_poff + l] = pp2[l];
     }
 }
 
@@ -695,15 +937,20 @@ inline int resident_grid(K kernel, int block, size_t lds, int cus) {
 
 }  // namespace
 
-size_t lds_sym_dw(int nw_max) { return dw_layout(nw_max, 0, 0, false).total; }
+size_t lds_sym_dw(int nw_max) { return sw_layout(nw_max).total; }
 size_t lds_num_dw(int nw_max, int r_max, int acc_bytes, int) { return dw_layout(nw_max, r_max, acc_bytes, true).total; }
 size_t lds_sym_dg(int nw_max) { return dg_layout(nw_max).total; }
 size_t lds_num_dg(int nw_max) { return dg_layout(nw_max).total; }
 
 hipError_t launch_sym_dw(const SymArgs &a, const LaunchCfg &c) {
     const size_t lds = lds_sym_dw(a.nw_max);
-    const int grid = c.grid > 0 ? c.grid : resident_grid(k_sym_dw, WAVE, lds, c.cus);
-    hipLaunchKernelGGL(k_sym_dw, dim3(grid), dim3(WAVE), lds, c.stream, a);
+    if (a.bcrp) {
+        const int grid = c.grid > 0 ? c.grid : resident_grid(k_sym_dw<true>, WAVE, lds, c.cus);
+        hipLaunchKernelGGL(k_sym_dw<true>, dim3(grid), dim3(WAVE), lds, c.stream, a);
+    } else {
+        const int grid = c.grid > 0 ? c.grid : resident_grid(k_sym_dw<false>, WAVE, lds, c.cus);
+        hipLaunchKernelGGL(k_sym_dw<false>, dim3(grid), dim3(WAVE), lds, c.stream, a);
+    }
     return hipGetLastError();
 }
 

@@ -104,6 +104,7 @@ struct SymArgs {
     const int64_t *plan_off;  // bit-window rows: where the row's (word, bits) pairs go
     const int32_t *plan_len;  // room for pairs per row (0: none stored)
     uint2 *plan;              // nullptr: no pairs stored
+    int b32;                  // nnz(B) < 2^30: B entries addressed with 32-bit byte offsets
     DevStats *st;
 };
 
