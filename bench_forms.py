@@ -3,7 +3,8 @@
 
 precision: symmetric R-MAT square (scale --rmat-scale, edge factor 16,
     (0.57, 0.19, 0.19, 0.05)); one symbolic, then numeric in FP64, FP32,
-    FP32 + compensated pairs, FP32 with FP64 accumulation.  Errors are stated
+    FP32 + compensated pairs, FP32 with FP64 accumulation, and FP32 with FP64
+    accumulation for the rows of at least 2^16 multiplications only.  Errors are stated
     against the FP64 oracle on sampled rows (the 200 heaviest rows and 2000
     uniform rows), relative to S = sum |a*b| per entry: max and median.
 batch: --batch-count products (n_i ~ U[1000, 65536], Poisson(lambda_i) rows,
@@ -74,10 +75,12 @@ def precision(args, log):
     rp_h = rp.cpu().numpy()
     idx = np.concatenate([np.arange(rp_h[i], rp_h[i + 1]) for i in sel])
     idx_t = torch.as_tensor(idx, device="cuda")
-    modes = {"fp64": (d64, torch.float64, 0), "fp32": (d32, torch.float32, 0),
-             "fp32_compensated": (d32, torch.float32, 1), "fp32_wide": (d32, torch.float32, 2)}
-    for name, (D, dt, mode) in modes.items():
-        hm = spg.Handle(stream=s, fp32_mode=mode)
+    heavy = 1 << 16  # rows with at least this many multiplications
+    modes = {"fp64": (d64, torch.float64, 0, 0), "fp32": (d32, torch.float32, 0, 0),
+             "fp32_compensated": (d32, torch.float32, 1, 0), "fp32_wide": (d32, torch.float32, 2, 0),
+             "fp32_heavy_rows_fp64": (d32, torch.float32, 0, heavy)}
+    for name, (D, dt, mode, thr) in modes.items():
+        hm = spg.Handle(stream=s, fp32_mode=mode, fp64_heavy_row_flops=thr)
         rpm, nnzm = spg.spgemm_symbolic(hm, D, D, torch.int64)
         ci = torch.empty(nnzm, dtype=torch.int32, device="cuda")
         va = torch.empty(nnzm, dtype=dt, device="cuda")
@@ -96,7 +99,8 @@ def precision(args, log):
         del C, ci, va
         hm.close()
         torch.cuda.empty_cache()
-    for k in ("fp32", "fp32_compensated", "fp32_wide"):
+    res["fp32_heavy_rows_fp64"]["heavy_row_flops"] = heavy
+    for k in ("fp32", "fp32_compensated", "fp32_wide", "fp32_heavy_rows_fp64"):
         res[k]["speedup_vs_fp64"] = round(res["fp64"]["numeric_ms"] / res[k]["numeric_ms"], 3)
     return res
 
@@ -130,10 +134,11 @@ def batch(args, log):
             spg.spgemm_batch_numeric(h, As, Bs, Cs)
         torch.cuda.synchronize()
         a, b = _ev()
-        a.record(s)
-        for _ in range(10):
-            g.replay()
-        b.record(s)
+        with torch.cuda.stream(s):  # a graph replays on the current stream: time it there
+            a.record(s)
+            for _ in range(10):
+                g.replay()
+            b.record(s)
         torch.cuda.synchronize()
         h.check_errors()
         ms = a.elapsed_time(b) / 10

@@ -180,9 +180,7 @@ def _distinct_columns(rng, counts: np.ndarray, ncols: int) -> tuple[np.ndarray, 
     rows = np.repeat(np.arange(m, dtype=np.int64), counts)
     cols = rng.integers(0, ncols, size=rows.shape[0], dtype=np.int64)
     while True:
-        keys = rows * ncols + cols
-        order = np.argsort(keys, kind="stable")
-        ks = keys[order]
+        ks = np.sort(rows * ncols + cols)
         dup = np.zeros(ks.shape[0], dtype=bool)
         dup[1:] = ks[1:] == ks[:-1]
         if not dup.any():
@@ -252,9 +250,19 @@ def batch_specs(count: int, seed: int, n_lo: int = 1000, n_hi: int = 65536,
                       seed * 100003 + 2 * i + 2) for i in range(count)]
 
 
-def batch_matrices(specs: list[BatchSpec]) -> list[tuple[Csr, Csr]]:
-    return [(poisson_square(s.n, s.lam, s.seed_a), poisson_square(s.n, s.lam, s.seed_b))
-            for s in specs]
+def _batch_pair(s: BatchSpec) -> tuple[Csr, Csr]:
+    return poisson_square(s.n, s.lam, s.seed_a), poisson_square(s.n, s.lam, s.seed_b)
+
+
+def batch_matrices(specs: list[BatchSpec], workers: int = 0) -> list[tuple[Csr, Csr]]:
+    """The batch's operands.  Each pair depends only on its own seeds, so with
+    workers > 1 they are generated in that many spawned processes (same result)."""
+    if workers <= 1 or len(specs) < 2 * workers:
+        return [_batch_pair(s) for s in specs]
+    import multiprocessing as mp
+
+    with mp.get_context("spawn").Pool(workers) as pool:
+        return pool.map(_batch_pair, specs, chunksize=max(1, len(specs) // (4 * workers)))
 
 
 def batch_revalue(pairs, recompute: int, base_seed: int):
