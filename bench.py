@@ -37,9 +37,9 @@ TRAFFIC = {
     "kernel": "k_num_pl",
     "sources": ["paper_1801_03065_amd/csrc/spg_plan.hip", "paper_1801_03065_amd/csrc/spg_internal.hpp",
                 "paper_1801_03065_amd/csrc/spg_accum.hpp"],
-    "sha256": "c8e003ba37da6d24e9526fd8fc77ef383336eb3a19c08ac2088367c462c49d14",
-    "read_bytes": 3.8404e9,
-    "write_bytes": 1.5082e9,
+    "sha256": "69a5b7a87bcd03282e3b71cdfbd51bf42c9cda0ec1f64e3ce8b52b4f5f4669a7",
+    "read_bytes": 3.8029e9,
+    "write_bytes": 1.5086e9,
 }
 
 
@@ -88,7 +88,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); "
-              "the path is single-GPU, see the sharding notes in DESIGN.md", file=sys.stderr)
+              "the library runs one product per GPU and has no multi-GPU sharding", file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -70,8 +70,10 @@ def precision(args, log):
     rng = np.random.default_rng(0)
     fl = oracle.flops(A, A)[2]
     sel = np.unique(np.concatenate([np.argsort(fl)[-200:], rng.integers(0, A.nrows, 2000)]))
-    orp, oci, oval, oS = oracle.rows(A.with_values(A.values.astype(np.float32).astype(np.float64)),
-                                     A.with_values(A.values.astype(np.float32).astype(np.float64)), sel)
+    A32 = A.with_values(A.values.astype(np.float32).astype(np.float64))
+    orp, oci, oval, oS = oracle.rows(A32, A32, sel)
+    _, _, oval64, oS64 = oracle.rows(A, A, sel)
+    log(f"[precision] oracle: {sel.size} sampled rows")
     rp_h = rp.cpu().numpy()
     idx = np.concatenate([np.arange(rp_h[i], rp_h[i + 1]) for i in sel])
     idx_t = torch.as_tensor(idx, device="cuda")
@@ -90,12 +92,13 @@ def precision(args, log):
         got_ci = C.col_idx[idx_t].cpu().numpy()
         got = C.values[idx_t].cpu().numpy().astype(np.float64)
         assert np.array_equal(got_ci, oci), name
-        ref = oval if dt == torch.float32 else oracle.rows(A, A, sel)[2]
-        S = oS if dt == torch.float32 else oracle.rows(A, A, sel)[3]
+        ref = oval if dt == torch.float32 else oval64
+        S = oS if dt == torch.float32 else oS64
         rel = np.abs(got - ref) / np.maximum(S, 1e-300)
         res[name] = {"numeric_ms": round(ms, 3), "gflops": round(2 * fm / (ms * 1e-3) / 1e9, 1),
                      "err_rel_S_max": float(rel.max()), "err_rel_S_median": float(np.median(rel)),
                      "sampled_entries": int(idx.size)}
+        log(f"[precision] {name}: {ms:.3f} ms, max err {rel.max():.3g} S")
         del C, ci, va
         hm.close()
         torch.cuda.empty_cache()
