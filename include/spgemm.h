@@ -124,7 +124,9 @@ typedef struct {
     int32_t n_kinds;                /* kinds in use: 0 empty, 1 bit window (wavefront),
                                        2 hash (wavefront), 3 bit window (workgroup),
                                        4 two-level hash, 5 word hash (numeric),
-                                       6 short rows (a team of lanes per row) */
+                                       6 short rows (a team of lanes per row),
+                                       7 stored structure (numeric on the (word, bits)
+                                       pairs the symbolic phase kept) */
     int64_t rows_symbolic[8];       /* rows per symbolic kernel kind */
     int64_t rows_numeric[8];        /* rows per numeric kernel kind */
     int32_t l2_spill_rows;          /* rows that used the level-2 (HBM) hash */

@@ -388,7 +388,21 @@ __global__ __launch_bounds__(BLK) void k_classify(int64_t m, const int64_t *rflo
                     else
                         k = wh_fit ? K_WH : (hw_fit ? K_HW : (dg_fit ? K_DG : K_HL));
             }
-            if (p.phase == 0 && p.plan_len) p.plan_len[i] = k == K_DW ? (int)min(words, (long long)p.plan_cap) : 0;
+            // heavy rows in segments: the symbolic bit window of a workgroup
+            // row cuts them, so rows that may exceed one segment go there
+            const long long eb = min(f, 32 * nw);  // entries bound
+            if (p.sg && p.phase == 0 && dg_fit &&
+                ((k == K_DW && eb > SG_CAP) || (k == K_HW && eb > p.hw_keys_max)))
+                k = K_DG;  // (a word-keyed hash row may still hold more entries than a numeric hash row)
+            if (p.sg && p.phase == 1 && k == K_DG && p.sym_kind[i] != K_DG && (bound > SG_CAP || nw > SG_NW))
+                k = hw_fit ? K_HW : K_HL;  // no segment list for this row
+            if (p.phase == 0 && p.plan_len) {
+                int room = 0;
+                if (k == K_DW && p.plan_cap > 0) room = (int)min(words, (long long)p.plan_cap);
+                if (k == K_DG && p.sg && (eb > SG_CAP || nw > SG_NW))
+                    room = (int)((eb + SG_CUT - 1) / SG_CUT + (nw + SG_NW - 1) / SG_NW + 2);
+                p.plan_len[i] = room;
+            }
             if (k == K_SR) bound = f;  // a short row's team size follows its multiplications
             a = (int)min(nw, (long long)INT_MAX);
             bnd = (int)min(bound, (long long)INT_MAX);

@@ -53,6 +53,8 @@ struct spg_handle_s {
     DevStats *hst = nullptr;            // pinned host copy of the device counters
     int64_t *hkoff = nullptr;           // pinned: [0] nnz(C), [1] stored-structure pairs
     bool planned = false;               // the symbolic phase stored row structure (K_PL rows)
+    bool sg_mode = false;               // heavy rows run in segments (B's rows sorted)
+    bool segmented = false;             // the symbolic phase wrote segment lists into plan
     spg_stats stats{};
 
     DevBuf arp64, brp64, binfo, ulist, uflag, bcrp, bcsi, bcs, rflops, rflopsc, rwin, row_nnz, coff, kind_sym,
@@ -388,13 +390,18 @@ static spg_status symbolic_core(spg_handle h, int64_t m, int64_t n, int64_t nnza
     cp.sample_stride = 1;
     cp.sr_f_max = SR_F_MAX;
     // stored row structure: bit-window rows keep their (word, bits) pairs for
-    // the numeric phase (selector only)
-    const bool want_plan = h->opt.accumulator == SPG_ACC_AUTO;
+    // the numeric phase (selector only); heavy rows keep their segment lists
+    // (selector and dense policy, B's rows sorted)
+    const bool want_pairs = h->opt.accumulator == SPG_ACC_AUTO;
+    const bool want_segs = hs1.unsorted == 0 &&
+                           (h->opt.accumulator == SPG_ACC_AUTO || h->opt.accumulator == SPG_ACC_DENSE);
+    const bool want_plan = want_pairs || want_segs;
     if (want_plan) {
         HIPCHK(ensure(h->plan_len, 4 * (m + 2)));  // one padding element (8-byte reads of the last row)
         HIPCHK(ensure(h->plan_off, 8 * (m + 1)));
-        cp.plan_cap = PL_CAP;
+        cp.plan_cap = want_pairs ? PL_CAP : 0;
         cp.plan_len = h->plan_len.as<int32_t>();
+        cp.sg = want_segs ? 1 : 0;
     }
     HIPCHK(launch_fill_i32(h->row_words.as<int32_t>(), std::max<int64_t>(m, 1), 0, st));
     HIPCHK(launch_classify(m, h->rflops.as<int64_t>(), h->rflopsc.as<int64_t>(), h->rwin.as<int2>(), nullptr,
@@ -409,12 +416,23 @@ static spg_status symbolic_core(spg_handle h, int64_t m, int64_t n, int64_t nnza
     if ((s = pull_stats(h)) != SPG_OK) return s;  // host sync 2: per-kind sizes, room for stored structure
     const DevStats hs2 = *h->hst;
     h->planned = false;
-    if (want_plan && hs2.kcount_sym[K_DW] > 0 && h->hkoff[1] > 0) {
-        // the pairs are an optimisation: without room for them the numeric
-        // phase rebuilds the structure itself
-        h->planned = ensure(h->plan, 8 * (size_t)h->hkoff[1]) == hipSuccess;
+    h->segmented = false;
+    const bool pairs_used = want_pairs && hs2.kcount_sym[K_DW] > 0;
+    const bool segs_used = want_segs && hs2.kcount_sym[K_DG] > 0;
+    bool plan_ok = false;
+    if ((pairs_used || segs_used) && h->hkoff[1] > 0) {
+        // without room for the pairs the numeric phase rebuilds the structure
+        // itself; without room for the segment lists heavy rows use the
+        // window-wide kernel
+        plan_ok = ensure(h->plan, 8 * (size_t)h->hkoff[1]) == hipSuccess;
         (void)hipGetLastError();
     }
+    h->planned = plan_ok && pairs_used;
+    h->segmented = plan_ok && segs_used;
+    // segments need a list wherever a row may exceed one (rows with a bound
+    // of room in plan_len): with lists missing, all heavy rows take the
+    // window-wide kernel
+    h->sg_mode = want_segs && (plan_ok || !segs_used || h->hkoff[1] == 0);
 
     SymArgs sa{};
     sa.arp = arp;
@@ -434,7 +452,7 @@ static spg_status symbolic_core(spg_handle h, int64_t m, int64_t n, int64_t nnza
     sa.st = dst;
     sa.lg_gs = lg_group(h->avg_len_c);
     sa.b32 = nnzb < (int64_t(1) << 30);
-    if (h->planned) {
+    if (h->planned || h->segmented) {
         sa.plan_off = h->plan_off.as<int64_t>();
         sa.plan_len = h->plan_len.as<int32_t>();
         sa.plan = h->plan.as<uint2>();
@@ -490,6 +508,7 @@ static spg_status symbolic_core(spg_handle h, int64_t m, int64_t n, int64_t nnza
     cp.phase = 1;
     cp.plan_cap = h->planned ? PL_CAP : 0;
     cp.sym_kind = h->kind_sym.as<uint8_t>();
+    cp.sg = h->sg_mode ? 1 : 0;
     const long long thr = h->opt.fp64_heavy_row_flops;
     cp.flops_lo = 0;
     cp.flops_hi = thr > 0 ? thr : 0;
@@ -636,7 +655,14 @@ static spg_status launch_kinds(spg_handle h, NumArgs<VT> na, const long long *kc
         na.ts = pow2_at_least(2 * (int64_t)kmax[K_HW][1], 64);
         HIPCHK(launch_num_hw<VT>(na, acc, lc));
     }
-    if (kcount[K_DG] > 0) {
+    if (kcount[K_DG] > 0 && h->sg_mode) {
+        na.rs.kind = K_DG;
+        na.rs.queue = h->queue.as<int32_t>() + XCDS * K_DG;
+        HIPCHK(launch_fill_i32(na.rs.queue, XCDS, 0, st));
+        lc.grid = std::min(grid_cap(kcount[K_DG]), sg_resident_grid(acc, sizeof(VT) == 8, h->cus));
+        HIPCHK(launch_num_sg<VT>(na, acc, lc));
+        lc.grid = 0;
+    } else if (kcount[K_DG] > 0) {
         na.rs.kind = K_DG;
         na.rs.queue = h->queue.as<int32_t>() + XCDS * K_DG;
         na.nw_max = ((kmax[K_DG][0] + 31) / 32) * 32;
@@ -770,10 +796,14 @@ static spg_status numeric_impl(spg_handle h, const VT *aval, const VT *bval, int
     na.rwin = h->rwin.as<int2>();
     na.coff = h->coff.as<int64_t>();
     na.b32 = h->fp.nnzb < (int64_t(1) << 29);
-    if (h->planned) {
+    if (h->planned || h->segmented) {
         na.plan_off = h->plan_off.as<int64_t>();
         na.plan = h->plan.as<uint2>();
         na.row_words = h->row_words.as<int32_t>();
+    }
+    if (h->segmented) {
+        na.plan_len = h->plan_len.as<int32_t>();
+        na.sym_kind = h->kind_sym.as<uint8_t>();
     }
     na.cci = cci;
     na.cval = cval;

@@ -810,6 +810,71 @@ __device__ __forceinline__ void dg_or_pass(int i, int wlo, const int64_t *arp, c
             });
 }
 
+// Segment list of a heavy row (the row's bit window is complete in bits /
+// summ): a segment starts at the touched word that holds entry q*SG_CUT for
+// each q, and at the first touched word of each aligned group of SG_NW words.
+// So a segment holds at most SG_CUT + 31 < SG_CAP entries and its words lie in
+// one group.  list[0] = (S, 0), list[1..S] = (first word, entries before it),
+// list[S+1] = (window words, row size).  Clears bits / summ; returns the row
+// size (low half) and touched words (high half).
+__device__ long long dg_segments(int nw, int ns, uint32_t *bits, uint32_t *summ, int *gfirst, long long *red,
+                                 uint2 *list, int cap, DevStats *st) {
+    const int t = threadIdx.x;
+    const int ng = (nw + SG_NW - 1) / SG_NW;
+    if (t < ng) gfirst[t] = INT_MAX;
+    __syncthreads();
+    for (int s = t; s < ns; s += WG_BIG) {
+        const uint32_t m = summ[s];
+        if (m) atomicMin(&gfirst[(s << 5) / SG_NW], (s << 5) + __ffs(m) - 1);
+    }
+    __syncthreads();
+    long long run = 0, words = 0, cuts = 0;
+    for (int s0 = 0; s0 < ns; s0 += WG_BIG) {
+        const int s = s0 + t;
+        const uint32_t m = s < ns ? summ[s] : 0u;
+        long long c = 0;
+        for (uint32_t mm = m; mm; mm &= mm - 1) c += __popc(bits[(s << 5) + __ffs(mm) - 1]);
+        long long tot;
+        const long long ex = block_excl_scan(c + ((long long)__popc(m) << 32), red, &tot);
+        const int pbeg = (int)(run + (ex & 0xffffffffll));
+        int p = pbeg, nc = 0;
+        for (uint32_t mm = m; mm; mm &= mm - 1) {
+            const int d = (s << 5) + __ffs(mm) - 1;
+            const int cd = __popc(bits[d]);
+            const int mult = ((p + SG_CUT - 1) / SG_CUT) * SG_CUT;  // first multiple of SG_CUT >= p
+            nc += (mult < p + cd || d == gfirst[d / SG_NW]) ? 1 : 0;
+            p += cd;
+        }
+        long long ctot;
+        long long idx = cuts + block_excl_scan(nc, red, &ctot);
+        p = pbeg;
+        for (uint32_t mm = m; mm; mm &= mm - 1) {
+            const int d = (s << 5) + __ffs(mm) - 1;
+            const int cd = __popc(bits[d]);
+            const int mult = ((p + SG_CUT - 1) / SG_CUT) * SG_CUT;
+            if (mult < p + cd || d == gfirst[d / SG_NW]) {
+                if (idx + 2 < cap) list[1 + idx] = make_uint2((uint32_t)d, (uint32_t)p);
+                ++idx;
+            }
+            p += cd;
+            bits[d] = 0;
+        }
+        if (s < ns) summ[s] = 0;
+        run += tot & 0xffffffffll;
+        words += tot >> 32;
+        cuts += ctot;
+    }
+    if (t == 0) {
+        if (cuts + 2 <= cap) {
+            list[0] = make_uint2((uint32_t)cuts, 0u);
+            list[1 + cuts] = make_uint2((uint32_t)nw, (uint32_t)run);
+        } else {
+            atomicAdd(&st->overflow, 1);
+        }
+    }
+    return run | (words << 32);
+}
+
 __global__ __launch_bounds__(WG_BIG) void k_sym_dg(SymArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     const DgLayout L = dg_layout(a.nw_max);
@@ -818,6 +883,7 @@ __global__ __launch_bounds__(WG_BIG) void k_sym_dg(SymArgs a) {
     int64_t *st_off = (int64_t *)(smem + L.st_off);
     int64_t *st_bs = (int64_t *)(smem + L.st_bs);
     long long *red = (long long *)(smem + L.red);
+    __shared__ int gfirst[DG_NW_MAX / SG_NW];
     const int t = threadIdx.x;
     const int nsm = (a.nw_max + 31) >> 5;
     for (int w = t; w < a.nw_max; w += WG_BIG) bits[w] = 0;
@@ -831,6 +897,16 @@ __global__ __launch_bounds__(WG_BIG) void k_sym_dg(SymArgs a) {
         const int2 win = a.rwin[i];
         const int ns = (win.y - win.x + 1 + 31) >> 5;
         dg_or_pass(i, win.x, a.arp, a.aci, a.brp, a.bci, a.bcrp, a.bcsi, a.bcs, bits, summ, st_off, st_bs, red);
+        const int cap = a.plan ? a.plan_len[i] : 0;
+        if (cap > 0) {
+            const long long r = dg_segments(win.y - win.x + 1, ns, bits, summ, gfirst, red, a.plan + a.plan_off[i],
+                                            cap, a.st);
+            if (t == 0) {
+                a.row_nnz[i] = (int32_t)(r & 0xffffffffll);
+                a.row_words[i] = (int32_t)(r >> 32);
+            }
+            continue;
+        }
         long long cnt = 0;
         for (int s = t; s < ns; s += WG_BIG) {
             uint32_t m = summ[s];

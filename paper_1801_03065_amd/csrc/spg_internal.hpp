@@ -62,6 +62,9 @@ constexpr int SR_F_MAX = 64;      // multiplications of a short row (one per lan
 constexpr int PL_CAP = 64;        // stored (word, bits) pairs per row (one per lane)
 constexpr int PL_NW_MAX = 8192;   // window words of the stored-structure kernel (byte map in LDS)
 constexpr int PL_R_MAX = 2048;    // row size of the stored-structure kernel
+constexpr int SG_NW = 4096;       // column-set words of one heavy-row segment (aligned groups)
+constexpr int SG_CAP = 4096;      // entries of one heavy-row segment (LDS values)
+constexpr int SG_CUT = SG_CAP - 32;  // a segment starts at the word holding each multiple of this
 
 // ------------------------------------------------------------ argument blocks
 struct RowSet {
@@ -136,6 +139,8 @@ struct NumArgs {
     const int64_t *plan_off;  // K_PL: the row's stored (word, bits) pairs
     const uint2 *plan;
     const int32_t *row_words; // K_PL: number of pairs of the row
+    const int32_t *plan_len;  // K_DG (segmented): room in plan per row
+    const uint8_t *sym_kind;  // K_DG (segmented): rows of symbolic kind K_DG with room hold a segment list
     int b32;               // nnz(B) * 8 < 2^32: B entries addressed with 32-bit offsets
     DevStats *st;
 };
@@ -340,6 +345,9 @@ struct ClassParams {
     int plan_cap;       // stored row structure: pairs per row (0: off)
     int32_t *plan_len;  // symbolic: room for pairs per row (written); numeric: read
     const uint8_t *sym_kind;  // numeric: kind of each row in the symbolic phase
+    int sg;             // heavy rows in segments (B's rows sorted): symbolic K_DG rows that may
+                        // need several segments get room for a list; numeric K_DG rows must
+                        // have one or fit a single segment
 };
 hipError_t launch_classify(int64_t m, const int64_t *rflops, const int64_t *rflopsc, const int2 *rwin,
                            const int32_t *row_nnz, const int32_t *row_words, ClassParams p, uint8_t *kind,
@@ -368,6 +376,10 @@ template <typename VT>
 hipError_t launch_num_dg(const NumArgs<VT> &a, int acc, const LaunchCfg &c);
 template <typename VT>
 hipError_t launch_num_hl(const NumArgs<VT> &a, int acc, const LaunchCfg &c);
+// Heavy rows in column segments (sorted B): the segment lists are in a.plan.
+template <typename VT>
+hipError_t launch_num_sg(const NumArgs<VT> &a, int acc, const LaunchCfg &c);
+int sg_resident_grid(int acc, bool dbl, int cus);
 template <typename VT>
 hipError_t launch_num_wh(const NumArgs<VT> &a, int acc, const LaunchCfg &c);
 template <typename VT>

@@ -1,0 +1,311 @@
+// Heavy rows in column segments: the dense accumulator of the Accumulators
+// subsection, cut to the size of LDS.
+//
+// A heavy row of C (thousands to a million entries spread over up to 2^20
+// columns) does not fit in LDS as a whole.  The symbolic phase, which holds
+// the row's complete bit window, cuts it into segments: runs of consecutive
+// column-set words with at most SG_CAP entries that stay inside one aligned
+// group of SG_NW words.  The numeric phase then walks the segments in column
+// order, one 256-lane workgroup per row:
+//
+//   1. the part of each B row that falls in the segment (B's columns are
+//      sorted, so it is one run, found by binary search; rows with one A
+//      entry chunk keep a cursor from segment to segment),
+//   2. structure: the run's columns OR-ed into an LDS bit array over the
+//      segment's words, Thread-Flat-Parallel over the segment's products,
+//   3. ranks: prefix popcounts of the words give every column its place in
+//      the row,
+//   4. values: each product added at its rank in LDS (Algorithm 1's
+//      accumulation), Thread-Flat-Parallel again,
+//   5. write-out: columns from the bits, values in rank order (coalesced),
+//      at the segment's offset in the row, which the symbolic phase recorded.
+//
+// Nothing lives in HBM but the inputs and C; a row with one segment (its
+// entries and window fit) runs the same steps once, with whole B rows.
+#include "spg_accum.hpp"
+#include "spg_internal.hpp"
+
+namespace spg {
+namespace {
+
+constexpr int SG_U = 4;  // products per lane per round of the flat walks (loads in flight)
+
+__device__ __forceinline__ long long sg_block_excl_scan(long long v, long long *red, long long *total) {
+    const int t = threadIdx.x, l = lane_id(), wv = t / WAVE;
+    const long long inc = wave_incl_scan64(v);
+    __syncthreads();
+    if (l == WAVE - 1) red[wv] = inc;
+    __syncthreads();
+    long long off = 0, tot = 0;
+#pragma unroll
+    for (int u = 0; u < WG_BIG / WAVE; ++u) {
+        const long long x = red[u];
+        if (u < wv) off += x;
+        tot += x;
+    }
+    *total = tot;
+    return off + inc - v;
+}
+
+__device__ __forceinline__ int sg_next_row(const RowSet &rs, int64_t lo, int64_t hi, int &x, long long *red) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int64_t t = xcd_grab(rs.queue, lo, hi, x);
+        red[WG_BIG / WAVE] = t < 0 ? -1 : rs.rows[t];
+        red[WG_BIG / WAVE + 1] = x;
+    }
+    __syncthreads();
+    x = (int)red[WG_BIG / WAVE + 1];
+    return (int)red[WG_BIG / WAVE];
+}
+
+// First index in [lo, hi) whose column is >= key (hi when none); the row's
+// columns are sorted.  The two ends are tested first: runs that start at the
+// row's start or end at its end need no search.
+__device__ __forceinline__ int64_t sg_lower_bound(const int32_t *bci, int64_t lo, int64_t hi, int64_t key) {
+    if (lo >= hi || (int64_t)bci[lo] >= key) return lo;
+    if ((int64_t)bci[hi - 1] < key) return hi;
+    ++lo;  // bci[lo] < key
+    --hi;  // bci[hi] >= key
+    while (lo < hi) {
+        const int64_t mid = lo + ((hi - lo) >> 1);
+        if ((int64_t)bci[mid] < key) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// Index k of the run that holds flat product f: the number of inclusive run
+// ends st_off[0..cn) that are <= f.
+__device__ __forceinline__ int sg_find(const int64_t *st_off, int cn, long long f) {
+    int k = 0;
+#pragma unroll
+    for (int step = WG_BIG / 2; step >= 1; step >>= 1)
+        if (k + step <= cn && st_off[k + step - 1] <= f) k += step;
+    return k;
+}
+
+template <typename VT, int ACC>
+__global__ __launch_bounds__(WG_BIG) void k_num_sg(NumArgs<VT> a) {
+    using A = Accum<VT, ACC>;
+    using S = typename A::store_t;
+    __shared__ __align__(16) uint32_t bits[SG_NW];
+    __shared__ uint16_t pre[SG_NW];
+    __shared__ S vals[SG_CAP];
+    __shared__ int64_t st_lo[WG_BIG];   // run start (B entry) per A entry of the chunk
+    __shared__ int64_t st_off[WG_BIG];  // inclusive prefix of the run lengths
+    __shared__ VT st_a[WG_BIG];
+    __shared__ long long red[WG_BIG / WAVE + 2];
+    const int t = threadIdx.x;
+    for (int w = t; w < SG_NW; w += WG_BIG) bits[w] = 0;
+    for (int r = t; r < SG_CAP; r += WG_BIG) vals[r] = A::zero();
+    int64_t qlo, qhi;
+    rs_bounds(a.rs, qlo, qhi);
+    const int64_t cbase = a.cbase_row >= 0 ? a.coff[a.cbase_row] : 0;
+    int x = blockIdx.x % XCDS;
+    for (;;) {
+        const int i = sg_next_row(a.rs, qlo, qhi, x, red);
+        if (i < 0) break;
+        const int2 win = a.rwin[i];
+        const int wlo = win.x, nw = win.y - win.x + 1;
+        const int64_t c0 = a.coff[i], nnz = a.coff[i + 1] - c0;
+        const int64_t ab = a.arp[i], ae = a.arp[i + 1];
+        const bool has_list = a.plan_len != nullptr && a.sym_kind[i] == K_DG && a.plan_len[i] > 0;
+        const uint2 *list = has_list ? a.plan + a.plan_off[i] : nullptr;
+        const int nseg = has_list ? (int)list[0].x : 1;
+        const bool single = nseg == 1;
+        const bool one_chunk = ae - ab <= WG_BIG;
+        // one chunk: lane t keeps A entry t for the whole row, with a cursor
+        // into its B row that moves from segment to segment
+        int64_t cur = 0, bend = 0;
+        int cn1 = 0;
+        if (one_chunk) {
+            cn1 = (int)(ae - ab);
+            if (t < cn1) {
+                const int j = a.aci[ab + t];
+                cur = a.brp[j];
+                bend = a.brp[j + 1];
+                st_a[t] = a.aval[ab + t];
+            }
+        }
+        int bad = 0;
+        for (int sg = 0; sg < nseg; ++sg) {
+            int w1 = 0, w2 = nw;
+            int64_t p1 = 0, p2 = nnz;
+            if (has_list) {
+                const uint2 d1 = list[1 + sg], d2 = list[2 + sg];
+                w1 = (int)d1.x;
+                p1 = d1.y;
+                w2 = (int)d2.x;
+                p2 = d2.y;
+            }
+            const int cnt = (int)(p2 - p1);
+            const int64_t col_lo = (int64_t)(wlo + w1) << 5, col_hi = (int64_t)(wlo + w2) << 5;
+            const int span = min(w2 - w1, SG_NW);
+            const int dbase = wlo + w1;  // column-set word of bits[0]
+            long long tot1 = 0;
+            if (one_chunk) {
+                long long len = 0;
+                if (t < cn1) {
+                    const int64_t e = single ? bend : sg_lower_bound(a.bci, cur, bend, col_hi);
+                    st_lo[t] = cur;
+                    len = e - cur;
+                    cur = e;
+                }
+                const long long ex = sg_block_excl_scan(len, red, &tot1);
+                if (t < cn1) st_off[t] = ex + len;
+                __syncthreads();
+            }
+            // pass 1 (structure) and pass 2 (values) walk the same runs
+            for (int pass = 0; pass < 2; ++pass) {
+                for (int64_t cb = ab; cb < ae; cb += WG_BIG) {
+                    int cn = cn1;
+                    long long tot = tot1;
+                    if (!one_chunk) {
+                        cn = (int)min((int64_t)WG_BIG, ae - cb);
+                        long long len = 0;
+                        if (t < cn) {
+                            const int j = a.aci[cb + t];
+                            int64_t s0 = a.brp[j], s1 = a.brp[j + 1];
+                            if (!single) {
+                                s0 = sg_lower_bound(a.bci, s0, s1, col_lo);
+                                s1 = sg_lower_bound(a.bci, s0, s1, col_hi);
+                            }
+                            st_lo[t] = s0;
+                            st_a[t] = a.aval[cb + t];
+                            len = s1 - s0;
+                        }
+                        const long long ex = sg_block_excl_scan(len, red, &tot);
+                        if (t < cn) st_off[t] = ex + len;
+                        __syncthreads();
+                    }
+                    for (long long f0 = 0; f0 < tot; f0 += (long long)WG_BIG * SG_U) {
+                        int64_t e[SG_U];
+                        int kk[SG_U];
+                        bool ok[SG_U];
+#pragma unroll
+                        for (int u = 0; u < SG_U; ++u) {
+                            const long long f = f0 + u * WG_BIG + t;
+                            ok[u] = f < tot;
+                            const int k = ok[u] ? sg_find(st_off, cn, f) : 0;
+                            kk[u] = k;
+                            e[u] = st_lo[k] + (f - (k ? st_off[k - 1] : 0));
+                        }
+                        int c[SG_U];
+#pragma unroll
+                        for (int u = 0; u < SG_U; ++u) c[u] = ok[u] ? a.bci[e[u]] : 0;
+                        if (pass == 0) {
+#pragma unroll
+                            for (int u = 0; u < SG_U; ++u) {
+                                const int d = (c[u] >> 5) - dbase;
+                                if (ok[u] && (unsigned)d < (unsigned)SG_NW) atomicOr(&bits[d], 1u << (c[u] & 31));
+                            }
+                        } else {
+                            VT v[SG_U];
+#pragma unroll
+                            for (int u = 0; u < SG_U; ++u) v[u] = ok[u] ? a.bval[e[u]] : VT(0);
+#pragma unroll
+                            for (int u = 0; u < SG_U; ++u) {
+                                const int d = (c[u] >> 5) - dbase;
+                                if (!ok[u] || (unsigned)d >= (unsigned)SG_NW) continue;
+                                const uint32_t below = (1u << (c[u] & 31)) - 1u;
+                                const int r = (int)pre[d] + __popc(bits[d] & below);
+                                if (r < SG_CAP) A::add(&vals[r], st_a[kk[u]], v[u]);
+                            }
+                        }
+                    }
+                    if (!one_chunk) __syncthreads();  // st_* are refilled for the next chunk
+                }
+                __syncthreads();
+                if (pass == 0) {
+                    // ranks: lane t scans words [t*SG_NW/WG_BIG, ...) of the segment
+                    constexpr int WPL = SG_NW / WG_BIG;
+                    const int wb = t * WPL;
+                    uint32_t wv[WPL];
+                    int sum = 0;
+#pragma unroll
+                    for (int u = 0; u < WPL; u += 4) {
+                        const uint4 q = *(const uint4 *)&bits[wb + u];
+                        wv[u] = q.x;
+                        wv[u + 1] = q.y;
+                        wv[u + 2] = q.z;
+                        wv[u + 3] = q.w;
+                    }
+#pragma unroll
+                    for (int u = 0; u < WPL; ++u) sum += __popc(wv[u]);
+                    long long tot;
+                    int run = (int)sg_block_excl_scan(sum, red, &tot);
+#pragma unroll
+                    for (int u = 0; u < WPL; ++u) {
+                        pre[wb + u] = (uint16_t)min(run, 65535);
+                        run += __popc(wv[u]);
+                    }
+                    if (tot != cnt) bad = 1;
+                    __syncthreads();
+                }
+            }
+            // write-out: columns from the bits (one word per lane, strided),
+            // values in rank order; both cleared for the next segment
+            const int64_t o = c0 + p1 - cbase;
+            for (int w = t; w < span; w += WG_BIG) {
+                uint32_t m = bits[w];
+                int r = pre[w];
+                const int colb = (dbase + w) << 5;
+                while (m) {
+                    const int b = __ffs(m) - 1;
+                    m &= m - 1;
+                    if (r < cnt) a.cci[o + r] = colb + b;
+                    ++r;
+                }
+                bits[w] = 0;
+            }
+            const int cw = min(cnt, SG_CAP);
+            for (int r = t; r < cw; r += WG_BIG) {
+                a.cval[o + r] = A::fin(vals[r]);
+                vals[r] = A::zero();
+            }
+            __syncthreads();
+        }
+        if (t == 0 && bad) atomicAdd(&a.st->mismatch, 1);
+    }
+}
+
+template <typename VT, int ACC>
+hipError_t num_sg_impl(const NumArgs<VT> &a, const LaunchCfg &c) {
+    int grid = c.grid;
+    if (grid <= 0) grid = sg_resident_grid(ACC, sizeof(VT) == 8, c.cus);
+    hipLaunchKernelGGL((k_num_sg<VT, ACC>), dim3(grid), dim3(WG_BIG), 0, c.stream, a);
+    return hipGetLastError();
+}
+
+template <typename K>
+int resident(K kernel, int cus) {
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, WG_BIG, 0) != hipSuccess || per_cu < 1)
+        per_cu = 1;
+    int g = per_cu * cus;
+    g = (g / XCDS) * XCDS;
+    return g < XCDS ? XCDS : g;
+}
+
+}  // namespace
+
+int sg_resident_grid(int acc, bool dbl, int cus) {
+    if (dbl) return resident(k_num_sg<double, ACC_NATIVE>, cus);
+    if (acc == ACC_COMP) return resident(k_num_sg<float, ACC_COMP>, cus);
+    if (acc == ACC_WIDE) return resident(k_num_sg<float, ACC_WIDE>, cus);
+    return resident(k_num_sg<float, ACC_NATIVE>, cus);
+}
+
+template <>
+hipError_t launch_num_sg<double>(const NumArgs<double> &a, int, const LaunchCfg &c) {
+    return num_sg_impl<double, ACC_NATIVE>(a, c);
+}
+template <>
+hipError_t launch_num_sg<float>(const NumArgs<float> &a, int acc, const LaunchCfg &c) {
+    if (acc == ACC_COMP) return num_sg_impl<float, ACC_COMP>(a, c);
+    if (acc == ACC_WIDE) return num_sg_impl<float, ACC_WIDE>(a, c);
+    return num_sg_impl<float, ACC_NATIVE>(a, c);
+}
+
+}  // namespace spg
