@@ -29,26 +29,19 @@ __global__ __launch_bounds__(BLK) void k_copy_rp(int64_t n1, const T *src, int64
     }
 }
 
-__global__ __launch_bounds__(BLK) void k_check_cols(int64_t nnz, const int32_t *ci, int64_t ncols, int *bad) {
-    int b = 0;
-    for (int64_t i = (int64_t)blockIdx.x * BLK + threadIdx.x; i < nnz; i += (int64_t)gridDim.x * BLK) {
-        const int32_t c = ci[i];
-        b |= (c < 0) | ((int64_t)c >= ncols);
-    }
-    if (__ballot(b) && lane_id() == 0) atomicOr(bad, 1);
-}
-
 // ------------------------------------------------------------------ B rows
 // One group of 16 lanes per row of B.  For rows whose columns are strictly
 // increasing, the number of distinct words col >> 5 is the number of word
 // changes along the row; other rows are queued for the LDS-bitmap kernel.
+// Columns outside [0, ncols) set the malformed-input flag.
 constexpr int BR_GS = 16;
 
-__global__ __launch_bounds__(BLK) void k_brow(int64_t n, const int64_t *brp, const int32_t *bci, BRow *out,
-                                               int32_t *ulist, DevStats *st) {
+__global__ __launch_bounds__(BLK) void k_brow(int64_t n, int64_t ncols, const int64_t *brp, const int32_t *bci,
+                                               BRow *out, int32_t *ulist, uint8_t *uflag, DevStats *st) {
     const int q = threadIdx.x & (BR_GS - 1);
     const int64_t g0 = ((int64_t)blockIdx.x * BLK + threadIdx.x) / BR_GS;
     const int64_t ng = (int64_t)gridDim.x * BLK / BR_GS;
+    int badcol = 0;
     for (int64_t r = g0; r < n; r += ng) {
         const int64_t b = brp[r], e = brp[r + 1];
         int cmin = INT_MAX, cmax = -1, heads = 0, unsorted = 0, prev_last = -1;
@@ -63,6 +56,7 @@ __global__ __launch_bounds__(BLK) void k_brow(int64_t n, const int64_t *brp, con
                 cmax = max(cmax, col);
                 unsorted |= (prevc >= col);
                 heads += ((col >> 5) != (prevc >> 5));
+                badcol |= (col < 0) | ((int64_t)col >= ncols);
             }
             prev_last = __shfl(col, BR_GS - 1, BR_GS);
         }
@@ -80,9 +74,11 @@ __global__ __launch_bounds__(BLK) void k_brow(int64_t n, const int64_t *brp, con
             o.wmin = (e > b) ? (cmin >> 5) : INT_MAX;
             o.wmax = (e > b) ? (cmax >> 5) : -1;
             out[r] = o;
+            uflag[r] = unsorted ? 1 : 0;
             if (unsorted) ulist[atomicAdd(&st->unsorted, 1)] = (int32_t)r;
         }
     }
+    if (__ballot(badcol) && lane_id() == 0) atomicOr(&st->bad_input, 1);
 }
 
 // One wavefront per listed row: OR every column bit into an LDS bitmap over
@@ -92,9 +88,11 @@ constexpr int UB_WORDS = 16384;
 
 __global__ __launch_bounds__(WAVE) void k_brow_unsorted(const int32_t *list, const int *count_p, const int64_t *brp,
                                                          const int32_t *bci, BRow *bi, const int64_t *bcrp,
-                                                         int32_t *bcsi, uint32_t *bcs, int mode, DevStats *st) {
+                                                         int32_t *bcsi, uint32_t *bcs, int mode, DevStats *st,
+                                                         const int *enable) {
     __shared__ uint32_t bits[UB_WORDS];
     const int l = lane_id();
+    if (enable && !*enable) return;
     const int count = *count_p;
     if ((int)blockIdx.x >= count) return;
     for (int w = l; w < UB_WORDS; w += WAVE) bits[w] = 0;
@@ -139,7 +137,9 @@ __global__ __launch_bounds__(WAVE) void k_brow_unsorted(const int32_t *list, con
 // chunk carries its partial bits there.
 __global__ __launch_bounds__(BLK) void k_compress_sorted(int64_t n, const int64_t *brp, const int32_t *bci,
                                                           const BRow *bi, const uint8_t *unsorted,
-                                                          const int64_t *bcrp, int32_t *bcsi, uint32_t *bcs) {
+                                                          const int64_t *bcrp, int32_t *bcsi, uint32_t *bcs,
+                                                          const int *enable) {
+    if (enable && !*enable) return;
     const int q = threadIdx.x & (BR_GS - 1);
     const int64_t g0 = ((int64_t)blockIdx.x * BLK + threadIdx.x) / BR_GS;
     const int64_t ng = (int64_t)gridDim.x * BLK / BR_GS;
@@ -186,11 +186,6 @@ __global__ __launch_bounds__(BLK) void k_compress_sorted(int64_t n, const int64_
     }
 }
 
-__global__ __launch_bounds__(BLK) void k_mark_unsorted(const int32_t *list, const int *count_p, uint8_t *flag) {
-    const int count = *count_p;
-    for (int t = blockIdx.x * BLK + threadIdx.x; t < count; t += gridDim.x * BLK) flag[list[t]] = 1;
-}
-
 // ------------------------------------------------------------------ A rows
 // 16 lanes per row of A: f_m(i) = sum |B(j,:)|, the same over compressed B,
 // and the word window [min wmin, max wmax] of the B rows it reads.
@@ -206,13 +201,24 @@ constexpr int RI_GRID = 2048;
 constexpr int RI_F = 6;  // rowinfo partial fields: fm, fmc, max, max compressed, fm and fmc of long rows
 static_assert(RI_F * RI_GRID <= RED_ELEMS && 4 * NK * CL_GRID <= RED_ELEMS, "analysis partials exceed scratch");
 
+// Compression rule of the Compression subsection, taken on the device from
+// the folded flop counts: compress when it removes more than (1 - thr) of the
+// flops of the rows that read B's structure word by word (all rows, or those
+// beyond the short-row limit when the selector is on).
+struct CompRule {
+    int opt;     // -1 by the rule, 0 never, 1 always
+    int sel;     // selector active: short rows read raw B
+    double thr;  // 0.85
+};
+
 __global__ __launch_bounds__(BLK) void k_rowinfo(int64_t m, int64_t n, const int64_t *arp, const int32_t *aci,
                                                   const BRow *bi, int64_t *rflops, int64_t *rflopsc,
-                                                  int2 *rwin, long long *part) {
+                                                  int2 *rwin, long long *part, DevStats *st) {
     const int q = threadIdx.x & (RI_GS - 1);
     const int64_t g0 = ((int64_t)blockIdx.x * BLK + threadIdx.x) / RI_GS;
     const int64_t ng = (int64_t)gridDim.x * BLK / RI_GS;
     long long s_fm = 0, s_fmc = 0, s_mx = 0, s_mxc = 0, s_fmb = 0, s_fmcb = 0;
+    int badcol = 0;
     for (int64_t i = g0; i < m; i += ng) {
         const int64_t b = arp[i], e = arp[i + 1];
         long long f = 0, fc = 0;
@@ -223,6 +229,7 @@ __global__ __launch_bounds__(BLK) void k_rowinfo(int64_t m, int64_t n, const int
             for (int u = 0; u < RI_U; ++u) {
                 const int64_t idx = base + q + u * RI_GS;
                 j[u] = idx < e ? aci[idx] : -1;
+                if (idx < e && (uint64_t)(int64_t)j[u] >= (uint64_t)n) badcol = 1;
                 if ((uint64_t)(int64_t)j[u] >= (uint64_t)n) j[u] = -1;  // out of range (flagged): skipped
             }
             BRow br[RI_U];
@@ -260,7 +267,7 @@ __global__ __launch_bounds__(BLK) void k_rowinfo(int64_t m, int64_t n, const int
         }
     }
     // per-block partials; k_rowinfo_fin folds them (same-address global
-    // atomics from every block would serialise in L2)
+    // atomics from every block would serialise)
     __shared__ long long red[RI_F][BLK / WAVE];
     s_fm = wave_sum64(s_fm);
     s_fmc = wave_sum64(s_fmc);
@@ -287,10 +294,12 @@ __global__ __launch_bounds__(BLK) void k_rowinfo(int64_t m, int64_t n, const int
         for (int u = 0; u < BLK / WAVE; ++u) v = (f == 2 || f == 3) ? max(v, red[f][u]) : v + red[f][u];
         part[RI_F * (int64_t)blockIdx.x + f] = v;
     }
+    if (__ballot(badcol) && lane_id() == 0) atomicOr(&st->bad_input, 1);
 }
 
-// One workgroup: fold the rowinfo partials of nb blocks into the statistics.
-__global__ __launch_bounds__(BLK) void k_rowinfo_fin(int nb, const long long *part, DevStats *st) {
+// One workgroup: fold the rowinfo partials of nb blocks into the statistics
+// and take the compression decision.
+__global__ __launch_bounds__(BLK) void k_rowinfo_fin(int nb, const long long *part, DevStats *st, CompRule rule) {
     long long v[RI_F];
 #pragma unroll
     for (int f = 0; f < RI_F; ++f) v[f] = 0;
@@ -314,39 +323,50 @@ __global__ __launch_bounds__(BLK) void k_rowinfo_fin(int nb, const long long *pa
             a[f] = 0;
             for (int u = 0; u < BLK / WAVE; ++u) a[f] = (f == 2 || f == 3) ? max(a[f], red[f][u]) : a[f] + red[f][u];
         }
-        if (a[0]) atomicAdd(&st->fm, ull(a[0]));
-        if (a[1]) atomicAdd(&st->fmc, ull(a[1]));
-        if (a[2]) atomicMax(&st->maxrf, ull(a[2]));
-        if (a[3]) atomicMax(&st->maxrfc, ull(a[3]));
-        if (a[4]) atomicAdd(&st->fmb, ull(a[4]));
-        if (a[5]) atomicAdd(&st->fmcb, ull(a[5]));
+        st->fm = ull(a[0]);
+        st->fmc = ull(a[1]);
+        st->maxrf = ull(a[2]);
+        st->maxrfc = ull(a[3]);
+        st->fmb = ull(a[4]);
+        st->fmcb = ull(a[5]);
+        int comp = rule.opt == 1;
+        if (rule.opt == -1) {
+            const double f0 = (double)(rule.sel ? a[4] : a[0]), f1 = (double)(rule.sel ? a[5] : a[1]);
+            comp = f0 > 0 && f1 < rule.thr * f0;
+        }
+        st->comp = comp;
     }
-}
-
-__global__ __launch_bounds__(BLK) void k_brow_lens(int64_t n, const BRow *bi, int which, int64_t *out) {
-    for (int64_t i = (int64_t)blockIdx.x * BLK + threadIdx.x; i < n; i += (int64_t)gridDim.x * BLK)
-        out[i] = which ? bi[i].lenc : bi[i].len;
 }
 
 // ------------------------------------------------------------------ classify
-__global__ __launch_bounds__(BLK) void k_classify(int64_t m, const int64_t *rflops, const int64_t *rflopsc,
-                                                   const int2 *rwin, const int32_t *row_nnz,
-                                                   const int32_t *row_words, ClassParams p, uint8_t *kind,
-                                                   int32_t *row_nnz_out, long long *part) {
+// One row per lane, CB rows per workgroup (contiguous, so the per-workgroup
+// kind counts are the counts of the stable partition).  Each workgroup writes
+// per kind: max window words, max bound, max touched words and its row count
+// (int32 x 4); k_classify_fold folds them into the phase's statistics and
+// turns the counts into the partition's offsets (kinds in order, workgroups in
+// row order within a kind).
+constexpr int CB = 1024;
+
+__global__ __launch_bounds__(CB) void k_classify(int64_t m, const int64_t *rflops, const int64_t *rflopsc,
+                                                  const int2 *rwin, const int32_t *row_nnz,
+                                                  const int32_t *row_words, ClassParams p, uint8_t *kind,
+                                                  int32_t *row_nnz_out, int32_t *blk) {
     __shared__ int smax[NK][3];
-    __shared__ long long scnt[NK];
-    if (threadIdx.x < NK) {
-        smax[threadIdx.x][0] = 0;
-        smax[threadIdx.x][1] = 0;
-        smax[threadIdx.x][2] = 0;
-        scnt[threadIdx.x] = 0;
+    __shared__ int scnt[NK];
+    const int t = threadIdx.x, l = lane_id();
+    if (t < NK) {
+        smax[t][0] = 0;
+        smax[t][1] = 0;
+        smax[t][2] = 0;
+        scnt[t] = 0;
     }
+    // device-side switches: compression decided by the analysis, segments
+    // only when every row of B is sorted
+    const bool compressed = p.comp_flag ? (*p.comp_flag != 0) : (p.compressed != 0);
+    const bool sg = p.sg && (p.unsorted == nullptr || *p.unsorted == 0);
     __syncthreads();
-    // every lane runs the same trip count so the wavefront reductions below
-    // see all 64 lanes active
-    const int64_t stride = (int64_t)gridDim.x * BLK;
-    for (int64_t i0 = (int64_t)blockIdx.x * BLK; i0 < m; i0 += stride) {
-        const int64_t i = i0 + threadIdx.x;
+    {
+        const int64_t i = (int64_t)blockIdx.x * CB + t;
         const bool valid = i < m;
         const bool sampled = p.sample_stride <= 1 || (i % p.sample_stride) == 0;
         long long f = (valid && sampled) ? rflops[i] : 0;
@@ -357,7 +377,7 @@ __global__ __launch_bounds__(BLK) void k_classify(int64_t m, const int64_t *rflo
             const long long nw = (long long)w.y - w.x + 1;
             long long bound, words;
             if (p.phase == 0) {
-                bound = p.compressed ? min((long long)rflopsc[i], nw) : min(f, 32 * nw);
+                bound = compressed ? min((long long)rflopsc[i], nw) : min(f, 32 * nw);
                 words = min(bound, nw);
             } else {
                 bound = row_nnz[i];
@@ -391,15 +411,15 @@ __global__ __launch_bounds__(BLK) void k_classify(int64_t m, const int64_t *rflo
             // heavy rows in segments: the symbolic bit window of a workgroup
             // row cuts them, so rows that may exceed one segment go there
             const long long eb = min(f, 32 * nw);  // entries bound
-            if (p.sg && p.phase == 0 && dg_fit &&
+            if (sg && p.phase == 0 && dg_fit &&
                 ((k == K_DW && eb > SG_CAP) || (k == K_HW && eb > p.hw_keys_max)))
                 k = K_DG;  // (a word-keyed hash row may still hold more entries than a numeric hash row)
-            if (p.sg && p.phase == 1 && k == K_DG && p.sym_kind[i] != K_DG && (bound > SG_CAP || nw > SG_NW))
+            if (sg && p.phase == 1 && k == K_DG && p.sym_kind[i] != K_DG && (bound > SG_CAP || nw > SG_NW))
                 k = hw_fit ? K_HW : K_HL;  // no segment list for this row
             if (p.phase == 0 && p.plan_len) {
                 int room = 0;
                 if (k == K_DW && p.plan_cap > 0) room = (int)min(words, (long long)p.plan_cap);
-                if (k == K_DG && p.sg && (eb > SG_CAP || nw > SG_NW))
+                if (k == K_DG && sg && (eb > SG_CAP || nw > SG_NW))
                     room = (int)((eb + SG_CUT - 1) / SG_CUT + (nw + SG_NW - 1) / SG_NW + 2);
                 p.plan_len[i] = room;
             }
@@ -412,151 +432,148 @@ __global__ __launch_bounds__(BLK) void k_classify(int64_t m, const int64_t *rflo
             if (p.plan_len) p.plan_len[i] = 0;
         }
         if (valid) kind[i] = (uint8_t)k;
-        // aggregate over the wavefront per kind, then one LDS atomic per kind
+        if (valid && p.words_out) p.words_out[i] = 0;  // the structure kernels fill it for their rows
         for (int kk = 0; kk < NK; ++kk) {
             const unsigned long long bal = __ballot(k == kk);
             if (!bal) continue;
             const int ma = wave_max(k == kk ? a : 0), mb = wave_max(k == kk ? bnd : 0);
             const int mc = wave_max(k == kk ? tw : 0);
-            if (lane_id() == 0) {
+            if (l == 0) {
                 atomicMax(&smax[kk][0], ma);
                 atomicMax(&smax[kk][1], mb);
                 atomicMax(&smax[kk][2], mc);
-                atomicAdd((unsigned long long *)&scnt[kk], (unsigned long long)__popcll(bal));
+                atomicAdd(&scnt[kk], __popcll(bal));
             }
         }
     }
     __syncthreads();
-    // per-block partials, folded by k_classify_fin
-    if (threadIdx.x < NK) {
-        long long *pp = part + 4 * ((int64_t)blockIdx.x * NK + threadIdx.x);
-        pp[0] = smax[threadIdx.x][0];
-        pp[1] = smax[threadIdx.x][1];
-        pp[2] = smax[threadIdx.x][2];
-        pp[3] = scnt[threadIdx.x];
+    if (t < NK) {
+        int32_t *q = blk + 4 * ((int64_t)blockIdx.x * NK + t);
+        q[0] = smax[t][0];
+        q[1] = smax[t][1];
+        q[2] = smax[t][2];
+        q[3] = scnt[t];
     }
 }
 
-// One workgroup: fold the classify partials of nb blocks into the per-kind
-// counts and maxima of the phase (only kinds that have rows are touched).
-// Each thread loads all fields of its blocks at once (the loads overlap).
-__global__ __launch_bounds__(BLK) void k_classify_fin(int nb, const long long *part, int phase, int heavy,
+// Inclusive max-scan over the 64 lanes (values >= 0) with DPP lane moves;
+// lane 63 holds the wavefront maximum.
+__device__ __forceinline__ int wave_maxscan_dpp(int v) {
+    v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x111, 0xF, 0xF, false));  // row_shr:1
+    v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x112, 0xF, 0xF, false));  // row_shr:2
+    v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x114, 0xF, 0xF, false));  // row_shr:4
+    v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x118, 0xF, 0xF, false));  // row_shr:8
+    v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x142, 0xA, 0xF, false));  // row_bcast:15
+    v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x143, 0xC, 0xF, false));  // row_bcast:31
+    return v;
+}
+
+// One workgroup over the nb classify workgroups: per kind the row total and
+// the maxima (into the phase's statistics), the kind offsets koff, and each
+// workgroup's count replaced by its exclusive offset (kinds in order, row order
+// within a kind).  Counts and offsets fit int32 (rows are int32).
+__global__ __launch_bounds__(CB) void k_classify_fold(int64_t nb, int32_t *blk, int64_t *koff, int phase, int heavy,
                                                        DevStats *st) {
-    __shared__ long long red[NK * 4][BLK / WAVE];
-    const int wv = threadIdx.x / WAVE;
-    long long acc[NK * 4];
-#pragma unroll
-    for (int f = 0; f < NK * 4; ++f) acc[f] = 0;
-    for (int k = threadIdx.x; k < nb; k += BLK) {
-        long long x[NK * 4];
-#pragma unroll
-        for (int f = 0; f < NK * 4; ++f) x[f] = part[4 * ((int64_t)k * NK) + f];
-#pragma unroll
-        for (int f = 0; f < NK * 4; ++f) acc[f] = (f & 3) == 3 ? acc[f] + x[f] : max(acc[f], x[f]);
-    }
-#pragma unroll
-    for (int f = 0; f < NK * 4; ++f) {
-        const long long v = (f & 3) == 3 ? wave_sum64(acc[f]) : wave_max64(acc[f]);
-        if (lane_id() == 0) red[f][wv] = v;
-    }
-    __syncthreads();
-    if (threadIdx.x < NK) {
-        const int kk = threadIdx.x;
-        long long m0 = 0, m1 = 0, m2 = 0, c = 0;
-        for (int u = 0; u < BLK / WAVE; ++u) {
-            m0 = max(m0, red[4 * kk][u]);
-            m1 = max(m1, red[4 * kk + 1][u]);
-            m2 = max(m2, red[4 * kk + 2][u]);
-            c += red[4 * kk + 3][u];
-        }
-        if (c) {
-            int *gm = phase == 0 ? &st->kmax_sym[kk][0] : heavy ? &st->kmax_heavy[kk][0] : &st->kmax_num[kk][0];
-            atomicMax(gm, (int)m0);
-            atomicMax(gm + 1, (int)m1);
-            atomicMax(gm + 2, (int)m2);
-            long long *gc = phase == 0 ? &st->kcount_sym[kk] : heavy ? &st->kcount_heavy[kk] : &st->kcount_num[kk];
-            atomicAdd((unsigned long long *)gc, (unsigned long long)c);
-        }
-    }
-}
-
-// ------------------------------------------------------------------ partition
-// Stable partition of rows by kind: per-block counts, a scan over blocks per
-// kind, then an in-order scatter using wavefront ballots.
-constexpr int PB = 1024;  // rows per block
-
-__global__ __launch_bounds__(PB) void k_part_count(int64_t m, const uint8_t *kind, int64_t *blk) {
-    __shared__ int cnt[NK];
-    if (threadIdx.x < NK) cnt[threadIdx.x] = 0;
-    __syncthreads();
-    const int64_t i = (int64_t)blockIdx.x * PB + threadIdx.x;
-    if (i < m) atomicAdd(&cnt[kind[i]], 1);
-    __syncthreads();
-    if (threadIdx.x < NK) blk[(int64_t)blockIdx.x * NK + threadIdx.x] = cnt[threadIdx.x];
-}
-
-__global__ __launch_bounds__(PB) void k_part_scan(int64_t nb, int64_t *blk, int64_t *koff) {
-    // one block.  Pass 1: per-kind totals -> koff (kinds in order).  Pass 2:
-    // every thread loads all kinds of its block at once, then one scan per
-    // kind over the blocks (loads overlap instead of one round trip per kind).
-    __shared__ long long wsum[NK][PB / WAVE];
-    __shared__ long long base[NK];
+    constexpr int NW = CB / WAVE;
+    __shared__ int smax[NK][3];
+    __shared__ int wsum[NK][NW];
+    __shared__ int woff[NK][NW];
+    __shared__ int base[NK];
+    __shared__ long long ktot[NK];
     const int t = threadIdx.x, l = lane_id(), wv = t / WAVE;
-    long long tot[NK];
+    if (t < NK) smax[t][0] = smax[t][1] = smax[t][2] = 0;
+    // pass 1: totals and maxima (a single chunk keeps its counts for pass 2)
+    int tot[NK], mx[NK][3], own[NK];
 #pragma unroll
-    for (int k = 0; k < NK; ++k) tot[k] = 0;
-    for (int64_t b = t; b < nb; b += PB)
+    for (int k = 0; k < NK; ++k) tot[k] = mx[k][0] = mx[k][1] = mx[k][2] = own[k] = 0;
+    for (int64_t b = t; b < nb; b += CB) {
+        const int4 *q = (const int4 *)(blk + 4 * b * NK);
 #pragma unroll
-        for (int k = 0; k < NK; ++k) tot[k] += blk[b * NK + k];
+        for (int k = 0; k < NK; ++k) {
+            const int4 v = q[k];
+            if (b == t) own[k] = v.w;
+            tot[k] += v.w;
+            mx[k][0] = max(mx[k][0], v.x);
+            mx[k][1] = max(mx[k][1], v.y);
+            mx[k][2] = max(mx[k][2], v.z);
+        }
+    }
+    __syncthreads();
 #pragma unroll
     for (int k = 0; k < NK; ++k) {
-        const long long v = wave_sum64(tot[k]);
-        if (l == 0) wsum[k][wv] = v;
+        const int ts = __builtin_amdgcn_readlane(wave_scan_dpp(tot[k]), 63);
+        const int m0 = __builtin_amdgcn_readlane(wave_maxscan_dpp(mx[k][0]), 63);
+        const int m1 = __builtin_amdgcn_readlane(wave_maxscan_dpp(mx[k][1]), 63);
+        const int m2 = __builtin_amdgcn_readlane(wave_maxscan_dpp(mx[k][2]), 63);
+        if (l == 0) {
+            wsum[k][wv] = ts;
+            atomicMax(&smax[k][0], m0);
+            atomicMax(&smax[k][1], m1);
+            atomicMax(&smax[k][2], m2);
+        }
+    }
+    __syncthreads();
+    if (t < NK) {
+        long long kt = 0;
+        for (int u = 0; u < NW; ++u) kt += wsum[t][u];
+        ktot[t] = kt;
     }
     __syncthreads();
     if (t == 0) {
         long long run = 0;
         for (int k = 0; k < NK; ++k) {
-            long long kt = 0;
-            for (int u = 0; u < PB / WAVE; ++u) kt += wsum[k][u];
+            const long long kt = ktot[k];
             koff[k] = run;
-            base[k] = run;
+            base[k] = (int)run;
             run += kt;
         }
         koff[NK] = run;
     }
+    if (t < NK && ktot[t]) {
+        const int k = t;
+        int *gm = phase == 0 ? &st->kmax_sym[k][0] : heavy ? &st->kmax_heavy[k][0] : &st->kmax_num[k][0];
+        gm[0] = max(gm[0], smax[k][0]);
+        gm[1] = max(gm[1], smax[k][1]);
+        gm[2] = max(gm[2], smax[k][2]);
+        long long *gc = phase == 0 ? &st->kcount_sym[k] : heavy ? &st->kcount_heavy[k] : &st->kcount_num[k];
+        *gc += ktot[k];
+    }
     __syncthreads();
-    for (int64_t c0 = 0; c0 < nb; c0 += PB) {
+    // pass 2: exclusive offsets per kind over the workgroups, in row order
+    for (int64_t c0 = 0; c0 < nb; c0 += CB) {
         const int64_t b = c0 + t;
-        long long v[NK], inc[NK];
-#pragma unroll
-        for (int k = 0; k < NK; ++k) v[k] = b < nb ? blk[b * NK + k] : 0;
+        int v[NK], inc[NK];
 #pragma unroll
         for (int k = 0; k < NK; ++k) {
-            inc[k] = wave_incl_scan64(v[k]);
+            v[k] = nb <= CB ? own[k] : (b < nb ? blk[4 * (b * NK + k) + 3] : 0);
+            inc[k] = wave_scan_dpp(v[k]);
             if (l == WAVE - 1) wsum[k][wv] = inc[k];
         }
         __syncthreads();
-#pragma unroll
-        for (int k = 0; k < NK; ++k) {
-            long long off = 0;
-            for (int u = 0; u < wv; ++u) off += wsum[k][u];
-            if (b < nb) blk[b * NK + k] = base[k] + off + inc[k] - v[k];
+        if (t < NK * NW) {  // exclusive prefix of the wavefront totals, per kind
+            const int k = t / NW, u = t % NW;
+            int o = 0;
+            for (int x = 0; x < u; ++x) o += wsum[k][x];
+            woff[k][u] = o;
         }
         __syncthreads();
-        if (t < NK) {
-            long long ct = 0;
-            for (int u = 0; u < PB / WAVE; ++u) ct += wsum[t][u];
-            base[t] += ct;
-        }
+#pragma unroll
+        for (int k = 0; k < NK; ++k)
+            if (b < nb) blk[4 * (b * NK + k) + 3] = base[k] + woff[k][wv] + inc[k] - v[k];
+        __syncthreads();
+        if (t < NK) base[t] += woff[t][NW - 1] + wsum[t][NW - 1];
         __syncthreads();
     }
 }
-__global__ __launch_bounds__(PB) void k_part_scatter(int64_t m, const uint8_t *kind, const int64_t *blk,
+
+// ------------------------------------------------------------------ partition
+// Stable partition of rows by kind: the classify workgroup offsets plus the
+// row's rank among the same kind in its workgroup (wavefront ballots).
+__global__ __launch_bounds__(CB) void k_part_scatter(int64_t m, const uint8_t *kind, const int32_t *blk,
                                                       int32_t *perm) {
-    __shared__ int wcnt[PB / WAVE][NK];
+    __shared__ int wcnt[CB / WAVE][NK];
     const int t = threadIdx.x, l = lane_id(), wv = t / WAVE;
-    const int64_t i = (int64_t)blockIdx.x * PB + t;
+    const int64_t i = (int64_t)blockIdx.x * CB + t;
     const int k = i < m ? kind[i] : -1;
     int rank = 0;
     for (int kk = 0; kk < NK; ++kk) {
@@ -568,15 +585,20 @@ __global__ __launch_bounds__(PB) void k_part_scatter(int64_t m, const uint8_t *k
     if (i < m) {
         int off = 0;
         for (int u = 0; u < wv; ++u) off += wcnt[u][k];
-        perm[blk[(int64_t)blockIdx.x * NK + k] + off + rank] = (int32_t)i;
+        perm[blk[4 * ((int64_t)blockIdx.x * NK + k) + 3] + off + rank] = (int32_t)i;
     }
 }
 
 // ------------------------------------------------------------------ scans
 constexpr int SC_T = 256, SC_E = 8, SC_B = SC_T * SC_E;
 
+// Local scans with block sums, one workgroup scans the block sums (total to
+// out[n]), then the block offsets are added.  enable (optional, device): when
+// it reads 0 the scan is skipped.
 template <typename T>
-__global__ __launch_bounds__(SC_T) void k_scan_local(int64_t n, const T *in, int64_t *out, int64_t *bsum) {
+__global__ __launch_bounds__(SC_T) void k_scan_local(int64_t n, const T *in, int stride, int64_t *out, int64_t *bsum,
+                                                      const int *enable) {
+    if (enable && !*enable) return;
     __shared__ long long wsum[SC_T / WAVE];
     const int t = threadIdx.x, l = lane_id(), wv = t / WAVE;
     const int64_t base = (int64_t)blockIdx.x * SC_B + (int64_t)t * SC_E;
@@ -584,7 +606,7 @@ __global__ __launch_bounds__(SC_T) void k_scan_local(int64_t n, const T *in, int
     long long s = 0;
 #pragma unroll
     for (int e = 0; e < SC_E; ++e) {
-        v[e] = (base + e < n) ? (long long)in[base + e] : 0;
+        v[e] = (base + e < n) ? (long long)in[(base + e) * stride] : 0;
         s += v[e];
     }
     const long long inc = wave_incl_scan64(s);
@@ -601,7 +623,8 @@ __global__ __launch_bounds__(SC_T) void k_scan_local(int64_t n, const T *in, int
     if (t == SC_T - 1) bsum[blockIdx.x] = off + inc;
 }
 
-__global__ __launch_bounds__(SC_T) void k_scan_top(int64_t nb, int64_t *bsum, int64_t *total_out) {
+__global__ __launch_bounds__(SC_T) void k_scan_top(int64_t nb, int64_t *bsum, int64_t *total_out, const int *enable) {
+    if (enable && !*enable) return;
     __shared__ long long wsum[SC_T / WAVE];
     __shared__ long long carry;
     const int t = threadIdx.x, l = lane_id(), wv = t / WAVE;
@@ -626,7 +649,8 @@ __global__ __launch_bounds__(SC_T) void k_scan_top(int64_t nb, int64_t *bsum, in
     if (t == 0) *total_out = carry;
 }
 
-__global__ __launch_bounds__(SC_T) void k_scan_add(int64_t n, int64_t *out, const int64_t *bsum) {
+__global__ __launch_bounds__(SC_T) void k_scan_add(int64_t n, int64_t *out, const int64_t *bsum, const int *enable) {
+    if (enable && !*enable) return;
     const int64_t base = (int64_t)blockIdx.x * SC_B;
     const long long add = bsum[blockIdx.x];
     for (int e = threadIdx.x; e < SC_B; e += SC_T)
@@ -685,16 +709,11 @@ hipError_t launch_copy_rp(int64_t n1, const void *src, int is64, int64_t nnz, in
     return hipGetLastError();
 }
 
-hipError_t launch_check_cols(int64_t nnz, const int32_t *ci, int64_t ncols, int *bad, hipStream_t s) {
-    if (nnz == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_check_cols, dim3(grid_for(nnz, BLK * 8, 8192)), dim3(BLK), 0, s, nnz, ci, ncols, bad);
-    return hipGetLastError();
-}
-
-hipError_t launch_brow(int64_t n, const int64_t *brp, const int32_t *bci, BRow *out, int32_t *ulist,
-                       DevStats *st, hipStream_t s) {
+hipError_t launch_brow(int64_t n, int64_t ncols, const int64_t *brp, const int32_t *bci, BRow *out,
+                       int32_t *ulist, uint8_t *uflag, DevStats *st, hipStream_t s) {
     if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_brow, dim3(grid_for(n * BR_GS, BLK)), dim3(BLK), 0, s, n, brp, bci, out, ulist, st);
+    hipLaunchKernelGGL(k_brow, dim3(grid_for(n * BR_GS, BLK)), dim3(BLK), 0, s, n, ncols, brp, bci, out, ulist, uflag,
+                       st);
     return hipGetLastError();
 }
 
@@ -705,67 +724,60 @@ constexpr int UB_GRID = 1024;
 hipError_t launch_brow_unsorted(const int32_t *list, const int *count, const int64_t *brp, const int32_t *bci,
                                 BRow *out, DevStats *st, hipStream_t s) {
     hipLaunchKernelGGL(k_brow_unsorted, dim3(UB_GRID), dim3(WAVE), 0, s, list, count, brp, bci, out,
-                       (const int64_t *)nullptr, (int32_t *)nullptr, (uint32_t *)nullptr, 0, st);
+                       (const int64_t *)nullptr, (int32_t *)nullptr, (uint32_t *)nullptr, 0, st, (const int *)nullptr);
     return hipGetLastError();
 }
 
 hipError_t launch_compress_unsorted(const int32_t *list, const int *count, const int64_t *brp,
                                     const int32_t *bci, const BRow *bi, const int64_t *bcrp, int32_t *bcsi,
-                                    uint32_t *bcs, hipStream_t s) {
+                                    uint32_t *bcs, const int *enable, hipStream_t s) {
     hipLaunchKernelGGL(k_brow_unsorted, dim3(UB_GRID), dim3(WAVE), 0, s, list, count, brp, bci, (BRow *)bi, bcrp,
-                       bcsi, bcs, 1, (DevStats *)nullptr);
-    return hipGetLastError();
-}
-
-hipError_t launch_mark_unsorted(const int32_t *list, const int *count, uint8_t *flag, hipStream_t s) {
-    hipLaunchKernelGGL(k_mark_unsorted, dim3(64), dim3(BLK), 0, s, list, count, flag);
+                       bcsi, bcs, 1, (DevStats *)nullptr, enable);
     return hipGetLastError();
 }
 
 hipError_t launch_compress_sorted_flags(int64_t n, const int64_t *brp, const int32_t *bci, const BRow *bi,
                                         const uint8_t *unsorted, const int64_t *bcrp, int32_t *bcsi,
-                                        uint32_t *bcs, hipStream_t s) {
+                                        uint32_t *bcs, const int *enable, hipStream_t s) {
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(k_compress_sorted, dim3(grid_for(n * BR_GS, BLK)), dim3(BLK), 0, s, n, brp, bci, bi,
-                       unsorted, bcrp, bcsi, bcs);
+                       unsorted, bcrp, bcsi, bcs, enable);
     return hipGetLastError();
 }
 
 hipError_t launch_rowinfo(int64_t m, int64_t n, const int64_t *arp, const int32_t *aci, const BRow *bi, int64_t *rflops,
-                          int64_t *rflopsc, int2 *rwin, DevStats *st, long long *part, hipStream_t s) {
-    if (m == 0) return hipSuccess;
-    const int g = grid_for(m * RI_GS, BLK, RI_GRID);
-    hipLaunchKernelGGL(k_rowinfo, dim3(g), dim3(BLK), 0, s, m, n, arp, aci, bi, rflops, rflopsc, rwin, part);
-    hipLaunchKernelGGL(k_rowinfo_fin, dim3(1), dim3(BLK), 0, s, g, (const long long *)part, st);
+                          int64_t *rflopsc, int2 *rwin, DevStats *st, long long *part, int comp_opt, int selector,
+                          double cf_threshold, hipStream_t s) {
+    const CompRule rule{comp_opt, selector, cf_threshold};
+    const int g = m > 0 ? grid_for(m * RI_GS, BLK, RI_GRID) : 1;
+    hipLaunchKernelGGL(k_rowinfo, dim3(g), dim3(BLK), 0, s, m, n, arp, aci, bi, rflops, rflopsc, rwin, part, st);
+    hipLaunchKernelGGL(k_rowinfo_fin, dim3(1), dim3(BLK), 0, s, g, (const long long *)part, st, rule);
     return hipGetLastError();
 }
 
-hipError_t launch_brow_lens(int64_t n, const BRow *bi, int which, int64_t *out, hipStream_t s) {
-    if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_brow_lens, dim3(grid_for(n, BLK)), dim3(BLK), 0, s, n, bi, which, out);
-    return hipGetLastError();
-}
-
+// tmp: block sums
 int64_t scan_tmp_elems(int64_t n) { return (n + SC_B - 1) / SC_B + 1; }
 
 template <typename T>
-static hipError_t scan_impl(int64_t n, const T *in, int64_t *out, int64_t *tmp, hipStream_t s) {
+static hipError_t scan_impl(int64_t n, const T *in, int stride, int64_t *out, int64_t *tmp, const int *enable,
+                            hipStream_t s) {
     const int64_t nb = (n + SC_B - 1) / SC_B;
     if (nb > 0) {
-        hipLaunchKernelGGL(k_scan_local<T>, dim3((unsigned)nb), dim3(SC_T), 0, s, n, in, out, tmp);
-        hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(SC_T), 0, s, nb, tmp, out + n);
-        hipLaunchKernelGGL(k_scan_add, dim3((unsigned)nb), dim3(SC_T), 0, s, n, out, tmp);
+        hipLaunchKernelGGL(k_scan_local<T>, dim3((unsigned)nb), dim3(SC_T), 0, s, n, in, stride, out, tmp, enable);
+        hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(SC_T), 0, s, nb, tmp, out + n, enable);
+        hipLaunchKernelGGL(k_scan_add, dim3((unsigned)nb), dim3(SC_T), 0, s, n, out, tmp, enable);
     } else {
         hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(BLK), 0, s, (int32_t *)out, (int64_t)2, 0);
     }
     return hipGetLastError();
 }
 
-hipError_t launch_scan_i64(int64_t n, const int64_t *in, int64_t *out, int64_t *tmp, hipStream_t s) {
-    return scan_impl<int64_t>(n, in, out, tmp, s);
+hipError_t launch_scan_i32s(int64_t n, const int32_t *in, int stride, int64_t *out, int64_t *tmp, const int *enable,
+                            hipStream_t s) {
+    return scan_impl<int32_t>(n, in, stride, out, tmp, enable, s);
 }
 hipError_t launch_scan_i32(int64_t n, const int32_t *in, int64_t *out, int64_t *tmp, hipStream_t s) {
-    return scan_impl<int32_t>(n, in, out, tmp, s);
+    return scan_impl<int32_t>(n, in, 1, out, tmp, nullptr, s);
 }
 
 hipError_t launch_store_rp(int64_t n1, const int64_t *src, void *dst, int is64, hipStream_t s) {
@@ -779,27 +791,26 @@ hipError_t launch_store_rp(int64_t n1, const int64_t *src, void *dst, int is64, 
 
 hipError_t launch_classify(int64_t m, const int64_t *rflops, const int64_t *rflopsc, const int2 *rwin,
                            const int32_t *row_nnz, const int32_t *row_words, ClassParams p, uint8_t *kind,
-                           int32_t *row_nnz_out, DevStats *st, long long *part, hipStream_t s) {
-    if (m == 0) return hipSuccess;
-    const int g = grid_for(m, BLK, CL_GRID);
-    hipLaunchKernelGGL(k_classify, dim3(g), dim3(BLK), 0, s, m, rflops, rflopsc, rwin, row_nnz, row_words, p, kind,
-                       row_nnz_out, part);
-    hipLaunchKernelGGL(k_classify_fin, dim3(1), dim3(BLK), 0, s, g, (const long long *)part, p.phase, p.heavy, st);
+                           int32_t *row_nnz_out, DevStats *st, int64_t *tmp, int64_t *koff, hipStream_t s) {
+    const int64_t nb = (m + CB - 1) / CB;
+    if (nb == 0) {
+        if (koff) hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(BLK), 0, s, (int32_t *)koff, (int64_t)(2 * (NK + 1)), 0);
+        return hipGetLastError();
+    }
+    hipLaunchKernelGGL(k_classify, dim3((unsigned)nb), dim3(CB), 0, s, m, rflops, rflopsc, rwin, row_nnz, row_words,
+                       p, kind, row_nnz_out, (int32_t *)tmp);
+    hipLaunchKernelGGL(k_classify_fold, dim3(1), dim3(CB), 0, s, nb, (int32_t *)tmp, koff, p.phase, p.heavy, st);
     return hipGetLastError();
 }
 
-int64_t part_tmp_elems(int64_t m) { return ((m + PB - 1) / PB) * NK + 1; }
+// tmp: per classify workgroup and kind, three maxima and the row count (then
+// offset), int32
+int64_t part_tmp_elems(int64_t m) { return 2 * ((m + CB - 1) / CB) * NK + 1; }
 
-hipError_t launch_partition(int64_t m, const uint8_t *kind, int32_t *perm, int64_t *koff, int64_t *tmp,
-                            hipStream_t s) {
-    const int64_t nb = (m + PB - 1) / PB;
-    if (nb == 0) {
-        hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(BLK), 0, s, (int32_t *)koff, (int64_t)(2 * (NK + 1)), 0);
-        return hipGetLastError();
-    }
-    hipLaunchKernelGGL(k_part_count, dim3((unsigned)nb), dim3(PB), 0, s, m, kind, tmp);
-    hipLaunchKernelGGL(k_part_scan, dim3(1), dim3(PB), 0, s, nb, tmp, koff);
-    hipLaunchKernelGGL(k_part_scatter, dim3((unsigned)nb), dim3(PB), 0, s, m, kind, tmp, perm);
+hipError_t launch_partition(int64_t m, const uint8_t *kind, int32_t *perm, const int64_t *tmp, hipStream_t s) {
+    const int64_t nb = (m + CB - 1) / CB;
+    if (nb == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_part_scatter, dim3((unsigned)nb), dim3(CB), 0, s, m, kind, (const int32_t *)tmp, perm);
     return hipGetLastError();
 }
 

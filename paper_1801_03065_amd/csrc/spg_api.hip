@@ -330,56 +330,43 @@ static spg_status plan_buffers(spg_handle h, int64_t m, int64_t n, int64_t nnzb)
 // The symbolic phase on validated, device-resident structure: h->arp64 (m+1),
 // h->brp64 (n+1) as int64, A's columns aci (row indices of B) and B's columns
 // bci.  Leaves the plan in the handle and C's int64 row offsets in h->coff.
-static spg_status symbolic_core(spg_handle h, int64_t m, int64_t n, int64_t nnza, int64_t nnzb,
+static spg_status symbolic_core(spg_handle h, int64_t m, int64_t n, int64_t k, int64_t nnza, int64_t nnzb,
                                 const int32_t *aci, const int32_t *bci, int64_t *nnzc_out) {
     spg_status s;
     hipStream_t st = h->stream;
     DevStats *dst = h->dstats.as<DevStats>();
     const int64_t *arp = h->arp64.as<int64_t>(), *brp = h->brp64.as<int64_t>();
     BRow *bi = h->binfo.as<BRow>();
-    HIPCHK(launch_brow(n, brp, bci, bi, h->ulist.as<int32_t>(), dst, st));
+    // Everything up to the first host sync runs on unchecked input: row
+    // pointers are clamped copies, columns out of range only raise the flag
+    // (k_brow, k_rowinfo) and are never used as indices before the sync.
+    HIPCHK(launch_brow(n, k, brp, bci, bi, h->ulist.as<int32_t>(), h->uflag.as<uint8_t>(), dst, st));
     HIPCHK(launch_brow_unsorted(h->ulist.as<int32_t>(), &dst->unsorted, brp, bci, bi, dst, st));
+    const bool sel = h->opt.accumulator == SPG_ACC_AUTO;
     HIPCHK(launch_rowinfo(m, n, arp, aci, bi, h->rflops.as<int64_t>(), h->rflopsc.as<int64_t>(),
-                          h->rwin.as<int2>(), dst, h->red.as<long long>(), st));
-    if ((s = pull_stats(h)) != SPG_OK) return s;  // host sync 1: input checks, flop counts
-    const DevStats hs1 = *h->hst;
-    if (hs1.bad_input) return fail(h, SPG_ERR_INVALID_ARG, "malformed CSR: row_ptr or col_idx out of range");
-    if (hs1.bad_window)
-        return fail(h, SPG_ERR_UNSUPPORTED, "a row of B with unsorted columns spans more than 2^19 columns");
-
-    const double fm = (double)hs1.fm, fmc = (double)hs1.fmc;
-    bool comp = false;
-    if (h->opt.compression == 1) {
-        comp = true;
-    } else if (h->opt.compression == -1) {
-        // the 15% rule over the rows that read compressed B: with the selector,
-        // short rows (a team of lanes, raw B) do not
-        const bool sel = h->opt.accumulator == SPG_ACC_AUTO;
-        const double f0 = sel ? (double)hs1.fmb : fm, f1 = sel ? (double)hs1.fmcb : fmc;
-        comp = f0 > 0 && f1 < h->opt.cf_threshold * f0;
-    }
-    h->avg_len = nnza ? std::max(1.0, fm / (double)nnza) : 1.0;
-    h->avg_len_c = nnza ? std::max(1.0, (comp ? fmc : fm) / (double)nnza) : 1.0;
-
-    if (comp) {
-        // compressed B (Compression subsection): lengths -> offsets -> (word, bits) pairs
-        HIPCHK(ensure(h->blens, 8 * std::max<int64_t>(n, 1)));
-        HIPCHK(launch_brow_lens(n, bi, 1, h->blens.as<int64_t>(), st));
-        HIPCHK(launch_scan_i64(n, h->blens.as<int64_t>(), h->bcrp.as<int64_t>(), h->tmp.as<int64_t>(), st));
+                          h->rwin.as<int2>(), dst, h->red.as<long long>(), h->opt.compression, sel ? 1 : 0,
+                          h->opt.cf_threshold, st));
+    // compressed B (Compression subsection): lengths -> offsets -> (word, bits)
+    // pairs, built when the analysis decided so (dst->comp, on the device)
+    const int *cflag = &dst->comp;
+    if (h->opt.compression != 0) {
         HIPCHK(ensure(h->bcsi, 4 * std::max<int64_t>(nnzb, 1)));
         HIPCHK(ensure(h->bcs, 4 * std::max<int64_t>(nnzb, 1)));
-        HIPCHK(launch_fill_i32(h->uflag.as<int32_t>(), (std::max<int64_t>(n, 1) + 3) / 4, 0, st));
-        HIPCHK(launch_mark_unsorted(h->ulist.as<int32_t>(), &dst->unsorted, h->uflag.as<uint8_t>(), st));
+        static_assert(sizeof(BRow) == 4 * sizeof(int32_t), "BRow is four int32");
+        HIPCHK(launch_scan_i32s(n, &bi->lenc, 4, h->bcrp.as<int64_t>(), h->tmp.as<int64_t>(), cflag, st));
         HIPCHK(launch_compress_sorted_flags(n, brp, bci, bi, h->uflag.as<uint8_t>(), h->bcrp.as<int64_t>(),
-                                            h->bcsi.as<int32_t>(), h->bcs.as<uint32_t>(), st));
+                                            h->bcsi.as<int32_t>(), h->bcs.as<uint32_t>(), cflag, st));
         HIPCHK(launch_compress_unsorted(h->ulist.as<int32_t>(), &dst->unsorted, brp, bci, bi,
-                                        h->bcrp.as<int64_t>(), h->bcsi.as<int32_t>(), h->bcs.as<uint32_t>(), st));
+                                        h->bcrp.as<int64_t>(), h->bcsi.as<int32_t>(), h->bcs.as<uint32_t>(), cflag,
+                                        st));
     }
 
     ClassParams cp{};
     cp.phase = 0;
     cp.accumulator = h->opt.accumulator;
-    cp.compressed = comp ? 1 : 0;
+    cp.compressed = 0;
+    cp.comp_flag = h->opt.compression != 0 ? cflag : nullptr;
+    cp.unsorted = &dst->unsorted;
     cp.dw_nw_max = DW_NW_MAX;
     cp.dw_r_max = DW_R_MAX;
     cp.hw_keys_max = HW_KEYS_MAX;
@@ -391,30 +378,41 @@ static spg_status symbolic_core(spg_handle h, int64_t m, int64_t n, int64_t nnza
     cp.sr_f_max = SR_F_MAX;
     // stored row structure: bit-window rows keep their (word, bits) pairs for
     // the numeric phase (selector only); heavy rows keep their segment lists
-    // (selector and dense policy, B's rows sorted)
-    const bool want_pairs = h->opt.accumulator == SPG_ACC_AUTO;
-    const bool want_segs = hs1.unsorted == 0 &&
-                           (h->opt.accumulator == SPG_ACC_AUTO || h->opt.accumulator == SPG_ACC_DENSE);
-    const bool want_plan = want_pairs || want_segs;
+    // (selector and dense policy, B's rows sorted: checked on the device)
+    const bool want_pairs = sel;
+    const bool want_segs_opt = sel || h->opt.accumulator == SPG_ACC_DENSE;
+    const bool want_plan = want_pairs || want_segs_opt;
     if (want_plan) {
         HIPCHK(ensure(h->plan_len, 4 * (m + 2)));  // one padding element (8-byte reads of the last row)
         HIPCHK(ensure(h->plan_off, 8 * (m + 1)));
         cp.plan_cap = want_pairs ? PL_CAP : 0;
         cp.plan_len = h->plan_len.as<int32_t>();
-        cp.sg = want_segs ? 1 : 0;
+        cp.sg = want_segs_opt ? 1 : 0;
     }
-    HIPCHK(launch_fill_i32(h->row_words.as<int32_t>(), std::max<int64_t>(m, 1), 0, st));
+    cp.words_out = h->row_words.as<int32_t>();
     HIPCHK(launch_classify(m, h->rflops.as<int64_t>(), h->rflopsc.as<int64_t>(), h->rwin.as<int2>(), nullptr,
-                           nullptr, cp, h->kind_sym.as<uint8_t>(), h->row_nnz.as<int32_t>(), dst, h->red.as<long long>(), st));
-    HIPCHK(launch_partition(m, h->kind_sym.as<uint8_t>(), h->perm_sym.as<int32_t>(), h->koff_sym.as<int64_t>(),
-                            h->tmp.as<int64_t>(), st));
+                           nullptr, cp, h->kind_sym.as<uint8_t>(), h->row_nnz.as<int32_t>(), dst, h->tmp.as<int64_t>(),
+                           h->koff_sym.as<int64_t>(), st));
+    HIPCHK(launch_partition(m, h->kind_sym.as<uint8_t>(), h->perm_sym.as<int32_t>(), h->tmp.as<int64_t>(), st));
     if (want_plan) {
         HIPCHK(launch_scan_i32(m, h->plan_len.as<int32_t>(), h->plan_off.as<int64_t>(), h->tmp.as<int64_t>(), st));
         HIPCHK(hipMemcpyAsync(h->hkoff + 1, h->plan_off.as<int64_t>() + m, sizeof(int64_t), hipMemcpyDeviceToHost,
                               st));
     }
-    if ((s = pull_stats(h)) != SPG_OK) return s;  // host sync 2: per-kind sizes, room for stored structure
+    // host sync 1: input checks, flop counts, compression, per-kind sizes,
+    // room for stored structure
+    if ((s = pull_stats(h)) != SPG_OK) return s;
     const DevStats hs2 = *h->hst;
+    const DevStats &hs1 = hs2;
+    if (hs1.bad_input) return fail(h, SPG_ERR_INVALID_ARG, "malformed CSR: row_ptr or col_idx out of range");
+    if (hs1.bad_window)
+        return fail(h, SPG_ERR_UNSUPPORTED, "a row of B with unsorted columns spans more than 2^19 columns");
+    const bool comp = h->opt.compression != 0 && hs1.comp != 0;
+    const double fm = (double)hs1.fm, fmc = (double)hs1.fmc;
+    h->avg_len = nnza ? std::max(1.0, fm / (double)nnza) : 1.0;
+    h->avg_len_c = nnza ? std::max(1.0, (comp ? fmc : fm) / (double)nnza) : 1.0;
+    const bool want_segs = want_segs_opt && hs1.unsorted == 0;
+
     h->planned = false;
     h->segmented = false;
     const bool pairs_used = want_pairs && hs2.kcount_sym[K_DW] > 0;
@@ -506,6 +504,7 @@ static spg_status symbolic_core(spg_handle h, int64_t m, int64_t n, int64_t nnza
     // scan -> C row offsets (int64 plan copy), then the numeric classification
     HIPCHK(launch_scan_i32(m, h->row_nnz.as<int32_t>(), h->coff.as<int64_t>(), h->tmp.as<int64_t>(), st));
     cp.phase = 1;
+    cp.words_out = nullptr;
     cp.plan_cap = h->planned ? PL_CAP : 0;
     cp.sym_kind = h->kind_sym.as<uint8_t>();
     cp.sg = h->sg_mode ? 1 : 0;
@@ -514,9 +513,8 @@ static spg_status symbolic_core(spg_handle h, int64_t m, int64_t n, int64_t nnza
     cp.flops_hi = thr > 0 ? thr : 0;
     HIPCHK(launch_classify(m, h->rflops.as<int64_t>(), h->rflopsc.as<int64_t>(), h->rwin.as<int2>(),
                            h->row_nnz.as<int32_t>(), h->row_words.as<int32_t>(), cp, h->kind_num.as<uint8_t>(),
-                           nullptr, dst, h->red.as<long long>(), st));
-    HIPCHK(launch_partition(m, h->kind_num.as<uint8_t>(), h->perm_num.as<int32_t>(), h->koff_num.as<int64_t>(),
-                            h->tmp.as<int64_t>(), st));
+                           nullptr, dst, h->tmp.as<int64_t>(), h->koff_num.as<int64_t>(), st));
+    HIPCHK(launch_partition(m, h->kind_num.as<uint8_t>(), h->perm_num.as<int32_t>(), h->tmp.as<int64_t>(), st));
     if (thr > 0) {  // rows at or above the threshold: their own kind lists (FP64 accumulation in FP32 mode)
         HIPCHK(ensure(h->kind_heavy, std::max<int64_t>(m, 1)));
         HIPCHK(ensure(h->perm_heavy, 4 * std::max<int64_t>(m, 1)));
@@ -527,12 +525,13 @@ static spg_status symbolic_core(spg_handle h, int64_t m, int64_t n, int64_t nnza
         ch.heavy = 1;
         HIPCHK(launch_classify(m, h->rflops.as<int64_t>(), h->rflopsc.as<int64_t>(), h->rwin.as<int2>(),
                                h->row_nnz.as<int32_t>(), h->row_words.as<int32_t>(), ch,
-                               h->kind_heavy.as<uint8_t>(), nullptr, dst, h->red.as<long long>(), st));
-        HIPCHK(launch_partition(m, h->kind_heavy.as<uint8_t>(), h->perm_heavy.as<int32_t>(),
-                                h->koff_heavy.as<int64_t>(), h->tmp.as<int64_t>(), st));
+                               h->kind_heavy.as<uint8_t>(), nullptr, dst, h->tmp.as<int64_t>(),
+                               h->koff_heavy.as<int64_t>(), st));
+        HIPCHK(launch_partition(m, h->kind_heavy.as<uint8_t>(), h->perm_heavy.as<int32_t>(), h->tmp.as<int64_t>(),
+                                st));
     }
     HIPCHK(hipMemcpyAsync(h->hkoff, h->coff.as<int64_t>() + m, sizeof(int64_t), hipMemcpyDeviceToHost, st));
-    if ((s = pull_stats(h)) != SPG_OK) return s;  // host sync 3: nnz(C), numeric kinds
+    if ((s = pull_stats(h)) != SPG_OK) return s;  // host sync 2: nnz(C), numeric kinds
     const DevStats hs3 = *h->hst;
     if (hs3.overflow) return fail(h, SPG_ERR_OUT_OF_MEMORY, "level-2 hash arena too small in the symbolic phase");
     const int64_t nnzc = h->hkoff[0];
@@ -589,10 +588,8 @@ spg_status spgemm_symbolic(spg_handle h, const spg_csr *A, const spg_csr *B, voi
     // any structure kernel indexes B by A's columns.
     HIPCHK(launch_copy_rp(m + 1, A->row_ptr, A->rp_type == SPG_I64, A->nnz, h->arp64.as<int64_t>(), bad, st));
     HIPCHK(launch_copy_rp(n + 1, B->row_ptr, B->rp_type == SPG_I64, B->nnz, h->brp64.as<int64_t>(), bad, st));
-    HIPCHK(launch_check_cols(A->nnz, A->col_idx, n, bad, st));
-    HIPCHK(launch_check_cols(B->nnz, B->col_idx, k, bad, st));
     int64_t nnzc = 0;
-    if ((s = symbolic_core(h, m, n, A->nnz, B->nnz, A->col_idx, B->col_idx, &nnzc)) != SPG_OK) return s;
+    if ((s = symbolic_core(h, m, n, k, A->nnz, B->nnz, A->col_idx, B->col_idx, &nnzc)) != SPG_OK) return s;
     if (c_rpt == SPG_I32 && nnzc > INT32_MAX)
         return fail(h, SPG_ERR_INDEX_OVERFLOW, "nnz(C) exceeds an int32 row_ptr; ask for SPG_I64");
     HIPCHK(launch_store_rp(m + 1, h->coff.as<int64_t>(), C_row_ptr, c_rpt == SPG_I64, st));
@@ -731,9 +728,8 @@ static spg_status autotune(spg_handle h, NumArgs<VT> na, int acc) {
         HIPCHK(hipMemsetAsync(&dst->kmax_num[0][0], 0, sizeof(dst->kmax_num), st));
         HIPCHK(launch_classify(m, h->rflops.as<int64_t>(), h->rflopsc.as<int64_t>(), h->rwin.as<int2>(),
                                h->row_nnz.as<int32_t>(), h->row_words.as<int32_t>(), cp, h->kind_tmp.as<uint8_t>(),
-                               nullptr, dst, h->red.as<long long>(), st));
-        HIPCHK(launch_partition(m, h->kind_tmp.as<uint8_t>(), h->perm_tmp.as<int32_t>(), h->koff_tmp.as<int64_t>(),
-                                h->tmp.as<int64_t>(), st));
+                               nullptr, dst, h->tmp.as<int64_t>(), h->koff_tmp.as<int64_t>(), st));
+        HIPCHK(launch_partition(m, h->kind_tmp.as<uint8_t>(), h->perm_tmp.as<int32_t>(), h->tmp.as<int64_t>(), st));
         if ((s = pull_stats(h)) != SPG_OK) break;
         const DevStats hs = *h->hst;
         na.rs.rows = h->perm_tmp.as<int32_t>();
@@ -764,9 +760,8 @@ static spg_status autotune(spg_handle h, NumArgs<VT> na, int acc) {
     HIPCHK(hipMemsetAsync(&dst->kmax_num[0][0], 0, sizeof(dst->kmax_num), st));
     HIPCHK(launch_classify(m, h->rflops.as<int64_t>(), h->rflopsc.as<int64_t>(), h->rwin.as<int2>(),
                            h->row_nnz.as<int32_t>(), h->row_words.as<int32_t>(), cp, h->kind_num.as<uint8_t>(),
-                           nullptr, dst, h->red.as<long long>(), st));
-    HIPCHK(launch_partition(m, h->kind_num.as<uint8_t>(), h->perm_num.as<int32_t>(), h->koff_num.as<int64_t>(),
-                            h->tmp.as<int64_t>(), st));
+                           nullptr, dst, h->tmp.as<int64_t>(), h->koff_num.as<int64_t>(), st));
+    HIPCHK(launch_partition(m, h->kind_num.as<uint8_t>(), h->perm_num.as<int32_t>(), h->tmp.as<int64_t>(), st));
     if ((s = pull_stats(h)) != SPG_OK) return s;
     h->lg_num = best_lg;
     h->tuned = true;
@@ -991,7 +986,7 @@ extern "C" spg_status spgemm_batch_symbolic(spg_handle h, int32_t count, const s
     if (h->hst->bad_input) return fail(h, SPG_ERR_INVALID_ARG, "malformed CSR in the batch");
     HIPCHK(hipMemsetAsync(dst, 0, sizeof(DevStats), st));
     int64_t nnzc = 0;
-    if ((s = symbolic_core(h, R, N, NA, NB, bt.aci.as<int32_t>(), bt.bci.as<int32_t>(), &nnzc)) != SPG_OK)
+    if ((s = symbolic_core(h, R, N, K, NA, NB, bt.aci.as<int32_t>(), bt.bci.as<int32_t>(), &nnzc)) != SPG_OK)
         return s;
     // per-product entries of C, then each C_i.row_ptr
     if ((s = upload_desc(h, bt.c, &dev)) != SPG_OK) return s;

@@ -42,6 +42,7 @@ struct DevStats {
     int bad_window;   // unsorted B rows too wide for the LDS window
     int mismatch;     // numeric: row size differs from the plan
     int overflow;     // level-2 arena exhausted
+    int comp;         // the analysis chose compressed B (Compression subsection rule)
     long long kcount_sym[NK];
     long long kcount_num[NK];
     long long kcount_heavy[NK];
@@ -303,32 +304,38 @@ struct LaunchCfg {
     int cus;   // compute units of the device
 };
 
-hipError_t launch_brow(int64_t n, const int64_t *brp, const int32_t *bci, BRow *out,
-                       int32_t *unsorted_list, DevStats *st, hipStream_t s);
+// Per row of B: length, distinct column-set words, word window, sortedness
+// (uflag, and the list of unsorted rows); columns out of [0, ncols) raise the
+// malformed-input flag.
+hipError_t launch_brow(int64_t n, int64_t ncols, const int64_t *brp, const int32_t *bci, BRow *out,
+                       int32_t *unsorted_list, uint8_t *uflag, DevStats *st, hipStream_t s);
 hipError_t launch_brow_unsorted(const int32_t *list, const int *count, const int64_t *brp, const int32_t *bci,
                                 BRow *out, DevStats *st, hipStream_t s);
+// The compression kernels and the scan take `enable` (device flag, nullable):
+// they do nothing when it reads 0.
 hipError_t launch_compress_sorted_flags(int64_t n, const int64_t *brp, const int32_t *bci, const BRow *bi,
                                         const uint8_t *unsorted, const int64_t *bcrp, int32_t *bcsi,
-                                        uint32_t *bcs, hipStream_t s);
-hipError_t launch_mark_unsorted(const int32_t *list, const int *count, uint8_t *flag, hipStream_t s);
+                                        uint32_t *bcs, const int *enable, hipStream_t s);
 hipError_t launch_compress_unsorted(const int32_t *list, const int *count, const int64_t *brp,
                                     const int32_t *bci, const BRow *bi, const int64_t *bcrp, int32_t *bcsi,
-                                    uint32_t *bcs, hipStream_t s);
-// Per-block partials of the analysis reductions (rowinfo, classify), folded
-// by a one-workgroup kernel: RED_ELEMS int64 of device scratch.
+                                    uint32_t *bcs, const int *enable, hipStream_t s);
+// Per-block partials of the rowinfo reduction (folded by a one-workgroup
+// kernel): RED_ELEMS int64 of device scratch.
 constexpr int RED_ELEMS = 16384;
+// Row flops, windows, A column checks; the totals are folded into st, where
+// the compression decision is taken (comp_opt -1 rule / 0 / 1).
 hipError_t launch_rowinfo(int64_t m, int64_t n, const int64_t *arp, const int32_t *aci, const BRow *bi,
-                          int64_t *rflops, int64_t *rflopsc, int2 *rwin, DevStats *st, long long *part,
-                          hipStream_t s);
+                          int64_t *rflops, int64_t *rflopsc, int2 *rwin, DevStats *st, long long *part, int comp_opt,
+                          int selector, double cf_threshold, hipStream_t s);
 hipError_t launch_copy_rp(int64_t n1, const void *src, int is64, int64_t nnz, int64_t *dst, int *bad,
                           hipStream_t s);
-hipError_t launch_check_cols(int64_t nnz, const int32_t *ci, int64_t ncols, int *bad, hipStream_t s);
-hipError_t launch_brow_lens(int64_t n, const BRow *bi, int which, int64_t *out, hipStream_t s);
 
 // Exclusive scan: out[0..n] (n+1 entries) of in[0..n), int64 result.
 // tmp must hold scan_tmp_elems(n) int64.
 int64_t scan_tmp_elems(int64_t n);
-hipError_t launch_scan_i64(int64_t n, const int64_t *in, int64_t *out, int64_t *tmp, hipStream_t s);
+// in[i * stride] (e.g. one field of an array of structs)
+hipError_t launch_scan_i32s(int64_t n, const int32_t *in, int stride, int64_t *out, int64_t *tmp, const int *enable,
+                            hipStream_t s);
 hipError_t launch_scan_i32(int64_t n, const int32_t *in, int64_t *out, int64_t *tmp, hipStream_t s);
 hipError_t launch_store_rp(int64_t n1, const int64_t *src, void *dst, int is64, hipStream_t s);
 
@@ -345,16 +352,22 @@ struct ClassParams {
     int plan_cap;       // stored row structure: pairs per row (0: off)
     int32_t *plan_len;  // symbolic: room for pairs per row (written); numeric: read
     const uint8_t *sym_kind;  // numeric: kind of each row in the symbolic phase
+    const int *comp_flag;     // symbolic: when set, compression as decided on the device (else `compressed`)
+    int32_t *words_out;       // symbolic: zeroed for every row (touched words, filled by the structure kernels)
+    const int *unsorted;      // when set: segments only if it reads 0 (rows of B with unsorted columns)
     int sg;             // heavy rows in segments (B's rows sorted): symbolic K_DG rows that may
                         // need several segments get room for a list; numeric K_DG rows must
                         // have one or fit a single segment
 };
+// Classification of every row into a kind, with per-kind counts and maxima
+// (into st) and the partition offsets per kind (koff, nullable) and per
+// classify workgroup (tmp, part_tmp_elems(m)); launch_partition then writes
+// the rows grouped by kind.
 hipError_t launch_classify(int64_t m, const int64_t *rflops, const int64_t *rflopsc, const int2 *rwin,
                            const int32_t *row_nnz, const int32_t *row_words, ClassParams p, uint8_t *kind,
-                           int32_t *row_nnz_out, DevStats *st, long long *part, hipStream_t s);
+                           int32_t *row_nnz_out, DevStats *st, int64_t *tmp, int64_t *koff, hipStream_t s);
 int64_t part_tmp_elems(int64_t m);
-hipError_t launch_partition(int64_t m, const uint8_t *kind, int32_t *perm, int64_t *koff, int64_t *tmp,
-                            hipStream_t s);
+hipError_t launch_partition(int64_t m, const uint8_t *kind, int32_t *perm, const int64_t *tmp, hipStream_t s);
 hipError_t launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s);
 hipError_t launch_kind_ranges(const int32_t *perm, const int64_t *koff, int64_t rb, int64_t re, int64_t *range,
                               hipStream_t s);
