@@ -46,8 +46,70 @@ __device__ __forceinline__ uint32_t sr_hash(int c, int lg) {
     return (__umul24((uint32_t)c & 0xFFFFFFu, 0x9E3779u) >> (24 - lg)) & ((1u << lg) - 1u);
 }
 
-template <bool NUM, typename VT, int ACC>
-__global__ __launch_bounds__(WAVE) void k_sr(SrArgs<VT> a) {
+// Inclusive prefix sum inside teams of 2^LG lanes with DPP lane moves (row
+// shifts inside each 16-lane row, masked at team edges below 16 lanes; row
+// broadcasts of lane 15 / lane 31 for teams of 32 / 64): no shuffle address
+// arithmetic.
+template <int LG>
+__device__ __forceinline__ int team_scan(int v, int q) {
+    if (LG >= 1) { const int t = __builtin_amdgcn_update_dpp(0, v, 0x111, 0xF, 0xF, false); v += (LG >= 4 || q >= 1) ? t : 0; }
+    if (LG >= 2) { const int t = __builtin_amdgcn_update_dpp(0, v, 0x112, 0xF, 0xF, false); v += (LG >= 4 || q >= 2) ? t : 0; }
+    if (LG >= 3) { const int t = __builtin_amdgcn_update_dpp(0, v, 0x114, 0xF, 0xF, false); v += (LG >= 4 || q >= 4) ? t : 0; }
+    if (LG >= 4) v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xF, 0xF, false);
+    if (LG >= 5) v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xA, 0xF, false);  // row_bcast:15 into rows 1, 3
+    if (LG >= 6) v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xC, 0xF, false);  // row_bcast:31 into rows 2, 3
+    return v;
+}
+// The same with max (values >= 0 after the first step; lanes without a
+// source read 0).
+template <int LG>
+__device__ __forceinline__ int team_maxscan(int v, int q) {
+    if (LG >= 1) { const int t = __builtin_amdgcn_update_dpp(0, v, 0x111, 0xF, 0xF, false); v = (LG >= 4 || q >= 1) ? max(v, t) : v; }
+    if (LG >= 2) { const int t = __builtin_amdgcn_update_dpp(0, v, 0x112, 0xF, 0xF, false); v = (LG >= 4 || q >= 2) ? max(v, t) : v; }
+    if (LG >= 3) { const int t = __builtin_amdgcn_update_dpp(0, v, 0x114, 0xF, 0xF, false); v = (LG >= 4 || q >= 4) ? max(v, t) : v; }
+    if (LG >= 4) v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x118, 0xF, 0xF, false));
+    if (LG >= 5) v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x142, 0xA, 0xF, false));
+    if (LG >= 6) v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x143, 0xC, 0xF, false));
+    return v;
+}
+// Value of lane (lane ^ J): DPP quad permutes for 1 and 2, a row rotation
+// for 8, swizzles inside 32 lanes for 4 and 16, a lane permute for 32.
+template <int J>
+__device__ __forceinline__ int lane_xor(int v) {
+    if (J == 1) return __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, false);   // quad_perm [1,0,3,2]
+    if (J == 2) return __builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, false);   // quad_perm [2,3,0,1]
+    if (J == 8) return __builtin_amdgcn_mov_dpp(v, 0x128, 0xF, 0xF, false);  // row_ror:8
+    if (J == 4) return __builtin_amdgcn_ds_swizzle(v, 0x1F | (4 << 10));
+    if (J == 16) return __builtin_amdgcn_ds_swizzle(v, 0x1F | (16 << 10));
+    return __shfl_xor(v, J);
+}
+// One compare-exchange step of the bitonic network (block size KK, distance J).
+template <int KK, int J>
+__device__ __forceinline__ void bitonic_step(int &key, int &slot, int q) {
+    const int ok = lane_xor<J>(key), os = lane_xor<J>(slot);
+    const bool up = (q & KK) == 0, lower = (q & J) == 0;
+    if (lower == up ? ok < key : ok > key) {
+        key = ok;
+        slot = os;
+    }
+}
+// Sort (key, slot) ascending inside blocks of P lanes (P <= 2^LG, a power of
+// two, wavefront-uniform): the stages for blocks above P are skipped.
+template <int LG>
+__device__ __forceinline__ void team_sort(int &key, int &slot, int q, int P) {
+#define SR_STAGE(KK, J) \
+    if (KK <= (1 << LG) && KK <= P) bitonic_step<KK, J>(key, slot, q);
+    SR_STAGE(2, 1)
+    SR_STAGE(4, 2) SR_STAGE(4, 1)
+    SR_STAGE(8, 4) SR_STAGE(8, 2) SR_STAGE(8, 1)
+    SR_STAGE(16, 8) SR_STAGE(16, 4) SR_STAGE(16, 2) SR_STAGE(16, 1)
+    SR_STAGE(32, 16) SR_STAGE(32, 8) SR_STAGE(32, 4) SR_STAGE(32, 2) SR_STAGE(32, 1)
+    SR_STAGE(64, 32) SR_STAGE(64, 16) SR_STAGE(64, 8) SR_STAGE(64, 4) SR_STAGE(64, 2) SR_STAGE(64, 1)
+#undef SR_STAGE
+}
+
+template <bool NUM, typename VT, int ACC, int LG>
+__global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_sr(SrArgs<VT> a) {
     using A = Accum<VT, ACC>;
     using S = typename A::store_t;
     __shared__ int32_t keys_all[2 * WAVE];
@@ -55,7 +117,9 @@ __global__ __launch_bounds__(WAVE) void k_sr(SrArgs<VT> a) {
     __shared__ int32_t own_all[WAVE];
     __shared__ int32_t uslot_all[NUM ? WAVE : 1];
     const int l = lane_id();
-    const int lgT = a.lg_t, T = 1 << lgT, q = l & (T - 1), team = l >> lgT, nteam = WAVE >> lgT;
+    constexpr int lgT = LG, T = 1 << LG;
+    const int q = l & (T - 1), team = l >> lgT;
+    constexpr int nteam = WAVE >> LG;
     int32_t *keys = keys_all + 2 * T * team;
     S *vals = vals_all + (NUM ? 2 * T * team : 0);
     int32_t *own = own_all + T * team;
@@ -134,27 +198,15 @@ __global__ __launch_bounds__(WAVE) void k_sr(SrArgs<VT> a) {
                     len = (int)(a.brp[j + 1] - b0);
                 }
             }
-            int inc = len;
-#pragma unroll
-            for (int d = 1; d < WAVE; d <<= 1) {
-                if (d >= T) break;
-                const int t = __shfl_up(inc, d, T);
-                if (q >= d) inc += t;
-            }
+            const int inc = team_scan<LG>(len, q);
             const int F = __shfl(inc, T - 1, T);  // products of this chunk (<= T for a short row)
             const int off = inc - len;
             own[q] = -1;
             wave_lds_sync();
             if (len > 0 && off < T) own[off] = q;
             wave_lds_sync();
-            int k = own[q];  // owner of product q: the last A entry starting at or before q
-#pragma unroll
-            for (int d = 1; d < WAVE; d <<= 1) {
-                if (d >= T) break;
-                const int t = __shfl_up(k, d, T);
-                if (q >= d) k = max(k, t);
-            }
-            k = max(k, 0);
+            // owner of product q: the last A entry starting at or before q
+            const int k = max(team_maxscan<LG>(own[q], q), 0);
             const int offk = __shfl(off, k, T);
             const int64_t b0k = __shfl(b0, k, T);
             VT avk = VT(0);
@@ -179,10 +231,7 @@ __global__ __launch_bounds__(WAVE) void k_sr(SrArgs<VT> a) {
             }
             wave_lds_sync();
         }
-        int cnt = nins;
-#pragma unroll
-        for (int d = WAVE / 2; d >= 1; d >>= 1)
-            if (d < T) cnt += __shfl_xor(cnt, d, T);
+        const int cnt = __shfl(team_scan<LG>(nins, q), T - 1, T);
 
         if (!NUM) {
             if (q == 0 && ic >= 0) {
@@ -195,14 +244,7 @@ __global__ __launch_bounds__(WAVE) void k_sr(SrArgs<VT> a) {
             // ---- compact the occupied slots, sort by column, write the row
             const int k0 = keys[q], k1 = keys[q + T];
             const int c = (k0 >= 0) + (k1 >= 0);
-            int pin = c;
-#pragma unroll
-            for (int d = 1; d < WAVE; d <<= 1) {
-                if (d >= T) break;
-                const int t = __shfl_up(pin, d, T);
-                if (q >= d) pin += t;
-            }
-            int p = pin - c;
+            int p = team_scan<LG>(c, q) - c;
             if (k0 >= 0) {
                 own[p] = k0;
                 uslot[p] = q;
@@ -215,18 +257,14 @@ __global__ __launch_bounds__(WAVE) void k_sr(SrArgs<VT> a) {
             wave_lds_sync();
             int key = q < cnt ? own[q] : INT_MAX;
             int slot = q < cnt ? uslot[q] : 0;
-            // bitonic sort of (key, slot) across the team, ascending
-            for (int kk = 2; kk <= T; kk <<= 1) {
-                for (int jj = kk >> 1; jj > 0; jj >>= 1) {
-                    const int ok = __shfl_xor(key, jj, T);
-                    const int os = __shfl_xor(slot, jj, T);
-                    const bool up = (q & kk) == 0, lower = (q & jj) == 0;
-                    if (lower == up ? ok < key : ok > key) {
-                        key = ok;
-                        slot = os;
-                    }
-                }
+            // bitonic sort of (key, slot) across the team, ascending, over the
+            // next power of two of the wavefront's largest row
+            int P = 2;
+            {
+                const int mc = __builtin_amdgcn_readfirstlane(wave_max(cnt));
+                while (P < mc) P <<= 1;
             }
+            team_sort<LG>(key, slot, q, P);
             const bool okrow = ic < 0 || ce - cb == cnt;
             if (q == 0 && !okrow) atomicAdd(&a.st->mismatch, 1);
             if (okrow && q < cnt) {
@@ -280,6 +318,13 @@ int sr_grid(K kernel, int cus, int64_t groups) {
     return (int)(g < XCDS ? XCDS : g);
 }
 
+template <typename VT, int ACC, int LG>
+hipError_t num_sr_lg(const SrArgs<VT> &a, const LaunchCfg &c, int64_t rows) {
+    const int grid = c.grid > 0 ? c.grid : sr_grid(k_sr<true, VT, ACC, LG>, c.cus, rows >> (6 - LG));
+    hipLaunchKernelGGL((k_sr<true, VT, ACC, LG>), dim3(grid), dim3(WAVE), 0, c.stream, a);
+    return hipGetLastError();
+}
+
 template <typename VT, int ACC>
 hipError_t num_sr_impl(const NumArgs<VT> &n, int lg_t, const LaunchCfg &c, int64_t rows) {
     SrArgs<VT> a{};
@@ -296,8 +341,16 @@ hipError_t num_sr_impl(const NumArgs<VT> &n, int lg_t, const LaunchCfg &c, int64
     a.rs = n.rs;
     a.lg_t = lg_t;
     a.st = n.st;
-    const int grid = c.grid > 0 ? c.grid : sr_grid(k_sr<true, VT, ACC>, c.cus, rows >> (6 - lg_t));
-    hipLaunchKernelGGL((k_sr<true, VT, ACC>), dim3(grid), dim3(WAVE), 0, c.stream, a);
+    if (lg_t <= 3) return num_sr_lg<VT, ACC, 3>(a, c, rows);
+    if (lg_t == 4) return num_sr_lg<VT, ACC, 4>(a, c, rows);
+    if (lg_t == 5) return num_sr_lg<VT, ACC, 5>(a, c, rows);
+    return num_sr_lg<VT, ACC, 6>(a, c, rows);
+}
+
+template <int LG>
+hipError_t sym_sr_lg(const SrArgs<double> &a, const LaunchCfg &c, int64_t rows) {
+    const int grid = c.grid > 0 ? c.grid : sr_grid(k_sr<false, double, ACC_NATIVE, LG>, c.cus, rows >> (6 - LG));
+    hipLaunchKernelGGL((k_sr<false, double, ACC_NATIVE, LG>), dim3(grid), dim3(WAVE), 0, c.stream, a);
     return hipGetLastError();
 }
 
@@ -316,9 +369,10 @@ hipError_t launch_sym_sr(const SymArgs &s, int lg_t, const LaunchCfg &c, int64_t
     a.lg_t = lg_t;
     a.st = s.st;
     a.cbase_row = -1;
-    const int grid = c.grid > 0 ? c.grid : sr_grid(k_sr<false, double, ACC_NATIVE>, c.cus, rows >> (6 - lg_t));
-    hipLaunchKernelGGL((k_sr<false, double, ACC_NATIVE>), dim3(grid), dim3(WAVE), 0, c.stream, a);
-    return hipGetLastError();
+    if (lg_t <= 3) return sym_sr_lg<3>(a, c, rows);
+    if (lg_t == 4) return sym_sr_lg<4>(a, c, rows);
+    if (lg_t == 5) return sym_sr_lg<5>(a, c, rows);
+    return sym_sr_lg<6>(a, c, rows);
 }
 
 template <>
