@@ -29,6 +29,41 @@ __global__ __launch_bounds__(BLK) void k_copy_rp(int64_t n1, const T *src, int64
     }
 }
 
+// ------------------------------------------------------------------ 16-lane groups
+// A group of 16 lanes is one DPP row: lane moves inside it need no shuffle
+// address arithmetic.
+__device__ __forceinline__ int row_prev(int v, int fill) {  // value of lane q-1 (fill at q = 0)
+    return __builtin_amdgcn_update_dpp(fill, v, 0x111, 0xF, 0xF, false);
+}
+__device__ __forceinline__ int row_next(int v, int fill) {  // value of lane q+1 (fill at q = 15)
+    return __builtin_amdgcn_update_dpp(fill, v, 0x101, 0xF, 0xF, false);
+}
+__device__ __forceinline__ int row_last(int v) {  // lane 15 of the row, to every lane of it
+    return __builtin_amdgcn_ds_swizzle(v, 0x10 | (0x0F << 5));
+}
+template <int N>
+__device__ __forceinline__ int row_ror(int v) {
+    return __builtin_amdgcn_mov_dpp(v, 0x120 + N, 0xF, 0xF, false);
+}
+__device__ __forceinline__ int row_sum(int v) {
+    v += row_ror<8>(v);
+    v += row_ror<4>(v);
+    v += row_ror<2>(v);
+    return v + row_ror<1>(v);
+}
+__device__ __forceinline__ int row_min(int v) {
+    v = min(v, row_ror<8>(v));
+    v = min(v, row_ror<4>(v));
+    v = min(v, row_ror<2>(v));
+    return min(v, row_ror<1>(v));
+}
+__device__ __forceinline__ int row_max(int v) {
+    v = max(v, row_ror<8>(v));
+    v = max(v, row_ror<4>(v));
+    v = max(v, row_ror<2>(v));
+    return max(v, row_ror<1>(v));
+}
+
 // ------------------------------------------------------------------ B rows
 // One group of 16 lanes per row of B.  For rows whose columns are strictly
 // increasing, the number of distinct words col >> 5 is the number of word
@@ -49,8 +84,7 @@ __global__ __launch_bounds__(BLK) void k_brow(int64_t n, int64_t ncols, const in
             const int64_t idx = c0 + q;
             const bool v = idx < e;
             const int col = v ? bci[idx] : INT_MAX;
-            int prevc = __shfl_up(col, 1, BR_GS);
-            if (q == 0) prevc = prev_last;
+            const int prevc = row_prev(col, prev_last);
             if (v) {
                 cmin = min(cmin, col);
                 cmax = max(cmax, col);
@@ -58,15 +92,12 @@ __global__ __launch_bounds__(BLK) void k_brow(int64_t n, int64_t ncols, const in
                 heads += ((col >> 5) != (prevc >> 5));
                 badcol |= (col < 0) | ((int64_t)col >= ncols);
             }
-            prev_last = __shfl(col, BR_GS - 1, BR_GS);
+            prev_last = row_last(col);
         }
-#pragma unroll
-        for (int d = BR_GS / 2; d >= 1; d >>= 1) {
-            cmin = min(cmin, __shfl_xor(cmin, d, BR_GS));
-            cmax = max(cmax, __shfl_xor(cmax, d, BR_GS));
-            heads += __shfl_xor(heads, d, BR_GS);
-            unsorted |= __shfl_xor(unsorted, d, BR_GS);
-        }
+        cmin = row_min(cmin);
+        cmax = row_max(cmax);
+        heads = row_sum(heads);
+        unsorted = row_max(unsorted);
         if (q == 0) {
             BRow o;
             o.len = (int32_t)(e - b);
@@ -153,35 +184,38 @@ __global__ __launch_bounds__(BLK) void k_compress_sorted(int64_t n, const int64_
             const int64_t idx = c0 + q;
             const bool v = idx < e;
             const int col = v ? bci[idx] : INT_MAX;
-            int prevc = __shfl_up(col, 1, BR_GS);
-            if (q == 0) prevc = prev_last;
-            int nextc = __shfl_down(col, 1, BR_GS);
-            if (q == BR_GS - 1) nextc = idx + 1 < e ? bci[idx + 1] : INT_MAX;
+            const int prevc = row_prev(col, prev_last);
+            const int nextc = row_next(col, (q == BR_GS - 1 && idx + 1 < e) ? bci[idx + 1] : INT_MAX);
             const int head = v && ((col >> 5) != (prevc >> 5));
             // inclusive count of heads in this chunk = run id (0 = run from previous chunk)
             int seg = head;
-#pragma unroll
-            for (int d = 1; d < BR_GS; d <<= 1) {
-                int t = __shfl_up(seg, d, BR_GS);
-                if (q >= d) seg += t;
-            }
+            seg += __builtin_amdgcn_update_dpp(0, seg, 0x111, 0xF, 0xF, false);
+            seg += __builtin_amdgcn_update_dpp(0, seg, 0x112, 0xF, 0xF, false);
+            seg += __builtin_amdgcn_update_dpp(0, seg, 0x114, 0xF, 0xF, false);
+            seg += __builtin_amdgcn_update_dpp(0, seg, 0x118, 0xF, 0xF, false);
             uint32_t acc = v ? (1u << (col & 31)) : 0u;
             if (seg == 0) acc |= carry;
-#pragma unroll
-            for (int d = 1; d < BR_GS; d <<= 1) {
-                uint32_t t = __shfl_up(acc, d, BR_GS);
-                int ts = __shfl_up(seg, d, BR_GS);
-                if (q >= d && ts == seg) acc |= t;
-            }
+            // OR-scan inside runs: a lane takes the bits of lane q-d when it is in the same run
+#define SR_OR_STEP(CTRL)                                                                      \
+    {                                                                                         \
+        const uint32_t t = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)acc, CTRL, 0xF, 0xF, false); \
+        const int ts = __builtin_amdgcn_update_dpp(-1, seg, CTRL, 0xF, 0xF, false);        \
+        if (ts == seg) acc |= t;                                                              \
+    }
+            SR_OR_STEP(0x111)
+            SR_OR_STEP(0x112)
+            SR_OR_STEP(0x114)
+            SR_OR_STEP(0x118)
+#undef SR_OR_STEP
             // the run ends here when the next column is in another word (or there is none)
             const bool tail = v && (idx + 1 >= e || (nextc >> 5) != (col >> 5));
             const int64_t pos = o0 + heads_before + seg - 1;
             if (head) bcsi[pos] = col >> 5;
             if (tail) bcs[pos] = acc;
             const bool open = v && !tail && q == BR_GS - 1;  // run continues into the next chunk
-            carry = __shfl(open ? acc : 0u, BR_GS - 1, BR_GS);
-            heads_before += __shfl(seg, BR_GS - 1, BR_GS);
-            prev_last = __shfl(col, BR_GS - 1, BR_GS);
+            carry = (uint32_t)row_last(open ? (int)acc : 0);
+            heads_before += row_last(seg);
+            prev_last = row_last(col);
         }
     }
 }
