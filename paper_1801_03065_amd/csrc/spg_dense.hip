@@ -35,7 +35,7 @@ namespace {
 // ============================================================ wavefront / row
 
 struct DwLayout {
-    size_t bits, summ, pre, wlist, vals, colbuf, st_bs, st_len, st_cbs, st_clen, st_a, total;
+    size_t bits, summ, pre, wlist, vals, st_bs, st_len, st_cbs, st_clen, st_a, total;
 };
 
 __host__ __device__ inline DwLayout dw_layout(int nwm, int rm, int acc_bytes, bool numeric) {
@@ -63,8 +63,6 @@ __host__ __device__ inline DwLayout dw_layout(int nwm, int rm, int acc_bytes, bo
         o += align16(2 * (size_t)rm);
         L.vals = o;
         o += align16((size_t)acc_bytes * rm);
-        L.colbuf = o;
-        o += align16(4 * (size_t)rm);
     }
     L.total = o;
     return L;
@@ -530,6 +528,11 @@ __global__ __launch_bounds__(WAVE) void k_sym_dw(SymArgs a) {
     }
 }
 
+// Numeric phase, bit-window accumulator, one wavefront per row.  Rows whose A
+// entries fit one chunk of 64 are software-pipelined: the next row's A
+// entries and B extents load while this row is processed and move into the
+// staging arrays once this row no longer reads them.  Columns are written
+// straight from the bit window and the word ranks.
 template <typename VT, int ACC>
 __global__ __launch_bounds__(WAVE) void k_num_dw(NumArgs<VT> a) {
     using A = Accum<VT, ACC>;
@@ -541,7 +544,6 @@ __global__ __launch_bounds__(WAVE) void k_num_dw(NumArgs<VT> a) {
     uint16_t *pre = (uint16_t *)(smem + L.pre);
     uint16_t *wlist = (uint16_t *)(smem + L.wlist);
     S *vals = (S *)(smem + L.vals);
-    int32_t *colbuf = (int32_t *)(smem + L.colbuf);
     int64_t *st_bs = (int64_t *)(smem + L.st_bs);
     int32_t *st_len = (int32_t *)(smem + L.st_len);
     int64_t *st_cbs = (int64_t *)(smem + L.st_cbs);
@@ -563,10 +565,37 @@ __global__ __launch_bounds__(WAVE) void k_num_dw(NumArgs<VT> a) {
     int i_next = r < sl.end ? a.rs.rows[r] : 0;
     RowDesc dn = r < sl.end ? row_desc(i_next, a.arp, a.rwin) : RowDesc{};
     int64_t c0n = r < sl.end ? a.coff[i_next] : 0, c1n = r < sl.end ? a.coff[i_next + 1] : 0;
+    // staging of the next row in registers (lane l: its A entry l), valid when staged_n
+    bool staged_n = false;
+    int64_t pb0 = 0, pc0 = 0;
+    int plen = 0, pclen = 0;
+    double pav = 0.0;
+    auto load_stage = [&](const RowDesc &dd) {
+        // two dependent steps: A entries, then the extents of their B rows
+        int j = 0;
+        pav = 0.0;
+        if (l < dd.ae - dd.ab) {
+            j = a.aci[dd.ab + l];
+            pav = (double)a.aval[dd.ab + l];
+        }
+        return j;
+    };
+    int pj = 0;
+    if (r < sl.end && dn.ae - dn.ab <= WAVE) {
+        pj = load_stage(dn);
+        if (l < dn.ae - dn.ab) {
+            pb0 = a.brp[pj];
+            plen = (int)(a.brp[pj + 1] - pb0);
+            pc0 = srp[pj];
+            pclen = (int)(srp[pj + 1] - pc0);
+        }
+        staged_n = true;
+    }
     while (r < sl.end) {
         const int i = i_next;
         const RowDesc d = dn;
         const int64_t cb = c0n, ce = c1n;
+        const bool staged = staged_n;
         r += sl.step;
         if (r < sl.end) {  // prefetch the next row's descriptor
             i_next = a.rs.rows[r];
@@ -576,12 +605,40 @@ __global__ __launch_bounds__(WAVE) void k_num_dw(NumArgs<VT> a) {
         }
         const int wlo = d.wlo, ns = d.ns;
         const bool one_chunk = d.ae - d.ab <= WAVE;
+        if (staged) {  // this row's staging, loaded during the previous row
+            if (l < d.ae - d.ab) {
+                st_bs[l] = pb0;
+                st_len[l] = plen;
+                st_a[l] = pav;
+                st_cbs[l] = pc0;
+                st_clen[l] = pclen;
+            }
+            wave_lds_sync();
+        }
+        // the next row's A entries (first dependent step of its staging)
+        staged_n = false;
+        if (r < sl.end && dn.ae - dn.ab <= WAVE) {
+            pj = load_stage(dn);
+            staged_n = true;
+        }
         // 1. structure of the row (staging kept for step 4 when the row fits one chunk)
         for (int64_t c0 = d.ab; c0 < d.ae; c0 += WAVE) {
-            const int cn = dw_stage<VT>(c0, d.ae, a.aci, a.aval, srp, a.brp, st_cbs, st_clen, st_bs, st_len, st_a);
-            wave_lds_sync();
+            int cn;
+            if (staged) {
+                cn = (int)(d.ae - d.ab);
+            } else {
+                cn = dw_stage<VT>(c0, d.ae, a.aci, a.aval, srp, a.brp, st_cbs, st_clen, st_bs, st_len, st_a);
+                wave_lds_sync();
+            }
             dw_or_staged(cn, wlo, comp, a.bci, a.bcsi, a.bcs, a.lg_gs_or, st_cbs, st_clen, bits, summ);
             wave_lds_sync();
+        }
+        // the next row's B extents (second step; its A entries have landed)
+        if (staged_n && l < dn.ae - dn.ab) {
+            pb0 = a.brp[pj];
+            plen = (int)(a.brp[pj + 1] - pb0);
+            pc0 = srp[pj];
+            pclen = (int)(srp[pj + 1] - pc0);
         }
         // 2. touched words in increasing order
         int T = 0;
@@ -589,7 +646,7 @@ __global__ __launch_bounds__(WAVE) void k_num_dw(NumArgs<VT> a) {
             const int s = s0 + l;
             uint32_t m = (s < ns) ? summ[s] : 0u;
             const int c = __popc(m);
-            const int inc = wave_incl_scan(c);
+            const int inc = wave_scan_dpp(c);
             int idx = T + inc - c;
             while (m) {
                 if (idx < a.r_max) wlist[idx] = (uint16_t)((s << 5) + __ffs(m) - 1);
@@ -597,7 +654,7 @@ __global__ __launch_bounds__(WAVE) void k_num_dw(NumArgs<VT> a) {
                 m &= m - 1;
             }
             if (s < ns) summ[s] = 0;
-            T += __shfl(inc, WAVE - 1);
+            T += __builtin_amdgcn_readlane(inc, WAVE - 1);
         }
         wave_lds_sync();
         if (T > a.r_max) {  // structure differs from the plan: flag, reset the window, skip the row
@@ -612,9 +669,9 @@ __global__ __launch_bounds__(WAVE) void k_num_dw(NumArgs<VT> a) {
             const int rr = r0 + l;
             const int w = rr < T ? wlist[rr] : 0;
             const int c = rr < T ? __popc(bits[w]) : 0;
-            const int inc = wave_incl_scan(c);
+            const int inc = wave_scan_dpp(c);
             if (rr < T) pre[w] = (uint16_t)(run + inc - c);
-            run += __shfl(inc, WAVE - 1);
+            run += __builtin_amdgcn_readlane(inc, WAVE - 1);
         }
         const int rnnz = run;
         const bool ok = (ce - cb == rnnz);
@@ -675,26 +732,24 @@ __global__ __launch_bounds__(WAVE) void k_num_dw(NumArgs<VT> a) {
             }
             wave_lds_sync();
         }
-        // 5. sorted columns, reset of the touched words
+        // 5. sorted columns straight from the words, values in rank order;
+        //    reset of the touched words
+        const int64_t ob = cb - cbase;
         for (int t = l; t < T; t += WAVE) {
             const int w = wlist[t];
             uint32_t m = bits[w];
             int p = pre[w];
             const int base = (wlo + w) << 5;
-            while (m) {
-                colbuf[p++] = base + __ffs(m) - 1;
-                m &= m - 1;
+            if (ok) {
+                while (m) {
+                    a.cci[ob + p++] = base + __ffs(m) - 1;
+                    m &= m - 1;
+                }
             }
             bits[w] = 0;
         }
-        wave_lds_sync();
-        if (ok) {
-            const int64_t ob = cb - cbase;
-            for (int t = l; t < rnnz; t += WAVE) {
-                a.cci[ob + t] = colbuf[t];
-                a.cval[ob + t] = A::fin(vals[t]);
-            }
-        }
+        if (ok)
+            for (int t = l; t < rnnz; t += WAVE) a.cval[ob + t] = A::fin(vals[t]);
         wave_lds_sync();
     }
 }
