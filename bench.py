@@ -37,9 +37,9 @@ TRAFFIC = {
     "kernel": "k_num_pl",
     "sources": ["paper_1801_03065_amd/csrc/spg_plan.hip", "paper_1801_03065_amd/csrc/spg_internal.hpp",
                 "paper_1801_03065_amd/csrc/spg_accum.hpp"],
-    "sha256": "69a5b7a87bcd03282e3b71cdfbd51bf42c9cda0ec1f64e3ce8b52b4f5f4669a7",
-    "read_bytes": 3.8029e9,
-    "write_bytes": 1.5086e9,
+    "sha256": "76910a30ac85721662532bad4c75baa08916bcc26938cd670ff9855e0fd7091b",
+    "read_bytes": 3.8291e9,
+    "write_bytes": 1.5082e9,
 }
 
 
