@@ -232,7 +232,9 @@ __device__ __forceinline__ long long wave_max64(long long v) {
 constexpr int RI_GS = 8;
 constexpr int RI_U = 4;  // A entries per lane in flight
 constexpr int RI_GRID = 2048;
-constexpr int RI_F = 6;  // rowinfo partial fields: fm, fmc, max, max compressed, fm and fmc of long rows
+constexpr int RI_F = 7;  // rowinfo partial fields: fm, fmc, max, max compressed, fm and fmc of long rows,
+                         // longest row of A
+__host__ __device__ constexpr bool ri_is_max(int f) { return f == 2 || f == 3 || f == 6; }
 static_assert(RI_F * RI_GRID <= RED_ELEMS && 4 * NK * CL_GRID <= RED_ELEMS, "analysis partials exceed scratch");
 
 // Compression rule of the Compression subsection, taken on the device from
@@ -251,7 +253,7 @@ __global__ __launch_bounds__(BLK) void k_rowinfo(int64_t m, int64_t n, const int
     const int q = threadIdx.x & (RI_GS - 1);
     const int64_t g0 = ((int64_t)blockIdx.x * BLK + threadIdx.x) / RI_GS;
     const int64_t ng = (int64_t)gridDim.x * BLK / RI_GS;
-    long long s_fm = 0, s_fmc = 0, s_mx = 0, s_mxc = 0, s_fmb = 0, s_fmcb = 0;
+    long long s_fm = 0, s_fmc = 0, s_mx = 0, s_mxc = 0, s_fmb = 0, s_fmcb = 0, s_mxa = 0;
     int badcol = 0;
     for (int64_t i = g0; i < m; i += ng) {
         const int64_t b = arp[i], e = arp[i + 1];
@@ -294,6 +296,7 @@ __global__ __launch_bounds__(BLK) void k_rowinfo(int64_t m, int64_t n, const int
             s_fmc += fc;
             s_mx = max(s_mx, f);
             s_mxc = max(s_mxc, fc);
+            s_mxa = max(s_mxa, (long long)(e - b));
             if (f > SR_F_MAX) {  // rows that read B's structure word by word
                 s_fmb += f;
                 s_fmcb += fc;
@@ -311,6 +314,7 @@ __global__ __launch_bounds__(BLK) void k_rowinfo(int64_t m, int64_t n, const int
     for (int d = 32; d >= 1; d >>= 1) {
         s_mx = max(s_mx, (long long)__shfl_xor(s_mx, d));
         s_mxc = max(s_mxc, (long long)__shfl_xor(s_mxc, d));
+        s_mxa = max(s_mxa, (long long)__shfl_xor(s_mxa, d));
     }
     const int wv = threadIdx.x / WAVE;
     if (lane_id() == 0) {
@@ -320,12 +324,13 @@ __global__ __launch_bounds__(BLK) void k_rowinfo(int64_t m, int64_t n, const int
         red[3][wv] = s_mxc;
         red[4][wv] = s_fmb;
         red[5][wv] = s_fmcb;
+        red[6][wv] = s_mxa;
     }
     __syncthreads();
     if (threadIdx.x < RI_F) {
         const int f = threadIdx.x;
         long long v = 0;
-        for (int u = 0; u < BLK / WAVE; ++u) v = (f == 2 || f == 3) ? max(v, red[f][u]) : v + red[f][u];
+        for (int u = 0; u < BLK / WAVE; ++u) v = ri_is_max(f) ? max(v, red[f][u]) : v + red[f][u];
         part[RI_F * (int64_t)blockIdx.x + f] = v;
     }
     if (__ballot(badcol) && lane_id() == 0) atomicOr(&st->bad_input, 1);
@@ -341,13 +346,13 @@ __global__ __launch_bounds__(BLK) void k_rowinfo_fin(int nb, const long long *pa
 #pragma unroll
         for (int f = 0; f < RI_F; ++f) {
             const long long x = part[RI_F * (int64_t)k + f];
-            v[f] = (f == 2 || f == 3) ? max(v[f], x) : v[f] + x;
+            v[f] = ri_is_max(f) ? max(v[f], x) : v[f] + x;
         }
     __shared__ long long red[RI_F][BLK / WAVE];
     const int wv = threadIdx.x / WAVE;
 #pragma unroll
     for (int f = 0; f < RI_F; ++f) {
-        const long long r = (f == 2 || f == 3) ? wave_max64(v[f]) : wave_sum64(v[f]);
+        const long long r = ri_is_max(f) ? wave_max64(v[f]) : wave_sum64(v[f]);
         if (lane_id() == 0) red[f][wv] = r;
     }
     __syncthreads();
@@ -355,7 +360,7 @@ __global__ __launch_bounds__(BLK) void k_rowinfo_fin(int nb, const long long *pa
         long long a[RI_F];
         for (int f = 0; f < RI_F; ++f) {
             a[f] = 0;
-            for (int u = 0; u < BLK / WAVE; ++u) a[f] = (f == 2 || f == 3) ? max(a[f], red[f][u]) : a[f] + red[f][u];
+            for (int u = 0; u < BLK / WAVE; ++u) a[f] = ri_is_max(f) ? max(a[f], red[f][u]) : a[f] + red[f][u];
         }
         st->fm = ull(a[0]);
         st->fmc = ull(a[1]);
@@ -363,6 +368,7 @@ __global__ __launch_bounds__(BLK) void k_rowinfo_fin(int nb, const long long *pa
         st->maxrfc = ull(a[3]);
         st->fmb = ull(a[4]);
         st->fmcb = ull(a[5]);
+        st->maxnnza = ull(a[6]);
         int comp = rule.opt == 1;
         if (rule.opt == -1) {
             const double f0 = (double)(rule.sel ? a[4] : a[0]), f1 = (double)(rule.sel ? a[5] : a[1]);

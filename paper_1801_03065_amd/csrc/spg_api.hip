@@ -64,7 +64,7 @@ struct spg_handle_s {
     ClassParams cparams{};                                   // classification of the last symbolic phase
     int lg_num = 4;                                          // log2 lanes per B row, numeric phase
     bool tuned = false;
-    DevBuf kind_tmp, perm_tmp, koff_tmp, krange, kind_heavy, perm_heavy, koff_heavy, krange_heavy;
+    DevBuf kind_tmp, perm_tmp, koff_tmp, krange, kind_heavy, perm_heavy, koff_heavy, krange_heavy, sgcur;
     long long heavy_thr = 0;  // FP64-accumulated rows of the plan (flops at or above), 0 = none
 
     struct Batch {
@@ -257,7 +257,7 @@ spg_status spg_destroy(spg_handle h) {
     DevBuf *bufs[] = {&h->arp64, &h->brp64, &h->binfo, &h->ulist, &h->uflag, &h->bcrp, &h->bcsi, &h->bcs,
                       &h->rflops, &h->rflopsc, &h->rwin, &h->row_nnz, &h->coff, &h->kind_sym, &h->kind_num,
                       &h->perm_sym, &h->perm_num, &h->koff_sym, &h->koff_num, &h->tmp, &h->dstats, &h->red, &h->queue, &h->plan_len, &h->plan_off, &h->plan,
-                      &h->arena, &h->l2k, &h->l2v, &h->blens, &h->row_words, &h->kind_tmp, &h->perm_tmp, &h->koff_tmp, &h->krange, &h->kind_heavy, &h->perm_heavy, &h->koff_heavy, &h->krange_heavy};
+                      &h->arena, &h->l2k, &h->l2v, &h->blens, &h->row_words, &h->kind_tmp, &h->perm_tmp, &h->koff_tmp, &h->krange, &h->kind_heavy, &h->perm_heavy, &h->koff_heavy, &h->krange_heavy, &h->sgcur};
     for (DevBuf *b : bufs) release(*b);
     if (h->hst) (void)hipHostFree(h->hst);
     if (h->hkoff) (void)hipHostFree(h->hkoff);
@@ -657,6 +657,19 @@ static spg_status launch_kinds(spg_handle h, NumArgs<VT> na, const long long *kc
         na.rs.queue = h->queue.as<int32_t>() + XCDS * K_DG;
         HIPCHK(launch_fill_i32(na.rs.queue, XCDS, 0, st));
         lc.grid = std::min(grid_cap(kcount[K_DG]), sg_resident_grid(acc, sizeof(VT) == 8, h->cus));
+        // rows with more than one chunk of A entries keep per-entry cursors in
+        // HBM scratch (without it they search each run from the B row's start)
+        na.sg_cur = nullptr;
+        na.sg_cap = 0;
+        const int64_t mxa = (int64_t)h->hst->maxnnza;
+        if (mxa > WG_BIG) {
+            const int cap = (int)std::min<int64_t>(mxa, 65536);
+            if (ensure(h->sgcur, (size_t)lc.grid * 2 * cap * sizeof(int32_t)) == hipSuccess) {
+                na.sg_cur = h->sgcur.as<int32_t>();
+                na.sg_cap = cap;
+            }
+            (void)hipGetLastError();
+        }
         HIPCHK(launch_num_sg<VT>(na, acc, lc));
         lc.grid = 0;
     } else if (kcount[K_DG] > 0) {

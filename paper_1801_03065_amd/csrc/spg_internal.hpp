@@ -36,6 +36,7 @@ enum Kind : int {
 struct DevStats {
     unsigned long long fm, fmc, maxrf, maxrfc, nnzbc;
     unsigned long long fmb, fmcb;  // flops (raw / compressed) of rows beyond the short-row limit
+    unsigned long long maxnnza;    // longest row of A
     unsigned long long nnzc;
     int bad_input;    // malformed CSR (row_ptr not monotone / not ending at nnz, column out of range)
     int unsorted;     // B rows whose columns are not sorted
@@ -142,6 +143,8 @@ struct NumArgs {
     const int32_t *row_words; // K_PL: number of pairs of the row
     const int32_t *plan_len;  // K_DG (segmented): room in plan per row
     const uint8_t *sym_kind;  // K_DG (segmented): rows of symbolic kind K_DG with room hold a segment list
+    int32_t *sg_cur;          // K_DG (segmented): per workgroup, sg_cap A entries x 2 int32 (cursor, run end)
+    int sg_cap;               //   (nullptr / 0: runs found by two searches per segment)
     int b32;               // nnz(B) * 8 < 2^32: B entries addressed with 32-bit offsets
     DevStats *st;
 };

@@ -28,7 +28,7 @@
 namespace spg {
 namespace {
 
-constexpr int SG_U = 4;  // products per lane per round of the flat walks (loads in flight)
+constexpr int SG_U = 8;  // products per lane per round of the flat walks (loads in flight)
 
 __device__ __forceinline__ long long sg_block_excl_scan(long long v, long long *red, long long *total) {
     const int t = threadIdx.x, l = lane_id(), wv = t / WAVE;
@@ -75,14 +75,41 @@ __device__ __forceinline__ int64_t sg_lower_bound(const int32_t *bci, int64_t lo
     return lo;
 }
 
-// Index k of the run that holds flat product f: the number of inclusive run
-// ends st_off[0..cn) that are <= f.
-__device__ __forceinline__ int sg_find(const int64_t *st_off, int cn, long long f) {
-    int k = 0;
-#pragma unroll
-    for (int step = WG_BIG / 2; step >= 1; step >>= 1)
-        if (k + step <= cn && st_off[k + step - 1] <= f) k += step;
-    return k;
+// First index in [lo, hi) whose column is >= key, searched from lo (the run
+// is usually short): the row's end first, then probes at lo + 1, 3, 7, ...
+// and a binary search in the last gap.
+__device__ __forceinline__ int64_t sg_gallop(const int32_t *bci, int64_t lo, int64_t hi, int64_t key) {
+    if (lo >= hi) return lo;
+    const int32_t first = bci[lo], last = bci[hi - 1];
+    if ((int64_t)first >= key) return lo;
+    if ((int64_t)last < key) return hi;
+    int64_t below = lo, step = 1;  // bci[below] < key, bci[hi - 1] >= key
+    while (below + step < hi - 1 && (int64_t)bci[below + step] < key) {
+        below += step;
+        step <<= 1;
+    }
+    int64_t a = below + 1, b = min(below + step, hi - 1);  // answer in [a, b]
+    while (a < b) {
+        const int64_t mid = a + ((b - a) >> 1);
+        if ((int64_t)bci[mid] < key) a = mid + 1;
+        else b = mid;
+    }
+    return a;
+}
+
+// Index k of the run that holds flat product f: the first k >= kc with
+// st_off[k] > f (inclusive run ends, nondecreasing).  A lane's products
+// increase, so its previous run kc is the usual answer (one LDS read for long
+// runs); otherwise a binary search over the rest.
+__device__ __forceinline__ int sg_find(const int64_t *st_off, int cn, long long f, int kc) {
+    if (st_off[kc] > f) return kc;
+    int lo = kc + 1, hi = cn - 1;  // st_off[cn - 1] > f for every product f of the chunk
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (st_off[mid] > f) hi = mid;
+        else lo = mid + 1;
+    }
+    return lo;
 }
 
 template <typename VT, int ACC>
@@ -115,6 +142,15 @@ __global__ __launch_bounds__(WG_BIG) void k_num_sg(NumArgs<VT> a) {
         const int nseg = has_list ? (int)list[0].x : 1;
         const bool single = nseg == 1;
         const bool one_chunk = ae - ab <= WG_BIG;
+        // several chunks: per A entry a cursor into its B row (offset of the
+        // segment's first entry) and the run end, in this workgroup's scratch
+        int32_t *cur_g = nullptr, *nxt_g = nullptr;
+        if (!one_chunk && !single && a.sg_cur != nullptr && ae - ab <= a.sg_cap) {
+            cur_g = a.sg_cur + (int64_t)blockIdx.x * 2 * a.sg_cap;
+            nxt_g = cur_g + a.sg_cap;
+            for (int64_t k = t; k < ae - ab; k += WG_BIG) cur_g[k] = 0;
+            __syncthreads();
+        }
         // one chunk: lane t keeps A entry t for the whole row, with a cursor
         // into its B row that moves from segment to segment
         int64_t cur = 0, bend = 0;
@@ -147,7 +183,7 @@ __global__ __launch_bounds__(WG_BIG) void k_num_sg(NumArgs<VT> a) {
             if (one_chunk) {
                 long long len = 0;
                 if (t < cn1) {
-                    const int64_t e = single ? bend : sg_lower_bound(a.bci, cur, bend, col_hi);
+                    const int64_t e = single ? bend : sg_gallop(a.bci, cur, bend, col_hi);
                     st_lo[t] = cur;
                     len = e - cur;
                     cur = e;
@@ -165,9 +201,22 @@ __global__ __launch_bounds__(WG_BIG) void k_num_sg(NumArgs<VT> a) {
                         cn = (int)min((int64_t)WG_BIG, ae - cb);
                         long long len = 0;
                         if (t < cn) {
+                            const int64_t k = cb - ab + t;
                             const int j = a.aci[cb + t];
+                            const int32_t ck = cur_g ? cur_g[k] : 0;
+                            const int32_t nk = (cur_g && pass == 1) ? nxt_g[k] : 0;
                             int64_t s0 = a.brp[j], s1 = a.brp[j + 1];
-                            if (!single) {
+                            if (cur_g) {
+                                const int64_t b0 = s0;
+                                s0 = b0 + ck;
+                                if (pass == 0) {
+                                    s1 = sg_gallop(a.bci, s0, s1, col_hi);
+                                    nxt_g[k] = (int32_t)(s1 - b0);
+                                } else {
+                                    s1 = b0 + nk;
+                                    cur_g[k] = nk;  // the next segment starts where this run ends
+                                }
+                            } else if (!single) {
                                 s0 = sg_lower_bound(a.bci, s0, s1, col_lo);
                                 s1 = sg_lower_bound(a.bci, s0, s1, col_hi);
                             }
@@ -179,6 +228,7 @@ __global__ __launch_bounds__(WG_BIG) void k_num_sg(NumArgs<VT> a) {
                         if (t < cn) st_off[t] = ex + len;
                         __syncthreads();
                     }
+                    int kc = 0;  // this lane's current run
                     for (long long f0 = 0; f0 < tot; f0 += (long long)WG_BIG * SG_U) {
                         int64_t e[SG_U];
                         int kk[SG_U];
@@ -187,7 +237,8 @@ __global__ __launch_bounds__(WG_BIG) void k_num_sg(NumArgs<VT> a) {
                         for (int u = 0; u < SG_U; ++u) {
                             const long long f = f0 + u * WG_BIG + t;
                             ok[u] = f < tot;
-                            const int k = ok[u] ? sg_find(st_off, cn, f) : 0;
+                            if (ok[u]) kc = sg_find(st_off, cn, f, kc);
+                            const int k = kc;
                             kk[u] = k;
                             e[u] = st_lo[k] + (f - (k ? st_off[k - 1] : 0));
                         }
