@@ -844,25 +844,82 @@ __device__ __forceinline__ int dg_next_row(const RowSet &rs, int64_t lo, int64_t
     return (int)red[WG_BIG / WAVE];
 }
 
+// Structure of a heavy row: its B rows' column-set words OR-ed into the LDS
+// window, Thread-Flat-Parallel over chunks of 256 A entries.  Each lane keeps
+// DG_U words in flight, and finds the B row of its next word from the one it
+// had (its words increase), so long rows cost one LDS read per word.
+constexpr int DG_U = 8;
+
+template <bool COMP>
+__device__ __forceinline__ void dg_or_batched(int64_t ab, int64_t ae, int wlo, const int32_t *aci,
+                                              const int64_t *srp, const int32_t *bci, const int32_t *bcsi,
+                                              const uint32_t *bcs, uint32_t *bits, uint32_t *summ,
+                                              int64_t *st_off, int64_t *st_bs, long long *red) {
+    const int t = threadIdx.x;
+    for (int64_t cb = ab; cb < ae; cb += WG_BIG) {
+        const int cn = (int)min((int64_t)WG_BIG, ae - cb);
+        long long len = 0;
+        if (t < cn) {
+            const int j = aci[cb + t];
+            const int64_t s0 = srp[j], s1 = srp[j + 1];
+            st_bs[t] = s0;
+            len = s1 - s0;
+        }
+        long long tot;
+        const long long ex = block_excl_scan(len, red, &tot);
+        if (t < cn) st_off[t] = ex + len;
+        __syncthreads();
+        int kc = 0;
+        for (long long f0 = 0; f0 < tot; f0 += (long long)WG_BIG * DG_U) {
+            int64_t e[DG_U];
+            bool ok[DG_U];
+#pragma unroll
+            for (int u = 0; u < DG_U; ++u) {
+                const long long f = f0 + u * WG_BIG + t;
+                ok[u] = f < tot;
+                if (ok[u] && st_off[kc] <= f) {  // next B row: binary search over the rest
+                    int lo = kc + 1, hi = cn - 1;
+                    while (lo < hi) {
+                        const int mid = (lo + hi) >> 1;
+                        if (st_off[mid] > f) hi = mid;
+                        else lo = mid + 1;
+                    }
+                    kc = lo;
+                }
+                e[u] = ok[u] ? st_bs[kc] + (f - (kc ? st_off[kc - 1] : 0)) : 0;
+            }
+            uint32_t d[DG_U], cs[DG_U];
+#pragma unroll
+            for (int u = 0; u < DG_U; ++u) {
+                if constexpr (COMP) {
+                    d[u] = (uint32_t)(bcsi[e[u]] - wlo);
+                    cs[u] = bcs[e[u]];
+                } else {
+                    const int c = bci[e[u]];
+                    d[u] = (uint32_t)((c >> 5) - wlo);
+                    cs[u] = 1u << (c & 31);
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < DG_U; ++u) {
+                if (ok[u]) {
+                    atomicOr(&bits[d[u]], cs[u]);
+                    atomicOr(&summ[d[u] >> 5], 1u << (d[u] & 31));
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
 __device__ __forceinline__ void dg_or_pass(int i, int wlo, const int64_t *arp, const int32_t *aci,
                                            const int64_t *brp, const int32_t *bci, const int64_t *bcrp,
                                            const int32_t *bcsi, const uint32_t *bcs, uint32_t *bits,
                                            uint32_t *summ, int64_t *st_off, int64_t *st_bs, long long *red) {
-    const bool comp = bcrp != nullptr;
-    dg_flat(arp[i], arp[i + 1], aci, comp ? bcrp : brp, st_off, st_bs, red,
-            [&](int, int64_t e, int64_t) {
-                uint32_t d, cs;
-                if (comp) {
-                    d = (uint32_t)(bcsi[e] - wlo);
-                    cs = bcs[e];
-                } else {
-                    const int c = bci[e];
-                    d = (uint32_t)((c >> 5) - wlo);
-                    cs = 1u << (c & 31);
-                }
-                atomicOr(&bits[d], cs);
-                atomicOr(&summ[d >> 5], 1u << (d & 31));
-            });
+    if (bcrp)
+        dg_or_batched<true>(arp[i], arp[i + 1], wlo, aci, bcrp, bci, bcsi, bcs, bits, summ, st_off, st_bs, red);
+    else
+        dg_or_batched<false>(arp[i], arp[i + 1], wlo, aci, brp, bci, bcsi, bcs, bits, summ, st_off, st_bs, red);
 }
 
 // Segment list of a heavy row (the row's bit window is complete in bits /
