@@ -6,7 +6,7 @@
 // the row's complete bit window, cuts it into segments: runs of consecutive
 // column-set words with at most SG_CAP entries that stay inside one aligned
 // group of SG_NW words.  The numeric phase then walks the segments in column
-// order, one 256-lane workgroup per row:
+// order, one 512-lane workgroup per row:
 //
 //   1. the part of each B row that falls in the segment (B's columns are
 //      sorted, so it is one run, found by binary search; rows with one A
@@ -29,6 +29,10 @@ namespace spg {
 namespace {
 
 constexpr int SG_U = 8;  // products per lane per round of the flat walks (loads in flight)
+// Lanes per workgroup (one heavy row).  LDS (~70 KB) allows two workgroups
+// per CU; 512 lanes rather than 256 double the loads in flight per CU for the
+// same LDS, with registers held to 128 (4 waves per SIMD).
+constexpr int SG_WG = 512;
 
 __device__ __forceinline__ long long sg_block_excl_scan(long long v, long long *red, long long *total) {
     const int t = threadIdx.x, l = lane_id(), wv = t / WAVE;
@@ -38,7 +42,7 @@ __device__ __forceinline__ long long sg_block_excl_scan(long long v, long long *
     __syncthreads();
     long long off = 0, tot = 0;
 #pragma unroll
-    for (int u = 0; u < WG_BIG / WAVE; ++u) {
+    for (int u = 0; u < SG_WG / WAVE; ++u) {
         const long long x = red[u];
         if (u < wv) off += x;
         tot += x;
@@ -51,12 +55,12 @@ __device__ __forceinline__ int sg_next_row(const RowSet &rs, int64_t lo, int64_t
     __syncthreads();
     if (threadIdx.x == 0) {
         const int64_t t = xcd_grab(rs.queue, lo, hi, x);
-        red[WG_BIG / WAVE] = t < 0 ? -1 : rs.rows[t];
-        red[WG_BIG / WAVE + 1] = x;
+        red[SG_WG / WAVE] = t < 0 ? -1 : rs.rows[t];
+        red[SG_WG / WAVE + 1] = x;
     }
     __syncthreads();
-    x = (int)red[WG_BIG / WAVE + 1];
-    return (int)red[WG_BIG / WAVE];
+    x = (int)red[SG_WG / WAVE + 1];
+    return (int)red[SG_WG / WAVE];
 }
 
 // First index in [lo, hi) whose column is >= key (hi when none); the row's
@@ -113,19 +117,19 @@ __device__ __forceinline__ int sg_find(const int64_t *st_off, int cn, long long 
 }
 
 template <typename VT, int ACC>
-__global__ __launch_bounds__(WG_BIG) void k_num_sg(NumArgs<VT> a) {
+__global__ __launch_bounds__(SG_WG) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_num_sg(NumArgs<VT> a) {
     using A = Accum<VT, ACC>;
     using S = typename A::store_t;
     __shared__ __align__(16) uint32_t bits[SG_NW];
     __shared__ uint16_t pre[SG_NW];
     __shared__ S vals[SG_CAP];
-    __shared__ int64_t st_lo[WG_BIG];   // run start (B entry) per A entry of the chunk
-    __shared__ int64_t st_off[WG_BIG];  // inclusive prefix of the run lengths
-    __shared__ VT st_a[WG_BIG];
-    __shared__ long long red[WG_BIG / WAVE + 2];
+    __shared__ int64_t st_lo[SG_WG];   // run start (B entry) per A entry of the chunk
+    __shared__ int64_t st_off[SG_WG];  // inclusive prefix of the run lengths
+    __shared__ VT st_a[SG_WG];
+    __shared__ long long red[SG_WG / WAVE + 2];
     const int t = threadIdx.x;
-    for (int w = t; w < SG_NW; w += WG_BIG) bits[w] = 0;
-    for (int r = t; r < SG_CAP; r += WG_BIG) vals[r] = A::zero();
+    for (int w = t; w < SG_NW; w += SG_WG) bits[w] = 0;
+    for (int r = t; r < SG_CAP; r += SG_WG) vals[r] = A::zero();
     int64_t qlo, qhi;
     rs_bounds(a.rs, qlo, qhi);
     const int64_t cbase = a.cbase_row >= 0 ? a.coff[a.cbase_row] : 0;
@@ -141,14 +145,14 @@ __global__ __launch_bounds__(WG_BIG) void k_num_sg(NumArgs<VT> a) {
         const uint2 *list = has_list ? a.plan + a.plan_off[i] : nullptr;
         const int nseg = has_list ? (int)list[0].x : 1;
         const bool single = nseg == 1;
-        const bool one_chunk = ae - ab <= WG_BIG;
+        const bool one_chunk = ae - ab <= SG_WG;
         // several chunks: per A entry a cursor into its B row (offset of the
         // segment's first entry) and the run end, in this workgroup's scratch
         int32_t *cur_g = nullptr, *nxt_g = nullptr;
         if (!one_chunk && !single && a.sg_cur != nullptr && ae - ab <= a.sg_cap) {
             cur_g = a.sg_cur + (int64_t)blockIdx.x * 2 * a.sg_cap;
             nxt_g = cur_g + a.sg_cap;
-            for (int64_t k = t; k < ae - ab; k += WG_BIG) cur_g[k] = 0;
+            for (int64_t k = t; k < ae - ab; k += SG_WG) cur_g[k] = 0;
             __syncthreads();
         }
         // one chunk: lane t keeps A entry t for the whole row, with a cursor
@@ -194,11 +198,11 @@ __global__ __launch_bounds__(WG_BIG) void k_num_sg(NumArgs<VT> a) {
             }
             // pass 1 (structure) and pass 2 (values) walk the same runs
             for (int pass = 0; pass < 2; ++pass) {
-                for (int64_t cb = ab; cb < ae; cb += WG_BIG) {
+                for (int64_t cb = ab; cb < ae; cb += SG_WG) {
                     int cn = cn1;
                     long long tot = tot1;
                     if (!one_chunk) {
-                        cn = (int)min((int64_t)WG_BIG, ae - cb);
+                        cn = (int)min((int64_t)SG_WG, ae - cb);
                         long long len = 0;
                         if (t < cn) {
                             const int64_t k = cb - ab + t;
@@ -229,13 +233,13 @@ __global__ __launch_bounds__(WG_BIG) void k_num_sg(NumArgs<VT> a) {
                         __syncthreads();
                     }
                     int kc = 0;  // this lane's current run
-                    for (long long f0 = 0; f0 < tot; f0 += (long long)WG_BIG * SG_U) {
+                    for (long long f0 = 0; f0 < tot; f0 += (long long)SG_WG * SG_U) {
                         int64_t e[SG_U];
                         int kk[SG_U];
                         bool ok[SG_U];
 #pragma unroll
                         for (int u = 0; u < SG_U; ++u) {
-                            const long long f = f0 + u * WG_BIG + t;
+                            const long long f = f0 + u * SG_WG + t;
                             ok[u] = f < tot;
                             if (ok[u]) kc = sg_find(st_off, cn, f, kc);
                             const int k = kc;
@@ -269,8 +273,8 @@ __global__ __launch_bounds__(WG_BIG) void k_num_sg(NumArgs<VT> a) {
                 }
                 __syncthreads();
                 if (pass == 0) {
-                    // ranks: lane t scans words [t*SG_NW/WG_BIG, ...) of the segment
-                    constexpr int WPL = SG_NW / WG_BIG;
+                    // ranks: lane t scans words [t*SG_NW/SG_WG, ...) of the segment
+                    constexpr int WPL = SG_NW / SG_WG;
                     const int wb = t * WPL;
                     uint32_t wv[WPL];
                     int sum = 0;
@@ -298,7 +302,7 @@ __global__ __launch_bounds__(WG_BIG) void k_num_sg(NumArgs<VT> a) {
             // write-out: columns from the bits (one word per lane, strided),
             // values in rank order; both cleared for the next segment
             const int64_t o = c0 + p1 - cbase;
-            for (int w = t; w < span; w += WG_BIG) {
+            for (int w = t; w < span; w += SG_WG) {
                 uint32_t m = bits[w];
                 int r = pre[w];
                 const int colb = (dbase + w) << 5;
@@ -311,7 +315,7 @@ __global__ __launch_bounds__(WG_BIG) void k_num_sg(NumArgs<VT> a) {
                 bits[w] = 0;
             }
             const int cw = min(cnt, SG_CAP);
-            for (int r = t; r < cw; r += WG_BIG) {
+            for (int r = t; r < cw; r += SG_WG) {
                 a.cval[o + r] = A::fin(vals[r]);
                 vals[r] = A::zero();
             }
@@ -325,14 +329,14 @@ template <typename VT, int ACC>
 hipError_t num_sg_impl(const NumArgs<VT> &a, const LaunchCfg &c) {
     int grid = c.grid;
     if (grid <= 0) grid = sg_resident_grid(ACC, sizeof(VT) == 8, c.cus);
-    hipLaunchKernelGGL((k_num_sg<VT, ACC>), dim3(grid), dim3(WG_BIG), 0, c.stream, a);
+    hipLaunchKernelGGL((k_num_sg<VT, ACC>), dim3(grid), dim3(SG_WG), 0, c.stream, a);
     return hipGetLastError();
 }
 
 template <typename K>
 int resident(K kernel, int cus) {
     int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, WG_BIG, 0) != hipSuccess || per_cu < 1)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, SG_WG, 0) != hipSuccess || per_cu < 1)
         per_cu = 1;
     int g = per_cu * cus;
     g = (g / XCDS) * XCDS;
