@@ -243,7 +243,7 @@ spg_status spg_create(spg_handle *out, void *stream, const spg_options *opt) {
     h->lds_max = (size_t)lds;
     // window words the workgroup dense kernel can hold next to its staging area
     // LDS bytes = 4*nw (bits) + nw/8 (summary) + staging + alignment slack
-    const size_t over = 8 * WG_BIG * 3 + 8 * (WG_BIG / WAVE + 2) + 128;
+    const size_t over = 8 * DG_WG * 3 + 8 * (DG_WG / WAVE + 2) + 128;
     int64_t words = h->lds_max > over ? (int64_t)((h->lds_max - over) * 8 / 33) : 0;
     words = (words / 32) * 32;
     h->dg_nw_max = (int)std::min<int64_t>(DG_NW_MAX, std::max<int64_t>(words, 32));

@@ -20,7 +20,7 @@
 // K_DW: one 64-lane wavefront per row, Thread-Parallel lane groups (a group
 //       of 2^lg_gs lanes walks one B row, several groups per wavefront),
 //       window up to 2048 words, row up to 1024 entries.
-// K_DG: one 256-lane workgroup per row, Thread-Flat-Parallel (each lane takes
+// K_DG: one 1024-lane workgroup per row, Thread-Flat-Parallel (each lane takes
 //       one multiplication of the flattened row; Partitioning Schemes
 //       subsection), window up to 32768 words in LDS, values in an HBM array
 //       over the window (one slice per resident workgroup: the memory pool of
@@ -769,19 +769,19 @@ __host__ __device__ inline DgLayout dg_layout(int nwm) {
     L.summ = o;
     o += align16(4 * (size_t)nsm);
     L.st_off = o;
-    o += 8 * WG_BIG;
+    o += 8 * DG_WG;
     L.st_bs = o;
-    o += 8 * WG_BIG;
+    o += 8 * DG_WG;
     L.st_a = o;
-    o += 8 * WG_BIG;
+    o += 8 * DG_WG;
     L.red = o;
-    o += 8 * (WG_BIG / WAVE + 2);
+    o += 8 * (DG_WG / WAVE + 2);
     L.total = o;
     return L;
 }
 
 // Block-wide exclusive scan of v; *total receives the sum.  red holds
-// WG_BIG/WAVE + 2 longs.
+// DG_WG/WAVE + 2 longs.
 __device__ __forceinline__ long long block_excl_scan(long long v, long long *red, long long *total) {
     const int t = threadIdx.x, l = lane_id(), wv = t / WAVE;
     const long long inc = wave_incl_scan64(v);
@@ -790,7 +790,7 @@ __device__ __forceinline__ long long block_excl_scan(long long v, long long *red
     __syncthreads();
     long long off = 0, tot = 0;
 #pragma unroll
-    for (int u = 0; u < WG_BIG / WAVE; ++u) {
+    for (int u = 0; u < DG_WG / WAVE; ++u) {
         const long long x = red[u];
         if (u < wv) off += x;
         tot += x;
@@ -806,8 +806,8 @@ template <typename F>
 __device__ __forceinline__ void dg_flat(int64_t ab, int64_t ae, const int32_t *aci, const int64_t *rp,
                                         int64_t *st_off, int64_t *st_bs, long long *red, F &&body) {
     const int t = threadIdx.x;
-    for (int64_t cb = ab; cb < ae; cb += WG_BIG) {
-        const int cn = (int)min((int64_t)WG_BIG, ae - cb);
+    for (int64_t cb = ab; cb < ae; cb += DG_WG) {
+        const int cn = (int)min((int64_t)DG_WG, ae - cb);
         long long len = 0;
         if (t < cn) {
             const int j = aci[cb + t];
@@ -819,7 +819,7 @@ __device__ __forceinline__ void dg_flat(int64_t ab, int64_t ae, const int32_t *a
         const long long ex = block_excl_scan(len, red, &tot);
         if (t < cn) st_off[t] = ex + len;
         __syncthreads();
-        for (long long f = t; f < tot; f += WG_BIG) {
+        for (long long f = t; f < tot; f += DG_WG) {
             int lo = 0, hi = cn - 1;
             while (lo < hi) {
                 const int mid = (lo + hi) >> 1;
@@ -836,12 +836,12 @@ __device__ __forceinline__ int dg_next_row(const RowSet &rs, int64_t lo, int64_t
     __syncthreads();
     if (threadIdx.x == 0) {
         const int64_t t = xcd_grab(rs.queue, lo, hi, x);
-        red[WG_BIG / WAVE] = t < 0 ? -1 : rs.rows[t];
-        red[WG_BIG / WAVE + 1] = x;
+        red[DG_WG / WAVE] = t < 0 ? -1 : rs.rows[t];
+        red[DG_WG / WAVE + 1] = x;
     }
     __syncthreads();
-    x = (int)red[WG_BIG / WAVE + 1];
-    return (int)red[WG_BIG / WAVE];
+    x = (int)red[DG_WG / WAVE + 1];
+    return (int)red[DG_WG / WAVE];
 }
 
 // Structure of a heavy row: its B rows' column-set words OR-ed into the LDS
@@ -856,8 +856,8 @@ __device__ __forceinline__ void dg_or_batched(int64_t ab, int64_t ae, int wlo, c
                                               const uint32_t *bcs, uint32_t *bits, uint32_t *summ,
                                               int64_t *st_off, int64_t *st_bs, long long *red) {
     const int t = threadIdx.x;
-    for (int64_t cb = ab; cb < ae; cb += WG_BIG) {
-        const int cn = (int)min((int64_t)WG_BIG, ae - cb);
+    for (int64_t cb = ab; cb < ae; cb += DG_WG) {
+        const int cn = (int)min((int64_t)DG_WG, ae - cb);
         long long len = 0;
         if (t < cn) {
             const int j = aci[cb + t];
@@ -870,12 +870,12 @@ __device__ __forceinline__ void dg_or_batched(int64_t ab, int64_t ae, int wlo, c
         if (t < cn) st_off[t] = ex + len;
         __syncthreads();
         int kc = 0;
-        for (long long f0 = 0; f0 < tot; f0 += (long long)WG_BIG * DG_U) {
+        for (long long f0 = 0; f0 < tot; f0 += (long long)DG_WG * DG_U) {
             int64_t e[DG_U];
             bool ok[DG_U];
 #pragma unroll
             for (int u = 0; u < DG_U; ++u) {
-                const long long f = f0 + u * WG_BIG + t;
+                const long long f = f0 + u * DG_WG + t;
                 ok[u] = f < tot;
                 if (ok[u] && st_off[kc] <= f) {  // next B row: binary search over the rest
                     int lo = kc + 1, hi = cn - 1;
@@ -935,13 +935,13 @@ __device__ long long dg_segments(int nw, int ns, uint32_t *bits, uint32_t *summ,
     const int ng = (nw + SG_NW - 1) / SG_NW;
     if (t < ng) gfirst[t] = INT_MAX;
     __syncthreads();
-    for (int s = t; s < ns; s += WG_BIG) {
+    for (int s = t; s < ns; s += DG_WG) {
         const uint32_t m = summ[s];
         if (m) atomicMin(&gfirst[(s << 5) / SG_NW], (s << 5) + __ffs(m) - 1);
     }
     __syncthreads();
     long long run = 0, words = 0, cuts = 0;
-    for (int s0 = 0; s0 < ns; s0 += WG_BIG) {
+    for (int s0 = 0; s0 < ns; s0 += DG_WG) {
         const int s = s0 + t;
         const uint32_t m = s < ns ? summ[s] : 0u;
         long long c = 0;
@@ -987,7 +987,7 @@ __device__ long long dg_segments(int nw, int ns, uint32_t *bits, uint32_t *summ,
     return run | (words << 32);
 }
 
-__global__ __launch_bounds__(WG_BIG) void k_sym_dg(SymArgs a) {
+__global__ __launch_bounds__(DG_WG) void k_sym_dg(SymArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     const DgLayout L = dg_layout(a.nw_max);
     uint32_t *bits = (uint32_t *)(smem + L.bits);
@@ -998,8 +998,8 @@ __global__ __launch_bounds__(WG_BIG) void k_sym_dg(SymArgs a) {
     __shared__ int gfirst[DG_NW_MAX / SG_NW];
     const int t = threadIdx.x;
     const int nsm = (a.nw_max + 31) >> 5;
-    for (int w = t; w < a.nw_max; w += WG_BIG) bits[w] = 0;
-    for (int w = t; w < nsm; w += WG_BIG) summ[w] = 0;
+    for (int w = t; w < a.nw_max; w += DG_WG) bits[w] = 0;
+    for (int w = t; w < nsm; w += DG_WG) summ[w] = 0;
     int64_t lo, hi;
     rs_bounds(a.rs, lo, hi);
     int x = blockIdx.x % XCDS;
@@ -1020,7 +1020,7 @@ __global__ __launch_bounds__(WG_BIG) void k_sym_dg(SymArgs a) {
             continue;
         }
         long long cnt = 0;
-        for (int s = t; s < ns; s += WG_BIG) {
+        for (int s = t; s < ns; s += DG_WG) {
             uint32_t m = summ[s];
             summ[s] = 0;
             cnt += (long long)__popc(m) << 32;  // touched words in the high half
@@ -1041,7 +1041,7 @@ __global__ __launch_bounds__(WG_BIG) void k_sym_dg(SymArgs a) {
 }
 
 template <typename VT, int ACC>
-__global__ __launch_bounds__(WG_BIG) void k_num_dg(NumArgs<VT> a) {
+__global__ __launch_bounds__(DG_WG) void k_num_dg(NumArgs<VT> a) {
     using A = Accum<VT, ACC>;
     using S = typename A::store_t;
     extern __shared__ __align__(16) unsigned char smem[];
@@ -1054,8 +1054,8 @@ __global__ __launch_bounds__(WG_BIG) void k_num_dg(NumArgs<VT> a) {
     S *gv = (S *)a.arena + (int64_t)blockIdx.x * a.arena_cap;  // this workgroup's window of values
     const int t = threadIdx.x;
     const int nsm = (a.nw_max + 31) >> 5;
-    for (int w = t; w < a.nw_max; w += WG_BIG) bits[w] = 0;
-    for (int w = t; w < nsm; w += WG_BIG) summ[w] = 0;
+    for (int w = t; w < a.nw_max; w += DG_WG) bits[w] = 0;
+    for (int w = t; w < nsm; w += DG_WG) summ[w] = 0;
     int64_t lo, hi;
     rs_bounds(a.rs, lo, hi);
     const int64_t cbase = a.cbase_row >= 0 ? a.coff[a.cbase_row] : 0;
@@ -1079,7 +1079,7 @@ __global__ __launch_bounds__(WG_BIG) void k_num_dg(NumArgs<VT> a) {
         const int64_t c0 = a.coff[i];
         const int64_t cend = a.coff[i + 1];
         long long run = 0;
-        for (int s0 = 0; s0 < ns; s0 += WG_BIG) {
+        for (int s0 = 0; s0 < ns; s0 += DG_WG) {
             const int s = s0 + t;
             const uint32_t m = (s < ns) ? summ[s] : 0u;
             long long cnt = 0;
@@ -1144,8 +1144,8 @@ hipError_t launch_sym_dw(const SymArgs &a, const LaunchCfg &c) {
 
 hipError_t launch_sym_dg(const SymArgs &a, const LaunchCfg &c) {
     const size_t lds = lds_sym_dg(a.nw_max);
-    const int grid = c.grid > 0 ? c.grid : resident_grid(k_sym_dg, WG_BIG, lds, c.cus);
-    hipLaunchKernelGGL(k_sym_dg, dim3(grid), dim3(WG_BIG), lds, c.stream, a);
+    const int grid = c.grid > 0 ? c.grid : resident_grid(k_sym_dg, DG_WG, lds, c.cus);
+    hipLaunchKernelGGL(k_sym_dg, dim3(grid), dim3(DG_WG), lds, c.stream, a);
     return hipGetLastError();
 }
 
@@ -1160,8 +1160,8 @@ static hipError_t num_dw_impl(const NumArgs<VT> &a, const LaunchCfg &c) {
 template <typename VT, int ACC>
 static hipError_t num_dg_impl(const NumArgs<VT> &a, const LaunchCfg &c) {
     const size_t lds = lds_num_dg(a.nw_max);
-    const int grid = c.grid > 0 ? c.grid : resident_grid(k_num_dg<VT, ACC>, WG_BIG, lds, c.cus);
-    hipLaunchKernelGGL((k_num_dg<VT, ACC>), dim3(grid), dim3(WG_BIG), lds, c.stream, a);
+    const int grid = c.grid > 0 ? c.grid : resident_grid(k_num_dg<VT, ACC>, DG_WG, lds, c.cus);
+    hipLaunchKernelGGL((k_num_dg<VT, ACC>), dim3(grid), dim3(DG_WG), lds, c.stream, a);
     return hipGetLastError();
 }
 
@@ -1188,10 +1188,10 @@ hipError_t launch_num_dg<float>(const NumArgs<float> &a, int acc, const LaunchCf
 
 // Grid of the persistent kernels: resident workgroups of the concrete kernel.
 int dg_resident_grid(int acc, bool dbl, size_t lds, int cus) {
-    if (dbl) return resident_grid(k_num_dg<double, ACC_NATIVE>, WG_BIG, lds, cus);
-    if (acc == ACC_COMP) return resident_grid(k_num_dg<float, ACC_COMP>, WG_BIG, lds, cus);
-    if (acc == ACC_WIDE) return resident_grid(k_num_dg<float, ACC_WIDE>, WG_BIG, lds, cus);
-    return resident_grid(k_num_dg<float, ACC_NATIVE>, WG_BIG, lds, cus);
+    if (dbl) return resident_grid(k_num_dg<double, ACC_NATIVE>, DG_WG, lds, cus);
+    if (acc == ACC_COMP) return resident_grid(k_num_dg<float, ACC_COMP>, DG_WG, lds, cus);
+    if (acc == ACC_WIDE) return resident_grid(k_num_dg<float, ACC_WIDE>, DG_WG, lds, cus);
+    return resident_grid(k_num_dg<float, ACC_NATIVE>, DG_WG, lds, cus);
 }
 
 }  // namespace spg

@@ -12,6 +12,10 @@ namespace spg {
 constexpr int WAVE = 64;  // CDNA wavefront width
 constexpr int XCDS = 8;   // accelerator complex dies on the MI355X
 constexpr int WG_BIG = 256;
+// Lanes of the bit-window workgroup kernels (one heavy row per workgroup):
+// their window (up to 128 KB of LDS) leaves room for one workgroup per CU, so
+// the workgroup is large to keep enough loads in flight.
+constexpr int DG_WG = 1024;
 
 // Per row of B: number of entries, number of distinct column-set words
 // (col >> 5) after compression, lowest and highest word touched.
