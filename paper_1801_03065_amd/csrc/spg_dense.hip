@@ -712,7 +712,7 @@ __global__ __launch_bounds__(WAVE) void k_num_dw(NumArgs<VT> a) {
                         const VT av = (VT)st_a[t0 + u * ng];
                         const int c = col[u];
                         const int w = (c >> 5) - wlo;
-                        const int rk = pre[w] + __popc(bits[w] & ((1u << (c & 31)) - 1u));
+                        const int rk = pre[w] + bits_below(bits[w], c & 31);
                         A::add(&vals[rk], av, bv[u]);
                     }
                 }
@@ -725,7 +725,7 @@ __global__ __launch_bounds__(WAVE) void k_num_dw(NumArgs<VT> a) {
                         const int64_t e = st_bs[t] + p;
                         const int c = a.bci[e];
                         const int w = (c >> 5) - wlo;
-                        const int rk = pre[w] + __popc(bits[w] & ((1u << (c & 31)) - 1u));
+                        const int rk = pre[w] + bits_below(bits[w], c & 31);
                         A::add(&vals[rk], avt, a.bval[e]);
                     }
                 }

@@ -238,6 +238,11 @@ __device__ __forceinline__ long long wave_incl_scan64(long long v) {
     }
     return v;
 }
+// Set bits of word w below bit b (b in [0, 31]): one bit-field extract of the
+// low b bits (width 0 gives 0) and a popcount.
+__device__ __forceinline__ int bits_below(uint32_t w, int b) {
+    return __popc(__builtin_amdgcn_ubfe(w, 0u, (uint32_t)b));
+}
 // Number of set bits of a 64-bit lane mask below this lane.
 __device__ __forceinline__ int mbcnt(unsigned long long m) {
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0));

@@ -267,7 +267,7 @@ __global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(4, 8))) vo
                         const int c = col[u];
                         const int s = map[(c >> 5) - wlo];
                         const unsigned long long e = bp[s];
-                        const int rk = (int)(uint32_t)(e >> 32) + __popc((uint32_t)e & ((1u << (c & 31)) - 1u));
+                        const int rk = (int)(uint32_t)(e >> 32) + bits_below((uint32_t)e, c & 31);
                         A::add(&vals[rk < rnnz ? rk : 0], (VT)st_a[g + u * ng], pv[u]);
                     }
                 }
@@ -294,7 +294,7 @@ __global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(4, 8))) vo
                             const int s = map[(c >> 5) - wlo];
                             const unsigned long long e = bp[s];
                             const int rk =
-                                (int)(uint32_t)(e >> 32) + __popc((uint32_t)e & ((1u << (c & 31)) - 1u));
+                                (int)(uint32_t)(e >> 32) + bits_below((uint32_t)e, c & 31);
                             A::add(&vals[rk < rnnz ? rk : 0], av, a.bval[bs + p]);
                         }
                     }

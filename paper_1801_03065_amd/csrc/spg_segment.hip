@@ -263,8 +263,7 @@ __global__ __launch_bounds__(SG_WG) __attribute__((amdgpu_waves_per_eu(4, 4))) v
                             for (int u = 0; u < SG_U; ++u) {
                                 const int d = (c[u] >> 5) - dbase;
                                 if (!ok[u] || (unsigned)d >= (unsigned)SG_NW) continue;
-                                const uint32_t below = (1u << (c[u] & 31)) - 1u;
-                                const int r = (int)pre[d] + __popc(bits[d] & below);
+                                const int r = (int)pre[d] + bits_below(bits[d], c[u] & 31);
                                 if (r < SG_CAP) A::add(&vals[r], st_a[kk[u]], v[u]);
                             }
                         }

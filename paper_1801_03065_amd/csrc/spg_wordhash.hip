@@ -308,7 +308,7 @@ __global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(4, 8))) vo
                             const int c = a.bci[bs + p];
                             const uint32_t h = wh_find(tkey, (uint32_t)((c >> 5) - wlo), lg_ts);
                             const unsigned long long e = tbp[h];
-                            const int rk = (int)(uint32_t)(e >> 32) + __popc((uint32_t)e & ((1u << (c & 31)) - 1u));
+                            const int rk = (int)(uint32_t)(e >> 32) + bits_below((uint32_t)e, c & 31);
                             A::add(&vals[rk], av, a.bval[bs + p]);
                         }
                     }
