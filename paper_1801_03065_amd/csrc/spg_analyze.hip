@@ -112,6 +112,37 @@ __global__ __launch_bounds__(BLK) void k_brow(int64_t n, int64_t ncols, const in
     if (__ballot(badcol) && lane_id() == 0) atomicOr(&st->bad_input, 1);
 }
 
+// The same per row of B for short rows (average length <= BR_SHORT): one
+// lane per row walks its columns.
+constexpr int BR_SHORT = 8;
+
+__global__ __launch_bounds__(BLK) void k_brow_short(int64_t n, int64_t ncols, const int64_t *brp, const int32_t *bci,
+                                                     BRow *out, int32_t *ulist, uint8_t *uflag, DevStats *st) {
+    int badcol = 0;
+    for (int64_t r = (int64_t)blockIdx.x * BLK + threadIdx.x; r < n; r += (int64_t)gridDim.x * BLK) {
+        const int64_t b = brp[r], e = brp[r + 1];
+        int cmin = INT_MAX, cmax = -1, heads = 0, unsorted = 0, prev = -1;
+        for (int64_t k = b; k < e; ++k) {
+            const int col = bci[k];
+            cmin = min(cmin, col);
+            cmax = max(cmax, col);
+            unsorted |= (prev >= col);
+            heads += ((col >> 5) != (prev >> 5));
+            badcol |= (col < 0) | ((int64_t)col >= ncols);
+            prev = col;
+        }
+        BRow o;
+        o.len = (int32_t)(e - b);
+        o.lenc = heads;
+        o.wmin = (e > b) ? (cmin >> 5) : INT_MAX;
+        o.wmax = (e > b) ? (cmax >> 5) : -1;
+        out[r] = o;
+        uflag[r] = unsorted ? 1 : 0;
+        if (unsorted) ulist[atomicAdd(&st->unsorted, 1)] = (int32_t)r;
+    }
+    if (__ballot(badcol) && lane_id() == 0) atomicOr(&st->bad_input, 1);
+}
+
 // One wavefront per listed row: OR every column bit into an LDS bitmap over
 // the row's word window; distinct words = nonzero bitmap words.  mode 0
 // writes the count, mode 1 writes the (word, bits) pairs in word order.
@@ -749,11 +780,15 @@ hipError_t launch_copy_rp(int64_t n1, const void *src, int is64, int64_t nnz, in
     return hipGetLastError();
 }
 
-hipError_t launch_brow(int64_t n, int64_t ncols, const int64_t *brp, const int32_t *bci, BRow *out,
+hipError_t launch_brow(int64_t n, int64_t nnz, int64_t ncols, const int64_t *brp, const int32_t *bci, BRow *out,
                        int32_t *ulist, uint8_t *uflag, DevStats *st, hipStream_t s) {
     if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_brow, dim3(grid_for(n * BR_GS, BLK)), dim3(BLK), 0, s, n, ncols, brp, bci, out, ulist, uflag,
-                       st);
+    if (nnz <= BR_SHORT * n)
+        hipLaunchKernelGGL(k_brow_short, dim3(grid_for(n, BLK, 4096)), dim3(BLK), 0, s, n, ncols, brp, bci, out, ulist,
+                           uflag, st);
+    else
+        hipLaunchKernelGGL(k_brow, dim3(grid_for(n * BR_GS, BLK, 8192)), dim3(BLK), 0, s, n, ncols, brp, bci, out,
+                           ulist, uflag, st);
     return hipGetLastError();
 }
 
@@ -780,7 +815,7 @@ hipError_t launch_compress_sorted_flags(int64_t n, const int64_t *brp, const int
                                         const uint8_t *unsorted, const int64_t *bcrp, int32_t *bcsi,
                                         uint32_t *bcs, const int *enable, hipStream_t s) {
     if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_compress_sorted, dim3(grid_for(n * BR_GS, BLK)), dim3(BLK), 0, s, n, brp, bci, bi,
+    hipLaunchKernelGGL(k_compress_sorted, dim3(grid_for(n * BR_GS, BLK, 8192)), dim3(BLK), 0, s, n, brp, bci, bi,
                        unsorted, bcrp, bcsi, bcs, enable);
     return hipGetLastError();
 }

@@ -340,7 +340,7 @@ static spg_status symbolic_core(spg_handle h, int64_t m, int64_t n, int64_t k, i
     // Everything up to the first host sync runs on unchecked input: row
     // pointers are clamped copies, columns out of range only raise the flag
     // (k_brow, k_rowinfo) and are never used as indices before the sync.
-    HIPCHK(launch_brow(n, k, brp, bci, bi, h->ulist.as<int32_t>(), h->uflag.as<uint8_t>(), dst, st));
+    HIPCHK(launch_brow(n, nnzb, k, brp, bci, bi, h->ulist.as<int32_t>(), h->uflag.as<uint8_t>(), dst, st));
     HIPCHK(launch_brow_unsorted(h->ulist.as<int32_t>(), &dst->unsorted, brp, bci, bi, dst, st));
     const bool sel = h->opt.accumulator == SPG_ACC_AUTO;
     HIPCHK(launch_rowinfo(m, n, arp, aci, bi, h->rflops.as<int64_t>(), h->rflopsc.as<int64_t>(),

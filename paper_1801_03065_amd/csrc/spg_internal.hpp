@@ -319,7 +319,7 @@ struct LaunchCfg {
 // Per row of B: length, distinct column-set words, word window, sortedness
 // (uflag, and the list of unsorted rows); columns out of [0, ncols) raise the
 // malformed-input flag.
-hipError_t launch_brow(int64_t n, int64_t ncols, const int64_t *brp, const int32_t *bci, BRow *out,
+hipError_t launch_brow(int64_t n, int64_t nnz, int64_t ncols, const int64_t *brp, const int32_t *bci, BRow *out,
                        int32_t *unsorted_list, uint8_t *uflag, DevStats *st, hipStream_t s);
 hipError_t launch_brow_unsorted(const int32_t *list, const int *count, const int64_t *brp, const int32_t *bci,
                                 BRow *out, DevStats *st, hipStream_t s);
