@@ -261,6 +261,16 @@ __device__ __forceinline__ long long wave_max64(long long v) {
 }
 
 constexpr int RI_GS = 8;
+// DPP lane moves inside groups of 8 lanes (quad permutes, half-row mirror)
+template <int CTRL>
+__device__ __forceinline__ int ri_x32(int v) {
+    return __builtin_amdgcn_mov_dpp(v, CTRL, 0xF, 0xF, false);
+}
+template <int CTRL>
+__device__ __forceinline__ long long ri_x(long long v) {
+    const int lo = ri_x32<CTRL>((int)(uint32_t)v), hi = ri_x32<CTRL>((int)((uint64_t)v >> 32));
+    return (long long)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
 constexpr int RI_U = 4;  // A entries per lane in flight
 constexpr int RI_GRID = 2048;
 constexpr int RI_F = 7;  // rowinfo partial fields: fm, fmc, max, max compressed, fm and fmc of long rows,
@@ -312,13 +322,21 @@ __global__ __launch_bounds__(BLK) void k_rowinfo(int64_t m, int64_t n, const int
                 }
             }
         }
-#pragma unroll
-        for (int d = RI_GS / 2; d >= 1; d >>= 1) {
-            f += __shfl_xor(f, d, RI_GS);
-            fc += __shfl_xor(fc, d, RI_GS);
-            wlo = min(wlo, __shfl_xor(wlo, d, RI_GS));
-            whi = max(whi, __shfl_xor(whi, d, RI_GS));
-        }
+        // reductions over the 8-lane group: DPP quad permutes (lane ^ 1,
+        // lane ^ 2), then the half-row mirror (lane i <-> 7 - i) joins the two
+        // quads
+        f += ri_x<0xB1>(f);
+        fc += ri_x<0xB1>(fc);
+        wlo = min(wlo, ri_x32<0xB1>(wlo));
+        whi = max(whi, ri_x32<0xB1>(whi));
+        f += ri_x<0x4E>(f);
+        fc += ri_x<0x4E>(fc);
+        wlo = min(wlo, ri_x32<0x4E>(wlo));
+        whi = max(whi, ri_x32<0x4E>(whi));
+        f += ri_x<0x141>(f);
+        fc += ri_x<0x141>(fc);
+        wlo = min(wlo, ri_x32<0x141>(wlo));
+        whi = max(whi, ri_x32<0x141>(whi));
         if (q == 0) {
             rflops[i] = f;
             rflopsc[i] = fc;
