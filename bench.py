@@ -37,9 +37,9 @@ TRAFFIC = {
     "kernel": "k_num_pl",
     "sources": ["paper_1801_03065_amd/csrc/spg_plan.hip", "paper_1801_03065_amd/csrc/spg_internal.hpp",
                 "paper_1801_03065_amd/csrc/spg_accum.hpp"],
-    "sha256": "76910a30ac85721662532bad4c75baa08916bcc26938cd670ff9855e0fd7091b",
-    "read_bytes": 3.8291e9,
-    "write_bytes": 1.5082e9,
+    "sha256": "e4c7d8a9fa536cee5978f95ae6b8799d1edfc71639dec38e7473b8cdfb7ae40d",
+    "read_bytes": 3.9011e9,
+    "write_bytes": 1.5083e9,
 }
 
 
