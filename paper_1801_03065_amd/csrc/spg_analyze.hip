@@ -251,6 +251,39 @@ __global__ __launch_bounds__(BLK) void k_compress_sorted(int64_t n, const int64_
     }
 }
 
+// The same for B with short rows: one lane per row walks its columns and
+// writes each word run where it ends.
+__global__ __launch_bounds__(BLK) void k_compress_short(int64_t n, const int64_t *brp, const int32_t *bci,
+                                                         const uint8_t *unsorted, const int64_t *bcrp, int32_t *bcsi,
+                                                         uint32_t *bcs, const int *enable) {
+    if (enable && !*enable) return;
+    for (int64_t r = (int64_t)blockIdx.x * BLK + threadIdx.x; r < n; r += (int64_t)gridDim.x * BLK) {
+        if (unsorted[r]) continue;
+        const int64_t b = brp[r], e = brp[r + 1];
+        int64_t pos = bcrp[r];
+        int curw = INT_MIN;
+        uint32_t bits = 0;
+        for (int64_t k = b; k < e; ++k) {
+            const int col = bci[k];
+            const int w = col >> 5;
+            if (w != curw) {
+                if (curw != INT_MIN) {
+                    bcsi[pos] = curw;
+                    bcs[pos] = bits;
+                    ++pos;
+                }
+                curw = w;
+                bits = 0;
+            }
+            bits |= 1u << (col & 31);
+        }
+        if (curw != INT_MIN) {
+            bcsi[pos] = curw;
+            bcs[pos] = bits;
+        }
+    }
+}
+
 // ------------------------------------------------------------------ A rows
 // 16 lanes per row of A: f_m(i) = sum |B(j,:)|, the same over compressed B,
 // and the word window [min wmin, max wmax] of the B rows it reads.
@@ -829,12 +862,16 @@ hipError_t launch_compress_unsorted(const int32_t *list, const int *count, const
     return hipGetLastError();
 }
 
-hipError_t launch_compress_sorted_flags(int64_t n, const int64_t *brp, const int32_t *bci, const BRow *bi,
+hipError_t launch_compress_sorted_flags(int64_t n, int64_t nnz, const int64_t *brp, const int32_t *bci, const BRow *bi,
                                         const uint8_t *unsorted, const int64_t *bcrp, int32_t *bcsi,
                                         uint32_t *bcs, const int *enable, hipStream_t s) {
     if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_compress_sorted, dim3(grid_for(n * BR_GS, BLK, 8192)), dim3(BLK), 0, s, n, brp, bci, bi,
-                       unsorted, bcrp, bcsi, bcs, enable);
+    if (nnz <= BR_SHORT * n)
+        hipLaunchKernelGGL(k_compress_short, dim3(grid_for(n, BLK, 4096)), dim3(BLK), 0, s, n, brp, bci, unsorted,
+                           bcrp, bcsi, bcs, enable);
+    else
+        hipLaunchKernelGGL(k_compress_sorted, dim3(grid_for(n * BR_GS, BLK, 8192)), dim3(BLK), 0, s, n, brp, bci, bi,
+                           unsorted, bcrp, bcsi, bcs, enable);
     return hipGetLastError();
 }
 

@@ -354,7 +354,7 @@ static spg_status symbolic_core(spg_handle h, int64_t m, int64_t n, int64_t k, i
         HIPCHK(ensure(h->bcs, 4 * std::max<int64_t>(nnzb, 1)));
         static_assert(sizeof(BRow) == 4 * sizeof(int32_t), "BRow is four int32");
         HIPCHK(launch_scan_i32s(n, &bi->lenc, 4, h->bcrp.as<int64_t>(), h->tmp.as<int64_t>(), cflag, st));
-        HIPCHK(launch_compress_sorted_flags(n, brp, bci, bi, h->uflag.as<uint8_t>(), h->bcrp.as<int64_t>(),
+        HIPCHK(launch_compress_sorted_flags(n, nnzb, brp, bci, bi, h->uflag.as<uint8_t>(), h->bcrp.as<int64_t>(),
                                             h->bcsi.as<int32_t>(), h->bcs.as<uint32_t>(), cflag, st));
         HIPCHK(launch_compress_unsorted(h->ulist.as<int32_t>(), &dst->unsorted, brp, bci, bi,
                                         h->bcrp.as<int64_t>(), h->bcsi.as<int32_t>(), h->bcs.as<uint32_t>(), cflag,

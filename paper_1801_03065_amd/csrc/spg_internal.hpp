@@ -325,7 +325,7 @@ hipError_t launch_brow_unsorted(const int32_t *list, const int *count, const int
                                 BRow *out, DevStats *st, hipStream_t s);
 // The compression kernels and the scan take `enable` (device flag, nullable):
 // they do nothing when it reads 0.
-hipError_t launch_compress_sorted_flags(int64_t n, const int64_t *brp, const int32_t *bci, const BRow *bi,
+hipError_t launch_compress_sorted_flags(int64_t n, int64_t nnz, const int64_t *brp, const int32_t *bci, const BRow *bi,
                                         const uint8_t *unsorted, const int64_t *bcrp, int32_t *bcsi,
                                         uint32_t *bcs, const int *enable, hipStream_t s);
 hipError_t launch_compress_unsorted(const int32_t *list, const int *count, const int64_t *brp,

@@ -308,10 +308,12 @@ def test_malformed_input_rejected_then_handle_reusable(case):
     check_f64(ref, S, got)
 
 
+@pytest.mark.parametrize("comp", [-1, 1])
 @pytest.mark.parametrize("acc", [0, 1])
-def test_short_unsorted_b_rows(acc):
-    """B whose rows hold 0-6 entries (one lane per B row in the analysis) with
-    shuffled columns: sortedness found per row, heavy rows without segments."""
+def test_short_unsorted_b_rows(acc, comp):
+    """B whose rows hold 0-6 entries (one lane per B row in the analysis and
+    in the compression) with shuffled columns: sortedness found per row, heavy
+    rows without segments; compression by the rule and forced."""
     rng = np.random.default_rng(41)
     m, n, k = 2000, 3000, 5000
     B = synth.shuffle_columns(synth.random_csr(n, k, rng.integers(0, 7, n), 42), 43)
@@ -319,5 +321,7 @@ def test_short_unsorted_b_rows(acc):
     counts[[5, 900]] = [2500, 1800]  # rows with thousands of entries in C
     A = synth.random_csr(m, n, counts, 44)
     ref, S = oracle_ref(A, B)
-    got, h = run(A, B, accumulator=acc)
+    got, h = run(A, B, accumulator=acc, compression=comp)
     check_f64(ref, S, got)
+    if comp == 1:
+        assert h.stats()["compressed"] == 1
