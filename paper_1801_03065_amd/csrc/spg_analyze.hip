@@ -150,7 +150,7 @@ constexpr int UB_WORDS = 16384;
 
 __global__ __launch_bounds__(WAVE) void k_brow_unsorted(const int32_t *list, const int *count_p, const int64_t *brp,
                                                          const int32_t *bci, BRow *bi, const int64_t *bcrp,
-                                                         int32_t *bcsi, uint32_t *bcs, int mode, DevStats *st,
+                                                         uint2 *bcw, int mode, DevStats *st,
                                                          const int *enable) {
     __shared__ uint32_t bits[UB_WORDS];
     const int l = lane_id();
@@ -182,8 +182,7 @@ __global__ __launch_bounds__(WAVE) void k_brow_unsorted(const int32_t *list, con
             const unsigned long long bal = __ballot(m != 0u);
             if (mode && m) {
                 const int64_t pos = out0 + run + mbcnt(bal);
-                bcsi[pos] = br.wmin + w;
-                bcs[pos] = m;
+                bcw[pos] = make_uint2((uint32_t)(br.wmin + w), m);
             }
             if (w < nw) bits[w] = 0;
             run += __popcll(bal);
@@ -194,13 +193,12 @@ __global__ __launch_bounds__(WAVE) void k_brow_unsorted(const int32_t *list, con
 }
 
 // Compressed B for rows with sorted columns: a 16-lane group per row; the
-// first lane of each word run writes the word index and the last lane of the
-// run its bit set (plain stores).  A run that crosses into the next 16-column
-// chunk carries its partial bits there.
+// last lane of each word run writes its (word, bits) record with one 8-byte
+// store.  A run that crosses into the next 16-column chunk carries its partial
+// bits there.
 __global__ __launch_bounds__(BLK) void k_compress_sorted(int64_t n, const int64_t *brp, const int32_t *bci,
                                                           const BRow *bi, const uint8_t *unsorted,
-                                                          const int64_t *bcrp, int32_t *bcsi, uint32_t *bcs,
-                                                          const int *enable) {
+                                                          const int64_t *bcrp, uint2 *bcw, const int *enable) {
     if (enable && !*enable) return;
     const int q = threadIdx.x & (BR_GS - 1);
     const int64_t g0 = ((int64_t)blockIdx.x * BLK + threadIdx.x) / BR_GS;
@@ -241,8 +239,7 @@ __global__ __launch_bounds__(BLK) void k_compress_sorted(int64_t n, const int64_
             // the run ends here when the next column is in another word (or there is none)
             const bool tail = v && (idx + 1 >= e || (nextc >> 5) != (col >> 5));
             const int64_t pos = o0 + heads_before + seg - 1;
-            if (head) bcsi[pos] = col >> 5;
-            if (tail) bcs[pos] = acc;
+            if (tail) bcw[pos] = make_uint2((uint32_t)(col >> 5), acc);  // one record per word run
             const bool open = v && !tail && q == BR_GS - 1;  // run continues into the next chunk
             carry = (uint32_t)row_last(open ? (int)acc : 0);
             heads_before += row_last(seg);
@@ -254,8 +251,8 @@ __global__ __launch_bounds__(BLK) void k_compress_sorted(int64_t n, const int64_
 // The same for B with short rows: one lane per row walks its columns and
 // writes each word run where it ends.
 __global__ __launch_bounds__(BLK) void k_compress_short(int64_t n, const int64_t *brp, const int32_t *bci,
-                                                         const uint8_t *unsorted, const int64_t *bcrp, int32_t *bcsi,
-                                                         uint32_t *bcs, const int *enable) {
+                                                         const uint8_t *unsorted, const int64_t *bcrp, uint2 *bcw,
+                                                         const int *enable) {
     if (enable && !*enable) return;
     for (int64_t r = (int64_t)blockIdx.x * BLK + threadIdx.x; r < n; r += (int64_t)gridDim.x * BLK) {
         if (unsorted[r]) continue;
@@ -267,20 +264,13 @@ __global__ __launch_bounds__(BLK) void k_compress_short(int64_t n, const int64_t
             const int col = bci[k];
             const int w = col >> 5;
             if (w != curw) {
-                if (curw != INT_MIN) {
-                    bcsi[pos] = curw;
-                    bcs[pos] = bits;
-                    ++pos;
-                }
+                if (curw != INT_MIN) bcw[pos++] = make_uint2((uint32_t)curw, bits);
                 curw = w;
                 bits = 0;
             }
             bits |= 1u << (col & 31);
         }
-        if (curw != INT_MIN) {
-            bcsi[pos] = curw;
-            bcs[pos] = bits;
-        }
+        if (curw != INT_MIN) bcw[pos] = make_uint2((uint32_t)curw, bits);
     }
 }
 
@@ -850,28 +840,28 @@ constexpr int UB_GRID = 1024;
 hipError_t launch_brow_unsorted(const int32_t *list, const int *count, const int64_t *brp, const int32_t *bci,
                                 BRow *out, DevStats *st, hipStream_t s) {
     hipLaunchKernelGGL(k_brow_unsorted, dim3(UB_GRID), dim3(WAVE), 0, s, list, count, brp, bci, out,
-                       (const int64_t *)nullptr, (int32_t *)nullptr, (uint32_t *)nullptr, 0, st, (const int *)nullptr);
+                       (const int64_t *)nullptr, (uint2 *)nullptr, 0, st, (const int *)nullptr);
     return hipGetLastError();
 }
 
 hipError_t launch_compress_unsorted(const int32_t *list, const int *count, const int64_t *brp,
-                                    const int32_t *bci, const BRow *bi, const int64_t *bcrp, int32_t *bcsi,
-                                    uint32_t *bcs, const int *enable, hipStream_t s) {
+                                    const int32_t *bci, const BRow *bi, const int64_t *bcrp, uint2 *bcw,
+                                    const int *enable, hipStream_t s) {
     hipLaunchKernelGGL(k_brow_unsorted, dim3(UB_GRID), dim3(WAVE), 0, s, list, count, brp, bci, (BRow *)bi, bcrp,
-                       bcsi, bcs, 1, (DevStats *)nullptr, enable);
+                       bcw, 1, (DevStats *)nullptr, enable);
     return hipGetLastError();
 }
 
 hipError_t launch_compress_sorted_flags(int64_t n, int64_t nnz, const int64_t *brp, const int32_t *bci, const BRow *bi,
-                                        const uint8_t *unsorted, const int64_t *bcrp, int32_t *bcsi,
-                                        uint32_t *bcs, const int *enable, hipStream_t s) {
+                                        const uint8_t *unsorted, const int64_t *bcrp, uint2 *bcw,
+                                        const int *enable, hipStream_t s) {
     if (n == 0) return hipSuccess;
     if (nnz <= BR_SHORT * n)
         hipLaunchKernelGGL(k_compress_short, dim3(grid_for(n, BLK, 4096)), dim3(BLK), 0, s, n, brp, bci, unsorted,
-                           bcrp, bcsi, bcs, enable);
+                           bcrp, bcw, enable);
     else
         hipLaunchKernelGGL(k_compress_sorted, dim3(grid_for(n * BR_GS, BLK, 8192)), dim3(BLK), 0, s, n, brp, bci, bi,
-                           unsorted, bcrp, bcsi, bcs, enable);
+                           unsorted, bcrp, bcw, enable);
     return hipGetLastError();
 }
 

@@ -57,7 +57,7 @@ struct spg_handle_s {
     bool segmented = false;             // the symbolic phase wrote segment lists into plan
     spg_stats stats{};
 
-    DevBuf arp64, brp64, binfo, ulist, uflag, bcrp, bcsi, bcs, rflops, rflopsc, rwin, row_nnz, coff, kind_sym,
+    DevBuf arp64, brp64, binfo, ulist, uflag, bcrp, bcw, rflops, rflopsc, rwin, row_nnz, coff, kind_sym,
         kind_num, perm_sym, perm_num, koff_sym, koff_num, tmp, dstats, red, queue, plan_len, plan_off, plan, arena, l2k, l2v, blens, row_words;
     size_t arena_bytes_zeroed = 0;
     const int32_t *aci_used = nullptr, *bci_used = nullptr;  // column arrays the kernels read
@@ -254,7 +254,7 @@ spg_status spg_create(spg_handle *out, void *stream, const spg_options *opt) {
 spg_status spg_destroy(spg_handle h) {
     if (!h) return SPG_ERR_INVALID_ARG;
     (void)hipStreamSynchronize(h->stream);
-    DevBuf *bufs[] = {&h->arp64, &h->brp64, &h->binfo, &h->ulist, &h->uflag, &h->bcrp, &h->bcsi, &h->bcs,
+    DevBuf *bufs[] = {&h->arp64, &h->brp64, &h->binfo, &h->ulist, &h->uflag, &h->bcrp, &h->bcw,
                       &h->rflops, &h->rflopsc, &h->rwin, &h->row_nnz, &h->coff, &h->kind_sym, &h->kind_num,
                       &h->perm_sym, &h->perm_num, &h->koff_sym, &h->koff_num, &h->tmp, &h->dstats, &h->red, &h->queue, &h->plan_len, &h->plan_off, &h->plan,
                       &h->arena, &h->l2k, &h->l2v, &h->blens, &h->row_words, &h->kind_tmp, &h->perm_tmp, &h->koff_tmp, &h->krange, &h->kind_heavy, &h->perm_heavy, &h->koff_heavy, &h->krange_heavy, &h->sgcur};
@@ -350,14 +350,13 @@ static spg_status symbolic_core(spg_handle h, int64_t m, int64_t n, int64_t k, i
     // pairs, built when the analysis decided so (dst->comp, on the device)
     const int *cflag = &dst->comp;
     if (h->opt.compression != 0) {
-        HIPCHK(ensure(h->bcsi, 4 * std::max<int64_t>(nnzb, 1)));
-        HIPCHK(ensure(h->bcs, 4 * std::max<int64_t>(nnzb, 1)));
+        HIPCHK(ensure(h->bcw, 8 * std::max<int64_t>(nnzb, 1)));
         static_assert(sizeof(BRow) == 4 * sizeof(int32_t), "BRow is four int32");
         HIPCHK(launch_scan_i32s(n, &bi->lenc, 4, h->bcrp.as<int64_t>(), h->tmp.as<int64_t>(), cflag, st));
         HIPCHK(launch_compress_sorted_flags(n, nnzb, brp, bci, bi, h->uflag.as<uint8_t>(), h->bcrp.as<int64_t>(),
-                                            h->bcsi.as<int32_t>(), h->bcs.as<uint32_t>(), cflag, st));
+                                            h->bcw.as<uint2>(), cflag, st));
         HIPCHK(launch_compress_unsorted(h->ulist.as<int32_t>(), &dst->unsorted, brp, bci, bi,
-                                        h->bcrp.as<int64_t>(), h->bcsi.as<int32_t>(), h->bcs.as<uint32_t>(), cflag,
+                                        h->bcrp.as<int64_t>(), h->bcw.as<uint2>(), cflag,
                                         st));
     }
 
@@ -439,8 +438,7 @@ static spg_status symbolic_core(spg_handle h, int64_t m, int64_t n, int64_t k, i
     sa.bci = bci;
     if (comp) {
         sa.bcrp = h->bcrp.as<int64_t>();
-        sa.bcsi = h->bcsi.as<int32_t>();
-        sa.bcs = h->bcs.as<uint32_t>();
+        sa.bcw = h->bcw.as<uint2>();
     }
     sa.rwin = h->rwin.as<int2>();
     sa.row_nnz = h->row_nnz.as<int32_t>();
@@ -449,7 +447,7 @@ static spg_status symbolic_core(spg_handle h, int64_t m, int64_t n, int64_t k, i
     sa.rs.koff = h->koff_sym.as<int64_t>();
     sa.st = dst;
     sa.lg_gs = lg_group(h->avg_len_c);
-    sa.b32 = nnzb < (int64_t(1) << 30);
+    sa.b32 = nnzb < (int64_t(1) << 29);  // 8-byte compressed records: 32-bit byte offsets
     if (h->planned || h->segmented) {
         sa.plan_off = h->plan_off.as<int64_t>();
         sa.plan_len = h->plan_len.as<int32_t>();
@@ -798,8 +796,7 @@ static spg_status numeric_impl(spg_handle h, const VT *aval, const VT *bval, int
     na.bval = bval;
     if (h->compressed) {
         na.bcrp = h->bcrp.as<int64_t>();
-        na.bcsi = h->bcsi.as<int32_t>();
-        na.bcs = h->bcs.as<uint32_t>();
+        na.bcw = h->bcw.as<uint2>();
     }
     na.rwin = h->rwin.as<int2>();
     na.coff = h->coff.as<int64_t>();

@@ -98,11 +98,12 @@ __device__ __forceinline__ int dw_stage(int64_t cb, int64_t ae, const int32_t *a
 // and its bits.  COMP is a template parameter so that the batched loads of
 // dw_or_staged stay branch-free and all issue before the first use.
 template <bool COMP>
-__device__ __forceinline__ void dw_word(int64_t e, int wlo, const int32_t *bci, const int32_t *bcsi,
-                                        const uint32_t *bcs, uint32_t &d, uint32_t &cs) {
+__device__ __forceinline__ void dw_word(int64_t e, int wlo, const int32_t *bci, const uint2 *bcw, uint32_t &d,
+                                        uint32_t &cs) {
     if constexpr (COMP) {
-        d = (uint32_t)(bcsi[e] - wlo);
-        cs = bcs[e];
+        const uint2 v = bcw[e];
+        d = v.x - (uint32_t)wlo;
+        cs = v.y;
     } else {
         const int c = bci[e];
         d = (uint32_t)((c >> 5) - wlo);
@@ -119,8 +120,8 @@ __device__ __forceinline__ void dw_or(uint32_t *bits, uint32_t *summ, uint32_t d
 // (2^lg_gs lanes) takes entries g, g+ng, ...; DW_U entries per group are
 // loaded before any is used, so each lane keeps DW_U loads in flight.
 template <bool COMP>
-__device__ __forceinline__ void dw_or_batched(int cn, int wlo, const int32_t *bci, const int32_t *bcsi,
-                                              const uint32_t *bcs, int lg_gs, const int64_t *st_cbs,
+__device__ __forceinline__ void dw_or_batched(int cn, int wlo, const int32_t *bci, const uint2 *bcw,
+                                              int lg_gs, const int64_t *st_cbs,
                                               const int32_t *st_clen, uint32_t *bits, uint32_t *summ) {
     const int l = lane_id();
     const int gs = 1 << lg_gs, g = l >> lg_gs, q = l & (gs - 1), ng = WAVE >> lg_gs;
@@ -139,7 +140,7 @@ __device__ __forceinline__ void dw_or_batched(int cn, int wlo, const int32_t *bc
         for (int u = 0; u < DW_U; ++u) {  // then every global load of the batch
             const bool ok = t0 + u * ng < cn && q < len[u];
             okm |= (unsigned)ok << u;
-            dw_word<COMP>(ok ? bs[u] + q : 0, wlo, bci, bcsi, bcs, d[u], cs[u]);
+            dw_word<COMP>(ok ? bs[u] + q : 0, wlo, bci, bcw, d[u], cs[u]);
         }
 #pragma unroll
         for (int u = 0; u < DW_U; ++u)
@@ -150,20 +151,20 @@ __device__ __forceinline__ void dw_or_batched(int cn, int wlo, const int32_t *bc
             const int tl = st_clen[t];
             for (int p = q + gs; p < tl; p += gs) {
                 uint32_t dd, cc;
-                dw_word<COMP>(st_cbs[t] + p, wlo, bci, bcsi, bcs, dd, cc);
+                dw_word<COMP>(st_cbs[t] + p, wlo, bci, bcw, dd, cc);
                 dw_or(bits, summ, dd, cc);
             }
         }
     }
 }
 
-__device__ __forceinline__ void dw_or_staged(int cn, int wlo, bool comp, const int32_t *bci, const int32_t *bcsi,
-                                             const uint32_t *bcs, int lg_gs, const int64_t *st_cbs,
+__device__ __forceinline__ void dw_or_staged(int cn, int wlo, bool comp, const int32_t *bci, const uint2 *bcw,
+                                             int lg_gs, const int64_t *st_cbs,
                                              const int32_t *st_clen, uint32_t *bits, uint32_t *summ) {
     if (comp)
-        dw_or_batched<true>(cn, wlo, bci, bcsi, bcs, lg_gs, st_cbs, st_clen, bits, summ);
+        dw_or_batched<true>(cn, wlo, bci, bcw, lg_gs, st_cbs, st_clen, bits, summ);
     else
-        dw_or_batched<false>(cn, wlo, bci, bcsi, bcs, lg_gs, st_cbs, st_clen, bits, summ);
+        dw_or_batched<false>(cn, wlo, bci, bcw, lg_gs, st_cbs, st_clen, bits, summ);
 }
 
 struct RowDesc {
@@ -371,8 +372,9 @@ __global__ __launch_bounds__(WAVE) void k_sym_dw(SymArgs a) {
                 okm |= (unsigned)ok << s2;
                 const uint32_t e = ok ? cb + (uint32_t)q : 0u;
                 if constexpr (COMP) {
-                    wd[s2] = (uint32_t)ld32(a.bcsi, e);
-                    wc[s2] = ld32(a.bcs, e);
+                    const uint2 v = ld32(a.bcw, e);  // (word, bits): one 8-byte load
+                    wd[s2] = v.x;
+                    wc[s2] = v.y;
                 } else {
                     const int c = ld32(a.bci, e);
                     wd[s2] = (uint32_t)(c >> 5);
@@ -400,7 +402,7 @@ __global__ __launch_bounds__(WAVE) void k_sym_dw(SymArgs a) {
                     const int len = st_clen[t];
                     for (int w = q + gs; w < len; w += gs) {
                         uint32_t dd, cc;
-                        dw_word<COMP>(cb + w, wlo, a.bci, a.bcsi, a.bcs, dd, cc);
+                        dw_word<COMP>(cb + w, wlo, a.bci, a.bcw, dd, cc);
                         dw_or(bits, summ, dd, cc);
                     }
                 }
@@ -426,7 +428,7 @@ __global__ __launch_bounds__(WAVE) void k_sym_dw(SymArgs a) {
                     const int len = sclen[t];
                     for (int w = q; w < len; w += gs) {
                         uint32_t dd, cc;
-                        dw_word<COMP>(cb + w, wlo, a.bci, a.bcsi, a.bcs, dd, cc);
+                        dw_word<COMP>(cb + w, wlo, a.bci, a.bcw, dd, cc);
                         dw_or(bits, summ, dd, cc);
                     }
                 }
@@ -630,7 +632,7 @@ __global__ __launch_bounds__(WAVE) void k_num_dw(NumArgs<VT> a) {
                 cn = dw_stage<VT>(c0, d.ae, a.aci, a.aval, srp, a.brp, st_cbs, st_clen, st_bs, st_len, st_a);
                 wave_lds_sync();
             }
-            dw_or_staged(cn, wlo, comp, a.bci, a.bcsi, a.bcs, a.lg_gs_or, st_cbs, st_clen, bits, summ);
+            dw_or_staged(cn, wlo, comp, a.bci, a.bcw, a.lg_gs_or, st_cbs, st_clen, bits, summ);
             wave_lds_sync();
         }
         // the next row's B extents (second step; its A entries have landed)
@@ -852,8 +854,8 @@ constexpr int DG_U = 8;
 
 template <bool COMP>
 __device__ __forceinline__ void dg_or_batched(int64_t ab, int64_t ae, int wlo, const int32_t *aci,
-                                              const int64_t *srp, const int32_t *bci, const int32_t *bcsi,
-                                              const uint32_t *bcs, uint32_t *bits, uint32_t *summ,
+                                              const int64_t *srp, const int32_t *bci, const uint2 *bcw,
+                                              uint32_t *bits, uint32_t *summ,
                                               int64_t *st_off, int64_t *st_bs, long long *red) {
     const int t = threadIdx.x;
     for (int64_t cb = ab; cb < ae; cb += DG_WG) {
@@ -892,8 +894,9 @@ __device__ __forceinline__ void dg_or_batched(int64_t ab, int64_t ae, int wlo, c
 #pragma unroll
             for (int u = 0; u < DG_U; ++u) {
                 if constexpr (COMP) {
-                    d[u] = (uint32_t)(bcsi[e[u]] - wlo);
-                    cs[u] = bcs[e[u]];
+                    const uint2 v = bcw[e[u]];
+                    d[u] = v.x - (uint32_t)wlo;
+                    cs[u] = v.y;
                 } else {
                     const int c = bci[e[u]];
                     d[u] = (uint32_t)((c >> 5) - wlo);
@@ -914,12 +917,12 @@ __device__ __forceinline__ void dg_or_batched(int64_t ab, int64_t ae, int wlo, c
 
 __device__ __forceinline__ void dg_or_pass(int i, int wlo, const int64_t *arp, const int32_t *aci,
                                            const int64_t *brp, const int32_t *bci, const int64_t *bcrp,
-                                           const int32_t *bcsi, const uint32_t *bcs, uint32_t *bits,
+                                           const uint2 *bcw, uint32_t *bits,
                                            uint32_t *summ, int64_t *st_off, int64_t *st_bs, long long *red) {
     if (bcrp)
-        dg_or_batched<true>(arp[i], arp[i + 1], wlo, aci, bcrp, bci, bcsi, bcs, bits, summ, st_off, st_bs, red);
+        dg_or_batched<true>(arp[i], arp[i + 1], wlo, aci, bcrp, bci, bcw, bits, summ, st_off, st_bs, red);
     else
-        dg_or_batched<false>(arp[i], arp[i + 1], wlo, aci, brp, bci, bcsi, bcs, bits, summ, st_off, st_bs, red);
+        dg_or_batched<false>(arp[i], arp[i + 1], wlo, aci, brp, bci, bcw, bits, summ, st_off, st_bs, red);
 }
 
 // Segment list of a heavy row (the row's bit window is complete in bits /
@@ -1008,7 +1011,7 @@ __global__ __launch_bounds__(DG_WG) void k_sym_dg(SymArgs a) {
         if (i < 0) break;
         const int2 win = a.rwin[i];
         const int ns = (win.y - win.x + 1 + 31) >> 5;
-        dg_or_pass(i, win.x, a.arp, a.aci, a.brp, a.bci, a.bcrp, a.bcsi, a.bcs, bits, summ, st_off, st_bs, red);
+        dg_or_pass(i, win.x, a.arp, a.aci, a.brp, a.bci, a.bcrp, a.bcw, bits, summ, st_off, st_bs, red);
         const int cap = a.plan ? a.plan_len[i] : 0;
         if (cap > 0) {
             const long long r = dg_segments(win.y - win.x + 1, ns, bits, summ, gfirst, red, a.plan + a.plan_off[i],
@@ -1067,7 +1070,7 @@ __global__ __launch_bounds__(DG_WG) void k_num_dg(NumArgs<VT> a) {
         const int wlo = win.x;
         const int ns = (win.y - win.x + 1 + 31) >> 5;
         const int64_t colbase = (int64_t)wlo << 5;  // first column of the row's window
-        dg_or_pass(i, wlo, a.arp, a.aci, a.brp, a.bci, a.bcrp, a.bcsi, a.bcs, bits, summ, st_off, st_bs, red);
+        dg_or_pass(i, wlo, a.arp, a.aci, a.brp, a.bci, a.bcrp, a.bcw, bits, summ, st_off, st_bs, red);
         const int64_t ab = a.arp[i], ae = a.arp[i + 1];
         dg_flat(ab, ae, a.aci, a.brp, st_off, st_bs, red, [&](int k, int64_t e, int64_t cb) {
             const VT av = a.aval[cb + k];

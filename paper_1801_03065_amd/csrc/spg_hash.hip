@@ -141,8 +141,9 @@ __global__ __launch_bounds__(WAVE) void k_sym_hw(SymArgs a) {
                     int32_t key;
                     uint32_t cs;
                     if (comp) {
-                        key = a.bcsi[bs + p];
-                        cs = a.bcs[bs + p];
+                        const uint2 v = a.bcw[bs + p];
+                        key = (int)v.x;
+                        cs = v.y;
                     } else {
                         key = a.bci[bs + p];
                         cs = 1u;
@@ -434,8 +435,9 @@ __global__ __launch_bounds__(WG_BIG) void k_sym_hl(SymArgs a) {
             int32_t key;
             uint32_t cs;
             if (comp) {
-                key = a.bcsi[e];
-                cs = a.bcs[e];
+                const uint2 v = a.bcw[e];
+                key = (int)v.x;
+                cs = v.y;
             } else {
                 key = a.bci[e];
                 cs = 1u;

@@ -97,8 +97,7 @@ struct SymArgs {
     const int64_t *brp;    // raw B structure
     const int32_t *bci;
     const int64_t *bcrp;   // compressed B (nullptr when not compressed)
-    const int32_t *bcsi;
-    const uint32_t *bcs;
+    const uint2 *bcw;      // compressed B: (column-set word, bits) per entry
     const int2 *rwin;      // per row: lowest / highest column-set word
     int32_t *row_nnz;
     int32_t *row_words;    // touched column-set words per row (exact, or a bound)
@@ -126,8 +125,7 @@ struct NumArgs {
     const int32_t *bci;
     const VT *bval;
     const int64_t *bcrp;
-    const int32_t *bcsi;
-    const uint32_t *bcs;
+    const uint2 *bcw;      // compressed B: (column-set word, bits) per entry
     const int2 *rwin;
     const int64_t *coff;   // C row offsets (plan copy, int64)
     int32_t *cci;          // written at coff[i] - coff[cbase_row] (0 when cbase_row < 0)
@@ -326,11 +324,11 @@ hipError_t launch_brow_unsorted(const int32_t *list, const int *count, const int
 // The compression kernels and the scan take `enable` (device flag, nullable):
 // they do nothing when it reads 0.
 hipError_t launch_compress_sorted_flags(int64_t n, int64_t nnz, const int64_t *brp, const int32_t *bci, const BRow *bi,
-                                        const uint8_t *unsorted, const int64_t *bcrp, int32_t *bcsi,
-                                        uint32_t *bcs, const int *enable, hipStream_t s);
+                                        const uint8_t *unsorted, const int64_t *bcrp, uint2 *bcw,
+                                        const int *enable, hipStream_t s);
 hipError_t launch_compress_unsorted(const int32_t *list, const int *count, const int64_t *brp,
-                                    const int32_t *bci, const BRow *bi, const int64_t *bcrp, int32_t *bcsi,
-                                    uint32_t *bcs, const int *enable, hipStream_t s);
+                                    const int32_t *bci, const BRow *bi, const int64_t *bcrp, uint2 *bcw,
+                                    const int *enable, hipStream_t s);
 // Per-block partials of the rowinfo reduction (folded by a one-workgroup
 // kernel): RED_ELEMS int64 of device scratch.
 constexpr int RED_ELEMS = 16384;
