@@ -255,6 +255,8 @@ __global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(4, 8))) vo
             bp[l] = (unsigned long long)mypw.y | ((unsigned long long)(uint32_t)pre << 32);
         }
         const bool ok = (d.ce - d.cb == rnnz) && rnnz <= a.r_max && d.nw <= PL_CAP;
+        const int rlast = rnnz > 0 ? rnnz - 1 : 0;  // ranks past the row (bad input) stay inside it
+        const uint8_t *mapw = map - wlo;              // indexed by absolute word (32-bit LDS addresses)
         if (l == 0 && !ok) atomicAdd(&a.st->mismatch, 1);
         wave_lds_sync();
 
@@ -265,10 +267,11 @@ __global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(4, 8))) vo
                 for (int u = 0; u < PL_U; ++u) {
                     if (okm & (1u << u)) {
                         const int c = col[u];
-                        const int s = map[(c >> 5) - wlo];
+                        const VT av = (VT)st_a[g + u * ng];  // issued with the word-map read
+                        const int s = mapw[c >> 5];
                         const unsigned long long e = bp[s];
                         const int rk = (int)(uint32_t)(e >> 32) + bits_below((uint32_t)e, c & 31);
-                        A::add(&vals[rk < rnnz ? rk : 0], (VT)st_a[g + u * ng], pv[u]);
+                        A::add(&vals[min(rk, rlast)], av, pv[u]);
                     }
                 }
             } else {
@@ -295,7 +298,7 @@ __global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(4, 8))) vo
                             const unsigned long long e = bp[s];
                             const int rk =
                                 (int)(uint32_t)(e >> 32) + bits_below((uint32_t)e, c & 31);
-                            A::add(&vals[rk < rnnz ? rk : 0], av, a.bval[bs + p]);
+                            A::add(&vals[min(rk, rlast)], av, a.bval[bs + p]);
                         }
                     }
                 }
