@@ -198,22 +198,31 @@ __global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(8, 8))) vo
                     len = (int)(a.brp[j + 1] - b0);
                 }
             }
-            const int inc = team_scan<LG>(len, q);
-            const int F = __shfl(inc, T - 1, T);  // products of this chunk (<= T for a short row)
-            const int off = inc - len;
-            own[q] = -1;
-            wave_lds_sync();
-            if (len > 0 && off < T) own[off] = q;
-            wave_lds_sync();
-            // owner of product q: the last A entry starting at or before q
-            const int k = max(team_maxscan<LG>(own[q], q), 0);
-            const int offk = __shfl(off, k, T);
-            const int64_t b0k = __shfl(b0, k, T);
-            VT avk = VT(0);
-            if (NUM) avk = __shfl(av, k, T);
-            if (q == 0 && F > T) atomicAdd(&a.st->mismatch, 1);  // not a short row: plan inconsistent
-            if (q < F) {
-                const int64_t e = b0k + (q - offk);
+            // B rows of at most one entry (every A entry makes at most one
+            // product, e.g. aggregation or injection operators): each lane
+            // forms its own product, no expansion
+            const bool unit = __ballot(len > 1) == 0;
+            int64_t e = b0;
+            VT avk = av;
+            bool mine = len > 0;
+            if (!unit) {
+                const int inc = team_scan<LG>(len, q);
+                const int F = __shfl(inc, T - 1, T);  // products of this chunk (<= T for a short row)
+                const int off = inc - len;
+                own[q] = -1;
+                wave_lds_sync();
+                if (len > 0 && off < T) own[off] = q;
+                wave_lds_sync();
+                // owner of product q: the last A entry starting at or before q
+                const int k = max(team_maxscan<LG>(own[q], q), 0);
+                const int offk = __shfl(off, k, T);
+                const int64_t b0k = __shfl(b0, k, T);
+                if (NUM) avk = __shfl(av, k, T);
+                if (q == 0 && F > T) atomicAdd(&a.st->mismatch, 1);  // not a short row: plan inconsistent
+                e = b0k + (q - offk);
+                mine = q < F;
+            }
+            if (mine) {
                 const int col = a.bci[e];
                 VT bv = VT(0);
                 if (NUM) bv = a.bval[e];
