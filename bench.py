@@ -37,9 +37,9 @@ TRAFFIC = {
     "kernel": "k_num_pl",
     "sources": ["paper_1801_03065_amd/csrc/spg_plan.hip", "paper_1801_03065_amd/csrc/spg_internal.hpp",
                 "paper_1801_03065_amd/csrc/spg_accum.hpp"],
-    "sha256": "e4c7d8a9fa536cee5978f95ae6b8799d1edfc71639dec38e7473b8cdfb7ae40d",
-    "read_bytes": 3.9011e9,
-    "write_bytes": 1.5083e9,
+    "sha256": "c77794301356c0df9c7aa3ece6fa2ff95d0ad4f2441520d76481aa2e242d40bf",
+    "read_bytes": 4.0865e9,
+    "write_bytes": 1.5078e9,
 }
 
 

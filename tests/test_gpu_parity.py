@@ -233,6 +233,26 @@ def test_short_rows_many_empty_b_rows():
     assert h.stats()["rows_numeric"]["short_rows"] == int(np.count_nonzero((fl > 0) & (fl <= 64)))
 
 
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_short_rows_unit_b_rows(dtype):
+    """B rows of zero or one entry (an injection with many repeated
+    columns): every A entry makes at most one product, and the teams form
+    them without the expansion; A rows of 1-150 entries (several chunks per
+    team), one B row of two entries in a few of them."""
+    rng = np.random.default_rng(71)
+    n, k = 3000, 40
+    nb = (rng.random(n) < 0.8).astype(np.int64)
+    nb[rng.integers(0, n, 3)] = 2
+    B = synth.random_csr(n, k, nb, 72)
+    A = synth.random_csr(2500, n, rng.integers(0, 150, 2500), 73)
+    if dtype == "f32":
+        A, B = f32_inputs(A), f32_inputs(B)
+    ref, S = oracle_ref(A, B)
+    got, h = run(A, B, dtype=dtype)
+    (check_f64 if dtype == "f64" else check_f32)(ref, S, got)
+    assert h.stats()["rows_numeric"]["short_rows"] > 0
+
+
 @pytest.mark.parametrize("mode", [0, 1, 2])
 def test_short_rows_fp32(mode):
     A = synth.stencil27(6)
