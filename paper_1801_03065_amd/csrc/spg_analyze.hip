@@ -16,16 +16,31 @@ constexpr int CL_GRID = 512;  // classify workgroups (rows per lane grow beyond)
 __device__ __forceinline__ unsigned long long ull(long long v) { return (unsigned long long)v; }
 
 // ------------------------------------------------------------------ row ptrs
-template <typename T>
-__global__ __launch_bounds__(BLK) void k_copy_rp(int64_t n1, const T *src, int64_t nnz, int64_t *dst, int *bad) {
-    for (int64_t i = (int64_t)blockIdx.x * BLK + threadIdx.x; i < n1; i += (int64_t)gridDim.x * BLK) {
-        int64_t v = (int64_t)src[i];
-        if ((i == 0 && v != 0) || (i > 0 && v < (int64_t)src[i - 1]) || (i == n1 - 1 && v != nnz))
+// One row-pointer array (int32 or int64) of n1 entries.
+struct RpCopy {
+    const void *src;
+    int is64;
+    int64_t n1, nnz;
+    int64_t *dst;
+};
+__device__ __forceinline__ int64_t rp_at(const RpCopy &c, int64_t i) {
+    return c.is64 ? ((const int64_t *)c.src)[i] : (int64_t)((const int32_t *)c.src)[i];
+}
+// Both operands' row pointers in one launch: entries [0, a.n1) are A's, the
+// rest B's.
+__global__ __launch_bounds__(BLK) void k_copy_rp(RpCopy a, RpCopy b, int *bad) {
+    const int64_t tot = a.n1 + b.n1;
+    for (int64_t t = (int64_t)blockIdx.x * BLK + threadIdx.x; t < tot; t += (int64_t)gridDim.x * BLK) {
+        const bool isa = t < a.n1;
+        const RpCopy &c = isa ? a : b;
+        const int64_t i = isa ? t : t - a.n1;
+        const int64_t v = rp_at(c, i);
+        if ((i == 0 && v != 0) || (i > 0 && v < rp_at(c, i - 1)) || (i == c.n1 - 1 && v != c.nnz))
             atomicOr(bad, 1);
         // the copy is clamped to [0, nnz]: every row range read through it is
         // empty or inside the arrays, so the analysis kernels that run before
         // the host sees the flag cannot read out of bounds
-        dst[i] = min(max(v, (int64_t)0), nnz);
+        c.dst[i] = min(max(v, (int64_t)0), c.nnz);
     }
 }
 
@@ -735,38 +750,28 @@ __global__ __launch_bounds__(SC_T) void k_scan_local(int64_t n, const T *in, int
     if (t == SC_T - 1) bsum[blockIdx.x] = off + inc;
 }
 
-__global__ __launch_bounds__(SC_T) void k_scan_top(int64_t nb, int64_t *bsum, int64_t *total_out, const int *enable) {
+// Each block adds the totals of all earlier blocks to its local scan: the
+// block totals are few (one per 2048 elements), so every block reduces its
+// own prefix of them instead of a separate one-block scan launch.  The last
+// block stores the grand total at out[n].
+__global__ __launch_bounds__(SC_T) void k_scan_add(int64_t n, int64_t nb, int64_t *out, const int64_t *bsum,
+                                                    const int *enable) {
     if (enable && !*enable) return;
     __shared__ long long wsum[SC_T / WAVE];
-    __shared__ long long carry;
     const int t = threadIdx.x, l = lane_id(), wv = t / WAVE;
-    if (t == 0) carry = 0;
+    const int64_t b = blockIdx.x;
+    long long part = 0;
+    for (int64_t u = t; u < b; u += SC_T) part += bsum[u];
+    part = wave_sum64(part);
+    if (l == 0) wsum[wv] = part;
     __syncthreads();
-    for (int64_t c0 = 0; c0 < nb; c0 += SC_T) {
-        const int64_t b = c0 + t;
-        const long long v = b < nb ? bsum[b] : 0;
-        const long long inc = wave_incl_scan64(v);
-        if (l == WAVE - 1) wsum[wv] = inc;
-        __syncthreads();
-        long long off = 0, tot = 0;
-        for (int u = 0; u < SC_T / WAVE; ++u) {
-            if (u < wv) off += wsum[u];
-            tot += wsum[u];
-        }
-        if (b < nb) bsum[b] = carry + off + inc - v;
-        __syncthreads();
-        if (t == 0) carry += tot;
-        __syncthreads();
-    }
-    if (t == 0) *total_out = carry;
-}
-
-__global__ __launch_bounds__(SC_T) void k_scan_add(int64_t n, int64_t *out, const int64_t *bsum, const int *enable) {
-    if (enable && !*enable) return;
-    const int64_t base = (int64_t)blockIdx.x * SC_B;
-    const long long add = bsum[blockIdx.x];
-    for (int e = threadIdx.x; e < SC_B; e += SC_T)
+    long long add = 0;
+#pragma unroll
+    for (int u = 0; u < SC_T / WAVE; ++u) add += wsum[u];
+    const int64_t base = b * SC_B;
+    for (int e = t; e < SC_B; e += SC_T)
         if (base + e < n) out[base + e] += add;
+    if (b == nb - 1 && t == 0) out[n] = add + bsum[b];
 }
 
 __global__ __launch_bounds__(BLK) void k_store_rp32(int64_t n1, const int64_t *src, int32_t *dst) {
@@ -811,13 +816,10 @@ inline int grid_for(int64_t work, int per_block, int cap = 65536) {
 
 }  // namespace
 
-hipError_t launch_copy_rp(int64_t n1, const void *src, int is64, int64_t nnz, int64_t *dst, int *bad,
-                          hipStream_t s) {
-    const int g = grid_for(n1, BLK);
-    if (is64)
-        hipLaunchKernelGGL(k_copy_rp<int64_t>, dim3(g), dim3(BLK), 0, s, n1, (const int64_t *)src, nnz, dst, bad);
-    else
-        hipLaunchKernelGGL(k_copy_rp<int32_t>, dim3(g), dim3(BLK), 0, s, n1, (const int32_t *)src, nnz, dst, bad);
+hipError_t launch_copy_rp(int64_t n1a, const void *srca, int is64a, int64_t nnza, int64_t *dsta, int64_t n1b,
+                          const void *srcb, int is64b, int64_t nnzb, int64_t *dstb, int *bad, hipStream_t s) {
+    const RpCopy a{srca, is64a, n1a, nnza, dsta}, b{srcb, is64b, n1b, nnzb, dstb};
+    hipLaunchKernelGGL(k_copy_rp, dim3(grid_for(n1a + n1b, BLK)), dim3(BLK), 0, s, a, b, bad);
     return hipGetLastError();
 }
 
@@ -884,8 +886,7 @@ static hipError_t scan_impl(int64_t n, const T *in, int stride, int64_t *out, in
     const int64_t nb = (n + SC_B - 1) / SC_B;
     if (nb > 0) {
         hipLaunchKernelGGL(k_scan_local<T>, dim3((unsigned)nb), dim3(SC_T), 0, s, n, in, stride, out, tmp, enable);
-        hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(SC_T), 0, s, nb, tmp, out + n, enable);
-        hipLaunchKernelGGL(k_scan_add, dim3((unsigned)nb), dim3(SC_T), 0, s, n, out, tmp, enable);
+        hipLaunchKernelGGL(k_scan_add, dim3((unsigned)nb), dim3(SC_T), 0, s, n, nb, out, tmp, enable);
     } else {
         hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(BLK), 0, s, (int32_t *)out, (int64_t)2, 0);
     }

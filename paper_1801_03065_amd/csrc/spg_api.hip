@@ -584,8 +584,8 @@ spg_status spgemm_symbolic(spg_handle h, const spg_csr *A, const spg_csr *B, voi
     // are skipped by the analysis, so the kernels that run before the first
     // host sync stay in bounds on malformed input; that sync rejects it before
     // any structure kernel indexes B by A's columns.
-    HIPCHK(launch_copy_rp(m + 1, A->row_ptr, A->rp_type == SPG_I64, A->nnz, h->arp64.as<int64_t>(), bad, st));
-    HIPCHK(launch_copy_rp(n + 1, B->row_ptr, B->rp_type == SPG_I64, B->nnz, h->brp64.as<int64_t>(), bad, st));
+    HIPCHK(launch_copy_rp(m + 1, A->row_ptr, A->rp_type == SPG_I64, A->nnz, h->arp64.as<int64_t>(), n + 1,
+                          B->row_ptr, B->rp_type == SPG_I64, B->nnz, h->brp64.as<int64_t>(), bad, st));
     int64_t nnzc = 0;
     if ((s = symbolic_core(h, m, n, k, A->nnz, B->nnz, A->col_idx, B->col_idx, &nnzc)) != SPG_OK) return s;
     if (c_rpt == SPG_I32 && nnzc > INT32_MAX)
@@ -747,12 +747,20 @@ static spg_status autotune(spg_handle h, NumArgs<VT> na, int acc) {
         na.rs.koff = h->koff_tmp.as<int64_t>();
         for (int lg = std::max(2, base - 1); lg <= std::min(6, base + 1); ++lg) {
             na.lg_gs = lg;
+            float ms = 0;
+            HIPCHK(hipEventRecord(e0, st));
             if ((s = launch_kinds<VT>(h, na, hs.kcount_num, hs.kmax_num, acc)) != SPG_OK) break;  // warm-up
+            HIPCHK(hipEventRecord(e1, st));
+            HIPCHK(hipEventSynchronize(e1));
+            HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+            // a policy whose warm-up run is far behind the best so far is not
+            // timed further (the column-hash policy on rows meant for the bit
+            // window can be an order of magnitude slower)
+            if (ms > 4.0f * best) break;
             HIPCHK(hipEventRecord(e0, st));
             if ((s = launch_kinds<VT>(h, na, hs.kcount_num, hs.kmax_num, acc)) != SPG_OK) break;
             HIPCHK(hipEventRecord(e1, st));
             HIPCHK(hipEventSynchronize(e1));
-            float ms = 0;
             HIPCHK(hipEventElapsedTime(&ms, e0, e1));
             if (ms < best) {
                 best = ms;

@@ -337,8 +337,10 @@ constexpr int RED_ELEMS = 16384;
 hipError_t launch_rowinfo(int64_t m, int64_t n, const int64_t *arp, const int32_t *aci, const BRow *bi,
                           int64_t *rflops, int64_t *rflopsc, int2 *rwin, DevStats *st, long long *part, int comp_opt,
                           int selector, double cf_threshold, hipStream_t s);
-hipError_t launch_copy_rp(int64_t n1, const void *src, int is64, int64_t nnz, int64_t *dst, int *bad,
-                          hipStream_t s);
+// Row pointers of A and B (int32 or int64) copied to int64, clamped to
+// [0, nnz], with a monotonicity / end check into *bad: one launch for both.
+hipError_t launch_copy_rp(int64_t n1a, const void *srca, int is64a, int64_t nnza, int64_t *dsta, int64_t n1b,
+                          const void *srcb, int is64b, int64_t nnzb, int64_t *dstb, int *bad, hipStream_t s);
 
 // Exclusive scan: out[0..n] (n+1 entries) of in[0..n), int64 result.
 // tmp must hold scan_tmp_elems(n) int64.
