@@ -52,7 +52,7 @@ typedef enum {
     SPG_ERR_NOT_READY = 5,          /* numeric called before a successful symbolic */
     SPG_ERR_STRUCTURE_MISMATCH = 6, /* numeric inputs differ from the symbolic ones */
     SPG_ERR_HIP = 7,                /* HIP runtime error (text in spg_last_error) */
-    SPG_ERR_UNSUPPORTED = 8,        /* valid input this build does not handle */
+    SPG_ERR_UNSUPPORTED = 8,        /* valid input the library does not handle */
     SPG_ERR_INTERNAL = 9
 } spg_status;
 
