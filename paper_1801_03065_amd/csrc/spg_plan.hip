@@ -66,7 +66,11 @@ struct RowDescP {
     int wlo, nw;  // nw: touched words (plan pairs)
 };
 
-template <typename VT, int ACC>
+// LGS: lanes per B row as a compile-time power of two (the launch's lg_gs),
+// so the staging offsets of a lane's products are immediates; NU products per
+// lane cover the fast path (NU * NG >= 64 or NU = PL_U), and every staged
+// index g + u * NG stays below 64.
+template <typename VT, int ACC, int LGS>
 __global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_num_pl(NumArgs<VT> a) {
     using A = Accum<VT, ACC>;
     using S = typename A::store_t;
@@ -78,7 +82,9 @@ __global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(4, 8))) vo
     auto half = [&](int b) -> unsigned char * { return smem + L.half0 + (size_t)b * L.hsize; };
     for (int b = 0; b < 2; ++b)
         for (int t = l; t < a.r_max; t += WAVE) ((S *)(half(b) + L.vals))[t] = A::zero();
-    const int gs = 1 << a.lg_gs, g = l >> a.lg_gs, q = l & (gs - 1), ng = WAVE >> a.lg_gs;
+    constexpr int gs = 1 << LGS, ng = WAVE >> LGS;
+    constexpr int NU = PL_U < WAVE / ng ? PL_U : WAVE / ng;
+    const int g = l >> LGS, q = l & (gs - 1);
     int64_t lo, hi;
     rs_bounds(a.rs, lo, hi);
     const int64_t cbase = a.cbase_row >= 0 ? a.coff[a.cbase_row] : 0;
@@ -130,7 +136,7 @@ __global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(4, 8))) vo
             ((int32_t *)(hb + L.st_len))[l] = len;
             ((int2 *)(hb + L.st_pk))[l] = make_int2((int)(uint32_t)b0, len);
         }
-        return a.b32 && na <= WAVE && cn <= ng * PL_U && __ballot(l < cn && len > gs) == 0;
+        return a.b32 && na <= WAVE && cn <= ng * NU && __ballot(l < cn && len > gs) == 0;
     };
     const int64_t step = sl.step;
     const int64_t p0 = sl.idx, pend = sl.end;
@@ -227,15 +233,15 @@ __global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(4, 8))) vo
         const int i4 = pp + 4 * step < pend ? a.rs.rows[pp + 4 * step] : 0;
 
         // ---- 3. gathers of row p: every product's column and value
-        int col[PL_U];
-        VT pv[PL_U];
+        int col[NU];
+        VT pv[NU];
         unsigned okm = 0;
         if (fast) {
-            int2 pk[PL_U];
+            int2 pk[NU];
 #pragma unroll
-            for (int u = 0; u < PL_U; ++u) pk[u] = st_pk[min(g + u * ng, cn - 1)];
+            for (int u = 0; u < NU; ++u) pk[u] = st_pk[g + u * ng];  // entries past cn are masked below
 #pragma unroll
-            for (int u = 0; u < PL_U; ++u) {
+            for (int u = 0; u < NU; ++u) {
                 const bool ok = (g + u * ng < cn) & (q < pk[u].y);
                 okm |= (unsigned)ok << u;
                 const uint32_t e = ok ? (uint32_t)pk[u].x + q : 0u;  // nnz(B) * 8 < 2^32 on this path
@@ -264,7 +270,7 @@ __global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(4, 8))) vo
         if (ok) {
             if (fast) {
 #pragma unroll
-                for (int u = 0; u < PL_U; ++u) {
+                for (int u = 0; u < NU; ++u) {
                     if (okm & (1u << u)) {
                         const int c = col[u];
                         const VT av = (VT)st_a[g + u * ng];  // issued with the word-map read
@@ -361,12 +367,26 @@ inline int resident_grid(K kernel, int block, size_t lds, int cus) {
     return g < XCDS ? XCDS : g;
 }
 
+template <typename VT, int ACC, int LGS>
+hipError_t num_pl_lg(const NumArgs<VT> &a, const LaunchCfg &c) {
+    const size_t lds = lds_num_pl(a.nw_max, a.r_max, sizeof(typename Accum<VT, ACC>::store_t));
+    const int grid = c.grid > 0 ? c.grid : resident_grid(k_num_pl<VT, ACC, LGS>, WAVE, lds, c.cus);
+    hipLaunchKernelGGL((k_num_pl<VT, ACC, LGS>), dim3(grid), dim3(WAVE), lds, c.stream, a);
+    return hipGetLastError();
+}
+
 template <typename VT, int ACC>
 hipError_t num_pl_impl(const NumArgs<VT> &a, const LaunchCfg &c) {
-    const size_t lds = lds_num_pl(a.nw_max, a.r_max, sizeof(typename Accum<VT, ACC>::store_t));
-    const int grid = c.grid > 0 ? c.grid : resident_grid(k_num_pl<VT, ACC>, WAVE, lds, c.cus);
-    hipLaunchKernelGGL((k_num_pl<VT, ACC>), dim3(grid), dim3(WAVE), lds, c.stream, a);
-    return hipGetLastError();
+    switch (a.lg_gs) {
+    case 0: return num_pl_lg<VT, ACC, 0>(a, c);
+    case 1: return num_pl_lg<VT, ACC, 1>(a, c);
+    case 2: return num_pl_lg<VT, ACC, 2>(a, c);
+    case 3: return num_pl_lg<VT, ACC, 3>(a, c);
+    case 4: return num_pl_lg<VT, ACC, 4>(a, c);
+    case 5: return num_pl_lg<VT, ACC, 5>(a, c);
+    case 6: return num_pl_lg<VT, ACC, 6>(a, c);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 }  // namespace
