@@ -37,9 +37,9 @@ TRAFFIC = {
     "kernel": "k_num_pl",
     "sources": ["paper_1801_03065_amd/csrc/spg_plan.hip", "paper_1801_03065_amd/csrc/spg_internal.hpp",
                 "paper_1801_03065_amd/csrc/spg_accum.hpp"],
-    "sha256": "c77794301356c0df9c7aa3ece6fa2ff95d0ad4f2441520d76481aa2e242d40bf",
-    "read_bytes": 4.0865e9,
-    "write_bytes": 1.5078e9,
+    "sha256": "31d5160dedac91265762164a16c03903f759720b9c918e7e39301c8a6c61a66a",
+    "read_bytes": 4.0193e9,
+    "write_bytes": 1.5087e9,
 }
 
 
