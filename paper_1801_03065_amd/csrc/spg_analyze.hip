@@ -750,28 +750,61 @@ __global__ __launch_bounds__(SC_T) void k_scan_local(int64_t n, const T *in, int
     if (t == SC_T - 1) bsum[blockIdx.x] = off + inc;
 }
 
-// Each block adds the totals of all earlier blocks to its local scan: the
-// block totals are few (one per 2048 elements), so every block reduces its
-// own prefix of them instead of a separate one-block scan launch.  The last
-// block stores the grand total at out[n].
+// Exclusive scan of the block totals in one workgroup (many blocks only).
+__global__ __launch_bounds__(SC_T) void k_scan_top(int64_t nb, int64_t *bsum, const int *enable) {
+    if (enable && !*enable) return;
+    __shared__ long long wsum[SC_T / WAVE];
+    __shared__ long long carry;
+    const int t = threadIdx.x, l = lane_id(), wv = t / WAVE;
+    if (t == 0) carry = 0;
+    __syncthreads();
+    for (int64_t c0 = 0; c0 < nb; c0 += SC_T) {
+        const int64_t b = c0 + t;
+        const long long v = b < nb ? bsum[b] : 0;
+        const long long inc = wave_incl_scan64(v);
+        if (l == WAVE - 1) wsum[wv] = inc;
+        __syncthreads();
+        long long off = 0, tot = 0;
+        for (int u = 0; u < SC_T / WAVE; ++u) {
+            if (u < wv) off += wsum[u];
+            tot += wsum[u];
+        }
+        if (b < nb) bsum[b] = carry + off + inc - v;
+        __syncthreads();
+        if (t == 0) carry += tot;
+        __syncthreads();
+    }
+    if (t == 0) bsum[nb] = carry;
+}
+
+// Each block adds the totals of all earlier blocks to its local scan and the
+// last block stores the grand total at out[n].  With few blocks (SC_FEW) every
+// block reduces its own prefix of the raw totals, saving the one-workgroup
+// scan launch; with more, k_scan_top has replaced them by their exclusive
+// scan (and the grand total at bsum[nb]).
+constexpr int64_t SC_FEW = 1024;
 __global__ __launch_bounds__(SC_T) void k_scan_add(int64_t n, int64_t nb, int64_t *out, const int64_t *bsum,
                                                     const int *enable) {
     if (enable && !*enable) return;
     __shared__ long long wsum[SC_T / WAVE];
     const int t = threadIdx.x, l = lane_id(), wv = t / WAVE;
     const int64_t b = blockIdx.x;
-    long long part = 0;
-    for (int64_t u = t; u < b; u += SC_T) part += bsum[u];
-    part = wave_sum64(part);
-    if (l == 0) wsum[wv] = part;
-    __syncthreads();
     long long add = 0;
+    if (nb <= SC_FEW) {
+        long long part = 0;
+        for (int64_t u = t; u < b; u += SC_T) part += bsum[u];
+        part = wave_sum64(part);
+        if (l == 0) wsum[wv] = part;
+        __syncthreads();
 #pragma unroll
-    for (int u = 0; u < SC_T / WAVE; ++u) add += wsum[u];
+        for (int u = 0; u < SC_T / WAVE; ++u) add += wsum[u];
+    } else {
+        add = bsum[b];
+    }
     const int64_t base = b * SC_B;
     for (int e = t; e < SC_B; e += SC_T)
         if (base + e < n) out[base + e] += add;
-    if (b == nb - 1 && t == 0) out[n] = add + bsum[b];
+    if (b == nb - 1 && t == 0) out[n] = nb <= SC_FEW ? add + bsum[b] : bsum[nb];
 }
 
 __global__ __launch_bounds__(BLK) void k_store_rp32(int64_t n1, const int64_t *src, int32_t *dst) {
@@ -886,6 +919,7 @@ static hipError_t scan_impl(int64_t n, const T *in, int stride, int64_t *out, in
     const int64_t nb = (n + SC_B - 1) / SC_B;
     if (nb > 0) {
         hipLaunchKernelGGL(k_scan_local<T>, dim3((unsigned)nb), dim3(SC_T), 0, s, n, in, stride, out, tmp, enable);
+        if (nb > SC_FEW) hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(SC_T), 0, s, nb, tmp, enable);
         hipLaunchKernelGGL(k_scan_add, dim3((unsigned)nb), dim3(SC_T), 0, s, n, nb, out, tmp, enable);
     } else {
         hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(BLK), 0, s, (int32_t *)out, (int64_t)2, 0);
