@@ -9,7 +9,7 @@ import pytest
 
 import oracle
 import synth
-from helpers import check_f32, check_f64, check_structure, f32_inputs, oracle_ref, run
+from helpers import check_f32, check_f64, check_structure, dev, f32_inputs, oracle_ref, run
 
 pytestmark = pytest.mark.gpu
 
@@ -140,6 +140,37 @@ def test_int64_row_ptrs():
     got, _ = run(A, A, rp="i64", crp="i64")
     check_structure(ref, got)
     assert np.array_equal(got[2], ref.values)
+
+
+@pytest.mark.parametrize("widths", [("i64", "i32"), ("i32", "i64")])
+def test_mixed_row_ptr_widths(widths):
+    """A and B with row pointers of different widths (one launch copies both)."""
+    import torch
+
+    import paper_1801_03065_amd as spg
+
+    A = synth.stencil27(7)
+    B = synth.random_csr(A.ncols, 500, np.random.default_rng(8).integers(0, 6, A.ncols), 9)
+    ref, S = oracle_ref(A, B)
+    h = spg.Handle()
+    dA, dB = dev(A, rp=widths[0]), dev(B, rp=widths[1])
+    rp, nnz = spg.spgemm_symbolic(h, dA, dB, torch.int64)
+    C = spg.spgemm_numeric(h, dA, dB, rp, nnz)
+    h.check_errors()
+    torch.cuda.synchronize()
+    check_f64(ref, S, (rp.cpu().numpy(), C.col_idx.cpu().numpy(), C.values.cpu().numpy()))
+
+
+def test_scan_over_many_blocks():
+    """2.2M rows: the row-size scan has more than 1024 blocks of 2048 entries
+    and takes its one-workgroup top scan."""
+    rng = np.random.default_rng(12)
+    m = n = 2_200_000
+    A = synth.random_csr(m, n, rng.integers(0, 3, m), 13)
+    B = synth.random_csr(n, 3000, rng.integers(0, 4, n), 14)
+    ref, S = oracle_ref(A, B)
+    got, _ = run(A, B)
+    check_f64(ref, S, got)
 
 
 @pytest.mark.parametrize("acc", [0, 1, 2, 3])
