@@ -376,3 +376,50 @@ def test_short_unsorted_b_rows(acc, comp):
     check_f64(ref, S, got)
     if comp == 1:
         assert h.stats()["compressed"] == 1
+
+
+def test_handle_reused_across_products():
+    """One handle through products of different shapes and kinds, growing and
+    shrinking: each plan replaces the previous one completely."""
+    import paper_1801_03065_amd as spg
+
+    A = synth.stencil27(6)
+    P, Pt = synth.aggregation_2x2x2(6)
+    AP = oracle.spgemm(A, P)
+    rng = np.random.default_rng(21)
+    R = synth.random_csr(5000, A.ncols, rng.integers(0, 40, 5000), 22)
+    big = synth.stencil27(12)
+    h = spg.Handle()
+    for L, Rm in ((A, A), (A, P), (Pt, AP), (R, A), (big, big), (A, A)):
+        ref, S = oracle_ref(L, Rm)
+        got, _ = run(L, Rm, handle=h)
+        check_f64(ref, S, got)
+
+
+def test_numeric_rejects_missing_or_different_plan():
+    """Numeric before any symbolic phase, with operands other than the plan's,
+    or with C of another size: clear errors, and the handle still works."""
+    import torch
+
+    import paper_1801_03065_amd as spg
+
+    A = synth.stencil27(4)
+    A2 = synth.stencil27(5)
+    h = spg.Handle()
+    dA, dA2 = dev(A), dev(A2)
+    rp0 = torch.zeros(A.nrows + 1, dtype=torch.int32, device="cuda")
+    with pytest.raises(spg.SpgemmError) as ei:
+        spg.spgemm_numeric(h, dA, dA, rp0, 1)
+    assert ei.value.status == spg.SPG_ERR_NOT_READY
+    rp, nnz = spg.spgemm_symbolic(h, dA, dA)
+    with pytest.raises(spg.SpgemmError) as ei:
+        spg.spgemm_numeric(h, dA2, dA2, rp, nnz)
+    assert ei.value.status in (spg.SPG_ERR_STRUCTURE_MISMATCH, spg.SPG_ERR_DIM_MISMATCH)
+    with pytest.raises(spg.SpgemmError) as ei:
+        spg.spgemm_numeric(h, dA, dA, rp, nnz - 1)
+    assert ei.value.status == spg.SPG_ERR_STRUCTURE_MISMATCH
+    C = spg.spgemm_numeric(h, dA, dA, rp, nnz)
+    h.check_errors()
+    torch.cuda.synchronize()
+    ref, S = oracle_ref(A, A)
+    check_f64(ref, S, (rp.cpu().numpy().astype(np.int64), C.col_idx.cpu().numpy(), C.values.cpu().numpy()))
