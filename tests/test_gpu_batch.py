@@ -118,3 +118,29 @@ def test_batch_fp32():
         ref, S = oracle.spgemm(f32_inputs(A), f32_inputs(B), with_abs=True)
         got = (C.row_ptr.cpu().numpy().astype(np.int64), C.col_idx.cpu().numpy(), C.values.cpu().numpy())
         check_f32(ref, S, got)
+
+
+def test_batch_with_degenerate_members():
+    """Members with no rows, a 1x1 product, a single output column and an
+    all-empty A among ordinary products, in one batched plan."""
+    import torch
+
+    import paper_1801_03065_amd as spg
+
+    specs, pairs = _batch(6, 31)
+    empty_rows = synth.Csr(0, 9, np.zeros(1, np.int64), np.zeros(0, np.int32), np.zeros(0))
+    pairs[1] = (empty_rows, synth.tiny_random(9, 4, 0.5, 3))
+    pairs[2] = (synth.Csr(1, 1, np.array([0, 1]), np.array([0], np.int32), np.array([2.5])),
+                synth.Csr(1, 1, np.array([0, 1]), np.array([0], np.int32), np.array([-3.0])))
+    pairs[3] = (synth.tiny_random(40, 30, 0.3, 4), synth.tiny_random(30, 1, 0.6, 5))
+    pairs[4] = (synth.tiny_random(25, 12, 0.0, 6), synth.tiny_random(12, 8, 0.4, 7))
+    h = spg.Handle()
+    As = spg.pack_batch([p[0] for p in pairs])
+    Bs = spg.pack_batch([p[1] for p in pairs])
+    rps, nnzs = spg.spgemm_batch_symbolic(h, As, Bs)
+    Cs = spg.batch_outputs(As, Bs, rps, nnzs, torch.float64)
+    spg.spgemm_batch_numeric(h, As, Bs, Cs)
+    torch.cuda.synchronize()
+    h.check_errors()
+    assert nnzs[1] == 0 and nnzs[2] == 1 and nnzs[4] == 0
+    _check(pairs, Cs)
