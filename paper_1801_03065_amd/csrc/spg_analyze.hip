@@ -469,9 +469,9 @@ __global__ __launch_bounds__(BLK) void k_rowinfo_fin(int nb, const long long *pa
 // One row per lane, CB rows per workgroup (contiguous, so the per-workgroup
 // kind counts are the counts of the stable partition).  Each workgroup writes
 // per kind: max window words, max bound, max touched words and its row count
-// (int32 x 4); k_classify_fold folds them into the phase's statistics and
-// turns the counts into the partition's offsets (kinds in order, workgroups in
-// row order within a kind).
+// (int32 x 4), and the row counts again compactly (int32 per kind); the
+// partition kernel folds them into the phase's statistics and the partition's
+// offsets (kinds in order, workgroups in row order within a kind).
 constexpr int CB = 1024;
 
 __global__ __launch_bounds__(CB) void k_classify(int64_t m, const int64_t *rflops, const int64_t *rflopsc,
@@ -580,6 +580,7 @@ __global__ __launch_bounds__(CB) void k_classify(int64_t m, const int64_t *rflop
         q[1] = smax[t][1];
         q[2] = smax[t][2];
         q[3] = scnt[t];
+        blk[4 * gridDim.x * NK + (int64_t)blockIdx.x * NK + t] = scnt[t];  // compact counts, read by every partition workgroup
     }
 }
 
@@ -599,108 +600,108 @@ __device__ __forceinline__ int wave_maxscan_dpp(int v) {
 // the maxima (into the phase's statistics), the kind offsets koff, and each
 // workgroup's count replaced by its exclusive offset (kinds in order, row order
 // within a kind).  Counts and offsets fit int32 (rows are int32).
-__global__ __launch_bounds__(CB) void k_classify_fold(int64_t nb, int32_t *blk, int64_t *koff, int phase, int heavy,
-                                                       DevStats *st) {
+// ------------------------------------------------------------------ partition
+// Stable partition of rows by kind.  Every workgroup folds the classify
+// workgroups' compact counts itself (a few KB: kind totals give the kind
+// bases, the workgroups before it its offset inside each kind), so no
+// one-workgroup fold kernel runs in between; workgroup 0 also folds the
+// maxima and counts into the phase's statistics and writes the kind offsets.
+// A row lands at base + offset + its rank among the same kind in the
+// workgroup (wavefront ballots).
+static_assert(NK == 8, "the partition reads a workgroup's kind counts as two int4");
+
+__global__ __launch_bounds__(CB) void k_part_scatter(int64_t m, int64_t nb, const uint8_t *kind, const int32_t *blk,
+                                                      int32_t *perm, int64_t *koff, int phase, int heavy,
+                                                      DevStats *st) {
     constexpr int NW = CB / WAVE;
+    __shared__ int wcnt[NW][NK];
+    __shared__ int wtot[NK][NW], wpre[NK][NW];
+    __shared__ int stot[NK], spre[NK], sbase[NK];
     __shared__ int smax[NK][3];
-    __shared__ int wsum[NK][NW];
-    __shared__ int woff[NK][NW];
-    __shared__ int base[NK];
-    __shared__ long long ktot[NK];
     const int t = threadIdx.x, l = lane_id(), wv = t / WAVE;
-    if (t < NK) smax[t][0] = smax[t][1] = smax[t][2] = 0;
-    // pass 1: totals and maxima (a single chunk keeps its counts for pass 2)
-    int tot[NK], mx[NK][3], own[NK];
+    const int64_t b = blockIdx.x;
+    const int32_t *cnt = blk + 4 * nb * NK;
+    // kind totals over all classify workgroups and over the ones before this
+    int tot[NK], pre[NK];
 #pragma unroll
-    for (int k = 0; k < NK; ++k) tot[k] = mx[k][0] = mx[k][1] = mx[k][2] = own[k] = 0;
-    for (int64_t b = t; b < nb; b += CB) {
-        const int4 *q = (const int4 *)(blk + 4 * b * NK);
+    for (int k = 0; k < NK; ++k) tot[k] = pre[k] = 0;
+    for (int64_t u = t; u < nb; u += CB) {
+        const int4 c0 = *(const int4 *)(cnt + u * NK), c1 = *(const int4 *)(cnt + u * NK + 4);
+        const int c[NK] = {c0.x, c0.y, c0.z, c0.w, c1.x, c1.y, c1.z, c1.w};
 #pragma unroll
         for (int k = 0; k < NK; ++k) {
-            const int4 v = q[k];
-            if (b == t) own[k] = v.w;
-            tot[k] += v.w;
-            mx[k][0] = max(mx[k][0], v.x);
-            mx[k][1] = max(mx[k][1], v.y);
-            mx[k][2] = max(mx[k][2], v.z);
+            tot[k] += c[k];
+            pre[k] += u < b ? c[k] : 0;
         }
     }
-    __syncthreads();
 #pragma unroll
     for (int k = 0; k < NK; ++k) {
         const int ts = __builtin_amdgcn_readlane(wave_scan_dpp(tot[k]), 63);
-        const int m0 = __builtin_amdgcn_readlane(wave_maxscan_dpp(mx[k][0]), 63);
-        const int m1 = __builtin_amdgcn_readlane(wave_maxscan_dpp(mx[k][1]), 63);
-        const int m2 = __builtin_amdgcn_readlane(wave_maxscan_dpp(mx[k][2]), 63);
+        const int ps = __builtin_amdgcn_readlane(wave_scan_dpp(pre[k]), 63);
         if (l == 0) {
-            wsum[k][wv] = ts;
-            atomicMax(&smax[k][0], m0);
-            atomicMax(&smax[k][1], m1);
-            atomicMax(&smax[k][2], m2);
+            wtot[k][wv] = ts;
+            wpre[k][wv] = ps;
         }
+    }
+    if (t < NK) smax[t][0] = smax[t][1] = smax[t][2] = 0;
+    __syncthreads();
+    if (t < NK) {
+        int T = 0, P = 0;
+        for (int u = 0; u < NW; ++u) {
+            T += wtot[t][u];
+            P += wpre[t][u];
+        }
+        stot[t] = T;
+        spre[t] = P;
     }
     __syncthreads();
     if (t < NK) {
-        long long kt = 0;
-        for (int u = 0; u < NW; ++u) kt += wsum[t][u];
-        ktot[t] = kt;
+        int base = 0;
+        for (int k = 0; k < t; ++k) base += stot[k];
+        sbase[t] = base;
+        if (b == 0 && koff) {
+            koff[t] = base;
+            if (t == NK - 1) koff[NK] = base + stot[t];
+        }
+    }
+    // workgroup 0: the per-kind maxima into the phase's statistics
+    if (b == 0) {
+        int mx[NK][3];
+#pragma unroll
+        for (int k = 0; k < NK; ++k) mx[k][0] = mx[k][1] = mx[k][2] = 0;
+        for (int64_t u = t; u < nb; u += CB) {
+#pragma unroll
+            for (int k = 0; k < NK; ++k) {
+                const int4 v = *(const int4 *)(blk + 4 * (u * NK + k));
+                mx[k][0] = max(mx[k][0], v.x);
+                mx[k][1] = max(mx[k][1], v.y);
+                mx[k][2] = max(mx[k][2], v.z);
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < NK; ++k) {
+            const int m0 = __builtin_amdgcn_readlane(wave_maxscan_dpp(mx[k][0]), 63);
+            const int m1 = __builtin_amdgcn_readlane(wave_maxscan_dpp(mx[k][1]), 63);
+            const int m2 = __builtin_amdgcn_readlane(wave_maxscan_dpp(mx[k][2]), 63);
+            if (l == 0) {
+                atomicMax(&smax[k][0], m0);
+                atomicMax(&smax[k][1], m1);
+                atomicMax(&smax[k][2], m2);
+            }
+        }
     }
     __syncthreads();
-    if (t == 0) {
-        long long run = 0;
-        for (int k = 0; k < NK; ++k) {
-            const long long kt = ktot[k];
-            koff[k] = run;
-            base[k] = (int)run;
-            run += kt;
-        }
-        koff[NK] = run;
-    }
-    if (t < NK && ktot[t]) {
+    if (b == 0 && t < NK && stot[t]) {
         const int k = t;
         int *gm = phase == 0 ? &st->kmax_sym[k][0] : heavy ? &st->kmax_heavy[k][0] : &st->kmax_num[k][0];
         gm[0] = max(gm[0], smax[k][0]);
         gm[1] = max(gm[1], smax[k][1]);
         gm[2] = max(gm[2], smax[k][2]);
         long long *gc = phase == 0 ? &st->kcount_sym[k] : heavy ? &st->kcount_heavy[k] : &st->kcount_num[k];
-        *gc += ktot[k];
+        *gc += stot[k];
     }
-    __syncthreads();
-    // pass 2: exclusive offsets per kind over the workgroups, in row order
-    for (int64_t c0 = 0; c0 < nb; c0 += CB) {
-        const int64_t b = c0 + t;
-        int v[NK], inc[NK];
-#pragma unroll
-        for (int k = 0; k < NK; ++k) {
-            v[k] = nb <= CB ? own[k] : (b < nb ? blk[4 * (b * NK + k) + 3] : 0);
-            inc[k] = wave_scan_dpp(v[k]);
-            if (l == WAVE - 1) wsum[k][wv] = inc[k];
-        }
-        __syncthreads();
-        if (t < NK * NW) {  // exclusive prefix of the wavefront totals, per kind
-            const int k = t / NW, u = t % NW;
-            int o = 0;
-            for (int x = 0; x < u; ++x) o += wsum[k][x];
-            woff[k][u] = o;
-        }
-        __syncthreads();
-#pragma unroll
-        for (int k = 0; k < NK; ++k)
-            if (b < nb) blk[4 * (b * NK + k) + 3] = base[k] + woff[k][wv] + inc[k] - v[k];
-        __syncthreads();
-        if (t < NK) base[t] += woff[t][NW - 1] + wsum[t][NW - 1];
-        __syncthreads();
-    }
-}
-
-// ------------------------------------------------------------------ partition
-// Stable partition of rows by kind: the classify workgroup offsets plus the
-// row's rank among the same kind in its workgroup (wavefront ballots).
-__global__ __launch_bounds__(CB) void k_part_scatter(int64_t m, const uint8_t *kind, const int32_t *blk,
-                                                      int32_t *perm) {
-    __shared__ int wcnt[CB / WAVE][NK];
-    const int t = threadIdx.x, l = lane_id(), wv = t / WAVE;
-    const int64_t i = (int64_t)blockIdx.x * CB + t;
+    // rows of this workgroup, stable within each kind
+    const int64_t i = b * CB + t;
     const int k = i < m ? kind[i] : -1;
     int rank = 0;
     for (int kk = 0; kk < NK; ++kk) {
@@ -712,7 +713,7 @@ __global__ __launch_bounds__(CB) void k_part_scatter(int64_t m, const uint8_t *k
     if (i < m) {
         int off = 0;
         for (int u = 0; u < wv; ++u) off += wcnt[u][k];
-        perm[blk[4 * ((int64_t)blockIdx.x * NK + k) + 3] + off + rank] = (int32_t)i;
+        perm[sbase[k] + spre[k] + off + rank] = (int32_t)i;
     }
 }
 
@@ -954,18 +955,20 @@ hipError_t launch_classify(int64_t m, const int64_t *rflops, const int64_t *rflo
     }
     hipLaunchKernelGGL(k_classify, dim3((unsigned)nb), dim3(CB), 0, s, m, rflops, rflopsc, rwin, row_nnz, row_words,
                        p, kind, row_nnz_out, (int32_t *)tmp);
-    hipLaunchKernelGGL(k_classify_fold, dim3(1), dim3(CB), 0, s, nb, (int32_t *)tmp, koff, p.phase, p.heavy, st);
     return hipGetLastError();
 }
 
 // tmp: per classify workgroup and kind, three maxima and the row count (then
 // offset), int32
-int64_t part_tmp_elems(int64_t m) { return 2 * ((m + CB - 1) / CB) * NK + 1; }
+// per classify workgroup: NK int4 records (maxima, count), then NK compact counts
+int64_t part_tmp_elems(int64_t m) { return (5 * ((m + CB - 1) / CB) * NK + 1) / 2 + 1; }
 
-hipError_t launch_partition(int64_t m, const uint8_t *kind, int32_t *perm, const int64_t *tmp, hipStream_t s) {
+hipError_t launch_partition(int64_t m, const uint8_t *kind, int32_t *perm, const int64_t *tmp, int64_t *koff,
+                            int phase, int heavy, DevStats *st, hipStream_t s) {
     const int64_t nb = (m + CB - 1) / CB;
     if (nb == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_part_scatter, dim3((unsigned)nb), dim3(CB), 0, s, m, kind, (const int32_t *)tmp, perm);
+    hipLaunchKernelGGL(k_part_scatter, dim3((unsigned)nb), dim3(CB), 0, s, m, nb, kind, (const int32_t *)tmp, perm,
+                       koff, phase, heavy, st);
     return hipGetLastError();
 }
 

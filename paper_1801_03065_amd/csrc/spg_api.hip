@@ -392,7 +392,8 @@ static spg_status symbolic_core(spg_handle h, int64_t m, int64_t n, int64_t k, i
     HIPCHK(launch_classify(m, h->rflops.as<int64_t>(), h->rflopsc.as<int64_t>(), h->rwin.as<int2>(), nullptr,
                            nullptr, cp, h->kind_sym.as<uint8_t>(), h->row_nnz.as<int32_t>(), dst, h->tmp.as<int64_t>(),
                            h->koff_sym.as<int64_t>(), st));
-    HIPCHK(launch_partition(m, h->kind_sym.as<uint8_t>(), h->perm_sym.as<int32_t>(), h->tmp.as<int64_t>(), st));
+    HIPCHK(launch_partition(m, h->kind_sym.as<uint8_t>(), h->perm_sym.as<int32_t>(), h->tmp.as<int64_t>(),
+                            h->koff_sym.as<int64_t>(), cp.phase, cp.heavy, dst, st));
     if (want_plan) {
         HIPCHK(launch_scan_i32(m, h->plan_len.as<int32_t>(), h->plan_off.as<int64_t>(), h->tmp.as<int64_t>(), st));
         HIPCHK(hipMemcpyAsync(h->hkoff + 1, h->plan_off.as<int64_t>() + m, sizeof(int64_t), hipMemcpyDeviceToHost,
@@ -512,7 +513,8 @@ static spg_status symbolic_core(spg_handle h, int64_t m, int64_t n, int64_t k, i
     HIPCHK(launch_classify(m, h->rflops.as<int64_t>(), h->rflopsc.as<int64_t>(), h->rwin.as<int2>(),
                            h->row_nnz.as<int32_t>(), h->row_words.as<int32_t>(), cp, h->kind_num.as<uint8_t>(),
                            nullptr, dst, h->tmp.as<int64_t>(), h->koff_num.as<int64_t>(), st));
-    HIPCHK(launch_partition(m, h->kind_num.as<uint8_t>(), h->perm_num.as<int32_t>(), h->tmp.as<int64_t>(), st));
+    HIPCHK(launch_partition(m, h->kind_num.as<uint8_t>(), h->perm_num.as<int32_t>(), h->tmp.as<int64_t>(),
+                            h->koff_num.as<int64_t>(), cp.phase, cp.heavy, dst, st));
     if (thr > 0) {  // rows at or above the threshold: their own kind lists (FP64 accumulation in FP32 mode)
         HIPCHK(ensure(h->kind_heavy, std::max<int64_t>(m, 1)));
         HIPCHK(ensure(h->perm_heavy, 4 * std::max<int64_t>(m, 1)));
@@ -526,7 +528,7 @@ static spg_status symbolic_core(spg_handle h, int64_t m, int64_t n, int64_t k, i
                                h->kind_heavy.as<uint8_t>(), nullptr, dst, h->tmp.as<int64_t>(),
                                h->koff_heavy.as<int64_t>(), st));
         HIPCHK(launch_partition(m, h->kind_heavy.as<uint8_t>(), h->perm_heavy.as<int32_t>(), h->tmp.as<int64_t>(),
-                                st));
+                                h->koff_heavy.as<int64_t>(), ch.phase, ch.heavy, dst, st));
     }
     HIPCHK(hipMemcpyAsync(h->hkoff, h->coff.as<int64_t>() + m, sizeof(int64_t), hipMemcpyDeviceToHost, st));
     if ((s = pull_stats(h)) != SPG_OK) return s;  // host sync 2: nnz(C), numeric kinds
@@ -740,7 +742,8 @@ static spg_status autotune(spg_handle h, NumArgs<VT> na, int acc) {
         HIPCHK(launch_classify(m, h->rflops.as<int64_t>(), h->rflopsc.as<int64_t>(), h->rwin.as<int2>(),
                                h->row_nnz.as<int32_t>(), h->row_words.as<int32_t>(), cp, h->kind_tmp.as<uint8_t>(),
                                nullptr, dst, h->tmp.as<int64_t>(), h->koff_tmp.as<int64_t>(), st));
-        HIPCHK(launch_partition(m, h->kind_tmp.as<uint8_t>(), h->perm_tmp.as<int32_t>(), h->tmp.as<int64_t>(), st));
+        HIPCHK(launch_partition(m, h->kind_tmp.as<uint8_t>(), h->perm_tmp.as<int32_t>(), h->tmp.as<int64_t>(),
+                                h->koff_tmp.as<int64_t>(), cp.phase, cp.heavy, dst, st));
         if ((s = pull_stats(h)) != SPG_OK) break;
         const DevStats hs = *h->hst;
         na.rs.rows = h->perm_tmp.as<int32_t>();
@@ -780,7 +783,8 @@ static spg_status autotune(spg_handle h, NumArgs<VT> na, int acc) {
     HIPCHK(launch_classify(m, h->rflops.as<int64_t>(), h->rflopsc.as<int64_t>(), h->rwin.as<int2>(),
                            h->row_nnz.as<int32_t>(), h->row_words.as<int32_t>(), cp, h->kind_num.as<uint8_t>(),
                            nullptr, dst, h->tmp.as<int64_t>(), h->koff_num.as<int64_t>(), st));
-    HIPCHK(launch_partition(m, h->kind_num.as<uint8_t>(), h->perm_num.as<int32_t>(), h->tmp.as<int64_t>(), st));
+    HIPCHK(launch_partition(m, h->kind_num.as<uint8_t>(), h->perm_num.as<int32_t>(), h->tmp.as<int64_t>(),
+                            h->koff_num.as<int64_t>(), cp.phase, cp.heavy, dst, st));
     if ((s = pull_stats(h)) != SPG_OK) return s;
     h->lg_num = best_lg;
     h->tuned = true;

@@ -372,14 +372,15 @@ struct ClassParams {
                         // have one or fit a single segment
 };
 // Classification of every row into a kind, with per-kind counts and maxima
-// (into st) and the partition offsets per kind (koff, nullable) and per
-// classify workgroup (tmp, part_tmp_elems(m)); launch_partition then writes
-// the rows grouped by kind.
+// per classify workgroup (tmp, part_tmp_elems(m)); launch_partition then folds
+// them into st (counts, maxima) and koff (offsets per kind) and writes the
+// rows grouped by kind.  (koff is only filled here when there are no rows.)
 hipError_t launch_classify(int64_t m, const int64_t *rflops, const int64_t *rflopsc, const int2 *rwin,
                            const int32_t *row_nnz, const int32_t *row_words, ClassParams p, uint8_t *kind,
                            int32_t *row_nnz_out, DevStats *st, int64_t *tmp, int64_t *koff, hipStream_t s);
 int64_t part_tmp_elems(int64_t m);
-hipError_t launch_partition(int64_t m, const uint8_t *kind, int32_t *perm, const int64_t *tmp, hipStream_t s);
+hipError_t launch_partition(int64_t m, const uint8_t *kind, int32_t *perm, const int64_t *tmp, int64_t *koff,
+                            int phase, int heavy, DevStats *st, hipStream_t s);
 hipError_t launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s);
 hipError_t launch_kind_ranges(const int32_t *perm, const int64_t *koff, int64_t rb, int64_t re, int64_t *range,
                               hipStream_t s);
