@@ -37,9 +37,9 @@ TRAFFIC = {
     "kernel": "k_num_pl",
     "sources": ["paper_1801_03065_amd/csrc/spg_plan.hip", "paper_1801_03065_amd/csrc/spg_internal.hpp",
                 "paper_1801_03065_amd/csrc/spg_accum.hpp"],
-    "sha256": "31d5160dedac91265762164a16c03903f759720b9c918e7e39301c8a6c61a66a",
-    "read_bytes": 4.0193e9,
-    "write_bytes": 1.5087e9,
+    "sha256": "40c505d6112deb35cc5517370be24a05114fca21b2ba8b0c21d28ce9d84e45c2",
+    "read_bytes": 4.0568e9,
+    "write_bytes": 1.5085e9,
 }
 
 
