@@ -394,13 +394,7 @@ static spg_status symbolic_core(spg_handle h, int64_t m, int64_t n, int64_t k, i
                            h->koff_sym.as<int64_t>(), st));
     HIPCHK(launch_partition(m, h->kind_sym.as<uint8_t>(), h->perm_sym.as<int32_t>(), h->tmp.as<int64_t>(),
                             h->koff_sym.as<int64_t>(), cp.phase, cp.heavy, dst, st));
-    if (want_plan) {
-        HIPCHK(launch_scan_i32(m, h->plan_len.as<int32_t>(), h->plan_off.as<int64_t>(), h->tmp.as<int64_t>(), st));
-        HIPCHK(hipMemcpyAsync(h->hkoff + 1, h->plan_off.as<int64_t>() + m, sizeof(int64_t), hipMemcpyDeviceToHost,
-                              st));
-    }
-    // host sync 1: input checks, flop counts, compression, per-kind sizes,
-    // room for stored structure
+    // host sync 1: input checks, flop counts, compression, per-kind sizes
     if ((s = pull_stats(h)) != SPG_OK) return s;
     const DevStats hs2 = *h->hst;
     const DevStats &hs1 = hs2;
@@ -417,12 +411,31 @@ static spg_status symbolic_core(spg_handle h, int64_t m, int64_t n, int64_t k, i
     h->segmented = false;
     const bool pairs_used = want_pairs && hs2.kcount_sym[K_DW] > 0;
     const bool segs_used = want_segs && hs2.kcount_sym[K_DG] > 0;
+    // room for stored structure: the scan of the rows' room gives each row's
+    // offset.  Bit-window rows hold at most PL_CAP pairs each, so while no
+    // segment room is in the scan (no heavy rows with lists) and that bound
+    // is modest, the plan is sized by it without waiting for the total;
+    // otherwise the exact total is fetched (one more host sync).
+    int64_t plan_room = 0;
+    if (pairs_used || segs_used) {
+        HIPCHK(launch_scan_i32(m, h->plan_len.as<int32_t>(), h->plan_off.as<int64_t>(), h->tmp.as<int64_t>(), st));
+        const int64_t bound = (int64_t)PL_CAP * hs2.kcount_sym[K_DW];
+        const bool seg_room = want_segs_opt && hs2.kcount_sym[K_DG] > 0;
+        if (!seg_room && bound <= (int64_t(1) << 27)) {
+            plan_room = bound;
+        } else {
+            HIPCHK(hipMemcpyAsync(h->hkoff + 1, h->plan_off.as<int64_t>() + m, sizeof(int64_t),
+                                  hipMemcpyDeviceToHost, st));
+            HIPCHK(hipStreamSynchronize(st));
+            plan_room = h->hkoff[1];
+        }
+    }
     bool plan_ok = false;
-    if ((pairs_used || segs_used) && h->hkoff[1] > 0) {
+    if ((pairs_used || segs_used) && plan_room > 0) {
         // without room for the pairs the numeric phase rebuilds the structure
         // itself; without room for the segment lists heavy rows use the
         // window-wide kernel
-        plan_ok = ensure(h->plan, 8 * (size_t)h->hkoff[1]) == hipSuccess;
+        plan_ok = ensure(h->plan, 8 * (size_t)plan_room) == hipSuccess;
         (void)hipGetLastError();
     }
     h->planned = plan_ok && pairs_used;
@@ -430,7 +443,7 @@ static spg_status symbolic_core(spg_handle h, int64_t m, int64_t n, int64_t k, i
     // segments need a list wherever a row may exceed one (rows with a bound
     // of room in plan_len): with lists missing, all heavy rows take the
     // window-wide kernel
-    h->sg_mode = want_segs && (plan_ok || !segs_used || h->hkoff[1] == 0);
+    h->sg_mode = want_segs && (plan_ok || !segs_used || plan_room == 0);
 
     SymArgs sa{};
     sa.arp = arp;
