@@ -1,10 +1,12 @@
 // Host side of the C ABI: the handle, the symbolic plan kept for reuse, and
 // the orchestration of the two phases (Algorithm 2):
 //   symbolic: row_ptr copies -> B row statistics -> per-row flops / windows
-//             -> [host reads f_m, compressed f_m] -> compression of B if it
-//             removes more than 15% of the flops -> rows classified by kernel
-//             kind -> [host reads per-kind sizes] -> one persistent launch per
-//             kind -> scan -> numeric classification -> [host reads nnz(C)]
+//             and, on the device, the compression decision (compress B if it
+//             removes more than 15% of the flops) -> compressed B -> rows
+//             classified by kernel kind -> [host reads the statistics and
+//             per-kind sizes] -> room for stored structure -> one persistent
+//             launch per kind -> scan -> numeric classification -> [host
+//             reads nnz(C)]
 //   numeric:  one persistent launch per kind, no host synchronisation.
 #include <algorithm>
 #include <cstdio>
