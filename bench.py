@@ -38,8 +38,8 @@ TRAFFIC = {
     "sources": ["paper_1801_03065_amd/csrc/spg_plan.hip", "paper_1801_03065_amd/csrc/spg_internal.hpp",
                 "paper_1801_03065_amd/csrc/spg_accum.hpp"],
     "sha256": "40c505d6112deb35cc5517370be24a05114fca21b2ba8b0c21d28ce9d84e45c2",
-    "read_bytes": 4.0568e9,
-    "write_bytes": 1.5085e9,
+    "read_bytes": 4.0396e9,
+    "write_bytes": 1.5084e9,
 }
 
 
