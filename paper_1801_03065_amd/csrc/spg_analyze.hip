@@ -871,7 +871,7 @@ hipError_t launch_brow(int64_t n, int64_t nnz, int64_t ncols, const int64_t *brp
 
 // The unsorted-row kernels read their row count from device memory, so they
 // are enqueued without a host round trip; surplus workgroups exit at once.
-constexpr int UB_GRID = 1024;
+constexpr int UB_GRID = 512;  // two 64 KB-LDS workgroups per CU are resident: one round of workgroups
 
 hipError_t launch_brow_unsorted(const int32_t *list, const int *count, const int64_t *brp, const int32_t *bci,
                                 BRow *out, DevStats *st, hipStream_t s) {
