@@ -110,6 +110,22 @@ typedef struct {
                                      level-2 spills */
     int32_t autotune;             /* 1 = time candidate kernels on sampled rows
                                      during symbolic and keep the fastest */
+    int32_t fp32_terms_max;       /* FP32 values: rows of A with more entries than
+                                     this accumulate in FP64, since each entry of C
+                                     then sums more products than FP32 (plain or
+                                     compensated) can add within 1e-5 of the sum of
+                                     |products|.  -1 = derived from fp32_mode (167
+                                     plain, 52730 compensated, none with FP64
+                                     accumulation), 0 = never, n > 0 = n.  Fixed at
+                                     the symbolic phase. */
+    int32_t verify_structure;     /* 1 = the symbolic phase records a 64-bit digest
+                                     of A's and B's row_ptr and col_idx, and every
+                                     spgemm_numeric, spgemm_numeric_rows and
+                                     spgemm_backward on the plan recomputes it on the
+                                     device first (one pass over both structures);
+                                     a difference is reported by spg_check_errors as
+                                     STRUCTURE_MISMATCH.  0 = pointers and sizes are
+                                     the only check.  Not applied to batch plans. */
 } spg_options;
 
 typedef struct {
@@ -119,7 +135,8 @@ typedef struct {
     int64_t max_row_flops_compressed;
     int64_t nnz_c;                  /* nnz(C) */
     int64_t max_row_nnz;            /* maxrs */
-    int64_t nnz_b_compressed;       /* (column-set index, column-set) pairs */
+    int64_t nnz_b_compressed;       /* (column-set index, column-set) pairs of compressed
+                                       B (0 when the symbolic phase did not compress B) */
     int32_t compressed;             /* 1 if the symbolic phase used compressed B */
     int32_t n_kinds;                /* kinds in use: 0 empty, 1 bit window (wavefront),
                                        2 hash (wavefront), 3 bit window (workgroup),
@@ -132,13 +149,16 @@ typedef struct {
     int32_t l2_spill_rows;          /* rows that used the level-2 (HBM) hash */
     int32_t tuned_policy;           /* autotune: 0 selector, 1 bit window first, 2 hash first */
     int32_t tuned_lanes;            /* autotune: lanes per B row in the numeric phase (0 = not tuned) */
-    int32_t reserved[5];
+    int32_t fp64_rows;              /* rows kept in the FP64-accumulated kind lists
+                                       (fp64_heavy_row_flops, fp32_terms_max) */
+    int32_t reserved[4];
 } spg_stats;
 
 typedef struct spg_handle_s *spg_handle;
 
 /* Fill *opt with the defaults (compression -1, cf_threshold 0.85, AUTO,
- * FP32_PLAIN, no FP64 heavy rows, LDS-sized hash, no autotune). */
+ * FP32_PLAIN, no flop threshold for FP64 rows, FP64 rows by the derived term
+ * limit, LDS-sized hash, no autotune). */
 void spg_default_options(spg_options *opt);
 
 /* Create a handle on the current HIP device.  hip_stream is a hipStream_t

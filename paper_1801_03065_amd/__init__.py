@@ -66,7 +66,8 @@ class spg_options(ctypes.Structure):
     _fields_ = [("compression", ctypes.c_int32), ("cf_threshold", ctypes.c_double),
                 ("accumulator", ctypes.c_int32), ("fp32_mode", ctypes.c_int32),
                 ("fp64_heavy_row_flops", ctypes.c_int64), ("l1_hash_slots", ctypes.c_int32),
-                ("autotune", ctypes.c_int32)]
+                ("autotune", ctypes.c_int32), ("fp32_terms_max", ctypes.c_int32),
+                ("verify_structure", ctypes.c_int32)]
 
 
 class spg_stats(ctypes.Structure):
@@ -77,7 +78,7 @@ class spg_stats(ctypes.Structure):
                 ("n_kinds", ctypes.c_int32), ("rows_symbolic", ctypes.c_int64 * 8),
                 ("rows_numeric", ctypes.c_int64 * 8), ("l2_spill_rows", ctypes.c_int32),
                 ("tuned_policy", ctypes.c_int32), ("tuned_lanes", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 5)]
+                ("fp64_rows", ctypes.c_int32), ("reserved", ctypes.c_int32 * 4)]
 
 
 _P = ctypes.c_void_p
@@ -306,6 +307,8 @@ class _SpGEMMFunction(torch.autograd.Function):
         A = prod.A.with_values(a_values)
         B = prod.B.with_values(b_values)
         C = spgemm_numeric(prod.handle, A, B, prod.row_ptr, prod.nnz)
+        if prod.check:
+            prod.handle.check_errors()
         ctx.prod = prod
         ctx.save_for_backward(a_values, b_values, C.col_idx)
         return C.values
@@ -318,6 +321,8 @@ class _SpGEMMFunction(torch.autograd.Function):
         B = prod.B.with_values(b_values)
         G = DeviceCsr(A.nrows, B.ncols, prod.row_ptr, c_col, grad_c.contiguous())
         dA, dB = spgemm_backward(prod.handle, A, B, G, ctx.needs_input_grad[0], ctx.needs_input_grad[1])
+        if prod.check:
+            prod.handle.check_errors()
         return dA, dB, None
 
 
@@ -328,11 +333,23 @@ class SparseProduct:
     numeric phase on new values (the reuse case) and returns C's values as an
     autograd-tracked tensor; C's row_ptr / col_idx are in .row_ptr / .col_idx
     after the first call.
+
+    The numeric and backward kernels never block the host, so a structure
+    changed in place behind the plan (same pointers and sizes, other columns)
+    is only reported by handle.check_errors().  With check=True the handle
+    fingerprints A's and B's structure at the symbolic phase
+    (verify_structure), and every forward and backward call compares the
+    fingerprint on the device and then runs that check (one stream
+    synchronisation each), raising SpgemmError (STRUCTURE_MISMATCH) instead
+    of returning values or gradients computed on the wrong structure.  A
+    handle passed in keeps its own options.
     """
 
-    def __init__(self, A: DeviceCsr, B: DeviceCsr, handle: Handle | None = None, rp_dtype=torch.int32):
+    def __init__(self, A: DeviceCsr, B: DeviceCsr, handle: Handle | None = None, rp_dtype=torch.int32,
+                 check: bool = False):
         self.A, self.B = A, B
-        self.handle = handle or Handle()
+        self.check = check
+        self.handle = handle or Handle(verify_structure=1 if check else 0)
         self.row_ptr, self.nnz = spgemm_symbolic(self.handle, A, B, rp_dtype)
         self.col_idx = None
 

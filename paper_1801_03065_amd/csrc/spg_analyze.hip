@@ -461,6 +461,9 @@ __global__ __launch_bounds__(BLK) void k_rowinfo_fin(int nb, const long long *pa
             const double f0 = (double)(rule.sel ? a[4] : a[0]), f1 = (double)(rule.sel ? a[5] : a[1]);
             comp = f0 > 0 && f1 < rule.thr * f0;
         }
+        // an unsorted row of B too wide for the word-count bitmap has no
+        // compressed form: the structure kernels then read raw B
+        if (st->bad_window) comp = 0;
         st->comp = comp;
     }
 }
@@ -497,7 +500,11 @@ __global__ __launch_bounds__(CB) void k_classify(int64_t m, const int64_t *rflop
         const bool valid = i < m;
         const bool sampled = p.sample_stride <= 1 || (i % p.sample_stride) == 0;
         long long f = (valid && sampled) ? rflops[i] : 0;
-        if (p.phase == 1 && (f < p.flops_lo || (p.flops_hi > 0 && f >= p.flops_hi))) f = 0;
+        if (p.phase == 1 && p.split && f > 0) {
+            const bool hv = (p.heavy_flops > 0 && f >= p.heavy_flops) ||
+                            (p.heavy_alen > 0 && p.arp[i + 1] - p.arp[i] > p.heavy_alen);
+            if (hv != (p.heavy != 0)) f = 0;
+        }
         const int2 w = valid ? rwin[i] : make_int2(0, -1);
         int k = valid ? K_EMPTY : -1, a = 0, bnd = 0, tw = 0;
         if (f > 0) {
@@ -601,6 +608,47 @@ __device__ __forceinline__ int wave_maxscan_dpp(int v) {
 // workgroup's count replaced by its exclusive offset (kinds in order, row order
 // within a kind).  Counts and offsets fit int32 (rows are int32).
 // ------------------------------------------------------------------ partition
+// Beyond PF_FEW classify workgroups, the compact counts are folded once by
+// one workgroup (k_part_fold) instead of by every partition workgroup, whose
+// reads would grow with the square of the workgroup count.
+constexpr int64_t PF_FEW = 1024;
+
+// One workgroup: the compact per-workgroup kind counts become exclusive
+// prefixes in place (row order within a kind), the kind totals follow them.
+__global__ __launch_bounds__(CB) void k_part_fold(int64_t nb, int32_t *cnt) {
+    constexpr int NW = CB / WAVE;
+    __shared__ int wsum[NK][NW];
+    __shared__ int carry[NK];
+    const int t = threadIdx.x, l = lane_id(), wv = t / WAVE;
+    if (t < NK) carry[t] = 0;
+    __syncthreads();
+    for (int64_t c0 = 0; c0 < nb; c0 += CB) {
+        const int64_t u = c0 + t;
+        int c[NK], inc[NK];
+#pragma unroll
+        for (int k = 0; k < NK; ++k) {
+            c[k] = u < nb ? cnt[u * NK + k] : 0;
+            inc[k] = wave_scan_dpp(c[k]);
+            if (l == WAVE - 1) wsum[k][wv] = inc[k];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < NK; ++k) {
+            int off = carry[k];
+            for (int w = 0; w < wv; ++w) off += wsum[k][w];
+            if (u < nb) cnt[u * NK + k] = off + inc[k] - c[k];
+        }
+        __syncthreads();
+        if (t < NK) {
+            int tt = 0;
+            for (int w = 0; w < NW; ++w) tt += wsum[t][w];
+            carry[t] += tt;
+        }
+        __syncthreads();
+    }
+    if (t < NK) cnt[nb * NK + t] = carry[t];
+}
+
 // Stable partition of rows by kind.  Every workgroup folds the classify
 // workgroups' compact counts itself (a few KB: kind totals give the kind
 // bases, the workgroups before it its offset inside each kind), so no
@@ -625,7 +673,18 @@ __global__ __launch_bounds__(CB) void k_part_scatter(int64_t m, int64_t nb, cons
     int tot[NK], pre[NK];
 #pragma unroll
     for (int k = 0; k < NK; ++k) tot[k] = pre[k] = 0;
-    for (int64_t u = t; u < nb; u += CB) {
+    if (nb > PF_FEW) {
+        // folded beforehand by k_part_fold: exclusive prefixes per workgroup,
+        // kind totals after them (the per-kind sums below see them in lane 0)
+        if (t == 0) {
+#pragma unroll
+            for (int k = 0; k < NK; ++k) {
+                tot[k] = cnt[nb * NK + k];
+                pre[k] = cnt[b * NK + k];
+            }
+        }
+    }
+    for (int64_t u = t; nb <= PF_FEW && u < nb; u += CB) {
         const int4 c0 = *(const int4 *)(cnt + u * NK), c1 = *(const int4 *)(cnt + u * NK + 4);
         const int c[NK] = {c0.x, c0.y, c0.z, c0.w, c1.x, c1.y, c1.z, c1.w};
 #pragma unroll
@@ -961,12 +1020,15 @@ hipError_t launch_classify(int64_t m, const int64_t *rflops, const int64_t *rflo
 // tmp: per classify workgroup and kind, three maxima and the row count (then
 // offset), int32
 // per classify workgroup: NK int4 records (maxima, count), then NK compact counts
-int64_t part_tmp_elems(int64_t m) { return (5 * ((m + CB - 1) / CB) * NK + 1) / 2 + 1; }
+// (and NK kind totals after them when k_part_fold runs)
+int64_t part_tmp_elems(int64_t m) { return (5 * ((m + CB - 1) / CB) * NK + NK + 1) / 2 + 1; }
 
 hipError_t launch_partition(int64_t m, const uint8_t *kind, int32_t *perm, const int64_t *tmp, int64_t *koff,
                             int phase, int heavy, DevStats *st, hipStream_t s) {
     const int64_t nb = (m + CB - 1) / CB;
     if (nb == 0) return hipSuccess;
+    if (nb > PF_FEW)
+        hipLaunchKernelGGL(k_part_fold, dim3(1), dim3(CB), 0, s, nb, (int32_t *)tmp + 4 * nb * NK);
     hipLaunchKernelGGL(k_part_scatter, dim3((unsigned)nb), dim3(CB), 0, s, m, nb, kind, (const int32_t *)tmp, perm,
                        koff, phase, heavy, st);
     return hipGetLastError();

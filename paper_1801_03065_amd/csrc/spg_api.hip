@@ -9,6 +9,7 @@
 //             reads nnz(C)]
 //   numeric:  one persistent launch per kind, no host synchronisation.
 #include <algorithm>
+#include <cmath>
 #include <cstdio>
 #include <cstring>
 #include <string>
@@ -67,7 +68,9 @@ struct spg_handle_s {
     int lg_num = 4;                                          // log2 lanes per B row, numeric phase
     bool tuned = false;
     DevBuf kind_tmp, perm_tmp, koff_tmp, krange, kind_heavy, perm_heavy, koff_heavy, krange_heavy, sgcur;
-    long long heavy_thr = 0;  // FP64-accumulated rows of the plan (flops at or above), 0 = none
+    bool heavy_split = false;  // the plan keeps FP64-accumulated rows in their own kind lists
+    bool verify = false;       // numeric / backward check the operands' structure fingerprint
+    StructRef sref{};          // the symbolic phase's operand structure (caller's arrays)
 
     struct Batch {
         int count = 0;
@@ -201,6 +204,30 @@ void spg_default_options(spg_options *o) {
     o->fp64_heavy_row_flops = 0;
     o->l1_hash_slots = 0;
     o->autotune = 0;
+    o->fp32_terms_max = -1;
+    o->verify_structure = 0;
+}
+
+// FP32 values: the most products one entry of C may sum in FP32 (plain or
+// compensated) and still meet |c - exact| <= 1e-5 * sum_k |a_ik * b_kj|.
+// Recursive summation of n rounded FP32 products in any order is within
+// gamma_n = n*u / (1 - n*u) of that sum (u = 2^-24); gamma_n <= 1e-5 gives
+// n <= 167.  The compensated pair (Dot2) is within u*|c| + gamma_n^2 * sum,
+// so gamma_n^2 <= 1e-5 - u gives n <= 52730.  An entry of row i sums at most
+// nnz(A(i,:)) products, so rows of A longer than the limit accumulate in FP64.
+// FP32 with FP64 accumulation needs no limit.
+static long long fp32_terms_limit(const spg_options &o) {
+    if (o.fp32_terms_max >= 0) return o.fp32_terms_max;
+    const double u = 1.0 / 16777216.0, tol = 1e-5;
+    double g;
+    if (o.fp32_mode == SPG_FP32_PLAIN)
+        g = tol;
+    else if (o.fp32_mode == SPG_FP32_COMPENSATED)
+        g = std::sqrt(tol - u);
+    else
+        return 0;
+    // largest n with n*u / (1 - n*u) <= g
+    return (long long)std::floor(g / (u * (1.0 + g)));
 }
 
 static spg_status check_options(spg_handle h, const spg_options *o) {
@@ -208,6 +235,9 @@ static spg_status check_options(spg_handle h, const spg_options *o) {
     if (!(o->cf_threshold > 0.0 && o->cf_threshold <= 1.0)) return fail(h, SPG_ERR_INVALID_ARG, "cf_threshold in (0, 1]");
     if (o->accumulator < 0 || o->accumulator > 3) return fail(h, SPG_ERR_INVALID_ARG, "bad accumulator");
     if (o->fp32_mode < 0 || o->fp32_mode > 2) return fail(h, SPG_ERR_INVALID_ARG, "bad fp32_mode");
+    if (o->verify_structure < 0 || o->verify_structure > 1)
+        return fail(h, SPG_ERR_INVALID_ARG, "verify_structure must be 0 or 1");
+    if (o->fp32_terms_max < -1) return fail(h, SPG_ERR_INVALID_ARG, "fp32_terms_max must be -1, 0 or positive");
     if (o->l1_hash_slots < 0 || (o->l1_hash_slots & (o->l1_hash_slots - 1)) != 0 ||
         (o->l1_hash_slots != 0 && o->l1_hash_slots < 8))
         return fail(h, SPG_ERR_INVALID_ARG, "l1_hash_slots must be 0 or a power of two >= 8");
@@ -401,8 +431,8 @@ static spg_status symbolic_core(spg_handle h, int64_t m, int64_t n, int64_t k, i
     const DevStats hs2 = *h->hst;
     const DevStats &hs1 = hs2;
     if (hs1.bad_input) return fail(h, SPG_ERR_INVALID_ARG, "malformed CSR: row_ptr or col_idx out of range");
-    if (hs1.bad_window)
-        return fail(h, SPG_ERR_UNSUPPORTED, "a row of B with unsorted columns spans more than 2^19 columns");
+    // (an unsorted row of B wider than the LDS bitmap of its word count makes
+    // the analysis skip compression: the structure kernels read raw B)
     const bool comp = h->opt.compression != 0 && hs1.comp != 0;
     const double fm = (double)hs1.fm, fmc = (double)hs1.fmc;
     h->avg_len = nnza ? std::max(1.0, fm / (double)nnza) : 1.0;
@@ -523,20 +553,24 @@ static spg_status symbolic_core(spg_handle h, int64_t m, int64_t n, int64_t k, i
     cp.sym_kind = h->kind_sym.as<uint8_t>();
     cp.sg = h->sg_mode ? 1 : 0;
     const long long thr = h->opt.fp64_heavy_row_flops;
-    cp.flops_lo = 0;
-    cp.flops_hi = thr > 0 ? thr : 0;
+    const long long tmax = fp32_terms_limit(h->opt);
+    const bool split = thr > 0 || tmax > 0;
+    cp.heavy_flops = thr > 0 ? thr : 0;
+    cp.heavy_alen = tmax > 0 ? tmax : 0;
+    cp.arp = arp;
+    cp.split = split ? 1 : 0;
+    cp.heavy = 0;
     HIPCHK(launch_classify(m, h->rflops.as<int64_t>(), h->rflopsc.as<int64_t>(), h->rwin.as<int2>(),
                            h->row_nnz.as<int32_t>(), h->row_words.as<int32_t>(), cp, h->kind_num.as<uint8_t>(),
                            nullptr, dst, h->tmp.as<int64_t>(), h->koff_num.as<int64_t>(), st));
     HIPCHK(launch_partition(m, h->kind_num.as<uint8_t>(), h->perm_num.as<int32_t>(), h->tmp.as<int64_t>(),
                             h->koff_num.as<int64_t>(), cp.phase, cp.heavy, dst, st));
-    if (thr > 0) {  // rows at or above the threshold: their own kind lists (FP64 accumulation in FP32 mode)
+    h->heavy_split = false;
+    if (split) {  // FP64-accumulated rows: their own kind lists (FP64 accumulation in FP32 mode)
         HIPCHK(ensure(h->kind_heavy, std::max<int64_t>(m, 1)));
         HIPCHK(ensure(h->perm_heavy, 4 * std::max<int64_t>(m, 1)));
         HIPCHK(ensure(h->koff_heavy, 8 * (NK + 1)));
         ClassParams ch = cp;
-        ch.flops_lo = thr;
-        ch.flops_hi = 0;
         ch.heavy = 1;
         HIPCHK(launch_classify(m, h->rflops.as<int64_t>(), h->rflopsc.as<int64_t>(), h->rwin.as<int2>(),
                                h->row_nnz.as<int32_t>(), h->row_words.as<int32_t>(), ch,
@@ -546,6 +580,9 @@ static spg_status symbolic_core(spg_handle h, int64_t m, int64_t n, int64_t k, i
                                 h->koff_heavy.as<int64_t>(), ch.phase, ch.heavy, dst, st));
     }
     HIPCHK(hipMemcpyAsync(h->hkoff, h->coff.as<int64_t>() + m, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    h->hkoff[2] = 0;
+    if (comp)  // pairs of compressed B: the end of its row offsets
+        HIPCHK(hipMemcpyAsync(h->hkoff + 2, h->bcrp.as<int64_t>() + n, sizeof(int64_t), hipMemcpyDeviceToHost, st));
     if ((s = pull_stats(h)) != SPG_OK) return s;  // host sync 2: nnz(C), numeric kinds
     const DevStats hs3 = *h->hst;
     if (hs3.overflow) return fail(h, SPG_ERR_OUT_OF_MEMORY, "level-2 hash arena too small in the symbolic phase");
@@ -560,6 +597,7 @@ static spg_status symbolic_core(spg_handle h, int64_t m, int64_t n, int64_t k, i
     o.max_row_flops_compressed = (int64_t)hs1.maxrfc;
     o.nnz_c = nnzc;
     o.compressed = comp ? 1 : 0;
+    o.nnz_b_compressed = comp ? h->hkoff[2] : 0;
     o.n_kinds = NK;
     int64_t maxrs = 0;
     for (int kk = 0; kk < NK; ++kk) {
@@ -569,10 +607,15 @@ static spg_status symbolic_core(spg_handle h, int64_t m, int64_t n, int64_t k, i
     }
     o.max_row_nnz = maxrs;
     o.l2_spill_rows = (int32_t)hs3.kcount_num[K_HL];
+    o.fp64_rows = 0;
+    if (split)
+        for (int kk = 1; kk < NK; ++kk) o.fp64_rows += hs3.kcount_heavy[kk];
+    if (split)
+        for (int kk = 1; kk < NK; ++kk) o.l2_spill_rows += (int32_t)(kk == K_HL ? hs3.kcount_heavy[kk] : 0);
     h->aci_used = aci;
     h->bci_used = bci;
     h->cparams = cp;
-    h->heavy_thr = thr;
+    h->heavy_split = split;
     h->lg_num = lg_group(h->avg_len);
     h->tuned = false;
     *nnzc_out = nnzc;
@@ -613,6 +656,11 @@ spg_status spgemm_symbolic(spg_handle h, const spg_csr *A, const spg_csr *B, voi
     fp.arp = A->row_ptr; fp.brp = B->row_ptr; fp.aci = A->col_idx; fp.bci = B->col_idx;
     fp.arpt = A->rp_type; fp.brpt = B->rp_type;
     h->nnzc = nnzc;
+    h->sref = StructRef{A->row_ptr, B->row_ptr, A->col_idx, B->col_idx, m, n, A->nnz, B->nnz,
+                        A->rp_type == SPG_I64, B->rp_type == SPG_I64};
+    h->verify = h->opt.verify_structure != 0;
+    if (h->verify)
+        HIPCHK(launch_struct_digest(h->sref, (unsigned long long *)h->red.p, &dst->sdigest, 0, &dst->mismatch, st));
     *nnz_c = nnzc;
     h->ready = true;
     return SPG_OK;
@@ -621,6 +669,17 @@ spg_status spgemm_symbolic(spg_handle h, const spg_csr *A, const spg_csr *B, voi
 }  // extern "C"
 
 // ------------------------------------------------------------------ numeric
+// With verify_structure: the operands' structure digest against the symbolic
+// phase's, on the device; a difference is counted as a mismatch that
+// spg_check_errors reports (no host sync here).
+static spg_status verify_struct(spg_handle h) {
+    if (!h->verify || h->batch.count) return SPG_OK;
+    DevStats *dst = h->dstats.as<DevStats>();
+    HIPCHK(launch_struct_digest(h->sref, (unsigned long long *)h->red.p, &dst->sdigest, 1, &dst->mismatch,
+                                h->stream));
+    return SPG_OK;
+}
+
 static int fp32_acc(spg_handle h) {
     return h->opt.fp32_mode == SPG_FP32_COMPENSATED ? ACC_COMP
            : h->opt.fp32_mode == SPG_FP32_WIDE      ? ACC_WIDE
@@ -854,7 +913,7 @@ static spg_status numeric_impl(spg_handle h, const VT *aval, const VT *bval, int
         na.rs.range = h->krange.as<int64_t>();
         na.cbase_row = row_begin;
         spg_status s = launch_kinds<VT>(h, na, hs.kcount_num, hs.kmax_num, acc);
-        if (s != SPG_OK || h->heavy_thr <= 0) return s;
+        if (s != SPG_OK || !h->heavy_split) return s;
         HIPCHK(ensure(h->krange_heavy, 16 * NK));
         HIPCHK(launch_kind_ranges(h->perm_heavy.as<int32_t>(), h->koff_heavy.as<int64_t>(), row_begin, row_end,
                                   h->krange_heavy.as<int64_t>(), h->stream));
@@ -871,7 +930,7 @@ static spg_status numeric_impl(spg_handle h, const VT *aval, const VT *bval, int
     na.rs.rows = h->perm_num.as<int32_t>();
     na.rs.koff = h->koff_num.as<int64_t>();
     spg_status s = launch_kinds<VT>(h, na, hs.kcount_num, hs.kmax_num, acc);
-    if (s != SPG_OK || h->heavy_thr <= 0) return s;
+    if (s != SPG_OK || !h->heavy_split) return s;
     // heaviest rows: FP64 accumulation for FP32 values (FP64 values: the same kernels)
     na.rs.rows = h->perm_heavy.as<int32_t>();
     na.rs.koff = h->koff_heavy.as<int64_t>();
@@ -896,6 +955,7 @@ extern "C" spg_status spgemm_numeric(spg_handle h, const spg_csr *A, const spg_c
     if (A->dtype != B->dtype || A->dtype != C->dtype)
         return fail(h, SPG_ERR_INVALID_ARG, "A, B and C must share one dtype");
     if (h->batch.count) return fail(h, SPG_ERR_STRUCTURE_MISMATCH, "the plan is a batch: use spgemm_batch_numeric");
+    if ((s = verify_struct(h)) != SPG_OK) return s;
     if (h->nnzc == 0) return SPG_OK;
     if (A->dtype == SPG_F64)
         return numeric_impl<double>(h, (const double *)A->values, (const double *)B->values, C->col_idx,
@@ -951,6 +1011,7 @@ extern "C" spg_status spgemm_backward(spg_handle h, const spg_csr *A, const spg_
         return fail(h, SPG_ERR_STRUCTURE_MISMATCH, "G must have the structure of C");
     if (A->dtype != B->dtype || A->dtype != G->dtype)
         return fail(h, SPG_ERR_INVALID_ARG, "A, B and G must share one dtype");
+    if ((s = verify_struct(h)) != SPG_OK) return s;
     if (A->dtype == SPG_F64) return backward_impl<double>(h, A, B, G, dA, dB);
     return backward_impl<float>(h, A, B, G, dA, dB);
 }
@@ -1159,6 +1220,7 @@ extern "C" spg_status spgemm_numeric_rows(spg_handle h, const spg_csr *A, const 
     if (A->dtype != B->dtype) return fail(h, SPG_ERR_INVALID_ARG, "A and B must share one dtype");
     if (row_begin == row_end || h->nnzc == 0) return SPG_OK;
     if (!C_col_idx || !C_values) return fail(h, SPG_ERR_INVALID_ARG, "panel arrays are NULL");
+    if ((s = verify_struct(h)) != SPG_OK) return s;
     if (A->dtype == SPG_F64)
         return numeric_impl<double>(h, (const double *)A->values, (const double *)B->values, C_col_idx,
                                     (double *)C_values, ACC_NATIVE, row_begin, row_end);

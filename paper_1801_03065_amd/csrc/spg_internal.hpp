@@ -4,6 +4,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <climits>
 #include <cstdint>
 
@@ -48,6 +49,7 @@ struct DevStats {
     int mismatch;     // numeric: row size differs from the plan
     int overflow;     // level-2 arena exhausted
     int comp;         // the analysis chose compressed B (Compression subsection rule)
+    unsigned long long sdigest;  // structure fingerprint of the symbolic phase's operands
     long long kcount_sym[NK];
     long long kcount_num[NK];
     long long kcount_heavy[NK];
@@ -358,7 +360,13 @@ struct ClassParams {
     int compressed;
     int dw_nw_max, dw_r_max, hw_keys_max, dg_nw_max, wh_nw_max, wh_r_max, wh_t_max;
     int sample_stride;  // numeric: only rows i with i % stride == 0 get a kind (others: empty)
-    long long flops_lo, flops_hi;  // numeric: only rows with flops in [lo, hi) get a kind (hi <= 0: no limit)
+    // numeric, FP64-accumulated rows: a row is "heavy" when its flops reach
+    // heavy_flops (> 0) or its A row has more than heavy_alen (> 0) entries
+    // (each entry of C then sums more than heavy_alen products); with split
+    // set only the rows on the side named by `heavy` get a kind (others: empty)
+    long long heavy_flops, heavy_alen;
+    const int64_t *arp;  // A's row offsets (int64), read when heavy_alen > 0
+    int split;
     int heavy;          // numeric: counts / maxima go to the heavy-row set
     int sr_f_max;       // selector: rows with at most this many multiplications are short rows (0: off)
     int plan_cap;       // stored row structure: pairs per row (0: off)
@@ -416,6 +424,19 @@ hipError_t launch_num_sr(const NumArgs<VT> &a, int acc, int lg_t, const LaunchCf
 size_t lds_num_wh(int ts, int nw_max, int r_max, int acc_bytes);
 template <typename VT>
 hipError_t launch_backward(const BwdArgs<VT> &a, const LaunchCfg &c);
+
+// Operand structure of one product (caller's arrays) for the fingerprint.
+struct StructRef {
+    const void *arp, *brp;
+    const int32_t *aci, *bci;
+    int64_t m, n, nnza, nnzb;
+    int arp64, brp64;
+};
+// Digest of A's and B's row pointers and columns: check = 0 stores it in
+// *ref, check = 1 compares and counts a mismatch (device-side, no host sync).
+// part: at least 1024 uint64 of scratch.
+hipError_t launch_struct_digest(const StructRef &s, unsigned long long *part, unsigned long long *ref, int check,
+                                int *mismatch, hipStream_t st);
 
 hipError_t launch_batch_struct(const BatchDesc *d, int count, int64_t max_work, int64_t *dst_rp, int32_t *dst_ci,
                                int *bad, hipStream_t s);

@@ -350,3 +350,109 @@ def test_rows_agree_with_the_whole_product():
         assert np.array_equal(ci[rp[t]:rp[t + 1]], C.col_idx[s:e])
         assert np.array_equal(va[rp[t]:rp[t + 1]], C.values[s:e])
         assert np.array_equal(ab[rp[t]:rp[t + 1]], S[s:e])
+
+
+# ---------------------------------------------------------------- column-set words (Compression subsection)
+def _run_words(c0, c1):
+    """Words of 32 columns spanned by the contiguous column run [c0, c1]."""
+    return (c1 >> 5) - (c0 >> 5) + 1
+
+
+def geometric_words_27pt(g):
+    """Column-set words per row of the 27-point operator on g^3, from grid
+    coordinates: each row reads, per neighbour line (y+dy, z+dz), the column
+    run x-1..x+1 (clipped) at offset g*(y+dy) + g^2*(z+dz).  Lines lie g > 35
+    columns apart, so no two share a word."""
+    p = np.arange(g ** 3, dtype=np.int64)
+    x, y, z = p % g, (p // g) % g, p // (g * g)
+    lo, hi = np.maximum(x - 1, 0), np.minimum(x + 1, g - 1)
+    out = np.zeros(p.size, dtype=np.int64)
+    for dz in (-1, 0, 1):
+        for dy in (-1, 0, 1):
+            ok = (y + dy >= 0) & (y + dy < g) & (z + dz >= 0) & (z + dz < g)
+            base = g * (y + dy) + g * g * (z + dz)
+            out += np.where(ok, _run_words(base + lo, base + hi), 0)
+    return out
+
+
+def geometric_words_5pt(g):
+    """The same for the 5-point operator on g^2 (g > 35): lines y-1 and y+1
+    hold one column, line y the run x-1..x+1."""
+    p = np.arange(g * g, dtype=np.int64)
+    x, y = p % g, p // g
+    lo, hi = np.maximum(x - 1, 0), np.minimum(x + 1, g - 1)
+    return (y > 0).astype(np.int64) + (y < g - 1) + _run_words(g * y + lo, g * y + hi)
+
+
+def geometric_words_ap(g):
+    """Rows of A*P (27-point operator times 2x2x2 aggregation, h = g/2 > 35
+    aggregates per line): fine point (x, y, z) reaches the aggregates of its
+    neighbours, i.e. per distinct aggregate line (Y, Z) among
+    ((y+dy)//2, (z+dz)//2) the aggregate run (x-1)//2 .. (x+1)//2 (clipped)."""
+    h = g // 2
+    p = np.arange(g ** 3, dtype=np.int64)
+    x, y, z = p % g, (p // g) % g, p // (g * g)
+    lo, hi = np.maximum(x - 1, 0) // 2, np.minimum(x + 1, g - 1) // 2
+    # distinct aggregate lines: Y in {(y-1)//2, (y+1)//2} (clipped), same for Z
+    ylo, yhi = np.maximum(y - 1, 0) // 2, np.minimum(y + 1, g - 1) // 2
+    zlo, zhi = np.maximum(z - 1, 0) // 2, np.minimum(z + 1, g - 1) // 2
+    out = np.zeros(p.size, dtype=np.int64)
+    for zsel in (0, 1):
+        for ysel in (0, 1):
+            Z = np.where(zsel == 0, zlo, zhi)
+            Y = np.where(ysel == 0, ylo, yhi)
+            ok = ((zsel == 0) | (zhi != zlo)) & ((ysel == 0) | (yhi != ylo))
+            base = h * Y + h * h * Z
+            out += np.where(ok, _run_words(base + lo, base + hi), 0)
+    return out
+
+
+def test_block_counts_27pt_geometric():
+    A = synth.stencil27(100)
+    want = geometric_words_27pt(100)
+    got = oracle.block_counts(A, 32)
+    assert np.array_equal(got, want)
+    # 9,413,224 pairs; compressed flops 250,303,600 of 704,969,000 (CF 0.355)
+    assert int(got.sum()) == 9_413_224
+    assert int(got[A.col_idx].sum()) == 250_303_600
+
+
+def test_block_counts_5pt_geometric():
+    A = synth.laplace2d_5pt(64, 64)
+    got = oracle.block_counts(A, 32)
+    assert np.array_equal(got, geometric_words_5pt(64))
+    assert int(got.sum()) == 12_288  # CF 0.607 over A*A's 100,104 flops
+    assert abs(got[A.col_idx].sum() / 100_104 - 0.607) < 5e-4
+
+
+def test_block_counts_galerkin_geometric():
+    A = synth.stencil27(100)
+    P, Pt = synth.aggregation_2x2x2(100)
+    AP = oracle.spgemm(A, P)
+    got = oracle.block_counts(AP, 32)
+    assert np.array_equal(got, geometric_words_ap(100))
+    # P^T reads every row of A*P once: compressed flops = pairs of compressed AP,
+    # f_m = nnz(A*P) = 198^3; CF 0.520
+    assert int(got[Pt.col_idx].sum()) == int(got.sum()) == 4_038_012
+    assert AP.nnz == 198 ** 3
+    assert abs(got.sum() / 198 ** 3 - 0.520) < 5e-4
+
+
+def test_block_counts_invariants():
+    rng = np.random.default_rng(5)
+    B = synth.shuffle_columns(synth.tiny_random(60, 1000, 0.05, 23), 4)
+    lens = B.row_lengths()
+    prev = oracle.block_counts(B, 1)
+    for w in (2, 4, 8, 16, 32, 64, 1000):
+        c = oracle.block_counts(B, w)
+        # at most one word per entry and at most ceil(k / w) words; coarser
+        # words never split a finer word
+        assert np.all(c <= lens) and np.all(c <= -(-1000 // w))
+        assert np.all(c <= prev)
+        assert np.all((c > 0) == (lens > 0))
+        prev = c
+    assert np.array_equal(oracle.block_counts(B, 1000), (lens > 0).astype(np.int64))
+    # a dense row of k columns has ceil(k / w) words
+    D = synth.Csr(1, 77, np.array([0, 77]), rng.permutation(77).astype(np.int32), np.ones(77))
+    for w in (1, 5, 32, 77):
+        assert oracle.block_counts(D, w)[0] == -(-77 // w)
