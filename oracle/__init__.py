@@ -11,6 +11,7 @@ Functions (each cites the passage of the paper it follows in the C source):
   spgemm(A, B, with_abs)  -> C (sorted columns) [, S]           Algorithm 1
   rows(A, B, rows)        -> selected rows of C (+ S) by the same definition
   grad(A, B, C, G)        -> (dA on pattern(A), dB on pattern(B))
+  masked(A, B, M)         -> (A*B) on pattern(M), or path counts       Background (graph analytics)
 """
 from __future__ import annotations
 
@@ -55,6 +56,8 @@ def _load():
         lib.spo_numeric.argtypes = [I, I, I, P, P, P, P, P, P, P, P, P, P]
         lib.spo_rows.restype = ctypes.c_int
         lib.spo_rows.argtypes = [I, I, I, P, P, P, P, P, P, I, P, P, P, P, P]
+        lib.spo_masked.restype = ctypes.c_int
+        lib.spo_masked.argtypes = [I, I, I, P, P, P, P, P, P, P, P, ctypes.c_int, P, P]
         lib.spo_grad.restype = ctypes.c_int
         lib.spo_grad.argtypes = [I, I, I, P, P, P, P, P, P, P, P, P, P, P]
         _lib = lib
@@ -165,3 +168,20 @@ def rows(A: Csr, B: Csr, sel):
     if rc:
         raise ValueError(f"spo_rows rc={rc}")
     return rp, ci[:nnz], va[:nnz], ab[:nnz]
+
+
+def masked(A: Csr, B: Csr, M: Csr, structural: bool = False, with_abs: bool = False):
+    """(A*B) on the stored entries of M (M's entry order); structural: path counts."""
+    _check_dims(A, B)
+    if M.nrows != A.nrows or M.ncols != B.ncols:
+        raise ValueError("mask must be A.nrows x B.ncols")
+    arp, aci, ava = _norm(A)
+    brp, bci, bva = _norm(B)
+    mrp, mci, _ = _norm(M)
+    out = np.zeros(max(M.nnz, 1))
+    ab = np.zeros(max(M.nnz, 1)) if with_abs else None
+    rc = _load().spo_masked(A.nrows, A.ncols, B.ncols, _p(arp), _p(aci), _p(ava), _p(brp), _p(bci), _p(bva),
+                            _p(mrp), _p(mci), 1 if structural else 0, _p(out), _p(ab) if with_abs else None)
+    if rc:
+        raise ValueError(f"spo_masked rc={rc}")
+    return (out[: M.nnz], ab[: M.nnz]) if with_abs else out[: M.nnz]

@@ -255,3 +255,52 @@ int spo_rows(int64_t m, int64_t n, int64_t k,
     free(mark); free(acc); free(aab); free(touched);
     return 0;
 }
+
+/* Masked product by definition (graph-analytics use of the symbolic
+ * structure, Background section; triangle counting over the compressed
+ * structure, Compression subsection): for every stored entry (i, j) of the
+ * mask M (m x k, values ignored),
+ *   out[e] = sum over stored A(i,k) with B(k,j) stored of A(i,k) * B(k,j)
+ * (0.0 when there is no such k), or, with structural != 0, the number of such
+ * k (values ignored; the count of paths i -> k -> j).  Row i of A*B is formed
+ * with the dense accumulator of spo_numeric, then read at M's columns.
+ * out_abs (nullable): sum of |A(i,k) * B(k,j)| per entry.  Returns 0 / -1 / -3. */
+int spo_masked(int64_t m, int64_t n, int64_t k,
+               const int64_t *arp, const int32_t *aci, const double *aval,
+               const int64_t *brp, const int32_t *bci, const double *bval,
+               const int64_t *mrp, const int32_t *mci, int structural,
+               double *out, double *out_abs) {
+    if (check_csr(m, n, arp, aci) || check_csr(n, k, brp, bci) || check_csr(m, k, mrp, mci)) return -1;
+    size_t kk = (size_t)(k > 0 ? k : 1);
+    int64_t *mark = (int64_t *)malloc(kk * sizeof(int64_t));
+    double *acc = (double *)malloc(kk * sizeof(double));
+    double *aab = (double *)malloc(kk * sizeof(double));
+    if (!mark || !acc || !aab) {
+        free(mark); free(acc); free(aab);
+        return -3;
+    }
+    for (int64_t j = 0; j < k; ++j) mark[j] = -1;
+    for (int64_t i = 0; i < m; ++i) {
+        for (int64_t e = arp[i]; e < arp[i + 1]; ++e) {
+            int64_t r = aci[e];
+            for (int64_t f = brp[r]; f < brp[r + 1]; ++f) {
+                int32_t j = bci[f];
+                double p = structural ? 1.0 : aval[e] * bval[f];
+                if (mark[j] != i) {
+                    mark[j] = i;
+                    acc[j] = 0.0;
+                    aab[j] = 0.0;
+                }
+                acc[j] = acc[j] + p;
+                aab[j] = aab[j] + (p < 0 ? -p : p);
+            }
+        }
+        for (int64_t e = mrp[i]; e < mrp[i + 1]; ++e) {
+            int32_t j = mci[e];
+            out[e] = mark[j] == i ? acc[j] : 0.0;
+            if (out_abs) out_abs[e] = mark[j] == i ? aab[j] : 0.0;
+        }
+    }
+    free(mark); free(acc); free(aab);
+    return 0;
+}

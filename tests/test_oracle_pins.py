@@ -456,3 +456,73 @@ def test_block_counts_invariants():
     D = synth.Csr(1, 77, np.array([0, 77]), rng.permutation(77).astype(np.int32), np.ones(77))
     for w in (1, 5, 32, 77):
         assert oracle.block_counts(D, w)[0] == -(-77 // w)
+
+
+# ---------------------------------------------------------------- masked product
+def _graph_lower(nv, edges):
+    """Strictly lower triangle L of an undirected graph's adjacency (sorted rows)."""
+    rows = [[] for _ in range(nv)]
+    for a, b in edges:
+        if a != b:
+            hi, lo = max(a, b), min(a, b)
+            if lo not in rows[hi]:
+                rows[hi].append(lo)
+    rp = np.zeros(nv + 1, dtype=np.int64)
+    rp[1:] = np.cumsum([len(r) for r in rows])
+    ci = np.array([c for r in rows for c in sorted(r)], dtype=np.int32)
+    return synth.Csr(nv, nv, rp, ci, np.ones(ci.size))
+
+
+def _triangles(nv, edges):
+    L = _graph_lower(nv, edges)
+    return float(oracle.masked(L, L, L, structural=True).sum())
+
+
+def test_masked_triangle_counts_known_graphs():
+    from itertools import combinations
+    for n in (3, 4, 7, 12):  # complete graph: C(n, 3) triangles
+        assert _triangles(n, list(combinations(range(n), 2))) == n * (n - 1) * (n - 2) / 6
+    for n in (4, 5, 9):  # wheel: hub 0 joined to a cycle of n vertices: n triangles
+        cyc = [(1 + i, 1 + (i + 1) % n) for i in range(n)]
+        assert _triangles(n + 1, cyc + [(0, 1 + i) for i in range(n)]) == n
+    outer = [(i, (i + 1) % 5) for i in range(5)]
+    spokes = [(i, i + 5) for i in range(5)]
+    inner = [(5 + i, 5 + (i + 2) % 5) for i in range(5)]
+    assert _triangles(10, outer + spokes + inner) == 0  # Petersen graph
+    assert _triangles(7, [(a, b) for a in range(3) for b in range(3, 7)]) == 0  # K_{3,4}
+    octa = [(a, b) for a, b in combinations(range(6), 2) if (a, b) not in ((0, 3), (1, 4), (2, 5))]
+    assert _triangles(6, octa) == 8  # octahedron K_{2,2,2}
+
+
+def test_masked_triangles_match_trace():
+    A = synth.rmat_symmetric(8, 8, seed=3)
+    D = (synth.to_dense(A) != 0).astype(np.float64)
+    want = np.trace(D @ D @ D) / 6
+    lower = np.tril(D, -1)
+    rr, cc = np.nonzero(lower)
+    rp = np.zeros(A.nrows + 1, dtype=np.int64)
+    np.add.at(rp, rr + 1, 1)
+    rp = np.cumsum(rp)
+    L = synth.Csr(A.nrows, A.nrows, rp, cc.astype(np.int32), np.ones(cc.size))
+    assert oracle.masked(L, L, L, structural=True).sum() == want
+
+
+@pytest.mark.parametrize("seed", range(10))
+def test_masked_brute_force(seed):
+    rng = np.random.default_rng(seed)
+    m, n, k = (int(x) for x in rng.integers(1, 30, 3))
+    A = synth.shuffle_columns(synth.tiny_random(m, n, rng.uniform(0, 0.6), seed), seed + 1)
+    B = synth.shuffle_columns(synth.tiny_random(n, k, rng.uniform(0, 0.6), seed + 2), seed + 3)
+    M = synth.shuffle_columns(synth.tiny_random(m, k, rng.uniform(0, 0.7), seed + 4), seed + 5)
+    Da, Db = synth.to_dense(A), synth.to_dense(B)
+    full = Da @ Db
+    cnt = synth.pattern_dense(A).astype(float) @ synth.pattern_dense(B).astype(float)  # stored zeros count
+    ab = np.abs(Da) @ np.abs(Db)
+    rows = np.repeat(np.arange(m), M.row_lengths())
+    got, S = oracle.masked(A, B, M, with_abs=True)
+    assert np.allclose(got, full[rows, M.col_idx], rtol=1e-13, atol=1e-13)
+    assert np.allclose(S, ab[rows, M.col_idx], rtol=1e-13, atol=1e-13)
+    assert np.array_equal(oracle.masked(A, B, M, structural=True), cnt[rows, M.col_idx])
+    # the mask equal to C's own pattern gives C's values in C's order
+    C = oracle.spgemm(A, B)
+    assert np.array_equal(oracle.masked(A, B, C), C.values)
