@@ -7,11 +7,18 @@ setup shapes on a 100^3 grid, FP64 values, int32 indices:
     R  = P^T * (A P)    the Galerkin coarse operator
 Reported `value`: whole-step GFLOP/s = 2 * sum f_m / step time (a multiply and
 an add per multiplication).  Symbolic and numeric phases are also reported
-separately per product, with achieved HBM GB/s from algorithmic bytes, and
-the numeric-only (Reuse) rate.  The `roofline` object covers the dominant
-kernel, the numeric kernel of A*A, timed with HIP events on its own stream.
+separately per product, with achieved HBM GB/s from algorithmic bytes
+(numeric: A, B and C once plus C's row pointers; symbolic: A's and B's
+structure, compressed B written and read once, C's row pointers), the
+compression factors CF (compressed / raw flops) and CMRF (the same for the
+longest row), the numeric-only (Reuse) rate and the rate on the known
+structure (position maps, values only).  The `roofline` object covers the
+dominant kernel, the numeric kernel of A*A, timed with HIP events on its own
+stream.  `forms` holds the other workloads (bench_forms.py): the 5-point
+latency case, R-MAT precision forms, the 512-product batch and the backward.
+Inputs of every workload are built on the host before the first GPU call.
 
-    python bench.py [--gpus 1] [--steps 5] [--warmup 1] [--no-cpu]
+    python bench.py [--gpus 1] [--steps 5] [--warmup 1] [--no-cpu] [--forms c1,precision,batch,backward]
 """
 from __future__ import annotations
 
@@ -81,9 +88,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--grid", type=int, default=100)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--forms", default="", help="comma list of extra forms: precision,batch,backward")
-    ap.add_argument("--rmat-scale", type=int, default=16)
-    ap.add_argument("--batch-count", type=int, default=64)
+    ap.add_argument("--forms", default="c1,precision,batch,backward",
+                    help="comma list of extra workloads: c1,precision,batch,backward ('' for none)")
+    ap.add_argument("--rmat-scale", type=int, default=20)
+    ap.add_argument("--batch-count", type=int, default=512)
     ap.add_argument("--diff-grid", type=int, default=64)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -91,17 +99,25 @@ def main():
               "the library runs one product per GPU and has no multi-GPU sharding", file=sys.stderr)
         sys.exit(2)
 
-    import torch
-
-    import paper_1801_03065_amd as spg
     import synth
+    import bench_forms
 
-    torch.cuda.set_device(0)
-    dev = torch.device("cuda:0")
     g = args.grid
     log(f"[bench] building inputs, grid {g}^3")
     A = synth.stencil27(g)
     P, Pt = synth.aggregation_2x2x2(g)
+    forms = [f for f in args.forms.split(",") if f]
+    form_data = {}
+    for f in forms:  # host-side inputs (and oracle samples) before any GPU call
+        log(f"[bench] preparing {f}")
+        form_data[f] = bench_forms.FORMS[f][0](args)
+
+    import torch
+
+    import paper_1801_03065_amd as spg
+
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda:0")
 
     def to_dev(M):
         return spg.DeviceCsr.from_arrays(M.nrows, M.ncols, M.row_ptr, M.col_idx, M.values)
@@ -185,21 +201,26 @@ def main():
         handles[k].check_errors()
     ms_per_step = (t1 - t0) * 1e3 / args.steps
 
-    # Reuse case: numeric phase only, same structure (timed separately)
-    reuse_ms = {}
+    # Reuse case: numeric phase only, same structure (timed separately), then
+    # on the known structure (position maps taken at the first call, values only)
+    reuse_ms, values_ms = {}, {}
     for k in names:
         L, R, rp, nnz, C = last[k]
         h = handles[k]
-        ts = []
-        for _ in range(args.steps):
-            a, b = events()
-            a.record(stream)
-            spg.spgemm_numeric(h, L, R, rp, nnz, out=C)
-            b.record(stream)
-            ts.append((a, b))
-        torch.cuda.synchronize()
-        h.check_errors()
-        reuse_ms[k] = float(np.mean([a.elapsed_time(b) for a, b in ts]))
+        for dst, fn in ((reuse_ms, lambda: spg.spgemm_numeric(h, L, R, rp, nnz, out=C)),
+                        (values_ms, lambda: spg.spgemm_numeric_values(h, L, R, C))):
+            fn()
+            torch.cuda.synchronize()
+            ts = []
+            for _ in range(args.steps):
+                a, b = events()
+                a.record(stream)
+                fn()
+                b.record(stream)
+                ts.append((a, b))
+            torch.cuda.synchronize()
+            h.check_errors()
+            dst[k] = float(np.mean([a.elapsed_time(b) for a, b in ts]))
 
     stats = {k: handles[k].stats() for k in names}
     fm = {k: stats[k]["flops"] for k in names}
@@ -218,18 +239,29 @@ def main():
         rb = csr_bytes(R) if R is not None else ap_bytes
         rstruct = (4 * (R.nrows + 1) + 4 * R.nnz) if R is not None else (4 * (P.nrows + 1) + 4 * nnz_ap)
         num_bytes = csr_bytes(L) + rb + 4 * (m + 1) + 12 * nnzc
-        nnzbc = stats[k]["flops_compressed"]
-        sym_bytes = (4 * (L.nrows + 1) + 4 * L.nnz) + rstruct + 4 * (m + 1)
+        # numeric on the known structure: A and B values, A's structure, C's values
+        rvals = (8 * R.nnz) if R is not None else 8 * nnz_ap
+        val_bytes = csr_bytes(L) + rvals + 4 * (m + 1) + 8 * nnzc
+        # compressed B: one (word, bits) record per pair plus its int64 row offsets
+        nbr = R.nrows if R is not None else P.nrows
+        bc_bytes = (8 * stats[k]["nnz_b_compressed"] + 8 * (nbr + 1)) if stats[k]["compressed"] else 0
+        sym_bytes = (4 * (L.nrows + 1) + 4 * L.nnz) + rstruct + 2 * bc_bytes + 4 * (m + 1)
         tsym = float(np.mean([a.elapsed_time(b) for a, b in rec[k]["sym"]]))
         tnum = float(np.mean([a.elapsed_time(b) for a, b in rec[k]["num"]]))
         phases[k] = {
             "flops_m": fm[k], "nnz_c": nnzc, "compressed": bool(stats[k]["compressed"]),
+            "cf": round(stats[k]["flops_compressed"] / max(1, fm[k]), 4),
+            "cmrf": round(stats[k]["max_row_flops_compressed"] / max(1, stats[k]["max_row_flops"]), 4),
+            "nnz_b_compressed": stats[k]["nnz_b_compressed"],
             "symbolic_ms": round(tsym, 4), "numeric_ms": round(tnum, 4), "reuse_numeric_ms": round(reuse_ms[k], 4),
+            "values_numeric_ms": round(values_ms[k], 4),
+            "values_hbm_gbps": round(val_bytes / (values_ms[k] * 1e-3) / 1e9, 1),
             "symbolic_gflops": round(2 * fm[k] / (tsym * 1e-3) / 1e9, 2),
             "numeric_gflops": round(2 * fm[k] / (tnum * 1e-3) / 1e9, 2),
             "numeric_hbm_gbps": round(num_bytes / (tnum * 1e-3) / 1e9, 1),
             "numeric_alg_bytes": int(num_bytes),
             "symbolic_hbm_gbps": round(sym_bytes / (tsym * 1e-3) / 1e9, 1),
+            "symbolic_alg_bytes": int(sym_bytes),
             "rows_numeric": {kk: v for kk, v in stats[k]["rows_numeric"].items() if v},
         }
 
@@ -261,7 +293,8 @@ def main():
         tc = (time.perf_counter() - t) / reps
         cpu = {"value": round(2 * total_fm / tc / 1e9, 3), "unit": "GFLOP/s", "cores": 1, "kind": "oracle",
                "sample": f"the full step (A*A, A*P, P^T*(AP) on 100^3, both phases), {reps} repetitions, "
-                         f"{tc:.2f} s each on one host core"}
+                         f"{tc:.2f} s each on one host core",
+               "cpu_model": bench_forms.cpu_model(), "host_threads": bench_forms.host_threads()}
 
     value = 2 * total_fm / (ms_per_step * 1e-3) / 1e9
     out = {
@@ -279,14 +312,14 @@ def main():
     }
     for k in names:
         handles[k].close()
-    forms = [f for f in args.forms.split(",") if f]
+    del last
+    torch.cuda.empty_cache()
     if forms:
-        import bench_forms
-
         out["forms"] = {}
         for f in forms:
             log(f"[bench] form {f}")
-            out["forms"][f] = getattr(bench_forms, f)(args, log)
+            out["forms"][f] = bench_forms.FORMS[f][1](args, form_data.pop(f), log)
+            torch.cuda.empty_cache()
     print(json.dumps(out), flush=True)
 
 

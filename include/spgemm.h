@@ -64,7 +64,13 @@ typedef enum {
     SPG_ACC_AUTO = 0,   /* per-row choice by the library's selector */
     SPG_ACC_DENSE = 1,  /* bit-window dense accumulator where it fits, else hash */
     SPG_ACC_HASH = 2,   /* linear-probing hash (LDS level 1, HBM level 2) */
-    SPG_ACC_HASH_L2 = 3 /* two-level hash for every non-empty row (tests the spill path) */
+    SPG_ACC_HASH_L2 = 3, /* two-level hash for every non-empty row (tests the spill path) */
+    SPG_ACC_LL = 4       /* the paper's kkmem choice: linked-list hashmap (Begins / Nexts /
+                            Ids / Values) per row, a group of lanes per row walking its B
+                            rows in turn (Thread-Sequential); rows of up to 1024 entries come
+                            out UNSORTED (slot order); longer rows use the two-level hash,
+                            sorted.  Position maps (spgemm_numeric_values) and
+                            spgemm_backward need sorted rows and are not available. */
 } spg_accumulator;
 
 /* Floating-point forms of the numeric phase for FP32 values. */
@@ -126,6 +132,9 @@ typedef struct {
                                      a difference is reported by spg_check_errors as
                                      STRUCTURE_MISMATCH.  0 = pointers and sizes are
                                      the only check.  Not applied to batch plans. */
+    int32_t sorted_output;        /* 1 (default) = columns strictly increasing per row;
+                                     0 = rows may come out unsorted: the autotuner
+                                     (autotune = 1) also times the LL hashmap */
 } spg_options;
 
 typedef struct {
@@ -147,7 +156,8 @@ typedef struct {
     int64_t rows_symbolic[8];       /* rows per symbolic kernel kind */
     int64_t rows_numeric[8];        /* rows per numeric kernel kind */
     int32_t l2_spill_rows;          /* rows that used the level-2 (HBM) hash */
-    int32_t tuned_policy;           /* autotune: 0 selector, 1 bit window first, 2 hash first */
+    int32_t tuned_policy;           /* autotune: 0 selector, 1 bit window first, 2 hash first,
+                                       4 LL hashmap (unsorted rows) */
     int32_t tuned_lanes;            /* autotune: lanes per B row in the numeric phase (0 = not tuned) */
     int32_t fp64_rows;              /* rows kept in the FP64-accumulated kind lists
                                        (fp64_heavy_row_flops, fp32_terms_max) */
@@ -195,6 +205,21 @@ spg_status spgemm_symbolic(spg_handle h, const spg_csr *A, const spg_csr *B,
  * OUT_OF_MEMORY, HIP. */
 spg_status spgemm_numeric(spg_handle h, const spg_csr *A, const spg_csr *B, spg_csr_out *C);
 
+/* Numeric phase on a known structure (the Reuse case: symbolic once, numeric
+ * repeated with new values).  Same arguments and errors as spgemm_numeric,
+ * but C->col_idx must already hold the columns an earlier spgemm_numeric on
+ * this plan wrote (the same array contents; the pointer may differ): only
+ * C->values is written.  The first call on a plan takes, from those columns,
+ * a position map -- the rank in its row of C of every multiplication of the
+ * rows in wavefront and team kinds (16 bits each) -- which blocks the host
+ * once and allocates 2 bytes per such multiplication; later calls add every
+ * product at its rank with no hashing or sorting.  Rows of the stored-
+ * structure kind skip their column writes; heavy rows run their full kernels
+ * (their columns are rewritten unchanged).  If the map cannot be allocated
+ * the call runs the full numeric phase.  A C whose columns were changed since
+ * is reported by spg_check_errors (STRUCTURE_MISMATCH) at the first call. */
+spg_status spgemm_numeric_values(spg_handle h, const spg_csr *A, const spg_csr *B, spg_csr_out *C);
+
 /* Batched symbolic phase of `count` independent products C_i = A_i * B_i
  * (host arrays A[count], B[count] of device operands; C_row_ptr[count] of
  * device arrays of A_i.nrows+1 entries of c_rp_type; nnz_c[count] on the
@@ -216,6 +241,24 @@ spg_status spgemm_batch_symbolic(spg_handle h, int32_t count, const spg_csr *A, 
 spg_status spgemm_batch_numeric(spg_handle h, int32_t count, const spg_csr *A, const spg_csr *B,
                                 spg_csr_out *C);
 
+/* spgemm_batch_numeric on a known structure (see spgemm_numeric_values): the
+ * C_i must lie back to back in one allocation (the zero-copy layout) and hold
+ * the columns an earlier spgemm_batch_numeric wrote; only values are written.
+ * With any other layout the call runs spgemm_batch_numeric. */
+spg_status spgemm_batch_numeric_values(spg_handle h, int32_t count, const spg_csr *A, const spg_csr *B,
+                                       spg_csr_out *C);
+
+/* Per-product choices of a batch plan (host arrays of `count`): the
+ * accumulator policy (spg_accumulator; SPG_ACC_AUTO = the selector) and the
+ * lanes per B row the numeric phase uses for C_i.  With autotune = 1 the
+ * first spgemm_batch_numeric groups the products by the average row size of
+ * C_i (at most 16, 128, 1024 entries, more) and times the candidates per
+ * group on sampled rows, so products of different shapes can get different
+ * choices; each group then has its own row lists and LDS sizing.  Without
+ * tuning every product reports the plan's one choice.  Errors: INVALID_ARG,
+ * NOT_READY (no batch plan). */
+spg_status spg_batch_choices(spg_handle h, int32_t count, int32_t *policy, int32_t *lanes);
+
 /* Backward of C = A * B restricted to the stored entries (differentiation
  * of the numeric phase: each multiplication A(i,k)*B(k,j) of Algorithm 1
  * contributes G(i,j)*B(k,j) to dA(i,k) and A(i,k)*G(i,j) to dB(k,j)):
@@ -229,6 +272,22 @@ spg_status spgemm_batch_numeric(spg_handle h, int32_t count, const spg_csr *A, c
  * reported by spg_check_errors as STRUCTURE_MISMATCH). */
 spg_status spgemm_backward(spg_handle h, const spg_csr *A, const spg_csr *B, const spg_csr *G,
                            void *dA_values, void *dB_values);
+
+/* Masked product (graph analytics on the product's structure, Background
+ * section; triangle counting, Compression subsection): for every stored
+ * entry (i, j) of the mask M (m x k, values not read),
+ *     out[e] = sum over k with A(i,k) and B(k,j) stored of A(i,k) * B(k,j)
+ * (0 where no such k exists), or with structural = 1 the NUMBER of such k
+ * (values of A and B not read, may be NULL): e.g. with A = B = M = L, the
+ * strictly lower triangle of a graph's adjacency, out sums to the graph's
+ * triangle count.  out: device array of M.nnz entries of A's dtype, in M's
+ * entry order (M's rows may be unsorted, without duplicate columns).  FP32
+ * inputs are accumulated in FP64 and rounded once.  No symbolic phase is
+ * needed and the handle's plan is left as it was.  Blocks the host (twice:
+ * to size the launches and to report malformed input).  Errors:
+ * INVALID_ARG (malformed CSR, bad dtype), DIM_MISMATCH, OUT_OF_MEMORY, HIP. */
+spg_status spgemm_masked(spg_handle h, const spg_csr *A, const spg_csr *B, const spg_csr *M, void *out,
+                         int structural);
 
 /* Synchronise the handle's stream and report errors the device found since
  * the last check: STRUCTURE_MISMATCH if a numeric call met a row whose size

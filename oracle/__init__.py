@@ -12,6 +12,7 @@ Functions (each cites the passage of the paper it follows in the C source):
   rows(A, B, rows)        -> selected rows of C (+ S) by the same definition
   grad(A, B, C, G)        -> (dA on pattern(A), dB on pattern(B))
   masked(A, B, M)         -> (A*B) on pattern(M), or path counts       Background (graph analytics)
+  rows_check(...)         -> compares candidate rows with the definition (comparison helper)
 """
 from __future__ import annotations
 
@@ -56,6 +57,9 @@ def _load():
         lib.spo_numeric.argtypes = [I, I, I, P, P, P, P, P, P, P, P, P, P]
         lib.spo_rows.restype = ctypes.c_int
         lib.spo_rows.argtypes = [I, I, I, P, P, P, P, P, P, I, P, P, P, P, P]
+        lib.spo_rows_check.restype = ctypes.c_int
+        lib.spo_rows_check.argtypes = [I, I, I, P, P, P, P, P, P, I, P, P, P, P, ctypes.c_double, ctypes.c_int,
+                                       P, I, P, I, P]
         lib.spo_masked.restype = ctypes.c_int
         lib.spo_masked.argtypes = [I, I, I, P, P, P, P, P, P, P, P, ctypes.c_int, P, P]
         lib.spo_grad.restype = ctypes.c_int
@@ -185,3 +189,27 @@ def masked(A: Csr, B: Csr, M: Csr, structural: bool = False, with_abs: bool = Fa
     if rc:
         raise ValueError(f"spo_masked rc={rc}")
     return (out[: M.nnz], ab[: M.nnz]) if with_abs else out[: M.nnz]
+
+
+def rows_check(A: Csr, B: Csr, sel, grp, gci, gval, tol: float, rel_mode: int, stride: int = 101,
+               sub_cap: int = 1 << 20):
+    """Compare candidate rows (grp offsets over `sel`, columns gci, values gval as
+    float64) with the definition; returns dict(max_rel_S, bad, entries, bad_rows,
+    sub = sampled |g-c|/S).  A comparison helper of the tests, not a method."""
+    _check_dims(A, B)
+    arp, aci, ava = _norm(A)
+    brp, bci, bva = _norm(B)
+    sel = np.ascontiguousarray(sel, dtype=np.int64)
+    grp = np.ascontiguousarray(grp, dtype=np.int64)
+    gci = np.ascontiguousarray(gci, dtype=np.int32)
+    gval = np.ascontiguousarray(gval, dtype=np.float64)
+    stats = np.zeros(4)
+    sub = np.zeros(max(sub_cap, 1), dtype=np.float32)
+    ns = ctypes.c_int64(0)
+    rc = _load().spo_rows_check(A.nrows, A.ncols, B.ncols, _p(arp), _p(aci), _p(ava), _p(brp), _p(bci), _p(bva),
+                                sel.shape[0], _p(sel), _p(grp), _p(gci), _p(gval), tol, rel_mode, _p(stats),
+                                stride, _p(sub), sub_cap, ctypes.byref(ns))
+    if rc:
+        raise ValueError(f"spo_rows_check rc={rc}")
+    return {"max_rel_S": float(stats[0]), "bad": int(stats[1]), "entries": int(stats[2]),
+            "bad_rows": int(stats[3]), "sub": sub[: ns.value]}

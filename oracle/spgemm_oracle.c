@@ -304,3 +304,83 @@ int spo_masked(int64_t m, int64_t n, int64_t k,
     free(mark); free(acc); free(aab);
     return 0;
 }
+
+/* Comparison helper for large products (test infrastructure, not part of
+ * the definition): for each selected row rows[s] of C = A * B, form the row
+ * by the definition above (dense accumulator, sorted columns) and compare it
+ * with a candidate row given as (gci, gval) at offsets grp[s] .. grp[s+1]:
+ * columns must be identical; each value must satisfy
+ *   |g - c| <= tol * max(|c|, S)   (rel_mode 0)   or   |g - c| <= tol * S  (rel_mode 1)
+ * with S = sum |A(i,k) * B(k,j)|.  stats[0] = max |g - c| / S over entries
+ * (S > 0), stats[1] = entries over the bound, stats[2] = entries compared,
+ * stats[3] = rows whose columns differ.  Every `stride`-th entry's |g - c| / S
+ * goes to sub[] (capacity sub_cap; *nsub counts them) for a median.
+ * Returns 0, or -1 / -3. */
+int spo_rows_check(int64_t m, int64_t n, int64_t k,
+                   const int64_t *arp, const int32_t *aci, const double *aval,
+                   const int64_t *brp, const int32_t *bci, const double *bval,
+                   int64_t nsel, const int64_t *rows,
+                   const int64_t *grp, const int32_t *gci, const double *gval,
+                   double tol, int rel_mode, double *stats,
+                   int64_t stride, float *sub, int64_t sub_cap, int64_t *nsub) {
+    if (check_csr(m, n, arp, aci) || check_csr(n, k, brp, bci)) return -1;
+    size_t kk = (size_t)(k > 0 ? k : 1);
+    int64_t *mark = (int64_t *)malloc(kk * sizeof(int64_t));
+    double *acc = (double *)malloc(kk * sizeof(double));
+    double *aab = (double *)malloc(kk * sizeof(double));
+    int32_t *touched = (int32_t *)malloc(kk * sizeof(int32_t));
+    if (!mark || !acc || !aab || !touched) {
+        free(mark); free(acc); free(aab); free(touched);
+        return -3;
+    }
+    for (int64_t j = 0; j < k; ++j) mark[j] = -1;
+    double mx = 0.0, bad = 0.0, cnt = 0.0, badrows = 0.0;
+    int64_t ns = 0, seen = 0;
+    for (int64_t s = 0; s < nsel; ++s) {
+        int64_t i = rows[s];
+        if (i < 0 || i >= m) { free(mark); free(acc); free(aab); free(touched); return -1; }
+        int64_t nt = 0;
+        for (int64_t e = arp[i]; e < arp[i + 1]; ++e) {
+            int64_t r = aci[e];
+            double a = aval[e];
+            for (int64_t f = brp[r]; f < brp[r + 1]; ++f) {
+                int32_t j = bci[f];
+                double p = a * bval[f];
+                if (mark[j] != s) {
+                    mark[j] = s;
+                    acc[j] = 0.0;
+                    aab[j] = 0.0;
+                    touched[nt++] = j;
+                }
+                acc[j] = acc[j] + p;
+                aab[j] = aab[j] + (p < 0 ? -p : p);
+            }
+        }
+        qsort(touched, (size_t)nt, sizeof(int32_t), cmp_i32);
+        int64_t g0 = grp[s], gn = grp[s + 1] - grp[s];
+        int same = gn == nt;
+        for (int64_t t = 0; same && t < nt; ++t) same = gci[g0 + t] == touched[t];
+        if (!same) { badrows += 1.0; continue; }
+        for (int64_t t = 0; t < nt; ++t) {
+            int32_t j = touched[t];
+            double c = acc[j], S = aab[j], g = gval[g0 + t];
+            double d = g - c;
+            if (d < 0) d = -d;
+            double ac = c < 0 ? -c : c;
+            double bound = tol * (rel_mode == 0 ? (ac > S ? ac : S) : S);
+            if (d > bound) bad += 1.0;
+            double rel = S > 0 ? d / S : 0.0;
+            if (rel > mx) mx = rel;
+            cnt += 1.0;
+            if (stride > 0 && (seen % stride) == 0 && ns < sub_cap) sub[ns++] = (float)rel;
+            ++seen;
+        }
+    }
+    stats[0] = mx;
+    stats[1] = bad;
+    stats[2] = cnt;
+    stats[3] = badrows;
+    *nsub = ns;
+    free(mark); free(acc); free(aab); free(touched);
+    return 0;
+}

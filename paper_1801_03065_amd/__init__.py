@@ -46,7 +46,7 @@ SPG_ERR_OUT_OF_MEMORY, SPG_ERR_NOT_READY, SPG_ERR_STRUCTURE_MISMATCH = 4, 5, 6
 SPG_ERR_HIP, SPG_ERR_UNSUPPORTED, SPG_ERR_INTERNAL = 7, 8, 9
 SPG_F64, SPG_F32 = 0, 1
 SPG_I32, SPG_I64 = 0, 1
-ACC_AUTO, ACC_DENSE, ACC_HASH, ACC_HASH_L2 = 0, 1, 2, 3
+ACC_AUTO, ACC_DENSE, ACC_HASH, ACC_HASH_L2, ACC_LL = 0, 1, 2, 3, 4
 FP32_PLAIN, FP32_COMPENSATED, FP32_WIDE = 0, 1, 2
 KIND_NAMES = ("empty", "dense_wave", "hash_wave", "dense_wg", "hash_two_level", "word_hash_wave", "short_rows",
               "planned_wave")
@@ -67,7 +67,7 @@ class spg_options(ctypes.Structure):
                 ("accumulator", ctypes.c_int32), ("fp32_mode", ctypes.c_int32),
                 ("fp64_heavy_row_flops", ctypes.c_int64), ("l1_hash_slots", ctypes.c_int32),
                 ("autotune", ctypes.c_int32), ("fp32_terms_max", ctypes.c_int32),
-                ("verify_structure", ctypes.c_int32)]
+                ("verify_structure", ctypes.c_int32), ("sorted_output", ctypes.c_int32)]
 
 
 class spg_stats(ctypes.Structure):
@@ -92,6 +92,12 @@ _sigs = {
     "spgemm_symbolic": (_S, [_P, ctypes.POINTER(spg_csr), ctypes.POINTER(spg_csr), _P, _S,
                              ctypes.POINTER(ctypes.c_int64)]),
     "spgemm_numeric": (_S, [_P, ctypes.POINTER(spg_csr), ctypes.POINTER(spg_csr), ctypes.POINTER(spg_csr_out)]),
+    "spgemm_numeric_values": (_S, [_P, ctypes.POINTER(spg_csr), ctypes.POINTER(spg_csr), ctypes.POINTER(spg_csr_out)]),
+    "spgemm_batch_numeric_values": (_S, [_P, ctypes.c_int32, ctypes.POINTER(spg_csr), ctypes.POINTER(spg_csr),
+                                         ctypes.POINTER(spg_csr_out)]),
+    "spgemm_masked": (_S, [_P, ctypes.POINTER(spg_csr), ctypes.POINTER(spg_csr), ctypes.POINTER(spg_csr), _P,
+                           ctypes.c_int]),
+    "spg_batch_choices": (_S, [_P, ctypes.c_int32, _P, _P]),
     "spg_check_errors": (_S, [_P]),
     "spgemm_numeric_rows": (_S, [_P, ctypes.POINTER(spg_csr), ctypes.POINTER(spg_csr), ctypes.c_int64,
                                  ctypes.c_int64, _P, _P]),
@@ -230,6 +236,17 @@ class Handle:
         d["rows_numeric"] = dict(zip(KIND_NAMES, list(st.rows_numeric)[:st.n_kinds]))
         return d
 
+    def batch_choices(self, count: int):
+        """Per product of the batch plan: (accumulator policy, lanes per B row)."""
+        import numpy as np
+
+        pol = np.zeros(count, dtype=np.int32)
+        lanes = np.zeros(count, dtype=np.int32)
+        rc = lib().spg_batch_choices(self._h, count, pol.ctypes.data_as(_P), lanes.ctypes.data_as(_P))
+        if rc != SPG_OK:
+            self._raise(rc)
+        return pol, lanes
+
     def check_errors(self):
         rc = lib().spg_check_errors(self._h)
         if rc != SPG_OK:
@@ -273,6 +290,21 @@ def spgemm_numeric(h: Handle, A: DeviceCsr, B: DeviceCsr, C_row_ptr: torch.Tenso
                     out.values.data_ptr() if out.nnz else None, _dtype(out.values))
     a, b = _csr(A), _csr(B)
     rc = lib().spgemm_numeric(h.ptr, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c))
+    if rc != SPG_OK:
+        h._raise(rc)
+    return out
+
+
+def spgemm_numeric_values(h: Handle, A: DeviceCsr, B: DeviceCsr, out: DeviceCsr) -> DeviceCsr:
+    """spgemm_numeric_values: new values on a known structure; out.col_idx must hold the
+    columns an earlier spgemm_numeric on this plan wrote, only out.values is written."""
+    if A.values is None or B.values is None:
+        raise ValueError("numeric phase needs values")
+    c = spg_csr_out(out.nrows, out.ncols, out.nnz, _itype(out.row_ptr), out.row_ptr.data_ptr(),
+                    out.col_idx.data_ptr() if out.nnz else None,
+                    out.values.data_ptr() if out.nnz else None, _dtype(out.values))
+    a, b = _csr(A), _csr(B)
+    rc = lib().spgemm_numeric_values(h.ptr, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c))
     if rc != SPG_OK:
         h._raise(rc)
     return out
@@ -404,6 +436,22 @@ def spgemm_batch_numeric(h: Handle, As: list, Bs: list, Cs: list):
                                         C.values.data_ptr() if C.nnz else None, _dtype(C.values))
                             for C in Cs])
     rc = lib().spgemm_batch_numeric(h.ptr, n, a, b, c)
+    if rc != SPG_OK:
+        h._raise(rc)
+    return Cs
+
+
+def spgemm_batch_numeric_values(h: Handle, As: list, Bs: list, Cs: list):
+    """spgemm_batch_numeric_values: new values on the batch's known structure (Cs back to
+    back, holding the columns an earlier spgemm_batch_numeric wrote)."""
+    n = len(As)
+    a = (spg_csr * n)(*[_csr(M) for M in As])
+    b = (spg_csr * n)(*[_csr(M) for M in Bs])
+    c = (spg_csr_out * n)(*[spg_csr_out(C.nrows, C.ncols, C.nnz, _itype(C.row_ptr), C.row_ptr.data_ptr(),
+                                        C.col_idx.data_ptr() if C.nnz else None,
+                                        C.values.data_ptr() if C.nnz else None, _dtype(C.values))
+                            for C in Cs])
+    rc = lib().spgemm_batch_numeric_values(h.ptr, n, a, b, c)
     if rc != SPG_OK:
         h._raise(rc)
     return Cs

@@ -500,6 +500,7 @@ __global__ __launch_bounds__(CB) void k_classify(int64_t m, const int64_t *rflop
         const bool valid = i < m;
         const bool sampled = p.sample_stride <= 1 || (i % p.sample_stride) == 0;
         long long f = (valid && sampled) ? rflops[i] : 0;
+        if (p.phase == 1 && p.row_cls && valid && p.row_cls[i] != p.cls) f = 0;
         if (p.phase == 1 && p.split && f > 0) {
             const bool hv = (p.heavy_flops > 0 && f >= p.heavy_flops) ||
                             (p.heavy_alen > 0 && p.arp[i + 1] - p.arp[i] > p.heavy_alen);
@@ -526,6 +527,7 @@ __global__ __launch_bounds__(CB) void k_classify(int64_t m, const int64_t *rflop
                     k = dw_fit ? K_DW : (dg_fit ? K_DG : (hw_fit ? K_HW : K_HL));
                     break;
                 case 2:  // hash
+                case 4:  // LL hashmap (numeric: hash-wave rows run the LL kernel)
                     k = hw_fit ? K_HW : K_HL;
                     break;
                 case 3:  // two-level hash everywhere

@@ -70,6 +70,23 @@ struct spg_handle_s {
     DevBuf kind_tmp, perm_tmp, koff_tmp, krange, kind_heavy, perm_heavy, koff_heavy, krange_heavy, sgcur;
     bool heavy_split = false;  // the plan keeps FP64-accumulated rows in their own kind lists
     bool verify = false;       // numeric / backward check the operands' structure fingerprint
+    DevBuf mflops, map_off, map;  // reuse: per-row mapped multiplications, map offsets, ranks
+    DevBuf mk_arp, mk_brp, mk_mrp, mk_rows, mk_cnt, mk_arena;  // masked product
+    bool maps_built = false;      // position maps taken for this plan (maps_ok: they exist)
+    long long kc_nomap[NK] = {};  // scratch: kind counts with the mapped kinds removed
+    bool maps_ok = false;
+    bool values_only = false;  // the current call writes C's values only (structure known)
+    int num_policy = 0;        // accumulator policy of the numeric classification (SPG_ACC_*)
+    // batch plans: products fall into classes by the average row size of C_i,
+    // and the autotuner picks (policy, lanes per B row) per class; each class
+    // then has its own classification, row lists and LDS sizing
+    int ncls = 0;              // 0: one launch set for the whole plan
+    bool cls_tuned = false;
+    int cls_rows[4] = {}, cls_lg[4] = {}, cls_pol[4] = {};
+    double cls_avg_b[4] = {};  // average B row length of the class's products
+    long long cls_kc[4][NK] = {};
+    int cls_km[4][NK][3] = {};
+    DevBuf row_cls, kind_cls, perm_cls, koff_cls;
     StructRef sref{};          // the symbolic phase's operand structure (caller's arrays)
 
     struct Batch {
@@ -206,6 +223,7 @@ void spg_default_options(spg_options *o) {
     o->autotune = 0;
     o->fp32_terms_max = -1;
     o->verify_structure = 0;
+    o->sorted_output = 1;
 }
 
 // FP32 values: the most products one entry of C may sum in FP32 (plain or
@@ -233,7 +251,8 @@ static long long fp32_terms_limit(const spg_options &o) {
 static spg_status check_options(spg_handle h, const spg_options *o) {
     if (o->compression < -1 || o->compression > 1) return fail(h, SPG_ERR_INVALID_ARG, "compression must be -1, 0 or 1");
     if (!(o->cf_threshold > 0.0 && o->cf_threshold <= 1.0)) return fail(h, SPG_ERR_INVALID_ARG, "cf_threshold in (0, 1]");
-    if (o->accumulator < 0 || o->accumulator > 3) return fail(h, SPG_ERR_INVALID_ARG, "bad accumulator");
+    if (o->accumulator < 0 || o->accumulator > 4) return fail(h, SPG_ERR_INVALID_ARG, "bad accumulator");
+    if (o->sorted_output < 0 || o->sorted_output > 1) return fail(h, SPG_ERR_INVALID_ARG, "sorted_output must be 0 or 1");
     if (o->fp32_mode < 0 || o->fp32_mode > 2) return fail(h, SPG_ERR_INVALID_ARG, "bad fp32_mode");
     if (o->verify_structure < 0 || o->verify_structure > 1)
         return fail(h, SPG_ERR_INVALID_ARG, "verify_structure must be 0 or 1");
@@ -289,7 +308,9 @@ spg_status spg_destroy(spg_handle h) {
     DevBuf *bufs[] = {&h->arp64, &h->brp64, &h->binfo, &h->ulist, &h->uflag, &h->bcrp, &h->bcw,
                       &h->rflops, &h->rflopsc, &h->rwin, &h->row_nnz, &h->coff, &h->kind_sym, &h->kind_num,
                       &h->perm_sym, &h->perm_num, &h->koff_sym, &h->koff_num, &h->tmp, &h->dstats, &h->red, &h->queue, &h->plan_len, &h->plan_off, &h->plan,
-                      &h->arena, &h->l2k, &h->l2v, &h->blens, &h->row_words, &h->kind_tmp, &h->perm_tmp, &h->koff_tmp, &h->krange, &h->kind_heavy, &h->perm_heavy, &h->koff_heavy, &h->krange_heavy, &h->sgcur};
+                      &h->arena, &h->l2k, &h->l2v, &h->blens, &h->row_words, &h->kind_tmp, &h->perm_tmp, &h->koff_tmp, &h->krange, &h->kind_heavy, &h->perm_heavy, &h->koff_heavy, &h->krange_heavy, &h->sgcur, &h->mflops, &h->map_off, &h->map,
+                      &h->mk_arp, &h->mk_brp, &h->mk_mrp, &h->mk_rows, &h->mk_cnt, &h->mk_arena,
+                      &h->row_cls, &h->kind_cls, &h->perm_cls, &h->koff_cls};
     for (DevBuf *b : bufs) release(*b);
     if (h->hst) (void)hipHostFree(h->hst);
     if (h->hkoff) (void)hipHostFree(h->hkoff);
@@ -357,6 +378,23 @@ static spg_status plan_buffers(spg_handle h, int64_t m, int64_t n, int64_t nnzb)
     HIPCHK(ensure(h->tmp, 8 * tmp_elems));
 
     return SPG_OK;
+}
+
+// Rows per numeric kind: the main lists plus, when the plan keeps FP64-
+// accumulated rows apart, their lists (whose rows the main classification
+// counted as empty).  main: per-kind counts of the main lists (nullptr: the
+// device statistics' numeric counts).
+static void rows_numeric_stats(spg_stats &o, const DevStats &hs, bool split, const long long *main) {
+    if (!main) main = hs.kcount_num;
+    long long heavy = 0;
+    for (int kk = 0; kk < NK; ++kk) {
+        o.rows_numeric[kk] = main[kk];
+        if (split && kk != K_EMPTY) {
+            o.rows_numeric[kk] += hs.kcount_heavy[kk];
+            heavy += hs.kcount_heavy[kk];
+        }
+    }
+    o.rows_numeric[K_EMPTY] -= heavy;
 }
 
 // The symbolic phase on validated, device-resident structure: h->arp64 (m+1),
@@ -554,7 +592,8 @@ static spg_status symbolic_core(spg_handle h, int64_t m, int64_t n, int64_t k, i
     cp.sg = h->sg_mode ? 1 : 0;
     const long long thr = h->opt.fp64_heavy_row_flops;
     const long long tmax = fp32_terms_limit(h->opt);
-    const bool split = thr > 0 || tmax > 0;
+    // (no separate lists unless some row of A is longer than the term limit)
+    const bool split = thr > 0 || (tmax > 0 && (long long)hs1.maxnnza > tmax);
     cp.heavy_flops = thr > 0 ? thr : 0;
     cp.heavy_alen = tmax > 0 ? tmax : 0;
     cp.arp = arp;
@@ -602,22 +641,23 @@ static spg_status symbolic_core(spg_handle h, int64_t m, int64_t n, int64_t k, i
     int64_t maxrs = 0;
     for (int kk = 0; kk < NK; ++kk) {
         o.rows_symbolic[kk] = hs3.kcount_sym[kk];
-        o.rows_numeric[kk] = hs3.kcount_num[kk];
         if (kk != K_EMPTY) maxrs = std::max<int64_t>(maxrs, hs3.kmax_num[kk][1]);
+        if (kk != K_EMPTY && split) maxrs = std::max<int64_t>(maxrs, hs3.kmax_heavy[kk][1]);
     }
+    rows_numeric_stats(h->stats, hs3, split, nullptr);
     o.max_row_nnz = maxrs;
-    o.l2_spill_rows = (int32_t)hs3.kcount_num[K_HL];
+    o.l2_spill_rows = (int32_t)o.rows_numeric[K_HL];
     o.fp64_rows = 0;
     if (split)
         for (int kk = 1; kk < NK; ++kk) o.fp64_rows += hs3.kcount_heavy[kk];
-    if (split)
-        for (int kk = 1; kk < NK; ++kk) o.l2_spill_rows += (int32_t)(kk == K_HL ? hs3.kcount_heavy[kk] : 0);
     h->aci_used = aci;
     h->bci_used = bci;
     h->cparams = cp;
     h->heavy_split = split;
     h->lg_num = lg_group(h->avg_len);
     h->tuned = false;
+    h->maps_built = h->maps_ok = false;
+    h->num_policy = h->opt.accumulator;
     *nnzc_out = nnzc;
     return SPG_OK;
 }
@@ -634,6 +674,7 @@ spg_status spgemm_symbolic(spg_handle h, const spg_csr *A, const spg_csr *B, voi
     if (A->ncols != B->nrows) return fail(h, SPG_ERR_DIM_MISMATCH, "A.ncols != B.nrows");
     h->ready = false;
     h->batch.count = 0;
+    h->ncls = 0;
     const int64_t m = A->nrows, n = B->nrows, k = B->ncols;
     hipStream_t st = h->stream;
     if ((s = plan_buffers(h, m, n, B->nnz)) != SPG_OK) return s;
@@ -692,17 +733,30 @@ static int fp32_acc(spg_handle h) {
 // One persistent launch per non-empty kind, sized by the kind's maxima.
 template <typename VT>
 static spg_status launch_kinds(spg_handle h, NumArgs<VT> na, const long long *kcount, const int (*kmax)[3],
-                               int acc) {
+                               int acc, bool vo = false, int pol = -1) {
+    if (pol < 0) pol = h->num_policy;
     hipStream_t st = h->stream;
     const size_t sbytes = (sizeof(VT) == 8 || acc != ACC_NATIVE) ? 8 : 4;
     LaunchCfg lc{st, 0, h->cus};
     auto grid_cap = [&](int64_t rows) { return (int)std::min<int64_t>(2048 * 8, ((rows + 7) / 8) * 8); };
 
+    na.values_only = vo ? 1 : 0;
     if (kcount[K_PL] > 0) {
         na.rs.kind = K_PL;
         na.nw_max = ((kmax[K_PL][0] + 31) / 32) * 32;
         na.r_max = std::max(kmax[K_PL][1], 1);
         HIPCHK(launch_num_pl<VT>(na, acc, lc));
+    }
+    if (vo && h->maps_ok) {  // structure known: every mapped kind on its position maps
+        for (int K : {K_SR, K_DW, K_WH, K_HW}) {
+            if (kcount[K] <= 0) continue;
+            na.rs.kind = K;
+            na.r_max = std::max(kmax[K][1], 1);
+            const int lgt = K == K_SR ? sr_lg(kmax[K_SR][1]) : 6;
+            HIPCHK(launch_num_map<VT>(na, acc, lgt, h->lg_num, lc, kcount[K]));
+        }
+        for (int kk = 0; kk < NK; ++kk) h->kc_nomap[kk] = map_kind(kk) ? 0 : kcount[kk];
+        kcount = h->kc_nomap;  // the remaining kinds below
     }
     if (kcount[K_SR] > 0) {
         na.rs.kind = K_SR;
@@ -721,7 +775,12 @@ static spg_status launch_kinds(spg_handle h, NumArgs<VT> na, const long long *kc
         na.ts = pow2_at_least(2 * (int64_t)std::max(kmax[K_WH][2], 1), 16);
         HIPCHK(launch_num_wh<VT>(na, acc, lc));
     }
-    if (kcount[K_HW] > 0) {
+    if (kcount[K_HW] > 0 && pol == SPG_ACC_LL) {  // LL hashmap, rows unsorted
+        na.rs.kind = K_HW;
+        na.r_max = std::max(kmax[K_HW][1], 1);
+        na.ts = pow2_at_least(na.r_max, 16);
+        HIPCHK(launch_num_ll<VT>(na, acc, na.lg_gs, lc, kcount[K_HW]));
+    } else if (kcount[K_HW] > 0) {
         na.rs.kind = K_HW;
         na.ts = pow2_at_least(2 * (int64_t)kmax[K_HW][1], 64);
         HIPCHK(launch_num_hw<VT>(na, acc, lc));
@@ -738,7 +797,8 @@ static spg_status launch_kinds(spg_handle h, NumArgs<VT> na, const long long *kc
         const int64_t mxa = (int64_t)h->hst->maxnnza;
         if (mxa > WG_BIG) {
             const int cap = (int)std::min<int64_t>(mxa, 65536);
-            if (ensure(h->sgcur, (size_t)lc.grid * 2 * cap * sizeof(int32_t)) == hipSuccess) {
+            const size_t bytes = (size_t)lc.grid * 2 * cap * sizeof(int32_t);
+            if (ensure(h->sgcur, bytes) == hipSuccess) {
                 na.sg_cur = h->sgcur.as<int32_t>();
                 na.sg_cap = cap;
             }
@@ -809,8 +869,14 @@ static spg_status autotune(spg_handle h, NumArgs<VT> na, int acc) {
     const int base = lg_group(h->avg_len);
     spg_status s = SPG_OK;
     const size_t koff_bytes = offsetof(DevStats, kcount_num);
-    for (int pol = 0; pol < 3 && s == SPG_OK; ++pol) {
+    // candidates: selector, bit window first, column hash first, and with
+    // unsorted rows allowed the LL hashmap (its classification is the hash
+    // policy's; the hash-wave rows then run the LL kernel)
+    const int npol = h->opt.sorted_output ? 3 : 4;
+    for (int ci = 0; ci < npol && s == SPG_OK; ++ci) {
+        const int pol = ci < 3 ? ci : SPG_ACC_LL;
         cp.accumulator = pol;
+        h->num_policy = pol;
         HIPCHK(hipMemsetAsync((char *)dst + koff_bytes, 0, sizeof(long long) * NK, st));
         HIPCHK(hipMemsetAsync(&dst->kmax_num[0][0], 0, sizeof(dst->kmax_num), st));
         HIPCHK(launch_classify(m, h->rflops.as<int64_t>(), h->rflopsc.as<int64_t>(), h->rwin.as<int2>(),
@@ -848,9 +914,13 @@ static spg_status autotune(spg_handle h, NumArgs<VT> na, int acc) {
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    if (s != SPG_OK) return s;
+    if (s != SPG_OK) {
+        h->num_policy = h->opt.accumulator;
+        return s;
+    }
     // final classification of every row with the winner
     cp.accumulator = best_pol;
+    h->num_policy = best_pol;
     cp.sample_stride = 1;
     HIPCHK(hipMemsetAsync((char *)dst + koff_bytes, 0, sizeof(long long) * NK, st));
     HIPCHK(hipMemsetAsync(&dst->kmax_num[0][0], 0, sizeof(dst->kmax_num), st));
@@ -864,13 +934,132 @@ static spg_status autotune(spg_handle h, NumArgs<VT> na, int acc) {
     h->tuned = true;
     h->stats.tuned_policy = best_pol;
     h->stats.tuned_lanes = 1 << best_lg;
-    for (int kk = 0; kk < NK; ++kk) h->stats.rows_numeric[kk] = h->hst->kcount_num[kk];
+    rows_numeric_stats(h->stats, *h->hst, h->heavy_split, nullptr);
+    return SPG_OK;
+}
+
+// Batch plans with product classes: the same measured selection per class.
+// For class c the candidates are timed on a strided sample of the class's
+// rows (other rows classified empty), lanes per B row centred on the class's
+// average B row length; the winner classifies the class's rows into their own
+// row lists (kinds, counts and maxima per class, so LDS is sized by the
+// class's largest rows, not the batch's).  Blocks the host; once per plan.
+template <typename VT>
+static spg_status autotune_classes(spg_handle h, NumArgs<VT> na, int acc) {
+    hipStream_t st = h->stream;
+    const int64_t m = h->fp.m;
+    DevStats *dst = h->dstats.as<DevStats>();
+    HIPCHK(ensure(h->kind_tmp, std::max<int64_t>(m, 1)));
+    HIPCHK(ensure(h->perm_tmp, 4 * std::max<int64_t>(m, 1)));
+    HIPCHK(ensure(h->koff_tmp, 8 * (NK + 1)));
+    HIPCHK(ensure(h->kind_cls, 4 * std::max<int64_t>(m, 1)));
+    HIPCHK(ensure(h->perm_cls, 16 * std::max<int64_t>(m, 1)));
+    HIPCHK(ensure(h->koff_cls, 8 * 4 * (NK + 1)));
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    const size_t koff_bytes = offsetof(DevStats, kcount_num);
+    spg_status s = SPG_OK;
+    const int npol = h->opt.sorted_output ? 3 : 4;
+    for (int c = 0; c < 4 && s == SPG_OK; ++c) {
+        for (int k = 0; k < NK; ++k) {
+            h->cls_kc[c][k] = 0;
+            h->cls_km[c][k][0] = h->cls_km[c][k][1] = h->cls_km[c][k][2] = 0;
+        }
+        h->cls_pol[c] = h->cparams.accumulator;
+        h->cls_lg[c] = lg_group(h->cls_avg_b[c]);
+        if (h->cls_rows[c] == 0) continue;
+        ClassParams cp = h->cparams;
+        cp.phase = 1;
+        cp.row_cls = h->row_cls.as<uint8_t>();
+        cp.cls = c;
+        cp.sample_stride = (int)std::max<int64_t>(1, std::min<int64_t>(16, h->cls_rows[c] / 16384));
+        float best = 3.4e38f;
+        int best_pol = cp.accumulator, best_lg = h->cls_lg[c];
+        const int base = lg_group(h->cls_avg_b[c]);
+        for (int ci = 0; ci < npol && s == SPG_OK; ++ci) {
+            const int pol = ci < 3 ? ci : SPG_ACC_LL;
+            cp.accumulator = pol;
+            HIPCHK(hipMemsetAsync((char *)dst + koff_bytes, 0, sizeof(long long) * NK, st));
+            HIPCHK(hipMemsetAsync(&dst->kmax_num[0][0], 0, sizeof(dst->kmax_num), st));
+            HIPCHK(launch_classify(m, h->rflops.as<int64_t>(), h->rflopsc.as<int64_t>(), h->rwin.as<int2>(),
+                                   h->row_nnz.as<int32_t>(), h->row_words.as<int32_t>(), cp,
+                                   h->kind_tmp.as<uint8_t>(), nullptr, dst, h->tmp.as<int64_t>(),
+                                   h->koff_tmp.as<int64_t>(), st));
+            HIPCHK(launch_partition(m, h->kind_tmp.as<uint8_t>(), h->perm_tmp.as<int32_t>(), h->tmp.as<int64_t>(),
+                                    h->koff_tmp.as<int64_t>(), cp.phase, cp.heavy, dst, st));
+            if ((s = pull_stats(h)) != SPG_OK) break;
+            const DevStats hs = *h->hst;
+            na.rs.rows = h->perm_tmp.as<int32_t>();
+            na.rs.koff = h->koff_tmp.as<int64_t>();
+            for (int lg = std::max(2, base - 1); lg <= std::min(6, base + 1); ++lg) {
+                na.lg_gs = lg;
+                float ms = 0;
+                HIPCHK(hipEventRecord(e0, st));
+                if ((s = launch_kinds<VT>(h, na, hs.kcount_num, hs.kmax_num, acc, false, pol)) != SPG_OK) break;
+                HIPCHK(hipEventRecord(e1, st));
+                HIPCHK(hipEventSynchronize(e1));
+                HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+                if (ms > 4.0f * best) break;
+                HIPCHK(hipEventRecord(e0, st));
+                if ((s = launch_kinds<VT>(h, na, hs.kcount_num, hs.kmax_num, acc, false, pol)) != SPG_OK) break;
+                HIPCHK(hipEventRecord(e1, st));
+                HIPCHK(hipEventSynchronize(e1));
+                HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+                if (ms < best) {
+                    best = ms;
+                    best_pol = pol;
+                    best_lg = lg;
+                }
+            }
+        }
+        if (s != SPG_OK) break;
+        // the class's rows with its winner, into its own lists
+        cp.accumulator = best_pol;
+        cp.sample_stride = 1;
+        uint8_t *kc = h->kind_cls.as<uint8_t>() + (size_t)c * m;
+        int32_t *pc = h->perm_cls.as<int32_t>() + (size_t)c * m;
+        int64_t *oc = h->koff_cls.as<int64_t>() + (size_t)c * (NK + 1);
+        HIPCHK(hipMemsetAsync((char *)dst + koff_bytes, 0, sizeof(long long) * NK, st));
+        HIPCHK(hipMemsetAsync(&dst->kmax_num[0][0], 0, sizeof(dst->kmax_num), st));
+        HIPCHK(launch_classify(m, h->rflops.as<int64_t>(), h->rflopsc.as<int64_t>(), h->rwin.as<int2>(),
+                               h->row_nnz.as<int32_t>(), h->row_words.as<int32_t>(), cp, kc, nullptr, dst,
+                               h->tmp.as<int64_t>(), oc, st));
+        HIPCHK(launch_partition(m, kc, pc, h->tmp.as<int64_t>(), oc, cp.phase, cp.heavy, dst, st));
+        if ((s = pull_stats(h)) != SPG_OK) break;
+        for (int k = 0; k < NK; ++k) {
+            h->cls_kc[c][k] = h->hst->kcount_num[k];
+            for (int f = 0; f < 3; ++f) h->cls_km[c][k][f] = h->hst->kmax_num[k][f];
+        }
+        h->cls_pol[c] = best_pol;
+        h->cls_lg[c] = best_lg;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (s != SPG_OK) return s;
+    // every row's kind in one array (position maps read it)
+    HIPCHK(launch_kind_merge(m, h->row_cls.as<uint8_t>(), h->kind_cls.as<uint8_t>(), h->kind_num.as<uint8_t>(), st));
+    h->cls_tuned = true;
+    h->tuned = true;
+    int major = 0;
+    for (int c = 1; c < 4; ++c)
+        if (h->cls_rows[c] > h->cls_rows[major]) major = c;
+    h->stats.tuned_policy = h->cls_pol[major];
+    h->stats.tuned_lanes = 1 << h->cls_lg[major];
+    long long tot[NK] = {};
+    for (int kk = 0; kk < NK; ++kk)
+        for (int c = 0; c < 4; ++c) tot[kk] += h->cls_kc[c][kk];
+    // every classified class's list counts the other classes' rows as empty
+    int used = 0;
+    for (int c = 0; c < 4; ++c) used += h->cls_rows[c] > 0;
+    tot[K_EMPTY] -= (long long)(used - 1) * h->fp.m;
+    rows_numeric_stats(h->stats, *h->hst, h->heavy_split, tot);
     return SPG_OK;
 }
 
 template <typename VT>
 static spg_status numeric_impl(spg_handle h, const VT *aval, const VT *bval, int32_t *cci, VT *cval, int acc,
-                               int64_t row_begin = -1, int64_t row_end = -1) {
+                               int64_t row_begin = -1, int64_t row_end = -1, bool vo = false) {
     hipStream_t st = h->stream;
     DevStats &hs = *h->hst;
     NumArgs<VT> na{};
@@ -922,23 +1111,37 @@ static spg_status numeric_impl(spg_handle h, const VT *aval, const VT *bval, int
         na.rs.range = h->krange_heavy.as<int64_t>();
         return launch_kinds<VT>(h, na, hs.kcount_heavy, hs.kmax_heavy, sizeof(VT) == 4 ? ACC_WIDE : acc);
     }
-    if (h->opt.autotune && !h->tuned) {
-        spg_status s = autotune<VT>(h, na, acc);
+    if (h->opt.autotune && !h->tuned && !vo) {
+        spg_status s = h->ncls ? autotune_classes<VT>(h, na, acc) : autotune<VT>(h, na, acc);
         if (s != SPG_OK) return s;
         na.lg_gs = h->lg_num;
     }
-    na.rs.rows = h->perm_num.as<int32_t>();
-    na.rs.koff = h->koff_num.as<int64_t>();
-    spg_status s = launch_kinds<VT>(h, na, hs.kcount_num, hs.kmax_num, acc);
+    if (vo && h->maps_ok) {
+        na.map_off = h->map_off.as<int64_t>();
+        na.map = h->map.as<uint16_t>();
+    }
+    spg_status s = SPG_OK;
+    if (h->ncls && h->cls_tuned) {  // one launch set per product class
+        for (int c = 0; c < 4 && s == SPG_OK; ++c) {
+            if (h->cls_rows[c] == 0) continue;
+            na.rs.rows = h->perm_cls.as<int32_t>() + (size_t)c * h->fp.m;
+            na.rs.koff = h->koff_cls.as<int64_t>() + (size_t)c * (NK + 1);
+            na.lg_gs = h->cls_lg[c];
+            s = launch_kinds<VT>(h, na, h->cls_kc[c], h->cls_km[c], acc, vo, h->cls_pol[c]);
+        }
+        na.lg_gs = h->lg_num;
+    } else {
+        na.rs.rows = h->perm_num.as<int32_t>();
+        na.rs.koff = h->koff_num.as<int64_t>();
+        s = launch_kinds<VT>(h, na, hs.kcount_num, hs.kmax_num, acc, vo);
+    }
     if (s != SPG_OK || !h->heavy_split) return s;
     // heaviest rows: FP64 accumulation for FP32 values (FP64 values: the same kernels)
     na.rs.rows = h->perm_heavy.as<int32_t>();
     na.rs.koff = h->koff_heavy.as<int64_t>();
-    return launch_kinds<VT>(h, na, hs.kcount_heavy, hs.kmax_heavy, sizeof(VT) == 4 ? ACC_WIDE : acc);
+    return launch_kinds<VT>(h, na, hs.kcount_heavy, hs.kmax_heavy, sizeof(VT) == 4 ? ACC_WIDE : acc, vo);
 }
-extern "C" spg_status spgemm_numeric(spg_handle h, const spg_csr *A, const spg_csr *B, spg_csr_out *C) {
-    if (!h) return SPG_ERR_INVALID_ARG;
-    h->err.clear();
+static spg_status numeric_check(spg_handle h, const spg_csr *A, const spg_csr *B, spg_csr_out *C) {
     if (!h->ready) return fail(h, SPG_ERR_NOT_READY, "spgemm_numeric before a successful spgemm_symbolic");
     spg_status s;
     if ((s = check_csr(h, A, "A", true)) != SPG_OK) return s;
@@ -955,16 +1158,205 @@ extern "C" spg_status spgemm_numeric(spg_handle h, const spg_csr *A, const spg_c
     if (A->dtype != B->dtype || A->dtype != C->dtype)
         return fail(h, SPG_ERR_INVALID_ARG, "A, B and C must share one dtype");
     if (h->batch.count) return fail(h, SPG_ERR_STRUCTURE_MISMATCH, "the plan is a batch: use spgemm_batch_numeric");
-    if ((s = verify_struct(h)) != SPG_OK) return s;
-    if (h->nnzc == 0) return SPG_OK;
-    if (A->dtype == SPG_F64)
-        return numeric_impl<double>(h, (const double *)A->values, (const double *)B->values, C->col_idx,
-                                    (double *)C->values, ACC_NATIVE);
-    return numeric_impl<float>(h, (const float *)A->values, (const float *)B->values, C->col_idx,
-                               (float *)C->values, fp32_acc(h));
+    return SPG_OK;
 }
 
+static spg_status numeric_entry(spg_handle h, const spg_csr *A, const spg_csr *B, spg_csr_out *C) {
+    spg_status s;
+    if ((s = numeric_check(h, A, B, C)) != SPG_OK) return s;
+    if ((s = verify_struct(h)) != SPG_OK) return s;
+    if (h->nnzc == 0) return SPG_OK;
+    const bool vo = h->values_only;
+    if (A->dtype == SPG_F64)
+        return numeric_impl<double>(h, (const double *)A->values, (const double *)B->values, C->col_idx,
+                                    (double *)C->values, ACC_NATIVE, -1, -1, vo);
+    return numeric_impl<float>(h, (const float *)A->values, (const float *)B->values, C->col_idx,
+                               (float *)C->values, fp32_acc(h), -1, -1, vo);
+}
 
+extern "C" spg_status spgemm_numeric(spg_handle h, const spg_csr *A, const spg_csr *B, spg_csr_out *C) {
+    if (!h) return SPG_ERR_INVALID_ARG;
+    h->err.clear();
+    return numeric_entry(h, A, B, C);
+}
+
+// ------------------------------------------------------------------ reuse maps
+// Position maps of the plan (Reuse case): for the rows of the wavefront and
+// team kinds, the rank in C's row of every multiplication, from C's sorted
+// columns cci (written by an earlier numeric call on this plan).  Sizes come
+// from a scan of the mapped rows' multiplications (one host sync); if the
+// maps cannot be allocated, reuse calls run the full numeric kernels.
+static spg_status build_maps(spg_handle h, const int32_t *cci) {
+    hipStream_t st = h->stream;
+    const int64_t m = h->fp.m;
+    h->maps_built = true;
+    h->maps_ok = false;
+    if (h->num_policy == SPG_ACC_LL) return SPG_OK;  // ranks need sorted rows: the full kernels run
+    if (h->ncls && h->cls_tuned)
+        for (int c = 0; c < 4; ++c)
+            if (h->cls_rows[c] && h->cls_pol[c] == SPG_ACC_LL) return SPG_OK;
+    HIPCHK(ensure(h->mflops, 4 * std::max<int64_t>(m, 1)));
+    HIPCHK(ensure(h->map_off, 8 * (m + 1)));
+    HIPCHK(launch_map_rows(m, h->kind_num.as<uint8_t>(), h->heavy_split ? h->kind_heavy.as<uint8_t>() : nullptr,
+                           h->rflops.as<int64_t>(), h->mflops.as<int32_t>(), st));
+    HIPCHK(launch_scan_i32(m, h->mflops.as<int32_t>(), h->map_off.as<int64_t>(), h->tmp.as<int64_t>(), st));
+    HIPCHK(hipMemcpyAsync(h->hkoff + 3, h->map_off.as<int64_t>() + m, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    const int64_t total = h->hkoff[3];
+    if (total == 0) return SPG_OK;
+    if (ensure(h->map, 2 * (size_t)total) != hipSuccess) {
+        (void)hipGetLastError();
+        return SPG_OK;
+    }
+    const DevStats &hs = *h->hst;
+    NumArgs<double> na{};
+    na.arp = h->arp64.as<int64_t>();
+    na.aci = h->aci_used;
+    na.brp = h->brp64.as<int64_t>();
+    na.bci = h->bci_used;
+    na.coff = h->coff.as<int64_t>();
+    na.map_off = h->map_off.as<int64_t>();
+    na.map = h->map.as<uint16_t>();
+    na.st = h->dstats.as<DevStats>();
+    LaunchCfg lc{st, 0, h->cus};
+    auto kinds = [&](const int32_t *perm, const int64_t *koff, const long long *kcount, const int (*kmax)[3]) {
+        na.rs.rows = perm;
+        na.rs.koff = koff;
+        for (int K : {K_SR, K_DW, K_WH, K_HW}) {
+            if (kcount[K] <= 0) continue;
+            na.rs.kind = K;
+            const int lgt = K == K_SR ? sr_lg(kmax[K_SR][1]) : 6;
+            hipError_t e = launch_posmap(na, cci, lgt, h->lg_num, lc, kcount[K]);
+            if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
+    };
+    if (h->ncls && h->cls_tuned) {
+        for (int c = 0; c < 4; ++c) {
+            if (h->cls_rows[c] == 0) continue;
+            HIPCHK(kinds(h->perm_cls.as<int32_t>() + (size_t)c * m, h->koff_cls.as<int64_t>() + (size_t)c * (NK + 1),
+                         h->cls_kc[c], h->cls_km[c]));
+        }
+    } else {
+        HIPCHK(kinds(h->perm_num.as<int32_t>(), h->koff_num.as<int64_t>(), hs.kcount_num, hs.kmax_num));
+    }
+    if (h->heavy_split)
+        HIPCHK(kinds(h->perm_heavy.as<int32_t>(), h->koff_heavy.as<int64_t>(), hs.kcount_heavy, hs.kmax_heavy));
+    h->maps_ok = true;
+    return SPG_OK;
+}
+
+extern "C" spg_status spgemm_numeric_values(spg_handle h, const spg_csr *A, const spg_csr *B, spg_csr_out *C) {
+    if (!h) return SPG_ERR_INVALID_ARG;
+    h->err.clear();
+    if (!h->ready) return fail(h, SPG_ERR_NOT_READY, "spgemm_numeric_values before a successful spgemm_symbolic");
+    if (h->batch.count) return fail(h, SPG_ERR_STRUCTURE_MISMATCH, "the plan is a batch: use spgemm_batch_numeric_values");
+    spg_status s = numeric_check(h, A, B, C);
+    if (s != SPG_OK) return s;
+    if (!h->maps_built && h->nnzc > 0 && (s = build_maps(h, C->col_idx)) != SPG_OK) return s;
+    h->values_only = true;
+    s = numeric_entry(h, A, B, C);
+    h->values_only = false;
+    return s;
+}
+
+extern "C" spg_status spg_batch_choices(spg_handle h, int32_t count, int32_t *policy, int32_t *lanes) {
+    if (!h || !policy || !lanes) return SPG_ERR_INVALID_ARG;
+    h->err.clear();
+    if (!h->ready || h->batch.count == 0) return fail(h, SPG_ERR_NOT_READY, "no batch plan");
+    if (count != h->batch.count) return fail(h, SPG_ERR_INVALID_ARG, "count differs from the batch");
+    for (int i = 0; i < count; ++i) {
+        const int c = h->batch.a[i].cls;
+        const bool per_cls = h->ncls && h->cls_tuned;
+        policy[i] = per_cls ? h->cls_pol[c] : h->num_policy;
+        lanes[i] = 1 << (per_cls ? h->cls_lg[c] : h->lg_num);
+    }
+    return SPG_OK;
+}
+
+// ------------------------------------------------------------------ masked
+template <typename VT>
+static spg_status masked_impl(spg_handle h, const spg_csr *A, const spg_csr *B, const spg_csr *M, VT *out,
+                              int structural) {
+    hipStream_t st = h->stream;
+    const int64_t m = A->nrows, n = B->nrows, k = B->ncols;
+    HIPCHK(ensure(h->mk_arp, 8 * (m + 1)));
+    HIPCHK(ensure(h->mk_brp, 8 * (n + 1)));
+    HIPCHK(ensure(h->mk_mrp, 8 * (m + 1)));
+    HIPCHK(ensure(h->mk_rows, 8 * std::max<int64_t>(m, 1)));
+    HIPCHK(ensure(h->mk_cnt, 8 * sizeof(int)));
+    int *cnt = h->mk_cnt.as<int>();  // [0..1] rows per kind, [2..3] longest mask row per kind, [4] bad input
+    int32_t *rows1 = h->mk_rows.as<int32_t>(), *rows2 = rows1 + m;
+    HIPCHK(launch_fill_i32(cnt, 8, 0, st));
+    HIPCHK(launch_copy_rp(m + 1, A->row_ptr, A->rp_type == SPG_I64, A->nnz, h->mk_arp.as<int64_t>(), n + 1,
+                          B->row_ptr, B->rp_type == SPG_I64, B->nnz, h->mk_brp.as<int64_t>(), cnt + 4, st));
+    HIPCHK(launch_copy_rp(m + 1, M->row_ptr, M->rp_type == SPG_I64, M->nnz, h->mk_mrp.as<int64_t>(), 0, nullptr, 0,
+                          0, nullptr, cnt + 4, st));
+    if (M->nnz > 0) HIPCHK(launch_fill_i32((int32_t *)out, M->nnz * (int64_t)(sizeof(VT) / 4), 0, st));
+    HIPCHK(launch_mask_class(m, h->mk_arp.as<int64_t>(), h->mk_mrp.as<int64_t>(), MW_MAX, rows1, rows2, cnt, st));
+    int *hc = (int *)(h->hkoff + 8);
+    HIPCHK(hipMemcpyAsync(hc, cnt, 5 * sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (hc[4]) return fail(h, SPG_ERR_INVALID_ARG, "malformed CSR: row_ptr out of range or not monotone");
+    MaskArgs<VT> a{};
+    a.arp = h->mk_arp.as<int64_t>();
+    a.aci = A->col_idx;
+    a.aval = structural ? nullptr : (const VT *)A->values;
+    a.brp = h->mk_brp.as<int64_t>();
+    a.bci = B->col_idx;
+    a.bval = structural ? nullptr : (const VT *)B->values;
+    a.mrp = h->mk_mrp.as<int64_t>();
+    a.mci = M->col_idx;
+    a.out = out;
+    a.n = n;
+    a.k = k;
+    a.lg_gs = lg_group(n ? std::max(1.0, (double)B->nnz / (double)n) : 1.0);
+    a.structural = structural;
+    a.bad = cnt + 4;
+    LaunchCfg lc{st, 0, h->cus};
+    if (hc[0] > 0) {
+        a.rows = rows1;
+        a.nrows = hc[0];
+        int lg = 4;
+        while ((1 << lg) < 2 * hc[2]) ++lg;
+        HIPCHK(launch_mask_w<VT>(a, lg, hc[2], lc));
+    }
+    if (hc[1] > 0) {
+        a.rows = rows2;
+        a.nrows = hc[1];
+        a.arena_cap = pow2_at_least(2 * (int64_t)hc[3], 64);
+        int grid = (int)std::min<int64_t>(((hc[1] + 7) / 8) * 8, 2 * (int64_t)h->cus);
+        HIPCHK(ensure(h->mk_arena, (size_t)12 * a.arena_cap * grid));
+        a.arena = h->mk_arena.p;
+        lc.grid = grid;
+        HIPCHK(launch_mask_g<VT>(a, lc));
+    }
+    HIPCHK(hipMemcpyAsync(hc + 4, cnt + 4, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (hc[4] & 1) return fail(h, SPG_ERR_INVALID_ARG, "malformed CSR: a column index out of range");
+    if (hc[4]) return fail(h, SPG_ERR_INTERNAL, "masked product: arena too small");
+    return SPG_OK;
+}
+
+extern "C" spg_status spgemm_masked(spg_handle h, const spg_csr *A, const spg_csr *B, const spg_csr *M, void *out,
+                                    int structural) {
+    if (!h) return SPG_ERR_INVALID_ARG;
+    h->err.clear();
+    spg_status s;
+    const bool vals = structural == 0;
+    if (structural != 0 && structural != 1) return fail(h, SPG_ERR_INVALID_ARG, "structural must be 0 or 1");
+    if ((s = check_csr(h, A, "A", vals)) != SPG_OK) return s;
+    if ((s = check_csr(h, B, "B", vals)) != SPG_OK) return s;
+    if ((s = check_csr(h, M, "M", false)) != SPG_OK) return s;
+    if (A->ncols != B->nrows) return fail(h, SPG_ERR_DIM_MISMATCH, "A.ncols != B.nrows");
+    if (M->nrows != A->nrows || M->ncols != B->ncols) return fail(h, SPG_ERR_DIM_MISMATCH, "M must be A.nrows x B.ncols");
+    if (A->dtype != SPG_F64 && A->dtype != SPG_F32) return fail(h, SPG_ERR_INVALID_ARG, "bad dtype");
+    if (vals && B->dtype != A->dtype) return fail(h, SPG_ERR_INVALID_ARG, "A and B must share one dtype");
+    if (M->nnz > 0 && !out) return fail(h, SPG_ERR_INVALID_ARG, "out is NULL");
+    if (M->nnz == 0) return SPG_OK;
+    if (A->dtype == SPG_F64) return masked_impl<double>(h, A, B, M, (double *)out, structural);
+    return masked_impl<float>(h, A, B, M, (float *)out, structural);
+}
 
 // ------------------------------------------------------------------ backward
 template <typename VT>
@@ -1002,6 +1394,9 @@ extern "C" spg_status spgemm_backward(spg_handle h, const spg_csr *A, const spg_
     if ((s = check_csr(h, A, "A", true)) != SPG_OK) return s;
     if ((s = check_csr(h, B, "B", true)) != SPG_OK) return s;
     if ((s = check_csr(h, G, "G", true)) != SPG_OK) return s;
+    if (h->num_policy == SPG_ACC_LL)
+        return fail(h, SPG_ERR_UNSUPPORTED, "backward needs C's columns sorted; the plan's numeric phase leaves "
+                                            "rows unsorted (SPG_ACC_LL)");
     const Fingerprint &f = h->fp;
     if (A->nrows != f.m || A->ncols != f.n || B->ncols != f.k || A->nnz != f.nnza || B->nnz != f.nnzb ||
         A->row_ptr != f.arp || B->row_ptr != f.brp || A->col_idx != f.aci || B->col_idx != f.bci ||
@@ -1107,6 +1502,32 @@ extern "C" spg_status spgemm_batch_symbolic(spg_handle h, int32_t count, const s
         nnz_c[i] = bt.c_nnz[i];
     }
     HIPCHK(launch_batch_rp_out(dev, count, bt.max_rows, h->coff.as<int64_t>(), st));
+    // product classes by the average row size of C_i (<= 16, 128, 1024, more)
+    h->ncls = 0;
+    h->cls_tuned = false;
+    {
+        int64_t rows_c[4] = {}, nb_c[4] = {}, nbr_c[4] = {};
+        for (int i = 0; i < count; ++i) {
+            const double avg = (double)bt.c_nnz[i] / (double)std::max<int64_t>(1, bt.a[i].nrows);
+            const int c = avg <= 16 ? 0 : avg <= 128 ? 1 : avg <= 1024 ? 2 : 3;
+            bt.a[i].cls = c;
+            rows_c[c] += bt.a[i].nrows;
+            nb_c[c] += bt.b[i].nnz;
+            nbr_c[c] += bt.b[i].nrows;
+        }
+        int used = 0;
+        for (int c = 0; c < 4; ++c) {
+            h->cls_rows[c] = (int)std::min<int64_t>(rows_c[c], INT32_MAX);
+            h->cls_avg_b[c] = nbr_c[c] ? std::max(1.0, (double)nb_c[c] / (double)nbr_c[c]) : 1.0;
+            used += rows_c[c] > 0;
+        }
+        if (used > 1) {
+            HIPCHK(ensure(h->row_cls, std::max<int64_t>(R, 1)));
+            if ((s = upload_desc(h, bt.a, &dev)) != SPG_OK) return s;
+            HIPCHK(launch_batch_row_class(dev, count, bt.max_rows, h->row_cls.as<uint8_t>(), st));
+            h->ncls = 4;
+        }
+    }
     h->nnzc = nnzc;
     Fingerprint &fp = h->fp;
     fp = Fingerprint{};
@@ -1118,7 +1539,7 @@ extern "C" spg_status spgemm_batch_symbolic(spg_handle h, int32_t count, const s
 
 template <typename VT>
 static spg_status batch_numeric_impl(spg_handle h, int32_t count, const spg_csr *A, const spg_csr *B,
-                                     spg_csr_out *C, int acc) {
+                                     spg_csr_out *C, int acc, bool vo) {
     auto &bt = h->batch;
     hipStream_t st = h->stream;
     const size_t vb = sizeof(VT);
@@ -1158,8 +1579,13 @@ static spg_status batch_numeric_impl(spg_handle h, int32_t count, const spg_csr 
         cci = bt.cci.as<int32_t>();
         cval = bt.cval.as<VT>();
     }
+    // structure known (values only): position maps from the back-to-back C
+    // columns an earlier call wrote; outputs gathered through staging take the
+    // full kernels
+    vo = vo && c_contig;
+    if (vo && !h->maps_built && h->nnzc > 0 && (s = build_maps(h, cci)) != SPG_OK) return s;
     if (h->nnzc > 0) {
-        if ((s = numeric_impl<VT>(h, aval, bval, cci, cval, acc)) != SPG_OK) return s;
+        if ((s = numeric_impl<VT>(h, aval, bval, cci, cval, acc, -1, -1, vo)) != SPG_OK) return s;
     }
     if (!c_contig) {
         std::vector<BatchDesc> d = bt.c;
@@ -1174,10 +1600,8 @@ static spg_status batch_numeric_impl(spg_handle h, int32_t count, const spg_csr 
     return SPG_OK;
 }
 
-extern "C" spg_status spgemm_batch_numeric(spg_handle h, int32_t count, const spg_csr *A, const spg_csr *B,
-                                           spg_csr_out *C) {
-    if (!h) return SPG_ERR_INVALID_ARG;
-    h->err.clear();
+static spg_status batch_entry(spg_handle h, int32_t count, const spg_csr *A, const spg_csr *B, spg_csr_out *C,
+                              bool vo) {
     auto &bt = h->batch;
     if (!h->ready || bt.count == 0) return fail(h, SPG_ERR_NOT_READY, "spgemm_batch_numeric before spgemm_batch_symbolic");
     if (count != bt.count || !A || !B || !C) return fail(h, SPG_ERR_STRUCTURE_MISMATCH, "batch size differs from the plan");
@@ -1197,8 +1621,22 @@ extern "C" spg_status spgemm_batch_numeric(spg_handle h, int32_t count, const sp
         if ((int)A[i].dtype != dt || (int)B[i].dtype != dt || (int)C[i].dtype != dt)
             return fail(h, SPG_ERR_INVALID_ARG, "one dtype for the whole batch");
     }
-    if (dt == SPG_F64) return batch_numeric_impl<double>(h, count, A, B, C, ACC_NATIVE);
-    return batch_numeric_impl<float>(h, count, A, B, C, fp32_acc(h));
+    if (dt == SPG_F64) return batch_numeric_impl<double>(h, count, A, B, C, ACC_NATIVE, vo);
+    return batch_numeric_impl<float>(h, count, A, B, C, fp32_acc(h), vo);
+}
+
+extern "C" spg_status spgemm_batch_numeric(spg_handle h, int32_t count, const spg_csr *A, const spg_csr *B,
+                                           spg_csr_out *C) {
+    if (!h) return SPG_ERR_INVALID_ARG;
+    h->err.clear();
+    return batch_entry(h, count, A, B, C, false);
+}
+
+extern "C" spg_status spgemm_batch_numeric_values(spg_handle h, int32_t count, const spg_csr *A,
+                                                  const spg_csr *B, spg_csr_out *C) {
+    if (!h) return SPG_ERR_INVALID_ARG;
+    h->err.clear();
+    return batch_entry(h, count, A, B, C, true);
 }
 
 extern "C" spg_status spgemm_numeric_rows(spg_handle h, const spg_csr *A, const spg_csr *B, int64_t row_begin,

@@ -73,6 +73,18 @@ __global__ __launch_bounds__(BB) void k_batch_bounds(const BatchDesc *d, int cou
     }
 }
 
+__global__ __launch_bounds__(BB) void k_batch_row_class(const BatchDesc *d, uint8_t *row_cls) {
+    const BatchDesc m = d[blockIdx.y];
+    for (int64_t r = (int64_t)blockIdx.x * BB + threadIdx.x; r < m.nrows; r += (int64_t)gridDim.x * BB)
+        row_cls[m.row_off + r] = (uint8_t)m.cls;
+}
+
+__global__ __launch_bounds__(BB) void k_kind_merge(int64_t m, const uint8_t *row_cls, const uint8_t *kind_cls,
+                                                   uint8_t *kind) {
+    for (int64_t i = (int64_t)blockIdx.x * BB + threadIdx.x; i < m; i += (int64_t)gridDim.x * BB)
+        kind[i] = kind_cls[(int64_t)row_cls[i] * m + i];
+}
+
 inline dim3 batch_grid(int64_t max_work, int count) {
     int64_t gx = (max_work + BB - 1) / BB;
     gx = gx < 1 ? 1 : (gx > 64 ? 64 : gx);
@@ -120,6 +132,19 @@ hipError_t launch_batch_rp_out(const BatchDesc *d, int count, int64_t max_rows, 
 hipError_t launch_batch_bounds(const BatchDesc *d, int count, const int64_t *coff, int64_t *out, hipStream_t s) {
     if (count == 0) return hipSuccess;
     hipLaunchKernelGGL(k_batch_bounds, dim3((count + BB - 1) / BB), dim3(BB), 0, s, d, count, coff, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_row_class(const BatchDesc *d, int count, int64_t max_rows, uint8_t *row_cls, hipStream_t s) {
+    if (count == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_batch_row_class, batch_grid(max_rows, count), dim3(BB), 0, s, d, row_cls);
+    return hipGetLastError();
+}
+
+hipError_t launch_kind_merge(int64_t m, const uint8_t *row_cls, const uint8_t *kind_cls, uint8_t *kind, hipStream_t s) {
+    if (m == 0) return hipSuccess;
+    const int64_t g = std::min<int64_t>(4096, (m + BB - 1) / BB);
+    hipLaunchKernelGGL(k_kind_merge, dim3((unsigned)g), dim3(BB), 0, s, m, row_cls, kind_cls, kind);
     return hipGetLastError();
 }
 

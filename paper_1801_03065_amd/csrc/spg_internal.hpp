@@ -150,6 +150,9 @@ struct NumArgs {
     int32_t *sg_cur;          // K_DG (segmented): per workgroup, sg_cap A entries x 2 int32 (cursor, run end)
     int sg_cap;               //   (nullptr / 0: runs found by two searches per segment)
     int b32;               // nnz(B) * 8 < 2^32: B entries addressed with 32-bit offsets
+    const int64_t *map_off;   // reuse: per row, where its products' ranks start in map
+    uint16_t *map;            // reuse: rank in C's row per multiplication
+    int values_only;          // K_PL: C's columns are already in place, write values only
     DevStats *st;
 };
 
@@ -182,6 +185,8 @@ struct BatchDesc {
     int64_t nnz_off;       // first entry in the concatenation
     int32_t col_add;       // added to column indices (A: B's row offset)
     int32_t rp64;
+    int32_t cls;           // product class of the batch autotuner (A descriptors)
+    int32_t pad;
 };
 
 // ------------------------------------------------------------ device helpers
@@ -236,6 +241,20 @@ __device__ __forceinline__ long long wave_incl_scan64(long long v) {
         long long t = __shfl_up(v, d);
         if (l >= d) v += t;
     }
+    return v;
+}
+// Inclusive prefix sum inside teams of 2^LG lanes with DPP lane moves (row
+// shifts inside each 16-lane row, masked at team edges below 16 lanes; row
+// broadcasts of lane 15 / lane 31 for teams of 32 / 64): no shuffle address
+// arithmetic.
+template <int LG>
+__device__ __forceinline__ int team_scan(int v, int q) {
+    if (LG >= 1) { const int t = __builtin_amdgcn_update_dpp(0, v, 0x111, 0xF, 0xF, false); v += (LG >= 4 || q >= 1) ? t : 0; }
+    if (LG >= 2) { const int t = __builtin_amdgcn_update_dpp(0, v, 0x112, 0xF, 0xF, false); v += (LG >= 4 || q >= 2) ? t : 0; }
+    if (LG >= 3) { const int t = __builtin_amdgcn_update_dpp(0, v, 0x114, 0xF, 0xF, false); v += (LG >= 4 || q >= 4) ? t : 0; }
+    if (LG >= 4) v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xF, 0xF, false);
+    if (LG >= 5) v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xA, 0xF, false);  // row_bcast:15 into rows 1, 3
+    if (LG >= 6) v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xC, 0xF, false);  // row_bcast:31 into rows 2, 3
     return v;
 }
 // Set bits of word w below bit b (b in [0, 31]): one bit-field extract of the
@@ -375,6 +394,8 @@ struct ClassParams {
     const int *comp_flag;     // symbolic: when set, compression as decided on the device (else `compressed`)
     int32_t *words_out;       // symbolic: zeroed for every row (touched words, filled by the structure kernels)
     const int *unsorted;      // when set: segments only if it reads 0 (rows of B with unsorted columns)
+    const uint8_t *row_cls;  // numeric, batch classes: only rows with row_cls[i] == cls get a kind
+    int cls;
     int sg;             // heavy rows in segments (B's rows sorted): symbolic K_DG rows that may
                         // need several segments get room for a list; numeric K_DG rows must
                         // have one or fit a single segment
@@ -424,6 +445,54 @@ hipError_t launch_num_sr(const NumArgs<VT> &a, int acc, int lg_t, const LaunchCf
 size_t lds_num_wh(int ts, int nw_max, int r_max, int acc_bytes);
 template <typename VT>
 hipError_t launch_backward(const BwdArgs<VT> &a, const LaunchCfg &c);
+// Reuse on a known structure: position maps of a kind's rows from C's sorted
+// columns (teams of 2^lgt lanes, 2^lgs lanes per B row), and the values of
+// those rows on their maps (LDS rows of a.r_max entries per team).
+hipError_t launch_posmap(const NumArgs<double> &a, const int32_t *cci, int lgt, int lgs, const LaunchCfg &c,
+                         int64_t rows);
+template <typename VT>
+hipError_t launch_num_map(const NumArgs<VT> &a, int acc, int lgt, int lgs, const LaunchCfg &c, int64_t rows);
+size_t lds_num_map(int r_max, int lgt, int acc_bytes);
+// LL hashmap, Thread-Sequential groups of 2^lgg lanes per row, unsorted rows:
+// a.ts buckets (power of two), a.r_max slots (>= the largest row of the kind).
+template <typename VT>
+hipError_t launch_num_ll(const NumArgs<VT> &a, int acc, int lgg, const LaunchCfg &c, int64_t rows);
+size_t lds_num_ll(int hb, int cap, int lgg, int acc_bytes);
+// Masked product: C = (A * B) on M's pattern, or path counts (structural).
+template <typename VT>
+struct MaskArgs {
+    const int64_t *arp;
+    const int32_t *aci;
+    const VT *aval;        // nullptr in structural mode
+    const int64_t *brp;
+    const int32_t *bci;
+    const VT *bval;
+    const int64_t *mrp;
+    const int32_t *mci;
+    VT *out;               // nnz(M), M's entry order
+    const int32_t *rows;   // rows of this launch
+    int64_t nrows;
+    int64_t n, k;          // A's columns < n, B's and M's < k
+    int lg_gs;             // lanes per B row
+    int structural;
+    void *arena;           // workgroup rows: 12 B per slot per workgroup
+    int64_t arena_cap;     // slots per workgroup (power of two >= 2 x longest mask row)
+    int *bad;              // bit 0: a column out of range, bit 1: arena too small
+};
+constexpr int MW_MAX = 512;  // mask row length of the wavefront kind
+hipError_t launch_mask_class(int64_t m, const int64_t *arp, const int64_t *mrp, int mw_max, int32_t *rows1,
+                             int32_t *rows2, int *cnt, hipStream_t s);
+template <typename VT>
+hipError_t launch_mask_w(const MaskArgs<VT> &a, int lg, int mmax, const LaunchCfg &c);
+template <typename VT>
+hipError_t launch_mask_g(const MaskArgs<VT> &a, const LaunchCfg &c);
+size_t lds_mask_w(int lg, int mmax);
+
+// Kinds whose rows get position maps: every row fits 1024 entries (16-bit ranks).
+__host__ __device__ inline bool map_kind(int k) { return k == K_SR || k == K_WH || k == K_HW || k == K_DW; }
+// out[i] = multiplications of row i if it gets a map, else 0 (kind_heavy nullable).
+hipError_t launch_map_rows(int64_t m, const uint8_t *kind, const uint8_t *kind_heavy, const int64_t *rflops,
+                           int32_t *out, hipStream_t s);
 
 // Operand structure of one product (caller's arrays) for the fingerprint.
 struct StructRef {
@@ -447,6 +516,10 @@ hipError_t launch_batch_scatter(const BatchDesc *d, int count, int64_t max_nnz, 
 hipError_t launch_batch_rp_out(const BatchDesc *d, int count, int64_t max_rows, const int64_t *coff,
                                hipStream_t s);
 hipError_t launch_batch_bounds(const BatchDesc *d, int count, const int64_t *coff, int64_t *out, hipStream_t s);
+// row_cls[row_off_i + r] = d[i].cls for the rows of every product
+hipError_t launch_batch_row_class(const BatchDesc *d, int count, int64_t max_rows, uint8_t *row_cls, hipStream_t s);
+// kind[i] = kind_cls[row_cls[i] * m + i]: the classes' kinds merged into one array
+hipError_t launch_kind_merge(int64_t m, const uint8_t *row_cls, const uint8_t *kind_cls, uint8_t *kind, hipStream_t s);
 
 // LDS bytes of the core kernels for given limits.
 size_t lds_sym_dw(int nw_max);

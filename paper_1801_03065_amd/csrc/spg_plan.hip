@@ -142,22 +142,19 @@ __global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(4, 8))) vo
     const int64_t p0 = sl.idx, pend = sl.end;
     auto row_at = [&](int64_t pp) -> int { return pp < pend ? read_first(a.rs.rows[pp]) : 0; };
 
-    // ---- prologue: fill the pipeline (waits here are once per kernel)
-    int64_t rn = p0 + step < pend ? load_desc(row_at(p0 + step)) : 0;    // raw, row p+s
-    int64_t r2 = p0 + 2 * step < pend ? load_desc(row_at(p0 + 2 * step)) : 0;  // raw, row p+2s
-    RowDescP d = p0 < pend ? to_uni(load_desc(row_at(p0))) : RowDescP{};   // row p
-    int64_t nan = p0 + step < pend ? lane64(rn, 1) - lane64(rn, 0) : 0;     // A entries of row p+s
-    int64_t f2ab = 0, f2na = 0, f2po = 0;                                    // row p+2s
-    int f2nw = 0;
-    if (p0 + 2 * step < pend) {
-        f2ab = lane64(r2, 0);
-        f2na = lane64(r2, 1) - f2ab;
-        f2po = lane64(r2, 4);
-        f2nw = (int)__builtin_amdgcn_readlane((uint32_t)r2, 6);
-    }
-    int i3u = row_at(p0 + 3 * step);  // uniform row index of row p+3s
+    // ---- prologue: fill the pipeline (waits here are once per kernel).
+    // Naming by distance from the current row p: *_m = row p+s, *_l = row
+    // p+2s; rn, r2, r3 = raw descriptors of rows p+s, p+2s, p+3s.
+    RowDescP d = p0 < pend ? to_uni(load_desc(row_at(p0))) : RowDescP{};      // row p
+    int64_t rn = p0 + step < pend ? load_desc(row_at(p0 + step)) : 0;
+    int64_t r2 = p0 + 2 * step < pend ? load_desc(row_at(p0 + 2 * step)) : 0;
+    int64_t r3 = p0 + 3 * step < pend ? load_desc(row_at(p0 + 3 * step)) : 0;
+    int i4 = p0 + 4 * step < pend ? a.rs.rows[p0 + 4 * step] : 0;            // row index of p+4s
     bool fast_c = false;
-    uint2 cpw = make_uint2(0u, 0u);
+    uint2 cpw = make_uint2(0u, 0u), npw_m = make_uint2(0u, 0u), npw_l = make_uint2(0u, 0u);
+    int64_t nb0n = 0, nb1n = 0;  // row p+s: B extents per A entry
+    double nav_m = 0.0, nav_l = 0.0;
+    int nj_l = 0;                // row p+2s: A columns
     if (p0 < pend) {  // row p: staged into half 0; its plan pair in a register
         const int cn = (int)min((int64_t)WAVE, d.ae - d.ab);
         int64_t b0 = 0, b1 = 0;
@@ -171,85 +168,69 @@ __global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(4, 8))) vo
         fast_c = stage(0, cn, d.ae - d.ab, b0, b1, av);
         if (l < d.nw) cpw = a.plan[d.po + l];
     }
-    int nj = 0;  // row p+s: A column, value, plan pair
-    double nav = 0.0;
-    uint2 npw = make_uint2(0u, 0u);
     if (p0 + step < pend) {
-        const RowDescP dn = to_uni(rn);
-        if (l < min((int64_t)WAVE, nan)) {
-            nj = a.aci[dn.ab + l];
-            nav = (double)a.aval[dn.ab + l];
+        const RowDescP d1 = to_uni(rn);
+        if (l < min((int64_t)WAVE, d1.ae - d1.ab)) {
+            const int j = a.aci[d1.ab + l];
+            nav_m = (double)a.aval[d1.ab + l];
+            nb0n = a.brp[j];
+            nb1n = a.brp[j + 1];
         }
-        if (l < dn.nw) npw = a.plan[dn.po + l];
+        if (l < d1.nw) npw_m = a.plan[d1.po + l];
     }
-    // the previous row's results, written out during the next row
-    bool prev_ok = false;
-    int64_t prev_ob = 0;
-    int prev_n = 0;
+    if (p0 + 2 * step < pend) {
+        const RowDescP d2 = to_uni(r2);
+        if (l < min((int64_t)WAVE, d2.ae - d2.ab)) {
+            nj_l = a.aci[d2.ab + l];
+            nav_l = (double)a.aval[d2.ab + l];
+        }
+        if (l < d2.nw) npw_l = a.plan[d2.po + l];
+    }
+    // gathers of a staged row (fast path): every product's column and value,
+    // issued a row ahead of the products that use them
+    int col[NU];
+    VT pv[NU];
+    unsigned okm = 0;
+    auto gather = [&](int hb_i, int cn_g) {
+        const int2 *pk_s = (const int2 *)(half(hb_i) + L.st_pk);
+        int2 pk[NU];
+#pragma unroll
+        for (int u = 0; u < NU; ++u) pk[u] = pk_s[g + u * ng];  // entries past cn are masked below
+        okm = 0;
+#pragma unroll
+        for (int u = 0; u < NU; ++u) {
+            const bool okg = (g + u * ng < cn_g) & (q < pk[u].y);
+            okm |= (unsigned)okg << u;
+            const uint32_t e = okg ? (uint32_t)pk[u].x + q : 0u;  // nnz(B) * 8 < 2^32 on this path
+            col[u] = ld32(a.bci, e);
+            pv[u] = ld32(a.bval, e);
+        }
+    };
+    wave_lds_sync();
+    if (p0 < pend && fast_c) gather(0, (int)min((int64_t)WAVE, d.ae - d.ab));
+
+    // Per row p: plan decode and products of p, p's stores, pipeline loads
+    // (p+2s B extents, p+3s A entries and plan pairs, p+4s descriptor, p+5s
+    // index), then the staging and gathers of p+s, issued last.  The
+    // vector-memory counter retires in order: when the products of p+s wait
+    // for its gathers, every earlier load has landed too, so a loaded value
+    // is only read (or copied) a row after its load, without a stall.
     int b = 0;  // half of the current row
     for (int64_t pp = p0; pp < pend; pp += step, b ^= 1) {
-        const bool has1 = pp + step < pend, has2 = pp + 2 * step < pend, has3 = pp + 3 * step < pend;
+        const bool has1 = pp + step < pend, has2 = pp + 2 * step < pend, has3 = pp + 3 * step < pend,
+                   has4 = pp + 4 * step < pend;
         const int wlo = d.wlo;
         unsigned char *hb = half(b);
         int64_t *st_bs = (int64_t *)(hb + L.st_bs);
         double *st_a = (double *)(hb + L.st_a);
         int32_t *st_len = (int32_t *)(hb + L.st_len);
-        const int2 *st_pk = (const int2 *)(hb + L.st_pk);
         S *vals = (S *)(hb + L.vals);
         int32_t *colbuf = (int32_t *)(hb + L.colbuf);
         const bool fast = fast_c;
         int cn = (int)min((int64_t)WAVE, d.ae - d.ab);
-        wave_lds_sync();
+        const int64_t ob = d.cb - cbase;
 
-        // ---- 1. stores of row p-1 (other half)
-        if (prev_ok) {
-            S *pvals = (S *)(half(b ^ 1) + L.vals);
-            const int32_t *pcol = (const int32_t *)(half(b ^ 1) + L.colbuf);
-            for (int t = l; t < prev_n; t += WAVE) {
-                a.cci[prev_ob + t] = pcol[t];
-                a.cval[prev_ob + t] = A::fin(pvals[t]);
-                pvals[t] = A::zero();
-            }
-        }
-        // ---- 2. pipeline loads (addresses from values that landed a row ago):
-        //      row p+s B extents, row p+2s A entries and plan pairs, row p+3s
-        //      descriptor, row p+4s index
-        int64_t nb0 = 0, nb1 = 0;
-        if (has1 && l < min((int64_t)WAVE, nan)) {
-            nb0 = a.brp[nj];
-            nb1 = a.brp[nj + 1];
-        }
-        int nnj = 0;
-        double nnav = 0.0;
-        uint2 nnpw = make_uint2(0u, 0u);
-        if (has2) {
-            if (l < min((int64_t)WAVE, f2na)) {
-                nnj = a.aci[f2ab + l];
-                nnav = (double)a.aval[f2ab + l];
-            }
-            if (l < f2nw) nnpw = a.plan[f2po + l];
-        }
-        const int64_t raw3 = has3 ? load_desc(i3u) : 0;
-        const int i4 = pp + 4 * step < pend ? a.rs.rows[pp + 4 * step] : 0;
-
-        // ---- 3. gathers of row p: every product's column and value
-        int col[NU];
-        VT pv[NU];
-        unsigned okm = 0;
-        if (fast) {
-            int2 pk[NU];
-#pragma unroll
-            for (int u = 0; u < NU; ++u) pk[u] = st_pk[g + u * ng];  // entries past cn are masked below
-#pragma unroll
-            for (int u = 0; u < NU; ++u) {
-                const bool ok = (g + u * ng < cn) & (q < pk[u].y);
-                okm |= (unsigned)ok << u;
-                const uint32_t e = ok ? (uint32_t)pk[u].x + q : 0u;  // nnz(B) * 8 < 2^32 on this path
-                col[u] = ld32(a.bci, e);
-                pv[u] = ld32(a.bval, e);
-            }
-        }
-        // ---- 4. decode the plan of row p: pre(word), word -> pair
+        // ---- 1. decode the plan of row p: pre(word), word -> pair
         const uint2 mypw = cpw;
         const bool have = l < d.nw;
         const int pc = have ? __popc(mypw.y) : 0;
@@ -266,7 +247,7 @@ __global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(4, 8))) vo
         if (l == 0 && !ok) atomicAdd(&a.st->mismatch, 1);
         wave_lds_sync();
 
-        // ---- 5. products into vals[rank]
+        // ---- 2. products into vals[rank]
         if (ok) {
             if (fast) {
 #pragma unroll
@@ -310,8 +291,8 @@ __global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(4, 8))) vo
                 }
             }
         }
-        // ---- 6. sorted columns of row p from its pairs
-        if (ok && have) {
+        // ---- 3. sorted columns of row p from its pairs, then p's stores
+        if (ok && have && !a.values_only) {
             uint32_t m = mypw.y;
             int p = pre;
             const int base = (int)(mypw.x << 5);
@@ -320,40 +301,60 @@ __global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(4, 8))) vo
                 m &= m - 1;
             }
         }
-        // ---- 7. next row: every load issued above has landed (the products
-        //      waited for the gathers, issued last, and loads retire in order),
-        //      so its values move to scalar registers without a stall
-        prev_ok = ok;
-        prev_ob = d.cb - cbase;
-        prev_n = rnnz;
-        if (has1) {
-            fast_c = stage(b ^ 1, (int)min((int64_t)WAVE, nan), nan, nb0, nb1, nav);
-            d = to_uni(rn);
-        }
-        if (has2) nan = lane64(r2, 1) - lane64(r2, 0);
+        // ---- 4. pipeline: values loaded a row ago move on; the addresses of
+        //      the new loads are formed before p's stores, so reading those
+        //      values never waits for the stores
+        const RowDescP dn = has1 ? to_uni(rn) : RowDescP{};  // row p+s
+        const int64_t nan1 = dn.ae - dn.ab;
+        const int64_t nan2 = has2 ? lane64(r2, 1) - lane64(r2, 0) : 0;
+        const int64_t nb0 = nb0n, nb1 = nb1n;
+        const double nav1 = nav_m;
+        const uint2 cpw_next = npw_m;
+        nav_m = nav_l;
+        npw_m = npw_l;
+        const bool ld_ext = has2 && l < min((int64_t)WAVE, nan2);
+        const int64_t *ext_p = a.brp + nj_l;                 // row p+2s: B extents
+        int64_t f3ab = 0, f3na = 0, f3po = 0;
+        int f3nw = 0;
         if (has3) {
-            f2ab = lane64(raw3, 0);
-            f2na = lane64(raw3, 1) - f2ab;
-            f2po = lane64(raw3, 4);
-            f2nw = (int)__builtin_amdgcn_readlane((uint32_t)raw3, 6);
+            f3ab = lane64(r3, 0);
+            f3na = lane64(r3, 1) - f3ab;
+            f3po = lane64(r3, 4);
+            f3nw = (int)__builtin_amdgcn_readlane((uint32_t)r3, 6);
         }
-        i3u = read_first(i4);
+        const bool ld_a = has3 && l < min((int64_t)WAVE, f3na), ld_pw = has3 && l < f3nw;
+        const int i4s = read_first(i4);                      // row p+4s
+        wave_lds_sync();
+        if (ok) {  // row p's stores
+            for (int t = l; t < rnnz; t += WAVE) {
+                if (!a.values_only) a.cci[ob + t] = colbuf[t];
+                a.cval[ob + t] = A::fin(vals[t]);
+                vals[t] = A::zero();
+            }
+        }
+        nb0n = ld_ext ? ext_p[0] : 0;
+        nb1n = ld_ext ? ext_p[1] : 0;
+        if (ld_a) {
+            nj_l = a.aci[f3ab + l];
+            nav_l = (double)a.aval[f3ab + l];
+        }
+        if (ld_pw) npw_l = a.plan[f3po + l];
         rn = r2;
-        r2 = raw3;
-        cpw = npw;
-        nj = nnj;
-        nav = nnav;
-        npw = nnpw;
-    }
-    // the last row's stores
-    wave_lds_sync();
-    if (prev_ok) {
-        S *pvals = (S *)(half(b ^ 1) + L.vals);
-        const int32_t *pcol = (const int32_t *)(half(b ^ 1) + L.colbuf);
-        for (int t = l; t < prev_n; t += WAVE) {
-            a.cci[prev_ob + t] = pcol[t];
-            a.cval[prev_ob + t] = A::fin(pvals[t]);
+        r2 = r3;
+        r3 = has4 ? load_desc(i4s) : 0;                                 // row p+4s
+        i4 = pp + 5 * step < pend ? a.rs.rows[pp + 5 * step] : 0;      // row p+5s
+        // ---- 5. row p+s: staged, then its gathers (the last memory
+        //      operations before its products)
+        if (has1) {
+            fast_c = stage(b ^ 1, (int)min((int64_t)WAVE, nan1), nan1, nb0, nb1, nav1);
+            d = dn;
+            cpw = cpw_next;
         }
+        wave_lds_sync();
+        // (issued even when there is no next fast row, with every lane masked
+        // to element 0: a fixed count of loads after the pipeline loads lets
+        // their wait at the loop's end skip the gathers)
+        gather(b ^ 1, has1 && fast_c ? (int)min((int64_t)WAVE, nan1) : 0);
     }
 }
 

@@ -46,20 +46,6 @@ __device__ __forceinline__ uint32_t sr_hash(int c, int lg) {
     return (__umul24((uint32_t)c & 0xFFFFFFu, 0x9E3779u) >> (24 - lg)) & ((1u << lg) - 1u);
 }
 
-// Inclusive prefix sum inside teams of 2^LG lanes with DPP lane moves (row
-// shifts inside each 16-lane row, masked at team edges below 16 lanes; row
-// broadcasts of lane 15 / lane 31 for teams of 32 / 64): no shuffle address
-// arithmetic.
-template <int LG>
-__device__ __forceinline__ int team_scan(int v, int q) {
-    if (LG >= 1) { const int t = __builtin_amdgcn_update_dpp(0, v, 0x111, 0xF, 0xF, false); v += (LG >= 4 || q >= 1) ? t : 0; }
-    if (LG >= 2) { const int t = __builtin_amdgcn_update_dpp(0, v, 0x112, 0xF, 0xF, false); v += (LG >= 4 || q >= 2) ? t : 0; }
-    if (LG >= 3) { const int t = __builtin_amdgcn_update_dpp(0, v, 0x114, 0xF, 0xF, false); v += (LG >= 4 || q >= 4) ? t : 0; }
-    if (LG >= 4) v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xF, 0xF, false);
-    if (LG >= 5) v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xA, 0xF, false);  // row_bcast:15 into rows 1, 3
-    if (LG >= 6) v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xC, 0xF, false);  // row_bcast:31 into rows 2, 3
-    return v;
-}
 // The same with max (values >= 0 after the first step; lanes without a
 // source read 0).
 template <int LG>

@@ -144,3 +144,46 @@ def test_batch_with_degenerate_members():
     h.check_errors()
     assert nnzs[1] == 0 and nnzs[2] == 1 and nnzs[4] == 0
     _check(pairs, Cs)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_batch_autotune_per_class(dtype):
+    """Products of very different shapes get their own (policy, lanes) choices:
+    C_i rows of ~16 entries over B rows of ~4 and rows of ~900 over B rows of
+    ~30 fall into different classes, whose lanes-per-B-row candidates do not
+    overlap; every product still equals the oracle."""
+    import torch
+
+    import paper_1801_03065_amd as spg
+    from helpers import check_f32, f32_inputs
+
+    small = synth.batch_specs(6, 11, n_lo=2000, n_hi=4000, lam_lo=3.5, lam_hi=4.5)
+    big = synth.batch_specs(6, 12, n_lo=2000, n_hi=4000, lam_lo=28.0, lam_hi=32.0)
+    specs = [s for pair in zip(small, big) for s in pair]
+    pairs = synth.batch_matrices(specs)
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    As = spg.pack_batch([p[0] for p in pairs], dtype=tdt)
+    Bs = spg.pack_batch([p[1] for p in pairs], dtype=tdt)
+    h = spg.Handle(autotune=1)
+    rps, nnzs = spg.spgemm_batch_symbolic(h, As, Bs)
+    Cs = spg.batch_outputs(As, Bs, rps, nnzs, tdt)
+    spg.spgemm_batch_numeric(h, As, Bs, Cs)
+    h.check_errors()
+    pol, lanes = h.batch_choices(len(pairs))
+    print("per-product policy", pol.tolist(), "lanes", lanes.tolist())
+    assert set(lanes[0::2].tolist()).isdisjoint(set(lanes[1::2].tolist()))
+    assert len(set(zip(pol.tolist(), lanes.tolist()))) >= 2
+    for r in range(2):  # a second call reuses the tuned classes
+        torch.cuda.synchronize()
+        for (A, B), C in zip(pairs, Cs):
+            got = (C.row_ptr.cpu().numpy().astype(np.int64), C.col_idx.cpu().numpy(), C.values.cpu().numpy())
+            if dtype == "f64":
+                ref, S = oracle.spgemm(A, B, with_abs=True)
+                check_f64(ref, S, got)
+            else:
+                ref, S = oracle.spgemm(f32_inputs(A), f32_inputs(B), with_abs=True)
+                check_f32(ref, S, got)
+        for C in Cs:
+            C.values.fill_(float("nan"))
+        spg.spgemm_batch_numeric(h, As, Bs, Cs)
+        h.check_errors()

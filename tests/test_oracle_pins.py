@@ -526,3 +526,21 @@ def test_masked_brute_force(seed):
     # the mask equal to C's own pattern gives C's values in C's order
     C = oracle.spgemm(A, B)
     assert np.array_equal(oracle.masked(A, B, C), C.values)
+
+
+def test_rows_check_helper_agrees_with_rows():
+    """The comparison helper accepts the oracle's own rows and flags a changed
+    value and a changed column."""
+    A = synth.shuffle_columns(synth.tiny_random(60, 50, 0.2, 31, dist="normal"), 32)
+    B = synth.tiny_random(50, 70, 0.2, 33, dist="normal")
+    sel = np.array([0, 5, 17, 59, 5])
+    rp, ci, va, ab = oracle.rows(A, B, sel)
+    ok = oracle.rows_check(A, B, sel, rp, ci, va, 1e-12, 0)
+    assert ok["bad"] == 0 and ok["bad_rows"] == 0 and ok["entries"] == rp[-1] and ok["max_rel_S"] == 0.0
+    va2 = va.copy()
+    va2[3] += 1e-3 * max(ab[3], 1.0)
+    r2 = oracle.rows_check(A, B, sel, rp, ci, va2, 1e-12, 0)
+    assert r2["bad"] == 1
+    ci2 = ci.copy()
+    ci2[0] = ci2[0] + 1000
+    assert oracle.rows_check(A, B, sel, rp, ci2, va, 1e-12, 0)["bad_rows"] == 1
