@@ -310,6 +310,23 @@ def spgemm_numeric_values(h: Handle, A: DeviceCsr, B: DeviceCsr, out: DeviceCsr)
     return out
 
 
+def spgemm_masked(h: Handle, A: DeviceCsr, B: DeviceCsr, M: DeviceCsr, structural: bool = False,
+                  dtype: torch.dtype | None = None) -> torch.Tensor:
+    """spgemm_masked: (A*B) on M's stored entries (M's entry order), or with
+    structural=True the number of paths i -> k -> j per entry.  Returns a tensor of
+    nnz(M) values (A's dtype; in structural mode A's values may be None, dtype names
+    the output type, float64 by default)."""
+    out_dtype = dtype or (A.values.dtype if A.values is not None else torch.float64)
+    out = torch.empty(M.nnz, dtype=out_dtype, device=M.col_idx.device)
+    a, b, mm = _csr(A), _csr(B), _csr(M)
+    a.dtype = _dtype(out)
+    rc = lib().spgemm_masked(h.ptr, ctypes.byref(a), ctypes.byref(b), ctypes.byref(mm),
+                             _P(out.data_ptr()) if M.nnz else None, 1 if structural else 0)
+    if rc != SPG_OK:
+        h._raise(rc)
+    return out
+
+
 def spgemm(A: DeviceCsr, B: DeviceCsr, handle: Handle | None = None, rp_dtype=torch.int32) -> DeviceCsr:
     """Both phases; the product with sorted columns."""
     h = handle or Handle()
