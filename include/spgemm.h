@@ -220,6 +220,22 @@ spg_status spgemm_numeric(spg_handle h, const spg_csr *A, const spg_csr *B, spg_
  * is reported by spg_check_errors (STRUCTURE_MISMATCH) at the first call. */
 spg_status spgemm_numeric_values(spg_handle h, const spg_csr *A, const spg_csr *B, spg_csr_out *C);
 
+/* spgemm_numeric for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same numeric phase, arguments, results and errors as spgemm_numeric,
+ * but it calls no hipMalloc / hipFree or other allocating routine.  Scratch
+ * the heavy-row kernels need (value windows, level-2 hash tables, per-entry
+ * cursors) comes from a static 64 MiB device array, one per GPU, that the
+ * library holds from its first spg_create on that GPU until the process
+ * ends; launches of heavy-row kinds are narrowed to fit it, and a plan whose
+ * heavy rows need more than 64 MiB even for 8 workgroups returns
+ * OUT_OF_MEMORY (nothing is written then).  The plan itself was allocated by
+ * spgemm_symbolic.  The autotuner does not run here: an untuned plan keeps
+ * the selector's kinds.  Every call on one GPU shares that array, so calls
+ * that overlap in time on one GPU (several streams or host threads) race:
+ * serialise them.  The current device must be the handle's device. */
+spg_status spgemm_numeric_noalloc(spg_handle h, const spg_csr *A, const spg_csr *B, spg_csr_out *C);
+
 /* Batched symbolic phase of `count` independent products C_i = A_i * B_i
  * (host arrays A[count], B[count] of device operands; C_row_ptr[count] of
  * device arrays of A_i.nrows+1 entries of c_rp_type; nnz_c[count] on the

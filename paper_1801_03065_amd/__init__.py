@@ -95,6 +95,8 @@ _sigs = {
     "spgemm_numeric_values": (_S, [_P, ctypes.POINTER(spg_csr), ctypes.POINTER(spg_csr), ctypes.POINTER(spg_csr_out)]),
     "spgemm_batch_numeric_values": (_S, [_P, ctypes.c_int32, ctypes.POINTER(spg_csr), ctypes.POINTER(spg_csr),
                                          ctypes.POINTER(spg_csr_out)]),
+    "spgemm_numeric_noalloc": (_S, [_P, ctypes.POINTER(spg_csr), ctypes.POINTER(spg_csr),
+                                    ctypes.POINTER(spg_csr_out)]),
     "spgemm_masked": (_S, [_P, ctypes.POINTER(spg_csr), ctypes.POINTER(spg_csr), ctypes.POINTER(spg_csr), _P,
                            ctypes.c_int]),
     "spg_batch_choices": (_S, [_P, ctypes.c_int32, _P, _P]),
@@ -305,6 +307,21 @@ def spgemm_numeric_values(h: Handle, A: DeviceCsr, B: DeviceCsr, out: DeviceCsr)
                     out.values.data_ptr() if out.nnz else None, _dtype(out.values))
     a, b = _csr(A), _csr(B)
     rc = lib().spgemm_numeric_values(h.ptr, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c))
+    if rc != SPG_OK:
+        h._raise(rc)
+    return out
+
+
+def spgemm_numeric_noalloc(h: Handle, A: DeviceCsr, B: DeviceCsr, out: DeviceCsr) -> DeviceCsr:
+    """spgemm_numeric_noalloc: the numeric phase into caller-allocated C, with no
+    device allocation inside the call (scratch from the library's static array)."""
+    if A.values is None or B.values is None:
+        raise ValueError("numeric phase needs values")
+    c = spg_csr_out(out.nrows, out.ncols, out.nnz, _itype(out.row_ptr), out.row_ptr.data_ptr(),
+                    out.col_idx.data_ptr() if out.nnz else None,
+                    out.values.data_ptr() if out.nnz else None, _dtype(out.values))
+    a, b = _csr(A), _csr(B)
+    rc = lib().spgemm_numeric_noalloc(h.ptr, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c))
     if rc != SPG_OK:
         h._raise(rc)
     return out

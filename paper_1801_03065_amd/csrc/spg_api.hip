@@ -12,6 +12,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -37,6 +38,33 @@ struct Fingerprint {
     int arpt = 0, brpt = 0;
 };
 
+}  // namespace
+
+// Scratch of spgemm_numeric_noalloc: a file-scope device array, one instance
+// per GPU the library runs on, held until the process ends.  In host code
+// `scratch` names a host-side stand-in; its device address comes from
+// hipGetSymbolAddress, taken once per device at spg_create with that device
+// current, and only that address is passed to kernels.
+constexpr size_t NOALLOC_SCRATCH_BYTES = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+namespace {
+constexpr int SCR_MAX_DEV = 64;
+std::mutex g_scr_mu;
+void *g_scr_ptr[SCR_MAX_DEV] = {};
+
+hipError_t scratch_address(int dev, void **out) {
+    *out = nullptr;
+    if (dev < 0 || dev >= SCR_MAX_DEV) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scr_mu);
+    if (!g_scr_ptr[dev]) {
+        void *p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scr_ptr[dev] = p;
+    }
+    *out = g_scr_ptr[dev];
+    return hipSuccess;
+}
 }  // namespace
 
 struct spg_handle_s {
@@ -75,6 +103,8 @@ struct spg_handle_s {
     bool maps_built = false;      // position maps taken for this plan (maps_ok: they exist)
     long long kc_nomap[NK] = {};  // scratch: kind counts with the mapped kinds removed
     bool maps_ok = false;
+    void *scr = nullptr;       // this device's static scratch array (device address)
+    bool noalloc = false;      // the current call carves its scratch from scr instead of hipMalloc
     bool values_only = false;  // the current call writes C's values only (structure known)
     int num_policy = 0;        // accumulator policy of the numeric classification (SPG_ACC_*)
     // batch plans: products fall into classes by the average row size of C_i,
@@ -287,6 +317,7 @@ spg_status spg_create(spg_handle *out, void *stream, const spg_options *opt) {
     if (e == hipSuccess) e = ensure(h->dstats, sizeof(DevStats));
     if (e == hipSuccess) e = ensure(h->red, sizeof(long long) * RED_ELEMS);
     if (e == hipSuccess) e = ensure(h->queue, sizeof(int32_t) * XCDS * NK);
+    if (e == hipSuccess) e = scratch_address(h->device, &h->scr);
     if (e != hipSuccess) {
         spg_destroy(h);
         return SPG_ERR_HIP;
@@ -727,6 +758,22 @@ static int fp32_acc(spg_handle h) {
                                                     : ACC_NATIVE;
 }
 
+// Device scratch for one launch of the numeric phase: a handle-owned buffer
+// grown with hipMalloc, or, in an allocation-free call, the front of this
+// device's static scratch array (the launches of a call are stream-ordered,
+// so each starts at the array's beginning).  per_wg: bytes per workgroup;
+// *grid is lowered (to a multiple of 8) until the scratch fits.  Returns
+// false when not even 8 workgroups fit.
+static bool scratch_grid(spg_handle h, size_t per_wg, int *grid) {
+    if (!h->noalloc) return true;
+    const size_t fit = per_wg ? NOALLOC_SCRATCH_BYTES / per_wg : (size_t)*grid;
+    int g = (int)std::min<size_t>((size_t)*grid, fit);
+    g = (g / XCDS) * XCDS;
+    if (g < XCDS) return false;
+    *grid = g;
+    return true;
+}
+
 // The numeric phase on the plan: A's values aval, B's values bval (entry order
 // of the structure the symbolic phase saw), C's columns / values written at the
 // plan's row offsets.
@@ -798,7 +845,12 @@ static spg_status launch_kinds(spg_handle h, NumArgs<VT> na, const long long *kc
         if (mxa > WG_BIG) {
             const int cap = (int)std::min<int64_t>(mxa, 65536);
             const size_t bytes = (size_t)lc.grid * 2 * cap * sizeof(int32_t);
-            if (ensure(h->sgcur, bytes) == hipSuccess) {
+            if (h->noalloc) {
+                if (bytes <= NOALLOC_SCRATCH_BYTES) {  // else runs are searched without cursors
+                    na.sg_cur = (int32_t *)h->scr;
+                    na.sg_cap = cap;
+                }
+            } else if (ensure(h->sgcur, bytes) == hipSuccess) {
                 na.sg_cur = h->sgcur.as<int32_t>();
                 na.sg_cap = cap;
             }
@@ -810,16 +862,23 @@ static spg_status launch_kinds(spg_handle h, NumArgs<VT> na, const long long *kc
         na.rs.kind = K_DG;
         na.rs.queue = h->queue.as<int32_t>() + XCDS * K_DG;
         na.nw_max = ((kmax[K_DG][0] + 31) / 32) * 32;
-        const int grid = std::min(grid_cap(kcount[K_DG]),
-                                  dg_resident_grid(acc, sizeof(VT) == 8, lds_num_dg(na.nw_max), h->cus));
+        int grid = std::min(grid_cap(kcount[K_DG]),
+                            dg_resident_grid(acc, sizeof(VT) == 8, lds_num_dg(na.nw_max), h->cus));
         na.arena_cap = (int64_t)na.nw_max * 32;
+        if (!scratch_grid(h, (size_t)na.arena_cap * sbytes, &grid))
+            return fail(h, SPG_ERR_OUT_OF_MEMORY, "heavy-row value windows exceed the static scratch");
         const size_t bytes = (size_t)na.arena_cap * grid * sbytes;
-        if (h->arena.cap < bytes || h->arena_bytes_zeroed < bytes) {
-            HIPCHK(ensure(h->arena, bytes));
-            HIPCHK(hipMemsetAsync(h->arena.p, 0, h->arena.cap, st));
-            h->arena_bytes_zeroed = h->arena.cap;
+        if (h->noalloc) {  // the window must start at zero; the kernel leaves it zero
+            HIPCHK(launch_fill_i32((int32_t *)h->scr, (int64_t)(bytes / 4), 0, st));
+            na.arena = h->scr;
+        } else {
+            if (h->arena.cap < bytes || h->arena_bytes_zeroed < bytes) {
+                HIPCHK(ensure(h->arena, bytes));
+                HIPCHK(hipMemsetAsync(h->arena.p, 0, h->arena.cap, st));
+                h->arena_bytes_zeroed = h->arena.cap;
+            }
+            na.arena = h->arena.p;
         }
-        na.arena = h->arena.p;
         HIPCHK(launch_fill_i32(na.rs.queue, XCDS, 0, st));
         lc.grid = grid;
         HIPCHK(launch_num_dg<VT>(na, acc, lc));
@@ -829,12 +888,18 @@ static spg_status launch_kinds(spg_handle h, NumArgs<VT> na, const long long *kc
         na.rs.kind = K_HL;
         na.rs.queue = h->queue.as<int32_t>() + XCDS * K_HL;
         na.l1_slots = h->opt.l1_hash_slots ? h->opt.l1_hash_slots : (sbytes == 8 ? 4096 : 8192);
-        const int grid = std::min(grid_cap(kcount[K_HL]),
-                                  hl_resident_grid(acc, sizeof(VT) == 8, lds_num_hl(na.l1_slots, (int)sbytes), h->cus));
+        int grid = std::min(grid_cap(kcount[K_HL]),
+                            hl_resident_grid(acc, sizeof(VT) == 8, lds_num_hl(na.l1_slots, (int)sbytes), h->cus));
         na.arena_cap = pow2_at_least(2 * (int64_t)std::max(1, kmax[K_HL][1]), 64);
+        if (!scratch_grid(h, (size_t)na.arena_cap * (8 + 2 * sbytes), &grid))
+            return fail(h, SPG_ERR_OUT_OF_MEMORY, "level-2 hash tables exceed the static scratch");
         const size_t bytes = (size_t)na.arena_cap * grid * (8 + 2 * sbytes);
-        if (h->l2k.cap < bytes) HIPCHK(ensure(h->l2k, bytes));
-        na.arena = h->l2k.p;
+        if (h->noalloc) {
+            na.arena = h->scr;
+        } else {
+            if (h->l2k.cap < bytes) HIPCHK(ensure(h->l2k, bytes));
+            na.arena = h->l2k.p;
+        }
         HIPCHK(launch_fill_i32(na.rs.queue, XCDS, 0, st));
         lc.grid = grid;
         HIPCHK(launch_num_hl<VT>(na, acc, lc));
@@ -1111,7 +1176,7 @@ static spg_status numeric_impl(spg_handle h, const VT *aval, const VT *bval, int
         na.rs.range = h->krange_heavy.as<int64_t>();
         return launch_kinds<VT>(h, na, hs.kcount_heavy, hs.kmax_heavy, sizeof(VT) == 4 ? ACC_WIDE : acc);
     }
-    if (h->opt.autotune && !h->tuned && !vo) {
+    if (h->opt.autotune && !h->tuned && !h->noalloc && !vo) {
         spg_status s = h->ncls ? autotune_classes<VT>(h, na, acc) : autotune<VT>(h, na, acc);
         if (s != SPG_OK) return s;
         na.lg_gs = h->lg_num;
@@ -1177,7 +1242,21 @@ static spg_status numeric_entry(spg_handle h, const spg_csr *A, const spg_csr *B
 extern "C" spg_status spgemm_numeric(spg_handle h, const spg_csr *A, const spg_csr *B, spg_csr_out *C) {
     if (!h) return SPG_ERR_INVALID_ARG;
     h->err.clear();
+    h->noalloc = false;
     return numeric_entry(h, A, B, C);
+}
+
+extern "C" spg_status spgemm_numeric_noalloc(spg_handle h, const spg_csr *A, const spg_csr *B, spg_csr_out *C) {
+    if (!h) return SPG_ERR_INVALID_ARG;
+    h->err.clear();
+    if (!h->scr) return fail(h, SPG_ERR_INTERNAL, "no static scratch address for this device");
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev != h->device)
+        return fail(h, SPG_ERR_INVALID_ARG, "the current device is not the handle's device");
+    h->noalloc = true;
+    spg_status s = numeric_entry(h, A, B, C);
+    h->noalloc = false;
+    return s;
 }
 
 // ------------------------------------------------------------------ reuse maps
@@ -1249,6 +1328,7 @@ static spg_status build_maps(spg_handle h, const int32_t *cci) {
 extern "C" spg_status spgemm_numeric_values(spg_handle h, const spg_csr *A, const spg_csr *B, spg_csr_out *C) {
     if (!h) return SPG_ERR_INVALID_ARG;
     h->err.clear();
+    h->noalloc = false;
     if (!h->ready) return fail(h, SPG_ERR_NOT_READY, "spgemm_numeric_values before a successful spgemm_symbolic");
     if (h->batch.count) return fail(h, SPG_ERR_STRUCTURE_MISMATCH, "the plan is a batch: use spgemm_batch_numeric_values");
     spg_status s = numeric_check(h, A, B, C);
@@ -1629,6 +1709,7 @@ extern "C" spg_status spgemm_batch_numeric(spg_handle h, int32_t count, const sp
                                            spg_csr_out *C) {
     if (!h) return SPG_ERR_INVALID_ARG;
     h->err.clear();
+    h->noalloc = false;
     return batch_entry(h, count, A, B, C, false);
 }
 
@@ -1636,6 +1717,7 @@ extern "C" spg_status spgemm_batch_numeric_values(spg_handle h, int32_t count, c
                                                   const spg_csr *B, spg_csr_out *C) {
     if (!h) return SPG_ERR_INVALID_ARG;
     h->err.clear();
+    h->noalloc = false;
     return batch_entry(h, count, A, B, C, true);
 }
 
