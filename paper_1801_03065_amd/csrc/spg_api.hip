@@ -563,6 +563,7 @@ static spg_status symbolic_core(spg_handle h, int64_t m, int64_t n, int64_t k, i
     sa.st = dst;
     sa.lg_gs = lg_group(h->avg_len_c);
     sa.b32 = nnzb < (int64_t(1) << 29);  // 8-byte compressed records: 32-bit byte offsets
+    sa.nnzb = nnzb;
     if (h->planned || h->segmented) {
         sa.plan_off = h->plan_off.as<int64_t>();
         sa.plan_len = h->plan_len.as<int32_t>();
@@ -1141,6 +1142,7 @@ static spg_status numeric_impl(spg_handle h, const VT *aval, const VT *bval, int
     na.rwin = h->rwin.as<int2>();
     na.coff = h->coff.as<int64_t>();
     na.b32 = h->fp.nnzb < (int64_t(1) << 29);
+    na.nnzb = h->fp.nnzb;
     if (h->planned || h->segmented) {
         na.plan_off = h->plan_off.as<int64_t>();
         na.plan = h->plan.as<uint2>();

@@ -185,7 +185,7 @@ __device__ __forceinline__ RowDesc row_desc(int i, const int64_t *arp, const int
 // LDS of the symbolic bit-window kernel: the window's bits and summary, and
 // two halves (row p, row p+1) of staging and of the row's (word, bits) list.
 struct SwLayout {
-    size_t bits, summ, half0, hsize, st_cbs, st_clen, pairs, total;
+    size_t bits, summ, half0, hsize, st_cbs, st_clen, st_pk, pairs, total;
 };
 
 __host__ __device__ inline SwLayout sw_layout(int nwm) {
@@ -202,6 +202,8 @@ __host__ __device__ inline SwLayout sw_layout(int nwm) {
     h += 8 * WAVE;
     L.st_clen = h;
     h += 4 * WAVE;
+    L.st_pk = h;  // fast path: (32-bit compressed extent, length) per A entry, length 0 past the row
+    h += 8 * WAVE;
     L.pairs = h;
     h += 8 * PL_CAP;
     L.hsize = h;
@@ -231,7 +233,7 @@ struct RowDescS {
 // other LDS half).  The memory counter retires in order, so waiting for the
 // gathers never waits for those stores, and the values for later rows have
 // landed by the time they are used.
-template <bool COMP>
+template <bool COMP, int LGS>
 __global__ __launch_bounds__(WAVE) void k_sym_dw(SymArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     const SwLayout L = sw_layout(a.nw_max);
@@ -246,7 +248,8 @@ __global__ __launch_bounds__(WAVE) void k_sym_dw(SymArgs a) {
     // word sources inside the unrolled gathers makes the compiler wait for
     // each load before issuing the next
     const int64_t *srp = COMP ? a.bcrp : a.brp;
-    const int gs = 1 << a.lg_gs, g = l >> a.lg_gs, q = l & (gs - 1), ng = WAVE >> a.lg_gs;
+    constexpr int gs = 1 << LGS, ng = WAVE >> LGS;
+    const int g = l >> LGS, q = l & (gs - 1);
     int64_t lo, hi;
     rs_bounds(a.rs, lo, hi);
     const Slice sl = xcd_slice(lo, hi);
@@ -290,6 +293,7 @@ __global__ __launch_bounds__(WAVE) void k_sym_dw(SymArgs a) {
             ((int64_t *)(half(b) + L.st_cbs))[l] = c0;
             ((int32_t *)(half(b) + L.st_clen))[l] = len;
         }
+        ((int2 *)(half(b) + L.st_pk))[l] = l < cn ? make_int2((int)(uint32_t)c0, len) : make_int2(0, 0);
         const bool fast = a.b32 && na <= WAVE && cn <= ng * SW_SLOTS;
         return fast ? 1 + (__ballot(l < cn && len > gs) != 0) : 0;
     };
@@ -353,24 +357,25 @@ __global__ __launch_bounds__(WAVE) void k_sym_dw(SymArgs a) {
 
         // ---- 2. gathers of row p: slot s2 covers B row t = g + s2 * ng, word q
         uint32_t wd[SW_SLOTS], wc[SW_SLOTS];
-        unsigned okm = 0;
+        int lenv[SW_SLOTS];  // per slot: the B row's length (0: no word for any lane)
         if (kk > 0) {
-            uint32_t cbv[SW_SLOTS];
-            int lenv[SW_SLOTS];
+            // a lane past its B row loads the entry its offset names, clamped
+            // to B's last entry, and is masked by the length when the words
+            // are ORed
+            const uint32_t elast = (uint32_t)max(a.nnzb - 1, (int64_t)0);
+            const int2 *st_pk = (const int2 *)(half(b) + L.st_pk);
+            int2 pk[SW_SLOTS];
 #pragma unroll
-            for (int s2 = 0; s2 < SW_SLOTS; ++s2) {  // staging reads first: one LDS wait for all
-                const int tt = min(g + s2 * ng, cn - 1);
-                cbv[s2] = (uint32_t)st_cbs[tt];  // B entries < 2^30 on this path
-                lenv[s2] = st_clen[tt];
-            }
+            for (int s2 = 0; s2 < SW_SLOTS; ++s2)  // staging reads first: one LDS wait for all
+                pk[s2] = st_pk[(g + s2 * ng) & (WAVE - 1)];  // entries past the row have length 0
 #pragma unroll
             for (int s2 = 0; s2 < SW_SLOTS; ++s2) {
-                const int t = g + s2 * ng;
-                const uint32_t cb = cbv[s2];
-                const int len = lenv[s2];
-                const bool ok = (t < cn) & (q < len);
-                okm |= (unsigned)ok << s2;
-                const uint32_t e = ok ? cb + (uint32_t)q : 0u;
+                const uint32_t cb = (uint32_t)pk[s2].x;  // B entries < 2^30 on this path
+                const int len = pk[s2].y;
+                // entries past the row have length 0; with more than 64
+                // slot entries the index wraps and needs its own test
+                lenv[s2] = (ng * SW_SLOTS <= WAVE || g + s2 * ng < cn) ? len : 0;
+                const uint32_t e = min(cb + (uint32_t)q, elast);
                 if constexpr (COMP) {
                     const uint2 v = ld32(a.bcw, e);  // (word, bits): one 8-byte load
                     wd[s2] = v.x;
@@ -395,7 +400,7 @@ __global__ __launch_bounds__(WAVE) void k_sym_dw(SymArgs a) {
         if (kk > 0) {
 #pragma unroll
             for (int s2 = 0; s2 < SW_SLOTS; ++s2)
-                if (okm & (1u << s2)) dw_or(bits, summ, wd[s2] - (uint32_t)wlo, wc[s2]);
+                if (q < lenv[s2]) dw_or(bits, summ, wd[s2] - (uint32_t)wlo, wc[s2]);
             if (kk == 2) {  // words beyond the lane group of B rows longer than it
                 for (int t = g; t < cn; t += ng) {
                     const int64_t cb = st_cbs[t];
@@ -1133,16 +1138,30 @@ size_t lds_num_dw(int nw_max, int r_max, int acc_bytes, int) { return dw_layout(
 size_t lds_sym_dg(int nw_max) { return dg_layout(nw_max).total; }
 size_t lds_num_dg(int nw_max) { return dg_layout(nw_max).total; }
 
-hipError_t launch_sym_dw(const SymArgs &a, const LaunchCfg &c) {
+template <bool COMP, int LGS>
+hipError_t sym_dw_lg(const SymArgs &a, const LaunchCfg &c) {
     const size_t lds = lds_sym_dw(a.nw_max);
-    if (a.bcrp) {
-        const int grid = c.grid > 0 ? c.grid : resident_grid(k_sym_dw<true>, WAVE, lds, c.cus);
-        hipLaunchKernelGGL(k_sym_dw<true>, dim3(grid), dim3(WAVE), lds, c.stream, a);
-    } else {
-        const int grid = c.grid > 0 ? c.grid : resident_grid(k_sym_dw<false>, WAVE, lds, c.cus);
-        hipLaunchKernelGGL(k_sym_dw<false>, dim3(grid), dim3(WAVE), lds, c.stream, a);
-    }
+    const int grid = c.grid > 0 ? c.grid : resident_grid(k_sym_dw<COMP, LGS>, WAVE, lds, c.cus);
+    hipLaunchKernelGGL((k_sym_dw<COMP, LGS>), dim3(grid), dim3(WAVE), lds, c.stream, a);
     return hipGetLastError();
+}
+
+template <bool COMP>
+hipError_t sym_dw_impl(const SymArgs &a, const LaunchCfg &c) {
+    switch (a.lg_gs) {
+    case 0: return sym_dw_lg<COMP, 0>(a, c);
+    case 1: return sym_dw_lg<COMP, 1>(a, c);
+    case 2: return sym_dw_lg<COMP, 2>(a, c);
+    case 3: return sym_dw_lg<COMP, 3>(a, c);
+    case 4: return sym_dw_lg<COMP, 4>(a, c);
+    case 5: return sym_dw_lg<COMP, 5>(a, c);
+    case 6: return sym_dw_lg<COMP, 6>(a, c);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_sym_dw(const SymArgs &a, const LaunchCfg &c) {
+    return a.bcrp ? sym_dw_impl<true>(a, c) : sym_dw_impl<false>(a, c);
 }
 
 hipError_t launch_sym_dg(const SymArgs &a, const LaunchCfg &c) {

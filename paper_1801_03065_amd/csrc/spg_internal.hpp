@@ -115,6 +115,7 @@ struct SymArgs {
     const int32_t *plan_len;  // room for pairs per row (0: none stored)
     uint2 *plan;              // nullptr: no pairs stored
     int b32;                  // nnz(B) < 2^30: B entries addressed with 32-bit byte offsets
+    int64_t nnzb;             // nnz(B): gathers clamp their offsets to its last entry
     DevStats *st;
 };
 
@@ -150,6 +151,7 @@ struct NumArgs {
     int32_t *sg_cur;          // K_DG (segmented): per workgroup, sg_cap A entries x 2 int32 (cursor, run end)
     int sg_cap;               //   (nullptr / 0: runs found by two searches per segment)
     int b32;               // nnz(B) * 8 < 2^32: B entries addressed with 32-bit offsets
+    int64_t nnzb;          // nnz(B): gathers clamp their offsets to its last entry
     const int64_t *map_off;   // reuse: per row, where its products' ranks start in map
     uint16_t *map;            // reuse: rank in C's row per multiplication
     int values_only;          // K_PL: C's columns are already in place, write values only

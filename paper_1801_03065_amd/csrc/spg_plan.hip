@@ -26,12 +26,22 @@ namespace {
 
 constexpr int PL_U = 16;  // products per lane held in registers (fast path)
 
+// Staged A entry: one 16-byte LDS record, so a product reads its A value and
+// its B row's length (which masks the lanes past the row) in one LDS read,
+// and a gather its B row's offset and length in another.  Entries past the
+// row have length 0.
+struct StRec {
+    double av;
+    uint32_t x8;  // 8 * (B row start): byte offset into FP64 values (fast path: nnz(B) * 8 < 2^32)
+    int32_t len;
+};
+
 // LDS of one wavefront.  Staging, values and sorted columns are double
 // buffered: row p's results leave from one half while row p+1 is staged into
 // the other.  Half b starts at half0 + b * hsize; offsets inside a half are
 // the same for both.
 struct PlLayout {
-    size_t bp, map, half0, hsize, st_bs, st_a, st_len, st_pk, vals, colbuf, total;
+    size_t bp, map, half0, hsize, st_bs, st_rec, vals, colbuf, total;
 };
 
 __host__ __device__ inline PlLayout pl_layout(int nw_max, int r_max, int acc_bytes) {
@@ -41,18 +51,14 @@ __host__ __device__ inline PlLayout pl_layout(int nw_max, int r_max, int acc_byt
     o += 8 * (size_t)PL_CAP;
     L.half0 = o;
     size_t h = 0;
-    L.st_bs = h;
+    L.st_bs = h;  // B row start per A entry (64-bit)
     h += 8 * WAVE;
-    L.st_a = h;
-    h += 8 * WAVE;
+    L.st_rec = h;  // per A entry: A value, byte offset of its B row's values (fast path), B row length
+    h += sizeof(StRec) * WAVE;
     L.vals = h;
     h += align16((size_t)acc_bytes * r_max);
     L.colbuf = h;
     h += align16(4 * (size_t)r_max);
-    L.st_len = h;
-    h += 4 * WAVE;
-    L.st_pk = h;  // fast path: (32-bit B offset, length) per A entry
-    h += 8 * WAVE;
     L.hsize = h;
     o += 2 * h;
     L.map = o;  // window word -> pair index (uint8)
@@ -129,13 +135,9 @@ __global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(4, 8))) vo
     // stage up to 64 A entries of a row into half b; returns the fast-path test
     auto stage = [&](int b, int cn, int64_t na, int64_t b0, int64_t b1, double av) -> bool {
         const int len = (int)(b1 - b0);
-        if (l < cn) {
-            unsigned char *hb = half(b);
-            ((int64_t *)(hb + L.st_bs))[l] = b0;
-            ((double *)(hb + L.st_a))[l] = av;
-            ((int32_t *)(hb + L.st_len))[l] = len;
-            ((int2 *)(hb + L.st_pk))[l] = make_int2((int)(uint32_t)b0, len);
-        }
+        unsigned char *hb = half(b);
+        if (l < cn) ((int64_t *)(hb + L.st_bs))[l] = b0;
+        ((StRec *)(hb + L.st_rec))[l] = StRec{av, (uint32_t)b0 * 8u, l < cn ? len : 0};
         return a.b32 && na <= WAVE && cn <= ng * NU && __ballot(l < cn && len > gs) == 0;
     };
     const int64_t step = sl.step;
@@ -187,27 +189,26 @@ __global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(4, 8))) vo
         if (l < d2.nw) npw_l = a.plan[d2.po + l];
     }
     // gathers of a staged row (fast path): every product's column and value,
-    // issued a row ahead of the products that use them
+    // issued a row ahead of the products that use them.  A lane past its B
+    // row loads the entry its offset names, clamped to B's last entry; the
+    // length test masks it when the products are added.
     int col[NU];
     VT pv[NU];
-    unsigned okm = 0;
-    auto gather = [&](int hb_i, int cn_g) {
-        const int2 *pk_s = (const int2 *)(half(hb_i) + L.st_pk);
-        int2 pk[NU];
+    const uint32_t q8 = 8u * (uint32_t)q, elast8 = 8u * (uint32_t)max(a.nnzb - 1, (int64_t)0);
+    auto gather = [&](int hb_i) {
+        const StRec *rec = (const StRec *)(half(hb_i) + L.st_rec);
+        uint2 xl[NU];
 #pragma unroll
-        for (int u = 0; u < NU; ++u) pk[u] = pk_s[g + u * ng];  // entries past cn are masked below
-        okm = 0;
+        for (int u = 0; u < NU; ++u) xl[u] = *(const uint2 *)&rec[g + u * ng].x8;
 #pragma unroll
         for (int u = 0; u < NU; ++u) {
-            const bool okg = (g + u * ng < cn_g) & (q < pk[u].y);
-            okm |= (unsigned)okg << u;
-            const uint32_t e = okg ? (uint32_t)pk[u].x + q : 0u;  // nnz(B) * 8 < 2^32 on this path
-            col[u] = ld32(a.bci, e);
-            pv[u] = ld32(a.bval, e);
+            const uint32_t e8 = min(xl[u].x + q8, elast8);
+            col[u] = *(const int *)((const char *)a.bci + (e8 >> 1));
+            pv[u] = *(const VT *)((const char *)a.bval + (sizeof(VT) == 8 ? e8 : e8 >> 1));
         }
     };
     wave_lds_sync();
-    if (p0 < pend && fast_c) gather(0, (int)min((int64_t)WAVE, d.ae - d.ab));
+    if (p0 < pend && fast_c) gather(0);
 
     // Per row p: plan decode and products of p, p's stores, pipeline loads
     // (p+2s B extents, p+3s A entries and plan pairs, p+4s descriptor, p+5s
@@ -222,8 +223,7 @@ __global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(4, 8))) vo
         const int wlo = d.wlo;
         unsigned char *hb = half(b);
         int64_t *st_bs = (int64_t *)(hb + L.st_bs);
-        double *st_a = (double *)(hb + L.st_a);
-        int32_t *st_len = (int32_t *)(hb + L.st_len);
+        StRec *rec = (StRec *)(hb + L.st_rec);
         S *vals = (S *)(hb + L.vals);
         int32_t *colbuf = (int32_t *)(hb + L.colbuf);
         const bool fast = fast_c;
@@ -250,11 +250,14 @@ __global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(4, 8))) vo
         // ---- 2. products into vals[rank]
         if (ok) {
             if (fast) {
+                int lenv[NU];  // every length first: one LDS wait, not one per product
+#pragma unroll
+                for (int u = 0; u < NU; ++u) lenv[u] = rec[g + u * ng].len;
 #pragma unroll
                 for (int u = 0; u < NU; ++u) {
-                    if (okm & (1u << u)) {
+                    if (q < lenv[u]) {
                         const int c = col[u];
-                        const VT av = (VT)st_a[g + u * ng];  // issued with the word-map read
+                        const VT av = (VT)rec[g + u * ng].av;  // issued with the word-map read
                         const int s = mapw[c >> 5];
                         const unsigned long long e = bp[s];
                         const int rk = (int)(uint32_t)(e >> 32) + bits_below((uint32_t)e, c & 31);
@@ -270,15 +273,15 @@ __global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(4, 8))) vo
                             const int j = a.aci[c0 + l];
                             const int64_t b0 = a.brp[j], b1 = a.brp[j + 1];
                             st_bs[l] = b0;
-                            st_len[l] = (int)(b1 - b0);
-                            st_a[l] = (double)a.aval[c0 + l];
+                            rec[l].len = (int)(b1 - b0);
+                            rec[l].av = (double)a.aval[c0 + l];
                         }
                         wave_lds_sync();
                     }
                     for (int t = g; t < cn; t += ng) {
                         const int64_t bs = st_bs[t];
-                        const int len = st_len[t];
-                        const VT av = (VT)st_a[t];
+                        const int len = rec[t].len;
+                        const VT av = (VT)rec[t].av;
                         for (int p = q; p < len; p += gs) {
                             const int c = a.bci[bs + p];
                             const int s = map[(c >> 5) - wlo];
@@ -351,10 +354,10 @@ __global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(4, 8))) vo
             cpw = cpw_next;
         }
         wave_lds_sync();
-        // (issued even when there is no next fast row, with every lane masked
-        // to element 0: a fixed count of loads after the pipeline loads lets
-        // their wait at the loop's end skip the gathers)
-        gather(b ^ 1, has1 && fast_c ? (int)min((int64_t)WAVE, nan1) : 0);
+        // (issued even when there is no next fast row: a fixed count of loads
+        // after the pipeline loads lets their wait at the loop's end skip the
+        // gathers; the offsets are clamped into B whatever the records hold)
+        gather(b ^ 1);
     }
 }
 

@@ -148,17 +148,20 @@ def test_batch_with_degenerate_members():
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 def test_batch_autotune_per_class(dtype):
-    """Products of very different shapes get their own (policy, lanes) choices:
-    C_i rows of ~16 entries over B rows of ~4 and rows of ~900 over B rows of
-    ~30 fall into different classes, whose lanes-per-B-row candidates do not
-    overlap; every product still equals the oracle."""
+    """Products of very different shapes get their own (policy, lanes) choices.
+    C_i rows of under 16 entries over B rows of ~3 fall into the first class
+    (average C row size <= 16), rows of several hundred over B rows of ~26
+    into the third (<= 1024); their lanes-per-B-row candidates (the rounded
+    average B row length and its neighbours: 4-8 against 16-64) do not
+    overlap, so the two groups must differ.  Every product still equals the
+    oracle."""
     import torch
 
     import paper_1801_03065_amd as spg
     from helpers import check_f32, f32_inputs
 
-    small = synth.batch_specs(6, 11, n_lo=2000, n_hi=4000, lam_lo=3.5, lam_hi=4.5)
-    big = synth.batch_specs(6, 12, n_lo=2000, n_hi=4000, lam_lo=28.0, lam_hi=32.0)
+    small = synth.batch_specs(6, 11, n_lo=2000, n_hi=4000, lam_lo=2.5, lam_hi=3.0)
+    big = synth.batch_specs(6, 12, n_lo=2000, n_hi=4000, lam_lo=24.0, lam_hi=28.0)
     specs = [s for pair in zip(small, big) for s in pair]
     pairs = synth.batch_matrices(specs)
     tdt = torch.float64 if dtype == "f64" else torch.float32
@@ -171,6 +174,10 @@ def test_batch_autotune_per_class(dtype):
     h.check_errors()
     pol, lanes = h.batch_choices(len(pairs))
     print("per-product policy", pol.tolist(), "lanes", lanes.tolist())
+    avg_c = np.array([int(n) / A.nrows for n, (A, _) in zip(nnzs, pairs)])
+    assert np.all(avg_c[0::2] <= 16) and np.all((avg_c[1::2] > 128) & (avg_c[1::2] <= 1024)), avg_c
+    for grp in (slice(0, None, 2), slice(1, None, 2)):  # one choice per class
+        assert len(set(zip(pol[grp].tolist(), lanes[grp].tolist()))) == 1
     assert set(lanes[0::2].tolist()).isdisjoint(set(lanes[1::2].tolist()))
     assert len(set(zip(pol.tolist(), lanes.tolist()))) >= 2
     for r in range(2):  # a second call reuses the tuned classes
