@@ -25,6 +25,7 @@ namespace spg {
 namespace {
 
 constexpr int PL_U = 16;  // products per lane held in registers (fast path)
+constexpr int PL_CH = 4;  // consecutive rows per chunk of a wavefront's rows
 
 // Staged A entry: one 16-byte LDS record, so a product reads its A value and
 // its B row's length (which masks the lanes past the row) in one LDS read,
@@ -94,11 +95,17 @@ __global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(4, 8))) vo
     int64_t lo, hi;
     rs_bounds(a.rs, lo, hi);
     const int64_t cbase = a.cbase_row >= 0 ? a.coff[a.cbase_row] : 0;
-    const Slice sl = xcd_slice(lo, hi);
+    // The wavefront takes its die's rows in chunks of PL_CH consecutive rows,
+    // chunk after chunk at the stride of all the die's wavefronts: neighbouring
+    // rows of C share most of their B rows (a stencil's rows i and i+1 share
+    // two thirds), so a chunk finds them in the CU's L1 and the die's L2
+    // (27-point A*A on 100^3: 44% less traffic beyond L2 than row by row).
+    const Slice sl = xcd_slice(lo, hi, PL_CH, 0);
 
-    // Software pipeline over the wavefront's rows p, p+s, p+2s, ...: while
-    // row p is processed, row p+s's B extents (second level) and row p+2s's A
-    // entries and plan pairs (first level) load; lane k < 7 loads field k of
+    // Software pipeline over the wavefront's rows p, p+s, p+2s, ... (p+s: the
+    // next row of its sequence, pos(t + 1)): while row p is processed, row
+    // p+s's B extents (second level) and row p+2s's A entries and plan pairs
+    // (first level) load; lane k < 7 loads field k of
     // row p+3s's descriptor (moved to scalar registers a row later) and the
     // row index of p+4s loads a row before that.  Memory operations are
     // issued in the order gathers of row p, pipeline loads, stores of row
@@ -142,16 +149,17 @@ __global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(4, 8))) vo
     };
     const int64_t step = sl.step;
     const int64_t p0 = sl.idx, pend = sl.end;
+    auto pos = [&](int64_t t) -> int64_t { return p0 + (t / PL_CH) * step + (t % PL_CH); };  // t-th row
     auto row_at = [&](int64_t pp) -> int { return pp < pend ? read_first(a.rs.rows[pp]) : 0; };
 
     // ---- prologue: fill the pipeline (waits here are once per kernel).
     // Naming by distance from the current row p: *_m = row p+s, *_l = row
     // p+2s; rn, r2, r3 = raw descriptors of rows p+s, p+2s, p+3s.
     RowDescP d = p0 < pend ? to_uni(load_desc(row_at(p0))) : RowDescP{};      // row p
-    int64_t rn = p0 + step < pend ? load_desc(row_at(p0 + step)) : 0;
-    int64_t r2 = p0 + 2 * step < pend ? load_desc(row_at(p0 + 2 * step)) : 0;
-    int64_t r3 = p0 + 3 * step < pend ? load_desc(row_at(p0 + 3 * step)) : 0;
-    int i4 = p0 + 4 * step < pend ? a.rs.rows[p0 + 4 * step] : 0;            // row index of p+4s
+    int64_t rn = pos(1) < pend ? load_desc(row_at(pos(1))) : 0;
+    int64_t r2 = pos(2) < pend ? load_desc(row_at(pos(2))) : 0;
+    int64_t r3 = pos(3) < pend ? load_desc(row_at(pos(3))) : 0;
+    int i4 = pos(4) < pend ? a.rs.rows[pos(4)] : 0;            // row index of p+4s
     bool fast_c = false;
     uint2 cpw = make_uint2(0u, 0u), npw_m = make_uint2(0u, 0u), npw_l = make_uint2(0u, 0u);
     int64_t nb0n = 0, nb1n = 0;  // row p+s: B extents per A entry
@@ -170,7 +178,7 @@ __global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(4, 8))) vo
         fast_c = stage(0, cn, d.ae - d.ab, b0, b1, av);
         if (l < d.nw) cpw = a.plan[d.po + l];
     }
-    if (p0 + step < pend) {
+    if (pos(1) < pend) {
         const RowDescP d1 = to_uni(rn);
         if (l < min((int64_t)WAVE, d1.ae - d1.ab)) {
             const int j = a.aci[d1.ab + l];
@@ -180,7 +188,7 @@ __global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(4, 8))) vo
         }
         if (l < d1.nw) npw_m = a.plan[d1.po + l];
     }
-    if (p0 + 2 * step < pend) {
+    if (pos(2) < pend) {
         const RowDescP d2 = to_uni(r2);
         if (l < min((int64_t)WAVE, d2.ae - d2.ab)) {
             nj_l = a.aci[d2.ab + l];
@@ -217,9 +225,9 @@ __global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(4, 8))) vo
     // for its gathers, every earlier load has landed too, so a loaded value
     // is only read (or copied) a row after its load, without a stall.
     int b = 0;  // half of the current row
-    for (int64_t pp = p0; pp < pend; pp += step, b ^= 1) {
-        const bool has1 = pp + step < pend, has2 = pp + 2 * step < pend, has3 = pp + 3 * step < pend,
-                   has4 = pp + 4 * step < pend;
+    for (int64_t t = 0; pos(t) < pend; ++t, b ^= 1) {
+        const bool has1 = pos(t + 1) < pend, has2 = pos(t + 2) < pend, has3 = pos(t + 3) < pend,
+                   has4 = pos(t + 4) < pend;
         const int wlo = d.wlo;
         unsigned char *hb = half(b);
         int64_t *st_bs = (int64_t *)(hb + L.st_bs);
@@ -345,7 +353,7 @@ __global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(4, 8))) vo
         rn = r2;
         r2 = r3;
         r3 = has4 ? load_desc(i4s) : 0;                                 // row p+4s
-        i4 = pp + 5 * step < pend ? a.rs.rows[pp + 5 * step] : 0;      // row p+5s
+        i4 = pos(t + 5) < pend ? a.rs.rows[pos(t + 5)] : 0;      // row p+5s
         // ---- 5. row p+s: staged, then its gathers (the last memory
         //      operations before its products)
         if (has1) {
