@@ -36,7 +36,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBPS = 8000.0
 
 # HBM bytes per launch of the dominant kernel, from two rocprofv3 counter
-# passes (FETCH_SIZE, WRITE_SIZE) over `bench.py --steps 1 --warmup 0 --no-cpu`,
+# passes (FETCH_SIZE, WRITE_SIZE) over `bench.py --forms "" --steps 1 --warmup 0 --no-cpu`,
 # each scaled by what the counter reads for the bench's 2 GiB device copy
 # (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0).  Valid only for the kernel sources they
 # were taken on: reported as null once those sources change.
@@ -44,9 +44,9 @@ TRAFFIC = {
     "kernel": "k_num_pl",
     "sources": ["paper_1801_03065_amd/csrc/spg_plan.hip", "paper_1801_03065_amd/csrc/spg_internal.hpp",
                 "paper_1801_03065_amd/csrc/spg_accum.hpp"],
-    "sha256": "40c505d6112deb35cc5517370be24a05114fca21b2ba8b0c21d28ce9d84e45c2",
-    "read_bytes": 4.0396e9,
-    "write_bytes": 1.5084e9,
+    "sha256": "685c5a294ecc8a39a02fc5dfc236e1faaeb739cf39dd68b20e328bf4c8d3c6af",
+    "read_bytes": 3.7630e9,
+    "write_bytes": 1.5282e9,
 }
 
 
