@@ -185,7 +185,7 @@ __device__ __forceinline__ RowDesc row_desc(int i, const int64_t *arp, const int
 // LDS of the symbolic bit-window kernel: the window's bits and summary, and
 // two halves (row p, row p+1) of staging and of the row's (word, bits) list.
 struct SwLayout {
-    size_t bits, summ, half0, hsize, st_cbs, st_clen, st_pk, pairs, total;
+    size_t bits, summ, half0, hsize, st_cbs, st_clen, pairs, total;
 };
 
 __host__ __device__ inline SwLayout sw_layout(int nwm) {
@@ -202,8 +202,6 @@ __host__ __device__ inline SwLayout sw_layout(int nwm) {
     h += 8 * WAVE;
     L.st_clen = h;
     h += 4 * WAVE;
-    L.st_pk = h;  // fast path: (32-bit compressed extent, length) per A entry, length 0 past the row
-    h += 8 * WAVE;
     L.pairs = h;
     h += 8 * PL_CAP;
     L.hsize = h;
@@ -289,11 +287,19 @@ __global__ __launch_bounds__(WAVE) void k_sym_dw(SymArgs a) {
     auto stage = [&](int b, int64_t na, int64_t c0, uint32_t c1lo) -> int {
         const int cn = (int)min((int64_t)WAVE, na);
         const int len = (int)(c1lo - (uint32_t)c0);
-        if (l < cn) {
+        // B entries below 2^32 (b32): the extent as (low word, length), and
+        // length 0 past the row, so the fast path reads both in one 8-byte
+        // LDS read; otherwise the 64-bit extent.  The slow paths read the
+        // extent's low word when b32 (later chunks store it 64-bit).  (A
+        // separate packed array, 512 more LDS bytes per half, made the
+        // batched symbolic launch of wide-window products 60% slower; the
+        // same launch with its grid cut to as many wavefronts but the
+        // smaller LDS was not.)
+        if (a.b32)
+            ((int2 *)(half(b) + L.st_cbs))[l] = l < cn ? make_int2((int)(uint32_t)c0, len) : make_int2(0, 0);
+        else if (l < cn)
             ((int64_t *)(half(b) + L.st_cbs))[l] = c0;
-            ((int32_t *)(half(b) + L.st_clen))[l] = len;
-        }
-        ((int2 *)(half(b) + L.st_pk))[l] = l < cn ? make_int2((int)(uint32_t)c0, len) : make_int2(0, 0);
+        if (l < cn) ((int32_t *)(half(b) + L.st_clen))[l] = len;
         const bool fast = a.b32 && na <= WAVE && cn <= ng * SW_SLOTS;
         return fast ? 1 + (__ballot(l < cn && len > gs) != 0) : 0;
     };
@@ -363,7 +369,7 @@ __global__ __launch_bounds__(WAVE) void k_sym_dw(SymArgs a) {
             // to B's last entry, and is masked by the length when the words
             // are ORed
             const uint32_t elast = (uint32_t)max(a.nnzb - 1, (int64_t)0);
-            const int2 *st_pk = (const int2 *)(half(b) + L.st_pk);
+            const int2 *st_pk = (const int2 *)st_cbs;  // fast path: packed (b32)
             int2 pk[SW_SLOTS];
 #pragma unroll
             for (int s2 = 0; s2 < SW_SLOTS; ++s2)  // staging reads first: one LDS wait for all
@@ -403,7 +409,7 @@ __global__ __launch_bounds__(WAVE) void k_sym_dw(SymArgs a) {
                 if (q < lenv[s2]) dw_or(bits, summ, wd[s2] - (uint32_t)wlo, wc[s2]);
             if (kk == 2) {  // words beyond the lane group of B rows longer than it
                 for (int t = g; t < cn; t += ng) {
-                    const int64_t cb = st_cbs[t];
+                    const int64_t cb = (uint32_t)((const int2 *)st_cbs)[t].x;
                     const int len = st_clen[t];
                     for (int w = q + gs; w < len; w += gs) {
                         uint32_t dd, cc;
@@ -429,7 +435,7 @@ __global__ __launch_bounds__(WAVE) void k_sym_dw(SymArgs a) {
                 // time (kept light: the kernel's register budget is set by the
                 // fast path)
                 for (int t = g; t < ccn; t += ng) {
-                    const int64_t cb = scbs[t];
+                    const int64_t cb = a.b32 ? (int64_t)(uint32_t)((const int2 *)scbs)[t].x : scbs[t];
                     const int len = sclen[t];
                     for (int w = q; w < len; w += gs) {
                         uint32_t dd, cc;
@@ -1138,10 +1144,17 @@ size_t lds_num_dw(int nw_max, int r_max, int acc_bytes, int) { return dw_layout(
 size_t lds_sym_dg(int nw_max) { return dg_layout(nw_max).total; }
 size_t lds_num_dg(int nw_max) { return dg_layout(nw_max).total; }
 
+// At most SW_WAVES_PER_CU resident wavefronts per CU: with small windows the
+// LDS would admit 21, and the 27-point A*A symbolic launch is fastest at 18
+// (1.01 ms against 1.17 at 21, 1.05 at 16, 1.14 at 12): more rows in flight
+// per CU than its L1 holds the B records of.
+constexpr int SW_WAVES_PER_CU = 18;
+
 template <bool COMP, int LGS>
 hipError_t sym_dw_lg(const SymArgs &a, const LaunchCfg &c) {
     const size_t lds = lds_sym_dw(a.nw_max);
-    const int grid = c.grid > 0 ? c.grid : resident_grid(k_sym_dw<COMP, LGS>, WAVE, lds, c.cus);
+    const int grid = c.grid > 0 ? c.grid
+                                : std::min(SW_WAVES_PER_CU * c.cus, resident_grid(k_sym_dw<COMP, LGS>, WAVE, lds, c.cus));
     hipLaunchKernelGGL((k_sym_dw<COMP, LGS>), dim3(grid), dim3(WAVE), lds, c.stream, a);
     return hipGetLastError();
 }
