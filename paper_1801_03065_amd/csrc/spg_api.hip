@@ -106,6 +106,7 @@ struct spg_handle_s {
     void *scr = nullptr;       // this device's static scratch array (device address)
     bool noalloc = false;      // the current call carves its scratch from scr instead of hipMalloc
     bool values_only = false;  // the current call writes C's values only (structure known)
+    int lg_map_cur = 2;        // lanes per B row (log2) of the position-map kernels in the current launch set
     int num_policy = 0;        // accumulator policy of the numeric classification (SPG_ACC_*)
     // batch plans: products fall into classes by the average row size of C_i,
     // and the autotuner picks (policy, lanes per B row) per class; each class
@@ -180,6 +181,15 @@ static int sr_lg(int max_flops) {
 int lg_group(double avg) {
     // lanes per B row: the average length rounded up to a power of two, 4..64
     int lg = 2;
+    while (lg < 6 && (double)(1 << lg) < avg) ++lg;
+    return lg;
+}
+
+// lanes per B row of the position-map kernels: the average B row length
+// rounded up to a power of two, 1..64 (products on maps carry no structure
+// work, so a B row of one entry gets one lane)
+static int lg_map(double avg) {
+    int lg = 0;
     while (lg < 6 && (double)(1 << lg) < avg) ++lg;
     return lg;
 }
@@ -801,7 +811,7 @@ static spg_status launch_kinds(spg_handle h, NumArgs<VT> na, const long long *kc
             na.rs.kind = K;
             na.r_max = std::max(kmax[K][1], 1);
             const int lgt = K == K_SR ? sr_lg(kmax[K_SR][1]) : 6;
-            HIPCHK(launch_num_map<VT>(na, acc, lgt, h->lg_num, lc, kcount[K]));
+            HIPCHK(launch_num_map<VT>(na, acc, lgt, h->lg_map_cur, lc, kcount[K]));
         }
         for (int kk = 0; kk < NK; ++kk) h->kc_nomap[kk] = map_kind(kk) ? 0 : kcount[kk];
         kcount = h->kc_nomap;  // the remaining kinds below
@@ -1194,18 +1204,21 @@ static spg_status numeric_impl(spg_handle h, const VT *aval, const VT *bval, int
             na.rs.rows = h->perm_cls.as<int32_t>() + (size_t)c * h->fp.m;
             na.rs.koff = h->koff_cls.as<int64_t>() + (size_t)c * (NK + 1);
             na.lg_gs = h->cls_lg[c];
+            h->lg_map_cur = lg_map(h->cls_avg_b[c]);
             s = launch_kinds<VT>(h, na, h->cls_kc[c], h->cls_km[c], acc, vo, h->cls_pol[c]);
         }
         na.lg_gs = h->lg_num;
     } else {
         na.rs.rows = h->perm_num.as<int32_t>();
         na.rs.koff = h->koff_num.as<int64_t>();
+        h->lg_map_cur = lg_map(h->avg_len);
         s = launch_kinds<VT>(h, na, hs.kcount_num, hs.kmax_num, acc, vo);
     }
     if (s != SPG_OK || !h->heavy_split) return s;
     // heaviest rows: FP64 accumulation for FP32 values (FP64 values: the same kernels)
     na.rs.rows = h->perm_heavy.as<int32_t>();
     na.rs.koff = h->koff_heavy.as<int64_t>();
+    h->lg_map_cur = lg_map(h->avg_len);
     return launch_kinds<VT>(h, na, hs.kcount_heavy, hs.kmax_heavy, sizeof(VT) == 4 ? ACC_WIDE : acc, vo);
 }
 static spg_status numeric_check(spg_handle h, const spg_csr *A, const spg_csr *B, spg_csr_out *C) {
@@ -1300,14 +1313,15 @@ static spg_status build_maps(spg_handle h, const int32_t *cci) {
     na.map = h->map.as<uint16_t>();
     na.st = h->dstats.as<DevStats>();
     LaunchCfg lc{st, 0, h->cus};
-    auto kinds = [&](const int32_t *perm, const int64_t *koff, const long long *kcount, const int (*kmax)[3]) {
+    auto kinds = [&](const int32_t *perm, const int64_t *koff, const long long *kcount, const int (*kmax)[3],
+                     double avg_b) {
         na.rs.rows = perm;
         na.rs.koff = koff;
         for (int K : {K_SR, K_DW, K_WH, K_HW}) {
             if (kcount[K] <= 0) continue;
             na.rs.kind = K;
             const int lgt = K == K_SR ? sr_lg(kmax[K_SR][1]) : 6;
-            hipError_t e = launch_posmap(na, cci, lgt, h->lg_num, lc, kcount[K]);
+            hipError_t e = launch_posmap(na, cci, lgt, lg_map(avg_b), lc, kcount[K]);
             if (e != hipSuccess) return e;
         }
         return hipSuccess;
@@ -1316,13 +1330,14 @@ static spg_status build_maps(spg_handle h, const int32_t *cci) {
         for (int c = 0; c < 4; ++c) {
             if (h->cls_rows[c] == 0) continue;
             HIPCHK(kinds(h->perm_cls.as<int32_t>() + (size_t)c * m, h->koff_cls.as<int64_t>() + (size_t)c * (NK + 1),
-                         h->cls_kc[c], h->cls_km[c]));
+                         h->cls_kc[c], h->cls_km[c], h->cls_avg_b[c]));
         }
     } else {
-        HIPCHK(kinds(h->perm_num.as<int32_t>(), h->koff_num.as<int64_t>(), hs.kcount_num, hs.kmax_num));
+        HIPCHK(kinds(h->perm_num.as<int32_t>(), h->koff_num.as<int64_t>(), hs.kcount_num, hs.kmax_num, h->avg_len));
     }
     if (h->heavy_split)
-        HIPCHK(kinds(h->perm_heavy.as<int32_t>(), h->koff_heavy.as<int64_t>(), hs.kcount_heavy, hs.kmax_heavy));
+        HIPCHK(kinds(h->perm_heavy.as<int32_t>(), h->koff_heavy.as<int64_t>(), hs.kcount_heavy, hs.kmax_heavy,
+                     h->avg_len));
     h->maps_ok = true;
     return SPG_OK;
 }

@@ -227,11 +227,13 @@ hipError_t num_map_ts(const NumArgs<VT> &a, const LaunchCfg &c, int64_t rows) {
     return hipGetLastError();
 }
 
-// lanes per B row: 4 .. T
+// lanes per B row: 1 .. T
 template <int LGT, typename F>
 hipError_t by_lgs(int lgs, F &&f) {
-    lgs = std::max(2, std::min(lgs, LGT));
+    lgs = std::max(0, std::min(lgs, LGT));
     switch (lgs) {
+    case 0: return f(std::integral_constant<int, 0>{});
+    case 1: return f(std::integral_constant<int, 1>{});
     case 2: return f(std::integral_constant<int, 2>{});
     case 3: return f(std::integral_constant<int, (LGT >= 3 ? 3 : 2)>{});
     case 4: return f(std::integral_constant<int, (LGT >= 4 ? 4 : 2)>{});
