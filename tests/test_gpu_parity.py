@@ -423,3 +423,38 @@ def test_numeric_rejects_missing_or_different_plan():
     torch.cuda.synchronize()
     ref, S = oracle_ref(A, A)
     check_f64(ref, S, (rp.cpu().numpy().astype(np.int64), C.col_idx.cpu().numpy(), C.values.cpu().numpy()))
+
+
+def _runs_matrix(m, n, seed):
+    """Rows made of runs of consecutive columns (1..12 long, up to 70 entries
+    per row): their B rows lie back to back in B's storage."""
+    rng = np.random.default_rng(seed)
+    rows = []
+    for _ in range(m):
+        cols = set()
+        for _ in range(int(rng.integers(0, 8))):
+            s0, ln = int(rng.integers(0, n - 12)), int(rng.integers(1, 13))
+            cols.update(range(s0, s0 + ln))
+        rows.append(sorted(cols)[:70])
+    rp = np.zeros(m + 1, dtype=np.int64)
+    rp[1:] = np.cumsum([len(r) for r in rows])
+    ci = np.array([c for r in rows for c in r], dtype=np.int32)
+    return synth.Csr(m, n, rp, ci, rng.standard_normal(ci.size))
+
+
+@pytest.mark.parametrize("comp", [-1, 0, 1])
+def test_bit_window_rows_of_column_runs(comp):
+    """Bit-window kernels on rows made of runs of consecutive columns (B rows
+    back to back in B's storage), with empty B rows inside the runs, B rows
+    longer than a lane group, rows beyond the fast path's slots and rows of
+    more than 64 entries; compression by the rule, off and on."""
+    rng = np.random.default_rng(21)
+    n = 2500
+    A = _runs_matrix(500, n, 22)
+    lens = np.where(rng.random(n) < 0.2, 0, rng.integers(1, 40, n))
+    B = synth.random_csr(n, 3000, lens, 23)
+    ref, S = oracle_ref(A, B)
+    got, h = run(A, B, accumulator=1, compression=comp)
+    check_f64(ref, S, got)
+    st = h.stats()
+    assert st["rows_symbolic"]["dense_wave"] > 0
