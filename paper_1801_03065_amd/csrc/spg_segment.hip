@@ -10,9 +10,12 @@
 //
 //   1. the part of each B row that falls in the segment (B's columns are
 //      sorted, so it is one run, found by binary search; rows with one A
-//      entry chunk keep a cursor from segment to segment),
+//      entry chunk keep a cursor from segment to segment); the nonempty runs
+//      are staged back to back, so that a lane's consecutive products lie in
+//      one run or the next,
 //   2. structure: the run's columns OR-ed into an LDS bit array over the
-//      segment's words, Thread-Flat-Parallel over the segment's products,
+//      segment's words, Thread-Flat-Parallel over the segment's products
+//      (a few consecutive products per lane),
 //   3. ranks: prefix popcounts of the words give every column its place in
 //      the row,
 //   4. values: each product added at its rank in LDS (Algorithm 1's
@@ -28,7 +31,11 @@
 namespace spg {
 namespace {
 
-constexpr int SG_U = 8;  // products per lane per round of the flat walks (loads in flight)
+constexpr int SG_U = 8;  // consecutive products per lane per round of the flat walks (loads in flight)
+// The staging scan adds (run length) + (1 << SG_SHIFT if the run is nonempty):
+// products below the shift, the nonempty run's slot above it.
+constexpr int SG_SHIFT = 48;
+constexpr long long SG_ONE = 1ll << SG_SHIFT, SG_LEN = SG_ONE - 1;
 // Lanes per workgroup (one heavy row).  LDS (~70 KB) allows two workgroups
 // per CU; 512 lanes rather than 256 double the loads in flight per CU for the
 // same LDS, with registers held to 128 (4 waves per SIMD).
@@ -102,9 +109,10 @@ __device__ __forceinline__ int64_t sg_gallop(const int32_t *bci, int64_t lo, int
 }
 
 // Index k of the run that holds flat product f: the first k >= kc with
-// st_off[k] > f (inclusive run ends, nondecreasing).  A lane's products
-// increase, so its previous run kc is the usual answer (one LDS read for long
-// runs); otherwise a binary search over the rest.
+// st_off[k] > f (run ends, increasing: only nonempty runs are staged).  A
+// lane's products increase, so its previous run kc is a lower bound and often
+// the answer; otherwise a binary search over the rest.  Called once per lane
+// and round: the lane's next products are in the same run or the next one.
 __device__ __forceinline__ int sg_find(const int64_t *st_off, int cn, long long f, int kc) {
     if (st_off[kc] > f) return kc;
     int lo = kc + 1, hi = cn - 1;  // st_off[cn - 1] > f for every product f of the chunk
@@ -159,13 +167,14 @@ __global__ __launch_bounds__(SG_WG) __attribute__((amdgpu_waves_per_eu(4, 4))) v
         // into its B row that moves from segment to segment
         int64_t cur = 0, bend = 0;
         int cn1 = 0;
+        VT av1 = VT(0);
         if (one_chunk) {
             cn1 = (int)(ae - ab);
             if (t < cn1) {
                 const int j = a.aci[ab + t];
                 cur = a.brp[j];
                 bend = a.brp[j + 1];
-                st_a[t] = a.aval[ab + t];
+                av1 = a.aval[ab + t];
             }
         }
         int bad = 0;
@@ -184,27 +193,38 @@ __global__ __launch_bounds__(SG_WG) __attribute__((amdgpu_waves_per_eu(4, 4))) v
             const int span = min(w2 - w1, SG_NW);
             const int dbase = wlo + w1;  // column-set word of bits[0]
             long long tot1 = 0;
+            int nz1 = 0;
             if (one_chunk) {
                 long long len = 0;
+                int64_t s0 = cur;
                 if (t < cn1) {
                     const int64_t e = single ? bend : sg_gallop(a.bci, cur, bend, col_hi);
-                    st_lo[t] = cur;
                     len = e - cur;
                     cur = e;
                 }
-                const long long ex = sg_block_excl_scan(len, red, &tot1);
-                if (t < cn1) st_off[t] = ex + len;
+                long long pt;
+                const long long ex = sg_block_excl_scan(len + (len > 0 ? SG_ONE : 0), red, &pt);
+                tot1 = pt & SG_LEN;
+                nz1 = (int)(pt >> SG_SHIFT);
+                if (len > 0) {
+                    const int k = (int)(ex >> SG_SHIFT);
+                    st_lo[k] = s0;
+                    st_off[k] = (ex & SG_LEN) + len;
+                    st_a[k] = av1;
+                }
                 __syncthreads();
             }
             // pass 1 (structure) and pass 2 (values) walk the same runs
             for (int pass = 0; pass < 2; ++pass) {
                 for (int64_t cb = ab; cb < ae; cb += SG_WG) {
-                    int cn = cn1;
+                    int cn = nz1;
                     long long tot = tot1;
                     if (!one_chunk) {
-                        cn = (int)min((int64_t)SG_WG, ae - cb);
+                        const int cnc = (int)min((int64_t)SG_WG, ae - cb);
                         long long len = 0;
-                        if (t < cn) {
+                        int64_t lo_t = 0;
+                        VT av_t = VT(0);
+                        if (t < cnc) {
                             const int64_t k = cb - ab + t;
                             const int j = a.aci[cb + t];
                             const int32_t ck = cur_g ? cur_g[k] : 0;
@@ -224,12 +244,20 @@ __global__ __launch_bounds__(SG_WG) __attribute__((amdgpu_waves_per_eu(4, 4))) v
                                 s0 = sg_lower_bound(a.bci, s0, s1, col_lo);
                                 s1 = sg_lower_bound(a.bci, s0, s1, col_hi);
                             }
-                            st_lo[t] = s0;
-                            st_a[t] = a.aval[cb + t];
+                            lo_t = s0;
+                            av_t = a.aval[cb + t];
                             len = s1 - s0;
                         }
-                        const long long ex = sg_block_excl_scan(len, red, &tot);
-                        if (t < cn) st_off[t] = ex + len;
+                        long long pt;
+                        const long long ex = sg_block_excl_scan(len + (len > 0 ? SG_ONE : 0), red, &pt);
+                        tot = pt & SG_LEN;
+                        cn = (int)(pt >> SG_SHIFT);
+                        if (len > 0) {
+                            const int k = (int)(ex >> SG_SHIFT);
+                            st_lo[k] = lo_t;
+                            st_off[k] = (ex & SG_LEN) + len;
+                            st_a[k] = av_t;
+                        }
                         __syncthreads();
                     }
                     int kc = 0;  // this lane's current run
@@ -237,15 +265,26 @@ __global__ __launch_bounds__(SG_WG) __attribute__((amdgpu_waves_per_eu(4, 4))) v
                         int64_t e[SG_U];
                         int kk[SG_U];
                         bool ok[SG_U];
+                        // the lane's SG_U consecutive products: one search, then
+                        // at most one step per product (every staged run is nonempty)
+                        const long long fb = f0 + (long long)t * SG_U;
+                        int k = fb < tot ? sg_find(st_off, cn, fb, kc) : kc;
+                        long long rb = k ? st_off[k - 1] : 0, re = st_off[k];
+                        int64_t lo = st_lo[k];
 #pragma unroll
                         for (int u = 0; u < SG_U; ++u) {
-                            const long long f = f0 + u * SG_WG + t;
+                            const long long f = fb + u;
                             ok[u] = f < tot;
-                            if (ok[u]) kc = sg_find(st_off, cn, f, kc);
-                            const int k = kc;
+                            if (ok[u] && f >= re) {
+                                ++k;
+                                rb = re;
+                                re = st_off[k];
+                                lo = st_lo[k];
+                            }
                             kk[u] = k;
-                            e[u] = st_lo[k] + (f - (k ? st_off[k - 1] : 0));
+                            e[u] = lo + (f - rb);
                         }
+                        kc = k;
                         int c[SG_U];
 #pragma unroll
                         for (int u = 0; u < SG_U; ++u) c[u] = ok[u] ? a.bci[e[u]] : 0;
