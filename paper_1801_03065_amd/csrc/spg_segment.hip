@@ -11,17 +11,19 @@
 //   1. the part of each B row that falls in the segment (B's columns are
 //      sorted, so it is one run, found by binary search; rows with one A
 //      entry chunk keep a cursor from segment to segment); the nonempty runs
-//      are staged back to back, so that a lane's consecutive products lie in
-//      one run or the next,
+//      are staged back to back,
 //   2. structure: the run's columns OR-ed into an LDS bit array over the
 //      segment's words, Thread-Flat-Parallel over the segment's products
-//      (a few consecutive products per lane),
+//      (neighbouring lanes on neighbouring products, so a run's loads
+//      coalesce; each wavefront finds the run of every product of its
+//      window from run starts marked in LDS and a forward fill),
 //   3. ranks: prefix popcounts of the words give every column its place in
 //      the row,
 //   4. values: each product added at its rank in LDS (Algorithm 1's
 //      accumulation), Thread-Flat-Parallel again,
-//   5. write-out: columns from the bits, values in rank order (coalesced),
-//      at the segment's offset in the row, which the symbolic phase recorded.
+//   5. write-out: values in rank order, then columns expanded from the bits
+//      into LDS and stored in rank order (both coalesced), at the segment's
+//      offset in the row, which the symbolic phase recorded.
 //
 // Nothing lives in HBM but the inputs and C; a row with one segment (its
 // entries and window fit) runs the same steps once, with whole B rows.
@@ -31,7 +33,7 @@
 namespace spg {
 namespace {
 
-constexpr int SG_U = 8;  // consecutive products per lane per round of the flat walks (loads in flight)
+constexpr int SG_U = 8;  // products per lane per round of the flat walks (loads in flight)
 // The staging scan adds (run length) + (1 << SG_SHIFT if the run is nonempty):
 // products below the shift, the nonempty run's slot above it.
 constexpr int SG_SHIFT = 48;
@@ -109,10 +111,9 @@ __device__ __forceinline__ int64_t sg_gallop(const int32_t *bci, int64_t lo, int
 }
 
 // Index k of the run that holds flat product f: the first k >= kc with
-// st_off[k] > f (run ends, increasing: only nonempty runs are staged).  A
-// lane's products increase, so its previous run kc is a lower bound and often
-// the answer; otherwise a binary search over the rest.  Called once per lane
-// and round: the lane's next products are in the same run or the next one.
+// st_off[k] > f (run ends, increasing: only nonempty runs are staged).  The
+// wavefront's window starts increase, so its previous run kc is a lower bound
+// and often the answer; otherwise a binary search over the rest.
 __device__ __forceinline__ int sg_find(const int64_t *st_off, int cn, long long f, int kc) {
     if (st_off[kc] > f) return kc;
     int lo = kc + 1, hi = cn - 1;  // st_off[cn - 1] > f for every product f of the chunk
@@ -135,6 +136,9 @@ __global__ __launch_bounds__(SG_WG) __attribute__((amdgpu_waves_per_eu(4, 4))) v
     __shared__ int64_t st_off[SG_WG];  // inclusive prefix of the run lengths
     __shared__ VT st_a[SG_WG];
     __shared__ long long red[SG_WG / WAVE + 2];
+    // per wavefront: the run of each product of its window (relative to the
+    // window's first run), so that neighbouring lanes take neighbouring products
+    __shared__ __align__(16) uint16_t widx[SG_WG / WAVE][SG_U * WAVE];
     const int t = threadIdx.x;
     for (int w = t; w < SG_NW; w += SG_WG) bits[w] = 0;
     for (int r = t; r < SG_CAP; r += SG_WG) vals[r] = A::zero();
@@ -260,31 +264,70 @@ __global__ __launch_bounds__(SG_WG) __attribute__((amdgpu_waves_per_eu(4, 4))) v
                         }
                         __syncthreads();
                     }
-                    int kc = 0;  // this lane's current run
+                    // Flat walk: per round, wavefront wv takes the SG_U * 64
+                    // products from F = f0 + wv * SG_U * 64 on, lane l the
+                    // products F + l + 64 u (neighbouring lanes, neighbouring
+                    // B entries).  The run of each product comes from a
+                    // per-wavefront index: run starts marked in LDS, then a
+                    // forward fill (max-scan) over the window.
+                    const int wv = t / WAVE, l = t % WAVE;
+                    uint16_t *wi = widx[wv];
+                    int kc = 0;  // the run of the wavefront's previous window start
                     for (long long f0 = 0; f0 < tot; f0 += (long long)SG_WG * SG_U) {
                         int64_t e[SG_U];
-                        int kk[SG_U];
                         bool ok[SG_U];
-                        // the lane's SG_U consecutive products: one search, then
-                        // at most one step per product (every staged run is nonempty)
-                        const long long fb = f0 + (long long)t * SG_U;
-                        int k = fb < tot ? sg_find(st_off, cn, fb, kc) : kc;
-                        long long rb = k ? st_off[k - 1] : 0, re = st_off[k];
-                        int64_t lo = st_lo[k];
-#pragma unroll
-                        for (int u = 0; u < SG_U; ++u) {
-                            const long long f = fb + u;
-                            ok[u] = f < tot;
-                            if (ok[u] && f >= re) {
-                                ++k;
-                                rb = re;
-                                re = st_off[k];
-                                lo = st_lo[k];
+                        const long long F = f0 + (long long)wv * (SG_U * WAVE);
+                        int klo = 0;
+                        if (F < tot) {  // the same for the whole wavefront
+                            klo = sg_find(st_off, cn, F, kc);
+                            kc = klo;
+                            *(uint4 *)&wi[l * SG_U] = make_uint4(0u, 0u, 0u, 0u);
+                            wave_lds_sync();
+                            const long long Fe = min(F + (long long)(SG_U * WAVE), tot);
+                            for (int k = klo + 1 + l; k < cn; k += WAVE) {
+                                const long long st = st_off[k - 1];  // run k's first product
+                                if (st >= Fe) break;                  // starts increase with k
+                                wi[st - F] = (uint16_t)(k - klo);
                             }
-                            kk[u] = k;
-                            e[u] = lo + (f - rb);
+                            wave_lds_sync();
+                            const uint4 q4 = *(const uint4 *)&wi[l * SG_U];
+                            uint32_t w4[4] = {q4.x, q4.y, q4.z, q4.w};
+                            int m[SG_U];
+#pragma unroll
+                            for (int u = 0; u < 4; ++u) {
+                                m[2 * u] = (int)(w4[u] & 0xFFFFu);
+                                m[2 * u + 1] = (int)(w4[u] >> 16);
+                            }
+#pragma unroll
+                            for (int u = 1; u < SG_U; ++u) m[u] = max(m[u], m[u - 1]);
+                            int incl = m[SG_U - 1];  // inclusive max-scan of the lanes' maxima
+                            incl = max(incl, __builtin_amdgcn_update_dpp(0, incl, 0x111, 0xF, 0xF, false));
+                            incl = max(incl, __builtin_amdgcn_update_dpp(0, incl, 0x112, 0xF, 0xF, false));
+                            incl = max(incl, __builtin_amdgcn_update_dpp(0, incl, 0x114, 0xF, 0xF, false));
+                            incl = max(incl, __builtin_amdgcn_update_dpp(0, incl, 0x118, 0xF, 0xF, false));
+                            incl = max(incl, __builtin_amdgcn_update_dpp(0, incl, 0x142, 0xA, 0xF, false));
+                            incl = max(incl, __builtin_amdgcn_update_dpp(0, incl, 0x143, 0xC, 0xF, false));
+                            const int before = __shfl_up(incl, 1);
+                            const int pm = l ? before : 0;
+#pragma unroll
+                            for (int u = 0; u < 4; ++u)
+                                w4[u] = (uint32_t)max(m[2 * u], pm) | ((uint32_t)max(m[2 * u + 1], pm) << 16);
+                            *(uint4 *)&wi[l * SG_U] = make_uint4(w4[0], w4[1], w4[2], w4[3]);
+                            wave_lds_sync();
+#pragma unroll
+                            for (int u = 0; u < SG_U; ++u) {
+                                const long long f = F + l + u * WAVE;
+                                ok[u] = f < tot;
+                                const int k = klo + (int)wi[l + u * WAVE];
+                                e[u] = st_lo[k] + (f - (k ? st_off[k - 1] : 0));
+                            }
+                        } else {
+#pragma unroll
+                            for (int u = 0; u < SG_U; ++u) {
+                                ok[u] = false;
+                                e[u] = 0;
+                            }
                         }
-                        kc = k;
                         int c[SG_U];
 #pragma unroll
                         for (int u = 0; u < SG_U; ++u) c[u] = ok[u] ? a.bci[e[u]] : 0;
@@ -303,7 +346,7 @@ __global__ __launch_bounds__(SG_WG) __attribute__((amdgpu_waves_per_eu(4, 4))) v
                                 const int d = (c[u] >> 5) - dbase;
                                 if (!ok[u] || (unsigned)d >= (unsigned)SG_NW) continue;
                                 const int r = (int)pre[d] + bits_below(bits[d], c[u] & 31);
-                                if (r < SG_CAP) A::add(&vals[r], st_a[kk[u]], v[u]);
+                                if (r < SG_CAP) A::add(&vals[r], st_a[klo + (int)wi[l + u * WAVE]], v[u]);
                             }
                         }
                     }
@@ -337,9 +380,15 @@ __global__ __launch_bounds__(SG_WG) __attribute__((amdgpu_waves_per_eu(4, 4))) v
                     __syncthreads();
                 }
             }
-            // write-out: columns from the bits (one word per lane, strided),
-            // values in rank order; both cleared for the next segment
+            // write-out at the segment's offset, both arrays in rank order with
+            // coalesced stores: first the values; then the columns, expanded
+            // from the bits (one word per lane) into the freed value array;
+            // the bits and values are cleared for the next segment
             const int64_t o = c0 + p1 - cbase;
+            const int cw = min(cnt, SG_CAP);
+            for (int r = t; r < cw; r += SG_WG) a.cval[o + r] = A::fin(vals[r]);
+            __syncthreads();
+            int32_t *colbuf = (int32_t *)vals;  // SG_CAP * sizeof(S) >= 4 * SG_CAP bytes
             for (int w = t; w < span; w += SG_WG) {
                 uint32_t m = bits[w];
                 int r = pre[w];
@@ -347,16 +396,15 @@ __global__ __launch_bounds__(SG_WG) __attribute__((amdgpu_waves_per_eu(4, 4))) v
                 while (m) {
                     const int b = __ffs(m) - 1;
                     m &= m - 1;
-                    if (r < cnt) a.cci[o + r] = colb + b;
+                    if (r < cw) colbuf[r] = colb + b;
                     ++r;
                 }
                 bits[w] = 0;
             }
-            const int cw = min(cnt, SG_CAP);
-            for (int r = t; r < cw; r += SG_WG) {
-                a.cval[o + r] = A::fin(vals[r]);
-                vals[r] = A::zero();
-            }
+            __syncthreads();
+            for (int r = t; r < cw; r += SG_WG) a.cci[o + r] = colbuf[r];
+            __syncthreads();
+            for (int r = t; r < cw; r += SG_WG) vals[r] = A::zero();
             __syncthreads();
         }
         if (t == 0 && bad) atomicAdd(&a.st->mismatch, 1);
