@@ -44,7 +44,7 @@ TRAFFIC = {
     "kernel": "k_num_pl",
     "sources": ["paper_1801_03065_amd/csrc/spg_plan.hip", "paper_1801_03065_amd/csrc/spg_internal.hpp",
                 "paper_1801_03065_amd/csrc/spg_accum.hpp"],
-    "sha256": "685c5a294ecc8a39a02fc5dfc236e1faaeb739cf39dd68b20e328bf4c8d3c6af",
+    "sha256": "719d8a4524ada7e55d1fa1e9f192a3d0e11229692fbd1783a3c566039b807076",
     "read_bytes": 3.7630e9,
     "write_bytes": 1.5282e9,
 }

@@ -848,14 +848,15 @@ static spg_status launch_kinds(spg_handle h, NumArgs<VT> na, const long long *kc
         na.rs.queue = h->queue.as<int32_t>() + XCDS * K_DG;
         HIPCHK(launch_fill_i32(na.rs.queue, XCDS, 0, st));
         lc.grid = std::min(grid_cap(kcount[K_DG]), sg_resident_grid(acc, sizeof(VT) == 8, h->cus));
-        // rows with more than one chunk of A entries keep per-entry cursors in
-        // HBM scratch (without it they search each run from the B row's start)
+        // rows with more than one chunk of A entries keep per-entry cursors
+        // (32-bit positions in B) in HBM scratch; without it (or with
+        // nnz(B) >= 2^31) they search each run from the B row's start
         na.sg_cur = nullptr;
         na.sg_cap = 0;
         const int64_t mxa = (int64_t)h->hst->maxnnza;
-        if (mxa > WG_BIG) {
+        if (mxa > WG_BIG && h->fp.nnzb < (int64_t(1) << 31)) {
             const int cap = (int)std::min<int64_t>(mxa, 65536);
-            const size_t bytes = (size_t)lc.grid * 2 * cap * sizeof(int32_t);
+            const size_t bytes = (size_t)lc.grid * 3 * cap * sizeof(int32_t);
             if (h->noalloc) {
                 if (bytes <= NOALLOC_SCRATCH_BYTES) {  // else runs are searched without cursors
                     na.sg_cur = (int32_t *)h->scr;

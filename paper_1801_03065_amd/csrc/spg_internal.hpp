@@ -148,7 +148,7 @@ struct NumArgs {
     const int32_t *row_words; // K_PL: number of pairs of the row
     const int32_t *plan_len;  // K_DG (segmented): room in plan per row
     const uint8_t *sym_kind;  // K_DG (segmented): rows of symbolic kind K_DG with room hold a segment list
-    int32_t *sg_cur;          // K_DG (segmented): per workgroup, sg_cap A entries x 2 int32 (cursor, run end)
+    int32_t *sg_cur;          // K_DG (segmented): per workgroup, sg_cap A entries x 3 int32 (cursor, run end, B row end)
     int sg_cap;               //   (nullptr / 0: runs found by two searches per segment)
     int b32;               // nnz(B) * 8 < 2^32: B entries addressed with 32-bit offsets
     int64_t nnzb;          // nnz(B): gathers clamp their offsets to its last entry

@@ -158,13 +158,20 @@ __global__ __launch_bounds__(SG_WG) __attribute__((amdgpu_waves_per_eu(4, 4))) v
         const int nseg = has_list ? (int)list[0].x : 1;
         const bool single = nseg == 1;
         const bool one_chunk = ae - ab <= SG_WG;
-        // several chunks: per A entry a cursor into its B row (offset of the
-        // segment's first entry) and the run end, in this workgroup's scratch
-        int32_t *cur_g = nullptr, *nxt_g = nullptr;
+        // several chunks: per A entry, in this workgroup's scratch, the B
+        // entry where its run in the segment starts (cursor), where that run
+        // ends, and the end of its B row (absolute positions: nnz(B) < 2^31),
+        // so that a chunk's staging loads no A column and no B row extent
+        int32_t *cur_g = nullptr, *nxt_g = nullptr, *end_g = nullptr;
         if (!one_chunk && !single && a.sg_cur != nullptr && ae - ab <= a.sg_cap) {
-            cur_g = a.sg_cur + (int64_t)blockIdx.x * 2 * a.sg_cap;
+            cur_g = a.sg_cur + (int64_t)blockIdx.x * 3 * a.sg_cap;
             nxt_g = cur_g + a.sg_cap;
-            for (int64_t k = t; k < ae - ab; k += SG_WG) cur_g[k] = 0;
+            end_g = nxt_g + a.sg_cap;
+            for (int64_t k = t; k < ae - ab; k += SG_WG) {
+                const int j = a.aci[ab + k];
+                cur_g[k] = (int32_t)a.brp[j];
+                end_g[k] = (int32_t)a.brp[j + 1];
+            }
             __syncthreads();
         }
         // one chunk: lane t keeps A entry t for the whole row, with a cursor
@@ -230,23 +237,24 @@ __global__ __launch_bounds__(SG_WG) __attribute__((amdgpu_waves_per_eu(4, 4))) v
                         VT av_t = VT(0);
                         if (t < cnc) {
                             const int64_t k = cb - ab + t;
-                            const int j = a.aci[cb + t];
-                            const int32_t ck = cur_g ? cur_g[k] : 0;
-                            const int32_t nk = (cur_g && pass == 1) ? nxt_g[k] : 0;
-                            int64_t s0 = a.brp[j], s1 = a.brp[j + 1];
+                            int64_t s0, s1;
                             if (cur_g) {
-                                const int64_t b0 = s0;
-                                s0 = b0 + ck;
+                                s0 = cur_g[k];
                                 if (pass == 0) {
-                                    s1 = sg_gallop(a.bci, s0, s1, col_hi);
-                                    nxt_g[k] = (int32_t)(s1 - b0);
+                                    s1 = sg_gallop(a.bci, s0, (int64_t)end_g[k], col_hi);
+                                    nxt_g[k] = (int32_t)s1;
                                 } else {
-                                    s1 = b0 + nk;
-                                    cur_g[k] = nk;  // the next segment starts where this run ends
+                                    s1 = nxt_g[k];
+                                    cur_g[k] = (int32_t)s1;  // the next segment starts where this run ends
                                 }
-                            } else if (!single) {
-                                s0 = sg_lower_bound(a.bci, s0, s1, col_lo);
-                                s1 = sg_lower_bound(a.bci, s0, s1, col_hi);
+                            } else {
+                                const int j = a.aci[cb + t];
+                                s0 = a.brp[j];
+                                s1 = a.brp[j + 1];
+                                if (!single) {
+                                    s0 = sg_lower_bound(a.bci, s0, s1, col_lo);
+                                    s1 = sg_lower_bound(a.bci, s0, s1, col_hi);
+                                }
                             }
                             lo_t = s0;
                             av_t = a.aval[cb + t];
