@@ -135,6 +135,7 @@ struct NumArgs {
     VT *cval;
     int64_t cbase_row;
     RowSet rs;
+    RowSet rs2;               // K_DG (segmented, FP64): a second row set taken first in the same launch (rows unset: none)
     int nw_max;
     int r_max;
     int ts;

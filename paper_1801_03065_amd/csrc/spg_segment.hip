@@ -146,9 +146,24 @@ __global__ __launch_bounds__(SG_WG) __attribute__((amdgpu_waves_per_eu(4, 4))) v
     rs_bounds(a.rs, qlo, qhi);
     const int64_t cbase = a.cbase_row >= 0 ? a.coff[a.cbase_row] : 0;
     int x = blockIdx.x % XCDS;
+    // a second row set (the heaviest rows, when FP64 values make their kernel
+    // this one) is drained first, then the first set
+    bool second = a.rs2.rows != nullptr;
+    int64_t qlo2 = 0, qhi2 = 0;
+    if (second) rs_bounds(a.rs2, qlo2, qhi2);
+    int x2 = x;
     for (;;) {
-        const int i = sg_next_row(a.rs, qlo, qhi, x, red);
-        if (i < 0) break;
+        int i;
+        if (second) {
+            i = sg_next_row(a.rs2, qlo2, qhi2, x2, red);
+            if (i < 0) {
+                second = false;
+                continue;
+            }
+        } else {
+            i = sg_next_row(a.rs, qlo, qhi, x, red);
+            if (i < 0) break;
+        }
         const int2 win = a.rwin[i];
         const int wlo = win.x, nw = win.y - win.x + 1;
         const int64_t c0 = a.coff[i], nnz = a.coff[i + 1] - c0;
