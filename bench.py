@@ -44,9 +44,9 @@ TRAFFIC = {
     "kernel": "k_num_pl",
     "sources": ["paper_1801_03065_amd/csrc/spg_plan.hip", "paper_1801_03065_amd/csrc/spg_internal.hpp",
                 "paper_1801_03065_amd/csrc/spg_accum.hpp"],
-    "sha256": "719d8a4524ada7e55d1fa1e9f192a3d0e11229692fbd1783a3c566039b807076",
-    "read_bytes": 3.7630e9,
-    "write_bytes": 1.5282e9,
+    "sha256": "156d6593d23d8bbb4435a340cf7bcd4ccc5b2a4da28cb76b0ed0a7bb9847ec1b",
+    "read_bytes": 3.7433e9,
+    "write_bytes": 1.5278e9,
 }
 
 
