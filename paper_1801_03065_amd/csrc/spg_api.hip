@@ -790,12 +790,13 @@ static bool scratch_grid(spg_handle h, size_t per_wg, int *grid) {
 // plan's row offsets.
 // One persistent launch per non-empty kind, sized by the kind's maxima.
 // dg: DG_OWN launches this set's segmented rows; DG_MERGE also takes the
-// rows of na.rs2 (rs2_count of them) in the same launch; DG_SKIP leaves them
-// to such a launch.
+// rows of na.rs2 (rs2_count of them, accumulated with acc2) in the same
+// launch; DG_SKIP leaves them to such a launch.
 enum { DG_OWN = 0, DG_MERGE = 1, DG_SKIP = 2 };
 template <typename VT>
 static spg_status launch_kinds(spg_handle h, NumArgs<VT> na, const long long *kcount, const int (*kmax)[3],
-                               int acc, bool vo = false, int pol = -1, int dg = DG_OWN, int64_t rs2_count = 0) {
+                               int acc, bool vo = false, int pol = -1, int dg = DG_OWN, int64_t rs2_count = 0,
+                               int acc2 = -1) {
     if (pol < 0) pol = h->num_policy;
     hipStream_t st = h->stream;
     const size_t sbytes = (sizeof(VT) == 8 || acc != ACC_NATIVE) ? 8 : 4;
@@ -852,6 +853,7 @@ static spg_status launch_kinds(spg_handle h, NumArgs<VT> na, const long long *kc
         na.rs.queue = h->queue.as<int32_t>() + XCDS * K_DG;
         HIPCHK(launch_fill_i32(na.rs.queue, XCDS, 0, st));
         int64_t dg_rows = kcount[K_DG];
+        const int acc_b = (dg == DG_MERGE && rs2_count > 0 && acc2 >= 0) ? acc2 : acc;
         if (dg == DG_MERGE && rs2_count > 0) {
             na.rs2.kind = K_DG;
             na.rs2.queue = h->queue.as<int32_t>() + XCDS * K_EMPTY;  // the empty kind has no queue of its own
@@ -860,7 +862,7 @@ static spg_status launch_kinds(spg_handle h, NumArgs<VT> na, const long long *kc
         } else {
             na.rs2 = RowSet{};
         }
-        lc.grid = std::min(grid_cap(dg_rows), sg_resident_grid(acc, sizeof(VT) == 8, h->cus));
+        lc.grid = std::min(grid_cap(dg_rows), sg_resident_grid(acc, acc_b, sizeof(VT) == 8, h->cus));
         // rows with more than one chunk of A entries keep per-entry cursors
         // (32-bit positions in B) in HBM scratch; without it (or with
         // nnz(B) >= 2^31) they search each run from the B row's start
@@ -881,7 +883,7 @@ static spg_status launch_kinds(spg_handle h, NumArgs<VT> na, const long long *kc
             }
             (void)hipGetLastError();
         }
-        HIPCHK(launch_num_sg<VT>(na, acc, lc));
+        HIPCHK(launch_num_sg<VT>(na, acc, acc_b, lc));
         lc.grid = 0;
     } else if (kcount[K_DG] > 0 && dg != DG_SKIP) {
         na.rs.kind = K_DG;
@@ -1212,8 +1214,11 @@ static spg_status numeric_impl(spg_handle h, const VT *aval, const VT *bval, int
         na.map = h->map.as<uint16_t>();
     }
     spg_status s = SPG_OK;
-    const bool merge_dg = sizeof(VT) == 8 && h->heavy_split && h->sg_mode && hs.kcount_heavy[K_DG] > 0 &&
-                          !(h->ncls && h->cls_tuned);
+    // the heaviest rows' segments (FP64 accumulation for FP32 values) go
+    // through the other segmented rows' launch, taken first, so that the two
+    // kinds of work overlap
+    const bool merge_dg = h->heavy_split && h->sg_mode && hs.kcount_heavy[K_DG] > 0 && !(h->ncls && h->cls_tuned);
+    const int acc_heavy = sizeof(VT) == 4 ? ACC_WIDE : acc;
     if (h->ncls && h->cls_tuned) {  // one launch set per product class
         for (int c = 0; c < 4 && s == SPG_OK; ++c) {
             if (h->cls_rows[c] == 0) continue;
@@ -1228,15 +1233,13 @@ static spg_status numeric_impl(spg_handle h, const VT *aval, const VT *bval, int
         na.rs.rows = h->perm_num.as<int32_t>();
         na.rs.koff = h->koff_num.as<int64_t>();
         h->lg_map_cur = lg_map(h->avg_len);
-        // FP64 values: the heaviest rows' segment kernel is the same, so one
-        // launch takes both row sets (heaviest first) and their work overlaps
         if (merge_dg) {
             na.rs2.rows = h->perm_heavy.as<int32_t>();
             na.rs2.koff = h->koff_heavy.as<int64_t>();
             na.rs2.range = nullptr;
         }
         s = launch_kinds<VT>(h, na, hs.kcount_num, hs.kmax_num, acc, vo, -1, merge_dg ? DG_MERGE : DG_OWN,
-                             merge_dg ? hs.kcount_heavy[K_DG] : 0);
+                             merge_dg ? hs.kcount_heavy[K_DG] : 0, acc_heavy);
         na.rs2 = RowSet{};
     }
     if (s != SPG_OK || !h->heavy_split) return s;
@@ -1244,8 +1247,7 @@ static spg_status numeric_impl(spg_handle h, const VT *aval, const VT *bval, int
     na.rs.rows = h->perm_heavy.as<int32_t>();
     na.rs.koff = h->koff_heavy.as<int64_t>();
     h->lg_map_cur = lg_map(h->avg_len);
-    return launch_kinds<VT>(h, na, hs.kcount_heavy, hs.kmax_heavy, sizeof(VT) == 4 ? ACC_WIDE : acc, vo, -1,
-                            merge_dg ? DG_SKIP : DG_OWN);
+    return launch_kinds<VT>(h, na, hs.kcount_heavy, hs.kmax_heavy, acc_heavy, vo, -1, merge_dg ? DG_SKIP : DG_OWN);
 }
 static spg_status numeric_check(spg_handle h, const spg_csr *A, const spg_csr *B, spg_csr_out *C) {
     if (!h->ready) return fail(h, SPG_ERR_NOT_READY, "spgemm_numeric before a successful spgemm_symbolic");

@@ -436,8 +436,8 @@ template <typename VT>
 hipError_t launch_num_hl(const NumArgs<VT> &a, int acc, const LaunchCfg &c);
 // Heavy rows in column segments (sorted B): the segment lists are in a.plan.
 template <typename VT>
-hipError_t launch_num_sg(const NumArgs<VT> &a, int acc, const LaunchCfg &c);
-int sg_resident_grid(int acc, bool dbl, int cus);
+hipError_t launch_num_sg(const NumArgs<VT> &a, int acc, int acc2, const LaunchCfg &c);  // acc2: rows of a.rs2
+int sg_resident_grid(int acc, int acc2, bool dbl, int cus);
 template <typename VT>
 hipError_t launch_num_wh(const NumArgs<VT> &a, int acc, const LaunchCfg &c);
 template <typename VT>

@@ -125,13 +125,20 @@ __device__ __forceinline__ int sg_find(const int64_t *st_off, int cn, long long 
     return lo;
 }
 
-template <typename VT, int ACC>
+// ACC accumulates the rows of a.rs, ACC2 those of a.rs2 (FP32 values: the
+// heaviest rows in FP64); the value array holds either kind of entry.
+template <typename VT, int ACC, int ACC2>
 __global__ __launch_bounds__(SG_WG) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_num_sg(NumArgs<VT> a) {
     using A = Accum<VT, ACC>;
     using S = typename A::store_t;
+    using A2 = Accum<VT, ACC2>;
+    using S2 = typename A2::store_t;
+    constexpr int VB = sizeof(S) > sizeof(S2) ? sizeof(S) : sizeof(S2);
     __shared__ __align__(16) uint32_t bits[SG_NW];
     __shared__ uint16_t pre[SG_NW];
-    __shared__ S vals[SG_CAP];
+    __shared__ __align__(16) unsigned char vals_raw[SG_CAP * VB];
+    S *vals = (S *)vals_raw;
+    S2 *vals2 = (S2 *)vals_raw;
     __shared__ int64_t st_lo[SG_WG];   // run start (B entry) per A entry of the chunk
     __shared__ int64_t st_off[SG_WG];  // inclusive prefix of the run lengths
     __shared__ VT st_a[SG_WG];
@@ -141,13 +148,12 @@ __global__ __launch_bounds__(SG_WG) __attribute__((amdgpu_waves_per_eu(4, 4))) v
     __shared__ __align__(16) uint16_t widx[SG_WG / WAVE][SG_U * WAVE];
     const int t = threadIdx.x;
     for (int w = t; w < SG_NW; w += SG_WG) bits[w] = 0;
-    for (int r = t; r < SG_CAP; r += SG_WG) vals[r] = A::zero();
+    for (int r = t; r < SG_CAP * VB / 4; r += SG_WG) ((uint32_t *)vals_raw)[r] = 0u;  // every kind of zero
     int64_t qlo, qhi;
     rs_bounds(a.rs, qlo, qhi);
     const int64_t cbase = a.cbase_row >= 0 ? a.coff[a.cbase_row] : 0;
     int x = blockIdx.x % XCDS;
-    // a second row set (the heaviest rows, when FP64 values make their kernel
-    // this one) is drained first, then the first set
+    // a second row set (the heaviest rows) is drained first, then the first set
     bool second = a.rs2.rows != nullptr;
     int64_t qlo2 = 0, qhi2 = 0;
     if (second) rs_bounds(a.rs2, qlo2, qhi2);
@@ -164,6 +170,7 @@ __global__ __launch_bounds__(SG_WG) __attribute__((amdgpu_waves_per_eu(4, 4))) v
             i = sg_next_row(a.rs, qlo, qhi, x, red);
             if (i < 0) break;
         }
+        const bool acc2 = ACC2 != ACC && second;  // this row accumulates with ACC2
         const int2 win = a.rwin[i];
         const int wlo = win.x, nw = win.y - win.x + 1;
         const int64_t c0 = a.coff[i], nnz = a.coff[i + 1] - c0;
@@ -369,7 +376,10 @@ __global__ __launch_bounds__(SG_WG) __attribute__((amdgpu_waves_per_eu(4, 4))) v
                                 const int d = (c[u] >> 5) - dbase;
                                 if (!ok[u] || (unsigned)d >= (unsigned)SG_NW) continue;
                                 const int r = (int)pre[d] + bits_below(bits[d], c[u] & 31);
-                                if (r < SG_CAP) A::add(&vals[r], st_a[klo + (int)wi[l + u * WAVE]], v[u]);
+                                if (r < SG_CAP) {
+                                    if (acc2) A2::add(&vals2[r], st_a[klo + (int)wi[l + u * WAVE]], v[u]);
+                                    else A::add(&vals[r], st_a[klo + (int)wi[l + u * WAVE]], v[u]);
+                                }
                             }
                         }
                     }
@@ -409,9 +419,9 @@ __global__ __launch_bounds__(SG_WG) __attribute__((amdgpu_waves_per_eu(4, 4))) v
             // the bits and values are cleared for the next segment
             const int64_t o = c0 + p1 - cbase;
             const int cw = min(cnt, SG_CAP);
-            for (int r = t; r < cw; r += SG_WG) a.cval[o + r] = A::fin(vals[r]);
+            for (int r = t; r < cw; r += SG_WG) a.cval[o + r] = acc2 ? A2::fin(vals2[r]) : A::fin(vals[r]);
             __syncthreads();
-            int32_t *colbuf = (int32_t *)vals;  // SG_CAP * sizeof(S) >= 4 * SG_CAP bytes
+            int32_t *colbuf = (int32_t *)vals_raw;  // SG_CAP * VB >= 4 * SG_CAP bytes
             for (int w = t; w < span; w += SG_WG) {
                 uint32_t m = bits[w];
                 int r = pre[w];
@@ -427,18 +437,21 @@ __global__ __launch_bounds__(SG_WG) __attribute__((amdgpu_waves_per_eu(4, 4))) v
             __syncthreads();
             for (int r = t; r < cw; r += SG_WG) a.cci[o + r] = colbuf[r];
             __syncthreads();
-            for (int r = t; r < cw; r += SG_WG) vals[r] = A::zero();
+            for (int r = t; r < cw; r += SG_WG) {  // all-zero bytes either way
+                if (acc2) vals2[r] = A2::zero();
+                else vals[r] = A::zero();
+            }
             __syncthreads();
         }
         if (t == 0 && bad) atomicAdd(&a.st->mismatch, 1);
     }
 }
 
-template <typename VT, int ACC>
+template <typename VT, int ACC, int ACC2>
 hipError_t num_sg_impl(const NumArgs<VT> &a, const LaunchCfg &c) {
     int grid = c.grid;
-    if (grid <= 0) grid = sg_resident_grid(ACC, sizeof(VT) == 8, c.cus);
-    hipLaunchKernelGGL((k_num_sg<VT, ACC>), dim3(grid), dim3(SG_WG), 0, c.stream, a);
+    if (grid <= 0) grid = sg_resident_grid(ACC, ACC2, sizeof(VT) == 8, c.cus);
+    hipLaunchKernelGGL((k_num_sg<VT, ACC, ACC2>), dim3(grid), dim3(SG_WG), 0, c.stream, a);
     return hipGetLastError();
 }
 
@@ -454,22 +467,26 @@ int resident(K kernel, int cus) {
 
 }  // namespace
 
-int sg_resident_grid(int acc, bool dbl, int cus) {
-    if (dbl) return resident(k_num_sg<double, ACC_NATIVE>, cus);
-    if (acc == ACC_COMP) return resident(k_num_sg<float, ACC_COMP>, cus);
-    if (acc == ACC_WIDE) return resident(k_num_sg<float, ACC_WIDE>, cus);
-    return resident(k_num_sg<float, ACC_NATIVE>, cus);
+int sg_resident_grid(int acc, int acc2, bool dbl, int cus) {
+    if (dbl) return resident(k_num_sg<double, ACC_NATIVE, ACC_NATIVE>, cus);
+    if (acc2 == ACC_WIDE && acc == ACC_NATIVE) return resident(k_num_sg<float, ACC_NATIVE, ACC_WIDE>, cus);
+    if (acc2 == ACC_WIDE && acc == ACC_COMP) return resident(k_num_sg<float, ACC_COMP, ACC_WIDE>, cus);
+    if (acc == ACC_COMP) return resident(k_num_sg<float, ACC_COMP, ACC_COMP>, cus);
+    if (acc == ACC_WIDE) return resident(k_num_sg<float, ACC_WIDE, ACC_WIDE>, cus);
+    return resident(k_num_sg<float, ACC_NATIVE, ACC_NATIVE>, cus);
 }
 
 template <>
-hipError_t launch_num_sg<double>(const NumArgs<double> &a, int, const LaunchCfg &c) {
-    return num_sg_impl<double, ACC_NATIVE>(a, c);
+hipError_t launch_num_sg<double>(const NumArgs<double> &a, int, int, const LaunchCfg &c) {
+    return num_sg_impl<double, ACC_NATIVE, ACC_NATIVE>(a, c);
 }
 template <>
-hipError_t launch_num_sg<float>(const NumArgs<float> &a, int acc, const LaunchCfg &c) {
-    if (acc == ACC_COMP) return num_sg_impl<float, ACC_COMP>(a, c);
-    if (acc == ACC_WIDE) return num_sg_impl<float, ACC_WIDE>(a, c);
-    return num_sg_impl<float, ACC_NATIVE>(a, c);
+hipError_t launch_num_sg<float>(const NumArgs<float> &a, int acc, int acc2, const LaunchCfg &c) {
+    if (acc2 == ACC_WIDE && acc == ACC_NATIVE) return num_sg_impl<float, ACC_NATIVE, ACC_WIDE>(a, c);
+    if (acc2 == ACC_WIDE && acc == ACC_COMP) return num_sg_impl<float, ACC_COMP, ACC_WIDE>(a, c);
+    if (acc == ACC_COMP) return num_sg_impl<float, ACC_COMP, ACC_COMP>(a, c);
+    if (acc == ACC_WIDE) return num_sg_impl<float, ACC_WIDE, ACC_WIDE>(a, c);
+    return num_sg_impl<float, ACC_NATIVE, ACC_NATIVE>(a, c);
 }
 
 }  // namespace spg
