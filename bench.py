@@ -44,7 +44,7 @@ TRAFFIC = {
     "kernel": "k_num_pl",
     "sources": ["paper_1801_03065_amd/csrc/spg_plan.hip", "paper_1801_03065_amd/csrc/spg_internal.hpp",
                 "paper_1801_03065_amd/csrc/spg_accum.hpp"],
-    "sha256": "156d6593d23d8bbb4435a340cf7bcd4ccc5b2a4da28cb76b0ed0a7bb9847ec1b",
+    "sha256": "4c45b3afc98c22126d6833664bd1d6381f35cb2efb3f81e45ebc5e462adf7e84",
     "read_bytes": 3.7433e9,
     "write_bytes": 1.5278e9,
 }
