@@ -2,11 +2,13 @@
 by the symbolic phase) against the oracle, element by element.
 
 The cases aim at each step of the segmented path: rows whose A entries fit one
-chunk of 256 (a cursor per B row moves from segment to segment) and rows with
-several chunks (runs found by binary search per segment), dense words (a cut
-falls inside a run of full words), wide windows with few entries (segments
-cut only at the aligned word groups), windows far from column 0, the FP32
-forms, row panels, and B with unsorted rows (the window-wide kernel instead).
+chunk of 512 (a cursor per B row moves from segment to segment) and rows with
+several chunks (cursors kept in scratch between segments; these rows, longer
+than FP32's term limit, share the launch of the others and are taken first),
+dense words (a cut falls inside a run of full words), wide windows with few
+entries (segments cut only at the aligned word groups), windows far from
+column 0, the FP32 forms, row panels, and B with unsorted rows (the
+window-wide kernel instead).
 """
 import numpy as np
 import pytest
@@ -37,7 +39,7 @@ def _contiguous_rows(n, k, lens, starts, seed):
 
 
 def test_one_chunk_many_segments():
-    """Heavy rows with <= 256 A entries over long B rows: tens of segments."""
+    """Heavy rows of one chunk (<= 512 A entries) over long B rows: tens of segments."""
     A, B = _heavy({3: 200, 40: 120, 41: 256, 99: 60}, 120, 700, 1 << 20, 300, 3000, 101)
     ref, S = oracle_ref(A, B)
     got, h = run(A, B)
@@ -48,8 +50,8 @@ def test_one_chunk_many_segments():
 
 
 def test_many_chunks_many_segments():
-    """Heavy rows with > 256 A entries (several chunks per segment)."""
-    A, B = _heavy({0: 257, 17: 900, 50: 2000}, 80, 3000, 1 << 20, 20, 400, 202)
+    """Heavy rows of exactly one chunk (512 A entries) and of several (513, 900, 2000)."""
+    A, B = _heavy({0: 512, 5: 513, 17: 900, 50: 2000}, 80, 3000, 1 << 20, 20, 400, 202)
     ref, S = oracle_ref(A, B)
     got, h = run(A, B)
     check_f64(ref, S, got)
