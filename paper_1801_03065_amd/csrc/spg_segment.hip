@@ -6,12 +6,14 @@
 // the row's complete bit window, cuts it into segments: runs of consecutive
 // column-set words with at most SG_CAP entries that stay inside one aligned
 // group of SG_NW words.  The numeric phase then walks the segments in column
-// order, one 512-lane workgroup per row:
+// order, one 512-lane workgroup per row (a launch may hold two row sets, the
+// second taken first and accumulated with its own accumulator):
 //
 //   1. the part of each B row that falls in the segment (B's columns are
-//      sorted, so it is one run, found by binary search; rows with one A
-//      entry chunk keep a cursor from segment to segment); the nonempty runs
-//      are staged back to back,
+//      sorted, so it is one run; each A entry keeps a cursor into its B row
+//      from segment to segment, in a register for rows of one chunk of A
+//      entries, in HBM scratch for longer rows, else binary search); the
+//      nonempty runs are staged back to back,
 //   2. structure: the run's columns OR-ed into an LDS bit array over the
 //      segment's words, Thread-Flat-Parallel over the segment's products
 //      (neighbouring lanes on neighbouring products, so a run's loads
@@ -38,7 +40,7 @@ constexpr int SG_U = 8;  // products per lane per round of the flat walks (loads
 // products below the shift, the nonempty run's slot above it.
 constexpr int SG_SHIFT = 48;
 constexpr long long SG_ONE = 1ll << SG_SHIFT, SG_LEN = SG_ONE - 1;
-// Lanes per workgroup (one heavy row).  LDS (~70 KB) allows two workgroups
+// Lanes per workgroup (one heavy row).  LDS (~76 KB) allows two workgroups
 // per CU; 512 lanes rather than 256 double the loads in flight per CU for the
 // same LDS, with registers held to 128 (4 waves per SIMD).
 constexpr int SG_WG = 512;
