@@ -14,7 +14,7 @@ import numpy as np
 import pytest
 
 import synth
-from helpers import check_f32, check_f64, dev, f32_inputs, oracle_ref, run
+from helpers import check_f32, check_f64, check_structure, dev, f32_inputs, oracle_ref, run
 
 pytestmark = pytest.mark.gpu
 
@@ -107,6 +107,35 @@ def test_fp32_forms_on_segments(mode):
     got, h = run(A32, B32, dtype="f32", **opts)
     check_f32(ref, S, got, rel=1e-5 if mode == "plain" else 1e-6)
     assert h.stats()["rows_numeric"]["dense_wg"] >= 2 or mode == "heavy_fp64"
+
+
+def test_fp32_rows_past_term_limit_accumulate_in_fp64():
+    """FP32 values: segmented rows longer than the FP32 term limit (167 A
+    entries) share the other rows' launch but accumulate in FP64.  About 40
+    terms meet in each entry of C, so FP32 accumulation shows (the plain mode
+    exceeds 1e-7 S somewhere) while FP64 accumulation leaves only the final
+    rounding to FP32 (below 1e-7 S on every entry of those rows)."""
+    rng = np.random.default_rng(909)
+    counts = rng.integers(20, 120, 6)
+    counts[[1, 4]] = 900
+    A = synth.random_csr(6, 2000, counts, 910)
+    B = synth.random_csr(2000, 70000, np.full(2000, 3000), 911)
+    A32, B32 = f32_inputs(A), f32_inputs(B)
+    ref, S = oracle_ref(A32, B32)
+    heavy = np.concatenate([np.arange(ref.row_ptr[i], ref.row_ptr[i + 1]) for i in (1, 4)])
+
+    def rel_err(got):
+        check_structure(ref, got)
+        return np.abs(got[2].astype(np.float64) - ref.values) / np.maximum(S, 1e-300)
+
+    plain, _ = run(A32, B32, dtype="f32", fp32_terms_max=0)
+    got, h = run(A32, B32, dtype="f32")
+    st = h.stats()
+    assert st["rows_numeric"]["dense_wg"] >= 2 and st["fp64_rows"] >= 2
+    assert rel_err(plain)[heavy].max() > 1e-7
+    e = rel_err(got)
+    assert e[heavy].max() <= 1e-7
+    assert e.max() <= 1e-5
 
 
 def test_panels_through_segmented_rows():
